@@ -1,0 +1,305 @@
+"""Seeded synthetic hypergraph workloads.
+
+This module only produces inputs: hypergraphs in CSR form (row offsets + member
+vertex ids + optional integer timestamps) and streams of update batches.  It
+holds none of the triad arithmetic and none of the ID-assignment rule: batches
+name the hyperedges they delete by *handle* (the position of the hyperedge in
+the stream of every hyperedge ever created), and each consumer translates
+handles to the IDs its own store handed out.
+
+The shapes follow the paper's workloads (Sec. V, Table III: large hypergraphs,
+skewed vertex popularity, heavy-tailed cardinality, 50/50 insert/delete
+batches, Poisson arrival times for temporal hypergraphs).  The paper's datasets
+are not available, so these generators stand in for them.
+
+Distributions
+-------------
+* cardinality: uniform on [lo, hi] or a discrete power law P(k) ~ k^-alpha on
+  [lo, hi], sampled by inverse CDF;
+* members: i.i.d. rank draws with weights (rank + q)^-s (Zipf for q = 0,
+  Zipf-Mandelbrot for q > 0, uniform for s = 0); a draw that repeats a vertex
+  already in the hyperedge is redrawn, column by column, until the hyperedge
+  has the requested number of distinct vertices; ranks map to vertex ids
+  through a seeded permutation so the hubs are not at id 0;
+* members are emitted in draw order (unsorted) so consumers exercise their own
+  canonicalisation;
+* timestamps: microseconds, cumulative floor(Exp(mean)) gaps (ties occur);
+* deletions: uniform without replacement over the handles live at batch start.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import List, Optional
+
+import numpy as np
+
+SEED_BASE = 20251221
+
+
+# --------------------------------------------------------------------------- #
+# samplers
+# --------------------------------------------------------------------------- #
+def uniform_cards(rng: np.random.Generator, n: int, lo: int, hi: int) -> np.ndarray:
+    return rng.integers(lo, hi + 1, size=n, dtype=np.int64)
+
+
+def power_law_cards(rng: np.random.Generator, n: int, alpha: float, lo: int, hi: int) -> np.ndarray:
+    ks = np.arange(lo, hi + 1, dtype=np.float64)
+    w = ks ** (-alpha)
+    cdf = np.cumsum(w)
+    cdf /= cdf[-1]
+    u = rng.random(n)
+    idx = np.searchsorted(cdf, u, side="right")
+    idx = np.minimum(idx, len(ks) - 1)
+    return (lo + idx).astype(np.int64)
+
+
+class Popularity:
+    """Vertex popularity: weight (rank + q)^-s over ranks 1..n, ranks mapped
+    to vertex ids by a seeded permutation."""
+
+    def __init__(self, n_vertices: int, s: float, q: float, rng: np.random.Generator):
+        self.n = int(n_vertices)
+        self.s = float(s)
+        self.q = float(q)
+        if self.s == 0.0:
+            self.cdf = None
+        else:
+            w = (np.arange(1, self.n + 1, dtype=np.float64) + self.q) ** (-self.s)
+            cdf = np.cumsum(w)
+            cdf /= cdf[-1]
+            self.cdf = cdf
+        self.perm = rng.permutation(self.n).astype(np.uint32)
+
+    def draw(self, rng: np.random.Generator, size) -> np.ndarray:
+        if self.cdf is None:
+            ranks = rng.integers(0, self.n, size=size)
+        else:
+            ranks = np.searchsorted(self.cdf, rng.random(size), side="right")
+            ranks = np.minimum(ranks, self.n - 1)
+        return self.perm[ranks]
+
+
+def draw_members(rng: np.random.Generator, cards: np.ndarray, pop: Popularity) -> np.ndarray:
+    """Members of len(cards) hyperedges, row-major (CSR order), each row made of
+    distinct vertices.  Column c of every row with card > c is drawn at once;
+    draws that repeat a vertex of an earlier column of the same row are redrawn."""
+    n = len(cards)
+    if n == 0:
+        return np.zeros(0, dtype=np.uint32)
+    if int(cards.max()) > pop.n:
+        raise ValueError("cardinality exceeds the number of vertices")
+    offsets = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(cards, out=offsets[1:])
+    out = np.zeros(int(offsets[-1]), dtype=np.uint32)
+    order = np.argsort(-cards, kind="stable")  # rows by decreasing card
+    sorted_cards = cards[order]
+    max_card = int(sorted_cards[0])
+    for c in range(max_card):
+        n_rows = int(np.searchsorted(-sorted_cards, -c, side="left"))  # rows with card > c
+        rows = order[:n_rows]
+        vals = pop.draw(rng, n_rows)
+        pending = np.arange(n_rows)
+        while True:
+            bad = np.zeros(len(pending), dtype=bool)
+            base = offsets[rows[pending]]
+            for p in range(c):
+                bad |= out[base + p] == vals[pending]
+            if not bad.any():
+                out[base + c] = vals[pending]
+                break
+            good = ~bad
+            out[base[good] + c] = vals[pending[good]]
+            pending = pending[bad]
+            vals[pending] = pop.draw(rng, len(pending))
+    return out
+
+
+def poisson_times(rng: np.random.Generator, n: int, mean_gap_us: float, t0: int = 0) -> np.ndarray:
+    gaps = np.floor(rng.exponential(mean_gap_us, size=n)).astype(np.int64)
+    return t0 + np.cumsum(gaps)
+
+
+# --------------------------------------------------------------------------- #
+# containers
+# --------------------------------------------------------------------------- #
+@dataclass
+class CSR:
+    offsets: np.ndarray            # uint64 [n + 1]
+    members: np.ndarray            # uint32 [offsets[-1]]
+    ts: Optional[np.ndarray] = None  # int64 [n] or None
+
+    @property
+    def n(self) -> int:
+        return len(self.offsets) - 1
+
+    def row(self, i: int) -> np.ndarray:
+        return self.members[int(self.offsets[i]):int(self.offsets[i + 1])]
+
+    def rows(self, idx: np.ndarray) -> "CSR":
+        idx = np.asarray(idx, dtype=np.int64)
+        lens = (self.offsets[idx + 1] - self.offsets[idx]).astype(np.int64)
+        offs = np.zeros(len(idx) + 1, dtype=np.uint64)
+        np.cumsum(lens, out=offs[1:])
+        if len(idx) and lens.sum():
+            starts = self.offsets[idx].astype(np.int64)
+            rep = np.repeat(starts - offs[:-1].astype(np.int64), lens)
+            src = np.arange(int(offs[-1]), dtype=np.int64) + rep
+            mem = self.members[src]
+        else:
+            mem = np.zeros(0, dtype=np.uint32)
+        ts = None if self.ts is None else self.ts[idx]
+        return CSR(offs, mem.astype(np.uint32), ts)
+
+
+def _csr(cards: np.ndarray, members: np.ndarray, ts=None) -> CSR:
+    offs = np.zeros(len(cards) + 1, dtype=np.uint64)
+    np.cumsum(cards, out=offs[1:])
+    return CSR(offs, members.astype(np.uint32), ts)
+
+
+@dataclass
+class Batch:
+    del_handles: np.ndarray   # int64, deletion order = batch rank
+    ins: CSR                  # inserted hyperedges (ts set for temporal streams)
+    ins_handles: np.ndarray   # int64, handles given to the inserts
+
+    @property
+    def n_updates(self) -> int:
+        return len(self.del_handles) + self.ins.n
+
+
+@dataclass
+class Stream:
+    name: str
+    n_vertices: int
+    initial: CSR
+    batches: List[Batch] = field(default_factory=list)
+    window: int = 0           # temporal triad window (same unit as ts), 0 if unused
+    params: dict = field(default_factory=dict)
+
+
+# --------------------------------------------------------------------------- #
+# generators
+# --------------------------------------------------------------------------- #
+def plain_stream(name: str, n_vertices: int, n_edges: int, card: tuple, pop_s: float, pop_q: float,
+                 n_batches: int, n_ins: int, n_del: int, seed: int) -> Stream:
+    """Static-style stream: build n_edges hyperedges, then n_batches batches of
+    n_del uniform deletions of live handles + n_ins fresh hyperedges from the
+    same distribution.  card = ("uniform", lo, hi) or ("power", alpha, lo, hi)."""
+    rng = np.random.default_rng(seed)
+    pop = Popularity(n_vertices, pop_s, pop_q, rng)
+
+    def cards_of(n):
+        if card[0] == "uniform":
+            return uniform_cards(rng, n, card[1], card[2])
+        return power_law_cards(rng, n, card[1], card[2], card[3])
+
+    c0 = cards_of(n_edges)
+    initial = _csr(c0, draw_members(rng, c0, pop))
+    st = Stream(name, n_vertices, initial,
+                params=dict(n_edges=n_edges, card=card, pop_s=pop_s, pop_q=pop_q, seed=seed))
+    live = np.arange(n_edges, dtype=np.int64)
+    next_handle = n_edges
+    for _ in range(n_batches):
+        k = min(n_del, len(live))
+        pick = rng.choice(len(live), size=k, replace=False)
+        dels = live[pick]
+        keep = np.ones(len(live), dtype=bool)
+        keep[pick] = False
+        ci = cards_of(n_ins)
+        ins = _csr(ci, draw_members(rng, ci, pop))
+        ih = np.arange(next_handle, next_handle + n_ins, dtype=np.int64)
+        next_handle += n_ins
+        live = np.concatenate([live[keep], ih])
+        st.batches.append(Batch(dels.astype(np.int64), ins, ih))
+    return st
+
+
+def temporal_stream(name: str, n_vertices: int, n_build: int, batch_size: int, n_batches: int,
+                    alpha: float, lo: int, hi: int, mean_gap_us: float, expire_us: int,
+                    window_us: int, seed: int, pop_s: float = 0.0, pop_q: float = 0.0) -> Stream:
+    """Arrival stream in timestamp order.  The first n_build arrivals form the
+    initial hypergraph; each batch inserts the next batch_size arrivals and
+    deletes every live hyperedge whose timestamp is older than
+    (largest timestamp of the batch) - expire_us, oldest first."""
+    rng = np.random.default_rng(seed)
+    pop = Popularity(n_vertices, pop_s, pop_q, rng)
+    n_total = n_build + batch_size * n_batches
+    cards = power_law_cards(rng, n_total, alpha, lo, hi)
+    members = draw_members(rng, cards, pop)
+    ts = poisson_times(rng, n_total, mean_gap_us)
+    full = _csr(cards, members, ts)
+    initial = full.rows(np.arange(n_build))
+    st = Stream(name, n_vertices, initial, window=int(window_us),
+                params=dict(n_build=n_build, batch_size=batch_size, alpha=alpha, lo=lo, hi=hi,
+                            mean_gap_us=mean_gap_us, expire_us=expire_us, seed=seed))
+    oldest_live = 0  # handles are in timestamp order; live handles form a suffix range
+    for b in range(n_batches):
+        lo_h = n_build + b * batch_size
+        hi_h = lo_h + batch_size
+        cutoff = int(ts[hi_h - 1]) - int(expire_us)
+        first_keep = int(np.searchsorted(ts[:lo_h], cutoff, side="left"))
+        first_keep = max(first_keep, oldest_live)
+        dels = np.arange(oldest_live, first_keep, dtype=np.int64)
+        oldest_live = first_keep
+        ih = np.arange(lo_h, hi_h, dtype=np.int64)
+        st.batches.append(Batch(dels, full.rows(ih), ih))
+    return st
+
+
+# --------------------------------------------------------------------------- #
+# the named workloads (full sizes) and scaled versions for tests
+# --------------------------------------------------------------------------- #
+def tiny(seed: int = SEED_BASE + 1) -> Stream:
+    """2,000 vertices, 1,000 hyperedges, card U[2,8], Zipf(1.2) popularity;
+    one batch of 100 inserts + 100 deletions."""
+    return plain_stream("tiny", 2000, 1000, ("uniform", 2, 8), 1.2, 0.0, 1, 100, 100, seed)
+
+
+def medium(seed: int = SEED_BASE + 2, q: float = 1.0e4, scale: float = 1.0, n_batches: int = 10) -> Stream:
+    """1M vertices, 2M hyperedges, card power law 2.5 on [2,64], vertex
+    popularity (rank + q)^-1.1; batches of 50k inserts + 50k deletions.
+    q = 0 is the literal Zipf(1.1); the default q = 1e4 keeps the hub degree
+    low enough for exact hyperedge-triad enumeration."""
+    nv = max(64, int(round(1_000_000 * scale)))
+    ne = max(16, int(round(2_000_000 * scale)))
+    nb = max(1, int(round(50_000 * scale)))
+    qq = q * scale if q > 0 else 0.0
+    return plain_stream("medium", nv, ne, ("power", 2.5, 2, 64), 1.1, qq, n_batches, nb, nb, seed)
+
+
+def temporal(seed: int = SEED_BASE + 3, scale: float = 1.0, n_batches: int = 10) -> Stream:
+    """500k vertices (uniform popularity), 4M initial hyperedges, card power
+    law 2.2 on [2,128], Poisson arrivals at 1e3/s (us timestamps); batches of
+    200k arrivals with expiry of hyperedges older than 3600 s; window 600 s."""
+    nv = max(256, int(round(500_000 * scale)))
+    nbld = max(64, int(round(4_000_000 * scale)))
+    bs = max(8, int(round(200_000 * scale)))
+    gap = 1000.0 / scale  # keep the same number of hyperedges per window at any scale
+    return temporal_stream("temporal", nv, nbld, bs, n_batches, 2.2, 2, 128, gap,
+                           int(3_600_000_000), int(600_000_000), seed)
+
+
+def log_uniform_int(rng: np.random.Generator, lo: float, hi: float, size=None) -> np.ndarray:
+    return np.round(np.exp(rng.uniform(np.log(lo), np.log(hi), size=size))).astype(np.int64)
+
+
+def batched(seed: int = SEED_BASE + 4, n_graphs: int = 256, e_lo: float = 1e3, e_hi: float = 2e5,
+            b_lo: float = 10, b_hi: float = 5e4, card_hi: int = 256) -> List[Stream]:
+    """n_graphs independent hypergraphs, |E_g| log-uniform in [e_lo, e_hi],
+    |V_g| = |E_g| / 2, card power law 2.5 on [2, card_hi], uniform popularity;
+    each with one batch of log-uniform size in [b_lo, b_hi] (60% inserts)."""
+    rng = np.random.default_rng(seed)
+    sizes = log_uniform_int(rng, e_lo, e_hi, n_graphs)
+    bsz = log_uniform_int(rng, b_lo, b_hi, n_graphs)
+    out = []
+    for g in range(n_graphs):
+        ne = int(sizes[g])
+        nv = max(card_hi, ne // 2)
+        n_b = int(min(bsz[g], ne))
+        n_i = int(round(0.6 * n_b))
+        n_d = n_b - n_i
+        out.append(plain_stream(f"batched[{g}]", nv, ne, ("power", 2.5, 2, card_hi), 0.0, 0.0,
+                                1, n_i, n_d, seed * 1000 + g))
+    return out

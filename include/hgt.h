@@ -1,0 +1,167 @@
+/*
+ * hgt.h -- C ABI of the dynamic-hypergraph triad-count library (HIP, gfx950).
+ *
+ * The library keeps one or more hypergraphs resident in device memory, applies
+ * batches of hyperedge deletions and insertions to them and keeps their triad
+ * counts up to date incrementally.  It follows the problem statement of the
+ * paper (ESCHER, arXiv 2512.21009): updates are batches of hyperedge
+ * insertions and deletions (Sec. III-B, "vertical operations"), deletions are
+ * applied before insertions (Alg. 3, step 3), counts are maintained as
+ * count - count_Del + count_Ins (Alg. 3, step 6), and the supported triad
+ * families are hyperedge-based, incident-vertex-based and temporal triads
+ * (Sec. II, "Hypergraph Triads").
+ *
+ * Conventions used by every entry point
+ *  - Every function returns an int status: HGT_OK (0) or a negative HGT_E*
+ *    code; hgt_status_str() names it.
+ *  - "device" pointers point to memory of the GPU the graph lives on (for
+ *    example the data_ptr() of a torch tensor); "host" pointers to ordinary
+ *    CPU memory.  The library never frees caller memory and never keeps a
+ *    caller pointer beyond the call (device inputs are read in stream order;
+ *    the caller must not overwrite them before the stream has passed the call).
+ *  - `stream` is a hipStream_t passed as void*; NULL means the default stream.
+ *  - IDs and vertex ids are uint32, CSR offsets uint64, timestamps int64 (any
+ *    unit, the same as the temporal window), counts uint64.  Counts are exact
+ *    and maintained modulo 2^64 (exact whenever the true count is below 2^64).
+ *  - A batch that fails validation is rejected as a whole: graph state and
+ *    counts stay as they were, and the error is returned by that call and
+ *    again by hgt_sync().
+ */
+#ifndef HGT_H
+#define HGT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define HGT_OK 0
+#define HGT_EINVAL (-1)      /* bad argument, empty/too large/repeated/out-of-range member list */
+#define HGT_ENOENT (-2)      /* a deleted ID is not live */
+#define HGT_EDUP (-3)        /* an ID appears twice in one deletion list */
+#define HGT_EORDER (-4)      /* temporal insert older than the resident stream, or unsorted batch */
+#define HGT_ENOMEM (-5)      /* device memory exhausted */
+#define HGT_ENOTTRACKED (-6) /* the triad type (or window) is not maintained by this graph */
+#define HGT_EDEVICE (-7)     /* HIP runtime failure; the graph must be destroyed */
+
+/* ---- triad families (Sec. II) ----------------------------------------- */
+/* Hyperedge-based: 30 uint64 classes.  A class is a Venn pattern of three
+ * connected hyperedges up to relabelling, indexed by ascending canonical
+ * pattern code (bit0 a only, bit1 b only, bit2 c only, bit3 a&b only,
+ * bit4 b&c only, bit5 c&a only, bit6 a&b&c; canonical = smallest code over
+ * the six labellings).  Codes 64, 65, 72 and 76 (indices 10, 11, 14, 17) need
+ * two or three identical vertex sets; the other 26 are the paper's 26 triads. */
+#define HGT_TRIAD_HYPEREDGE 0
+/* Incident-vertex-based: 3 uint64 = types 1, 2, 3 with hyperedge
+ * multiplicity: vertex triples {u,v,w} with one witness hyperedge per pair;
+ * type 1 all witnesses equal, type 2 exactly two equal, type 3 all distinct. */
+#define HGT_TRIAD_INCIDENT_VERTEX 1
+/* Temporal: 96 uint64 classes.  Connected triples ordered by (timestamp,
+ * arrival sequence) whose first and last timestamps differ by at most the
+ * window; class = Venn pattern in time order, indexed by ascending code. */
+#define HGT_TRIAD_TEMPORAL 2
+
+#define HGT_N_HE_CLASSES 30
+#define HGT_N_IV_CLASSES 3
+#define HGT_N_TEMPORAL_CLASSES 96
+
+/* Largest accepted hyperedge cardinality. */
+#define HGT_MAX_CARD 8192
+
+typedef struct hgt_graph hgt_graph;
+
+/* ---- build ------------------------------------------------------------ */
+typedef struct {
+    uint32_t n_vertices;       /* vertex ids are 0 .. n_vertices-1                          */
+    uint64_t n_edges;          /* initial hyperedges; they get IDs 0 .. n_edges-1 in order    */
+    const uint64_t* offsets;   /* device [n_edges+1], non-decreasing                           */
+    const uint32_t* members;   /* device: row j is members[offsets[j]-offsets[0] ..
+                                  offsets[j+1]-offsets[0]), member vertex ids in any order      */
+    const int64_t* timestamps; /* device [n_edges] or NULL; required when temporal is tracked  */
+    uint32_t track_mask;       /* bit (1 << HGT_TRIAD_*) for every family to maintain          */
+    int64_t temporal_window;   /* window of the temporal family (>= 0)                         */
+    uint64_t edge_capacity;    /* initial ID capacity, 0 = automatic (grows on demand)          */
+    uint64_t pool_words;       /* initial words per incidence pool, 0 = automatic (grows)       */
+    void* stream;              /* hipStream_t for the build work                               */
+} hgt_build_desc;
+
+/* Copies the hypergraph into the library's device pools (the caller keeps its
+ * buffers) and computes the initial counts of every tracked family.  Rows are
+ * sets: each must hold 1..HGT_MAX_CARD distinct vertex ids < n_vertices.
+ * Initial timestamps may be in any order; their arrival sequence is the input
+ * order.  Synchronises `stream`.  On success *out owns the graph. */
+int hgt_build(const hgt_build_desc* d, hgt_graph** out);
+
+/* ---- batch update (Alg. 3) -------------------------------------------- */
+/* Applies one batch: first deletes the n_del hyperedges del_ids[0..n_del)
+ * (device; distinct live IDs; batch order = deletion rank), then inserts the
+ * n_ins hyperedges given as device CSR: ins_offsets[0..n_ins] non-decreasing,
+ * row j = ins_members[ins_offsets[j]-ins_offsets[0] .. ins_offsets[j+1]-ins_offsets[0])
+ * (n_ins_members = ins_offsets[n_ins] - ins_offsets[0] entries, members in any order),
+ * with device timestamps ins_ts[0..n_ins) (required iff temporal is tracked;
+ * non-decreasing and not older than any timestamp inserted before).
+ * ID reuse (Alg. 2, "thread j finds the j-th available node"): with F the
+ * ascending list of free IDs including this batch's deletions, the j-th
+ * insert gets F[j]; later inserts get fresh consecutive IDs.  The IDs are
+ * written to out_ins_ids[0..n_ins) (device, may be NULL).
+ * Then every tracked count is updated incrementally.  All work is queued on
+ * `stream`; the call waits once for a small validation/allocation summary,
+ * so a rejected batch returns its error here and leaves everything unchanged.
+ * Pointers may be NULL when the matching count is 0. */
+int hgt_apply_batch(hgt_graph* g, const uint32_t* del_ids, uint64_t n_del,
+                    const uint64_t* ins_offsets, const uint32_t* ins_members,
+                    uint64_t n_ins_members, const int64_t* ins_ts, uint64_t n_ins,
+                    uint32_t* out_ins_ids, void* stream);
+
+/* ---- queries ---------------------------------------------------------- */
+/* Copies the maintained counts of family `type` to out_host[0..n_out) (host).
+ * n_out must be at least 30 / 3 / 96.  `window` must be 0 for the hyperedge
+ * and incident-vertex families and equal the tracked window for temporal
+ * (else HGT_ENOTTRACKED).  Synchronises the graph's last stream. */
+int hgt_triad_counts(hgt_graph* g, int type, int64_t window, uint64_t* out_host, uint32_t n_out);
+
+/* Waits for the graph's queued work; *status (may be NULL) receives the
+ * sticky status of the graph (HGT_OK or the first error). */
+int hgt_sync(hgt_graph* g, int* status);
+
+/* Releases every device buffer of the graph. */
+int hgt_destroy(hgt_graph* g);
+
+const char* hgt_status_str(int status);
+
+/* ---- introspection (tests, tools) -------------------------------------- */
+typedef struct {
+    uint32_t n_vertices;
+    uint32_t track_mask;
+    uint64_t next_id;        /* IDs in use are < next_id                        */
+    uint64_t n_live;         /* live hyperedges                                 */
+    uint64_t n_incidences;   /* sum of live cardinalities                       */
+    uint64_t edge_capacity;
+    uint64_t h2v_pool_words, h2v_used_words;
+    uint64_t v2h_pool_words, v2h_used_words;
+    int64_t temporal_window;
+    uint64_t batches;        /* batches applied since build                     */
+} hgt_info;
+
+int hgt_get_info(hgt_graph* g, hgt_info* out);
+
+/* Copies the hyperedge->vertex map to host CSR indexed by ID:
+ * offsets_host[0..next_id], members_host[0..n_incidences) (each row sorted),
+ * live_host[0..next_id) (1 = live).  Dead IDs have empty rows. */
+int hgt_export_h2v(hgt_graph* g, uint64_t* offsets_host, uint32_t* members_host, uint8_t* live_host);
+
+/* Copies the vertex->hyperedge map to host CSR indexed by vertex:
+ * offsets_host[0..n_vertices], members_host[0..n_incidences) (rows ascending). */
+int hgt_export_v2h(hgt_graph* g, uint64_t* offsets_host, uint32_t* members_host);
+
+/* Class codes of the hyperedge (30) or temporal (96) family, ascending;
+ * host out[0..n).  Returns the number of classes or a negative status. */
+int hgt_class_codes(int type, int32_t* out_host, uint32_t n);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HGT_H */

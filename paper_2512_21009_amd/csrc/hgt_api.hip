@@ -1,0 +1,839 @@
+// hgt_api.hip -- the C ABI (include/hgt.h): graph objects, batch orchestration,
+// device memory management and the class tables.
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "store.h"
+#include "triad.h"
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// class tables: Venn pattern code -> class index (built from the definitions)
+// ---------------------------------------------------------------------------
+// label set of each region bit, labels a=bit0, b=bit1, c=bit2
+constexpr int kRegionLabels[7] = {1, 2, 4, 3, 6, 5, 7};
+
+bool is_triad_code(int code) {
+    int covered = 0, meets = 0;
+    for (int r = 0; r < 7; r++)
+        if (code & (1 << r)) covered |= kRegionLabels[r];
+    if (covered != 7) return false;
+    for (int pair : {3, 6, 5}) {
+        bool m = false;
+        for (int r = 0; r < 7; r++)
+            if ((code & (1 << r)) && (kRegionLabels[r] & pair) == pair) m = true;
+        meets += m;
+    }
+    return meets >= 2;
+}
+
+int permute_code(int code, const int to[3]) {  // old label l becomes label to[l]
+    int out = 0;
+    for (int r = 0; r < 7; r++) {
+        if (!(code & (1 << r))) continue;
+        int labels = 0;
+        for (int l = 0; l < 3; l++)
+            if (kRegionLabels[r] & (1 << l)) labels |= 1 << to[l];
+        for (int q = 0; q < 7; q++)
+            if (kRegionLabels[q] == labels) out |= 1 << q;
+    }
+    return out;
+}
+
+struct ClassTables {
+    uint8_t he[128], tmp[128];
+    std::vector<int32_t> he_codes, tmp_codes;
+    ClassTables() {
+        const int perms[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+        int canon[128];
+        for (int c = 0; c < 128; c++) {
+            canon[c] = -1;
+            if (!is_triad_code(c)) continue;
+            canon[c] = c;
+            for (auto& p : perms) canon[c] = std::min(canon[c], permute_code(c, p));
+            tmp_codes.push_back(c);
+        }
+        for (int c = 0; c < 128; c++)
+            if (canon[c] == c) he_codes.push_back(c);
+        for (int c = 0; c < 128; c++) {
+            he[c] = tmp[c] = 255;
+            if (canon[c] < 0) continue;
+            he[c] = (uint8_t)(std::lower_bound(he_codes.begin(), he_codes.end(), canon[c]) - he_codes.begin());
+            tmp[c] = (uint8_t)(std::lower_bound(tmp_codes.begin(), tmp_codes.end(), c) - tmp_codes.begin());
+        }
+    }
+};
+
+const ClassTables& tables() {
+    static ClassTables t;
+    return t;
+}
+
+// ---------------------------------------------------------------------------
+// device buffers
+// ---------------------------------------------------------------------------
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    template <class T> T* as() const { return (T*)p; }
+};
+
+int dev_alloc(DevBuf& b, size_t bytes) {
+    if (bytes == 0) bytes = 256;
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return HGT_ENOMEM;
+    }
+    b.p = p;
+    b.bytes = bytes;
+    return HGT_OK;
+}
+
+void dev_free(DevBuf& b) {
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+}
+
+// grow-only scratch (contents not preserved)
+int ensure(DevBuf& b, size_t bytes) {
+    if (b.p && b.bytes >= bytes) return HGT_OK;
+    size_t nb = std::max(bytes, b.bytes + b.bytes / 2);
+    nb = (nb + 4095) & ~(size_t)4095;
+    dev_free(b);
+    return dev_alloc(b, nb);
+}
+
+// grow preserving the first `keep` bytes
+int grow_keep(DevBuf& b, size_t bytes, size_t keep, hipStream_t s) {
+    if (b.p && b.bytes >= bytes) return HGT_OK;
+    DevBuf nb;
+    int rc = dev_alloc(nb, (bytes + 4095) & ~(size_t)4095);
+    if (rc) return rc;
+    if (keep && b.p) {
+        if (hipMemcpyAsync(nb.p, b.p, std::min(keep, b.bytes), hipMemcpyDeviceToDevice, s) != hipSuccess) {
+            dev_free(nb);
+            return HGT_EDEVICE;
+        }
+        if (hipStreamSynchronize(s) != hipSuccess) {
+            dev_free(nb);
+            return HGT_EDEVICE;
+        }
+    }
+    dev_free(b);
+    b = nb;
+    return HGT_OK;
+}
+
+int bits_for(uint64_t max_value) {  // bits to hold values 0..max_value
+    int b = 1;
+    while (b < 64 && (max_value >> b)) b++;
+    return b;
+}
+
+constexpr int CNT_HE = 0, CNT_IV = 30, CNT_TMP = 33, CNT_N = 129;
+// phase accumulators follow the counts
+constexpr int ACC_HE_M = 129, ACC_HE_P = 159, ACC_TMP_M = 189, ACC_TMP_P = 285, ACC_IV_M = 381, ACC_IV_P = 383,
+              ACC_T1 = 385, ACC_N = 387;
+
+}  // namespace
+
+struct hgt_graph {
+    int device = 0;
+    int n_cu = 256;
+    hipStream_t last_stream = nullptr;
+    uint32_t track_mask = 0;
+    int64_t window = 0;
+    StoreDev st{};
+    DevBuf h_off, h_len, h_cap, h_ts, h_seq, free_bm, mark_del, mark_ins;
+    DevBuf h2v, v_off, v_len, v_cap, v2h;
+    DevBuf scal, counts, tabs;
+    // batch scratch
+    DevBuf s_sum, s_del_bm, s_del_card, s_del_poff, s_ins_rel, s_ins_card, s_canon, s_big, s_small, s_popc, s_scan,
+        s_assigned, s_h_need, s_h_rel, s_keys, s_keys_alt, s_sort, s_head, s_is_ins, s_tv, s_tseg, s_D, s_I, s_It,
+        s_vp, s_staging, s_dst;
+    // triad scratch
+    DevBuf t_ctr, t_big_list, t_big_rank, t_big_scratch;
+    DevBuf iv_keys, iv_alt, iv_sort, iv_head, iv_uniq, iv_p2, iv_scan;
+    // host mirrors (valid after each synchronisation)
+    uint64_t next_id = 0, h_bump = 0, v_bump = 0, next_seq = 0, n_live = 0, n_inc = 0;
+    uint32_t epoch = 0;
+    int sticky = HGT_OK;
+    uint64_t batches = 0;
+    BatchSummary* h_sum = nullptr;  // pinned
+    DevScalars* h_sc = nullptr;     // pinned
+};
+
+namespace {
+
+#define HIP_OK(expr)                          \
+    do {                                      \
+        if ((expr) != hipSuccess) {           \
+            (void)hipGetLastError();          \
+            return HGT_EDEVICE;               \
+        }                                     \
+    } while (0)
+
+void refresh_view(hgt_graph* g) {
+    StoreDev& s = g->st;
+    s.h_off = g->h_off.as<uint64_t>();
+    s.h_len = g->h_len.as<uint32_t>();
+    s.h_cap = g->h_cap.as<uint32_t>();
+    s.h_ts = (g->track_mask & (1u << HGT_TRIAD_TEMPORAL)) ? g->h_ts.as<int64_t>() : nullptr;
+    s.h_seq = g->h_seq.as<uint64_t>();
+    s.free_bm = g->free_bm.as<uint64_t>();
+    s.h2v = g->h2v.as<uint32_t>();
+    s.h2v_words = g->h2v.bytes / 4;
+    s.v_off = g->v_off.as<uint64_t>();
+    s.v_len = g->v_len.as<uint32_t>();
+    s.v_cap = g->v_cap.as<uint32_t>();
+    s.v2h = g->v2h.as<uint32_t>();
+    s.v2h_words = g->v2h.bytes / 4;
+    s.mark_del = g->mark_del.as<uint64_t>();
+    s.mark_ins = g->mark_ins.as<uint64_t>();
+    s.sc = g->scal.as<DevScalars>();
+}
+
+GraphView view_of(hgt_graph* g) {
+    GraphView v;
+    v.h_off = g->st.h_off;
+    v.h_len = g->st.h_len;
+    v.h2v = g->st.h2v;
+    v.v_off = g->st.v_off;
+    v.v_len = g->st.v_len;
+    v.v2h = g->st.v2h;
+    v.h_ts = g->st.h_ts;
+    v.h_seq = g->st.h_seq;
+    return v;
+}
+
+// ID-indexed arrays hold id_cap entries; contents below the old capacity are kept.
+int ensure_id_cap(hgt_graph* g, uint64_t need, hipStream_t s) {
+    if (need <= g->st.id_cap) return HGT_OK;
+    if (need > 0xfffffff0ull) return HGT_ENOMEM;
+    uint64_t cap = std::max<uint64_t>(need, g->st.id_cap + g->st.id_cap / 2);
+    cap = (cap + 63) & ~63ull;
+    uint64_t old = g->st.id_cap;
+    struct { DevBuf* b; size_t esz; } arrs[] = {{&g->h_off, 8}, {&g->h_len, 4}, {&g->h_cap, 4}, {&g->h_ts, 8},
+                                                {&g->h_seq, 8}, {&g->mark_del, 8}, {&g->mark_ins, 8}};
+    for (auto& a : arrs) {
+        int rc = grow_keep(*a.b, cap * a.esz, old * a.esz, s);
+        if (rc) return rc;
+    }
+    int rc = grow_keep(g->free_bm, cap / 8, (old + 7) / 8, s);
+    if (rc) return rc;
+    // new entries: zero (length 0, capacity 0, not free, no marks)
+    HIP_OK(hipMemsetAsync(g->h_len.as<uint32_t>() + old, 0, (cap - old) * 4, s));
+    HIP_OK(hipMemsetAsync(g->h_cap.as<uint32_t>() + old, 0, (cap - old) * 4, s));
+    HIP_OK(hipMemsetAsync(g->mark_del.as<uint64_t>() + old, 0, (cap - old) * 8, s));
+    HIP_OK(hipMemsetAsync(g->mark_ins.as<uint64_t>() + old, 0, (cap - old) * 8, s));
+    HIP_OK(hipMemsetAsync((char*)g->free_bm.p + old / 8, 0, (cap - old) / 8, s));
+    g->st.id_cap = cap;
+    refresh_view(g);
+    return HGT_OK;
+}
+
+int ensure_pool(DevBuf& pool, uint64_t used_words, uint64_t need_words, hipStream_t s) {
+    uint64_t want = used_words + need_words;
+    if (pool.p && pool.bytes / 4 >= want) return HGT_OK;
+    uint64_t cap = std::max<uint64_t>(want + want / 4, pool.bytes / 4 * 2);
+    return grow_keep(pool, cap * 4, used_words * 4, s);
+}
+
+struct Sizes {
+    uint64_t n_del, n_ins, n_mem, pairs_cap, words;
+};
+
+int ensure_plan_scratch(hgt_graph* g, const Sizes& z, PlanScratch& w) {
+    const uint64_t nd = std::max<uint64_t>(z.n_del, 1), ni = std::max<uint64_t>(z.n_ins, 1);
+    const uint64_t nm = std::max<uint64_t>(z.n_mem, 1), pc = std::max<uint64_t>(z.pairs_cap, 1);
+    const uint64_t words = std::max<uint64_t>(z.words, 1);
+    int rc = 0;
+    rc |= ensure(g->s_sum, sizeof(BatchSummary));
+    rc |= ensure(g->s_del_bm, (g->st.id_cap / 64 + 1) * 8);
+    rc |= ensure(g->s_del_card, nd * 8);
+    rc |= ensure(g->s_del_poff, nd * 8);
+    rc |= ensure(g->s_ins_rel, (ni + 1) * 8);
+    rc |= ensure(g->s_ins_card, ni * 8);
+    rc |= ensure(g->s_canon, nm * 4);
+    rc |= ensure(g->s_big, ni * 4);
+    rc |= ensure(g->s_small, 64 * 8);
+    rc |= ensure(g->s_popc, words * 8);
+    size_t scan_b = std::max({hgt_scan_tmp_bytes(words), hgt_scan_tmp_bytes(ni), hgt_scan_tmp_bytes(nd),
+                              hgt_scan_tmp_bytes(pc)});
+    rc |= ensure(g->s_scan, scan_b);
+    rc |= ensure(g->s_assigned, ni * 4);
+    rc |= ensure(g->s_h_need, ni * 8);
+    rc |= ensure(g->s_h_rel, ni * 8);
+    rc |= ensure(g->s_keys, pc * 8);
+    rc |= ensure(g->s_keys_alt, pc * 8);
+    rc |= ensure(g->s_sort, hgt_radix_tmp_bytes(pc));
+    rc |= ensure(g->s_head, pc * 8);
+    rc |= ensure(g->s_is_ins, pc * 8);
+    rc |= ensure(g->s_tv, pc * 4);
+    rc |= ensure(g->s_tseg, (pc + 1) * 8);
+    rc |= ensure(g->s_D, pc * 4);
+    rc |= ensure(g->s_I, pc * 4);
+    rc |= ensure(g->s_It, pc * 4);
+    rc |= ensure(g->s_vp, pc * (8 * 6 + 4 * 3) + 64);
+    rc |= ensure(g->s_dst, pc * 8);
+    if (rc) return HGT_ENOMEM;
+    w.sum = g->s_sum.as<BatchSummary>();
+    w.del_bm = g->s_del_bm.as<uint64_t>();
+    w.del_card = g->s_del_card.as<uint64_t>();
+    w.del_poff = g->s_del_poff.as<uint64_t>();
+    w.ins_rel = g->s_ins_rel.as<uint64_t>();
+    w.ins_card = g->s_ins_card.as<uint64_t>();
+    w.canon = g->s_canon.as<uint32_t>();
+    w.big_list = g->s_big.as<uint32_t>();
+    uint64_t* sm = g->s_small.as<uint64_t>();
+    w.big_count = (uint32_t*)(sm + 0);
+    w.n_words = sm + 1;
+    w.n_free = sm + 2;
+    w.h2v_total = sm + 3;
+    w.n_pairs = sm + 4;
+    w.n_touched = sm + 5;
+    w.n_ins_pairs = sm + 6;
+    w.v2h_total = sm + 7;
+    w.stage_total = sm + 8;
+    w.popc = g->s_popc.as<uint64_t>();
+    w.scan_tmp = g->s_scan.p;
+    w.assigned = g->s_assigned.as<uint32_t>();
+    w.h_need = g->s_h_need.as<uint64_t>();
+    w.h_rel = g->s_h_rel.as<uint64_t>();
+    w.pairs_cap = pc;
+    w.keys = g->s_keys.as<uint64_t>();
+    w.keys_alt = g->s_keys_alt.as<uint64_t>();
+    w.sort_tmp = g->s_sort.p;
+    w.head = g->s_head.as<uint64_t>();
+    w.is_ins = g->s_is_ins.as<uint64_t>();
+    w.tv = g->s_tv.as<uint32_t>();
+    w.tseg = g->s_tseg.as<uint64_t>();
+    w.D_all = g->s_D.as<uint32_t>();
+    w.I_all = g->s_I.as<uint32_t>();
+    w.I_t = g->s_It.as<uint32_t>();
+    uint64_t* vp = g->s_vp.as<uint64_t>();
+    w.vp.dstart = vp;
+    w.vp.istart = vp + pc;
+    w.vp.old_len = vp + 2 * pc;
+    w.vp.need = vp + 3 * pc;
+    w.vp.rel = vp + 4 * pc;
+    w.vp.stage_off = vp + 5 * pc;
+    uint32_t* vp32 = (uint32_t*)(vp + 6 * pc);
+    w.vp.nD = vp32;
+    w.vp.nI = vp32 + pc;
+    w.vp.new_len = vp32 + 2 * pc;
+    w.dst = g->s_dst.as<uint64_t>();
+    w.staging = g->s_staging.as<uint32_t>();
+    return HGT_OK;
+}
+
+// ---- triad phases ---------------------------------------------------------
+int run_he_phase(hgt_graph* g, const uint32_t* centres, uint64_t n, const uint64_t* mark, uint32_t epoch,
+                 uint64_t max_lh, bool minus, hipStream_t s) {
+    bool do_he = g->track_mask & (1u << HGT_TRIAD_HYPEREDGE);
+    bool do_tmp = g->track_mask & (1u << HGT_TRIAD_TEMPORAL);
+    if (!(do_he || do_tmp) || n == 0) return HGT_OK;
+    int rc = 0;
+    rc |= ensure(g->t_ctr, 64);
+    rc |= ensure(g->t_big_list, n * 4);
+    rc |= ensure(g->t_big_rank, n * 4);
+    if (rc) return HGT_ENOMEM;
+    uint64_t max_card = std::min<uint64_t>(HGT_MAX_CARD, std::max<uint64_t>(max_lh, 1));
+    BigLayout L = triad_big_layout(std::max<uint64_t>(max_lh, 1), max_card);
+    // at most ~1 GiB of global tables for the large-centre kernel
+    uint64_t grid_big = std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)g->n_cu * 2, (1ull << 28) / L.words_per_wg));
+    if (ensure(g->t_big_scratch, grid_big * L.words_per_wg * 4)) return HGT_ENOMEM;
+    TriadParams P{};
+    P.g = view_of(g);
+    P.centres = centres;
+    P.n_centres = n;
+    P.mark = mark;
+    P.epoch = epoch;
+    P.do_he = do_he;
+    P.do_tmp = do_tmp;
+    P.window = g->window;
+    uint64_t* cnt = g->counts.as<uint64_t>();
+    P.out_he = cnt + (minus ? ACC_HE_M : ACC_HE_P);
+    P.out_tmp = cnt + (minus ? ACC_TMP_M : ACC_TMP_P);
+    P.he_tab = g->tabs.as<uint8_t>();
+    P.tmp_tab = g->tabs.as<uint8_t>() + 128;
+    P.status = &g->st.sc->status;
+    uint32_t* ctr = g->t_ctr.as<uint32_t>();
+    P.queue = ctr;
+    P.big_queue = ctr + 1;
+    P.big_count = ctr + 2;
+    P.big_list = g->t_big_list.as<uint32_t>();
+    P.big_rank = g->t_big_rank.as<uint32_t>();
+    P.big_scratch = g->t_big_scratch.as<uint32_t>();
+    P.big = L;
+    unsigned grid_small = (unsigned)std::min<uint64_t>((uint64_t)g->n_cu * 3, n);
+    triad_he_launch(P, grid_small, (unsigned)grid_big, s);
+    return HGT_OK;
+}
+
+// IV pair list: unique vertex pairs inside the changed hyperedges.
+__global__ void k_iv_gen(const uint32_t* __restrict__ ids, uint64_t n, const uint64_t* __restrict__ h_off,
+                         const uint32_t* __restrict__ h_len, const uint32_t* __restrict__ h2v,
+                         const uint32_t* __restrict__ canon, const uint64_t* __restrict__ rel,
+                         const uint64_t* __restrict__ p2off, uint64_t base, int vb, uint64_t* keys, uint64_t* t1,
+                         const DevScalars* sc) {
+    if (sc->status) return;
+    const int lane = threadIdx.x & 63;
+    uint64_t i = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (i >= n) return;
+    const uint32_t* m;
+    uint64_t d;
+    if (ids) {
+        m = h2v + h_off[ids[i]];
+        d = h_len[ids[i]];
+    } else {
+        m = canon + rel[i];
+        d = rel[i + 1] - rel[i];
+    }
+    uint64_t o = base + p2off[i];
+    for (uint64_t a = lane; a < d; a += 64) {
+        uint64_t start = o + a * (2 * d - a - 1) / 2;
+        uint64_t ua = m[a];
+        for (uint64_t b = a + 1; b < d; b++) keys[start + (b - a - 1)] = (ua << vb) | m[b];
+    }
+    if (lane == 0) atomicAdd((unsigned long long*)t1, (unsigned long long)choose3(d));
+}
+
+__global__ void k_c2(const uint64_t* __restrict__ card, uint64_t n, uint64_t* out) {
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = choose2(card[i]);
+}
+
+__global__ void k_uniq_heads(const uint64_t* __restrict__ keys, uint64_t n, uint64_t* head) {
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) head[i] = (i == 0 || keys[i] != keys[i - 1]) ? 1 : 0;
+}
+
+__global__ void k_uniq_write(const uint64_t* __restrict__ keys, uint64_t n, const uint64_t* __restrict__ pos, int vb,
+                             uint64_t* out) {
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (i == 0 || keys[i] != keys[i - 1]) {
+        uint64_t k = keys[i];
+        out[pos[i]] = ((k >> vb) << 32) | (k & ((1ull << vb) - 1));
+    }
+}
+
+__global__ void k_iv_update(uint64_t* cnt, int iv, int m, int p, int t1) {
+    if (threadIdx.x || blockIdx.x) return;
+    uint64_t d1 = cnt[t1 + 1] - cnt[t1];           // change of type 1
+    uint64_t ds = cnt[p] - cnt[m];                 // change of sum m_p w_p
+    uint64_t dx = cnt[p + 1] - cnt[m + 1];         // change of the triangle sum
+    uint64_t d2 = ds - 3 * d1;
+    cnt[iv] += d1;
+    cnt[iv + 1] += d2;
+    cnt[iv + 2] += dx - d1 - d2;
+}
+
+inline unsigned nblk(uint64_t n, unsigned per = 256) {
+    uint64_t b = (n + per - 1) / per;
+    return (unsigned)(b ? b : 1);
+}
+
+struct IvPlan {
+    uint64_t n_keys = 0;
+    uint64_t* uniq = nullptr;
+    uint64_t* n_uniq = nullptr;
+};
+
+int iv_prepare(hgt_graph* g, const BatchIn& b, const PlanScratch& w, const BatchSummary& sum, IvPlan& ip,
+               hipStream_t s) {
+    uint64_t nk = sum.del_pairs2 + sum.ins_pairs2;
+    ip.n_keys = nk;
+    uint64_t nmax = std::max<uint64_t>(nk, 1);
+    uint64_t nh = std::max<uint64_t>(std::max(b.n_del, b.n_ins), 1);
+    int rc = 0;
+    rc |= ensure(g->iv_keys, nmax * 8);
+    rc |= ensure(g->iv_alt, nmax * 8);
+    rc |= ensure(g->iv_sort, hgt_radix_tmp_bytes(nmax));
+    rc |= ensure(g->iv_head, nmax * 8);
+    rc |= ensure(g->iv_uniq, nmax * 8 + 64);
+    rc |= ensure(g->iv_p2, (nh + 1) * 8);
+    rc |= ensure(g->iv_scan, std::max(hgt_scan_tmp_bytes(nmax), hgt_scan_tmp_bytes(nh)));
+    if (rc) return HGT_ENOMEM;
+    uint64_t* cnt = g->counts.as<uint64_t>();
+    uint64_t* keys = g->iv_keys.as<uint64_t>();
+    uint64_t* p2 = g->iv_p2.as<uint64_t>();
+    int vb = g->st.vb;
+    if (b.n_del) {
+        k_c2<<<nblk(b.n_del), 256, 0, s>>>(w.del_card, b.n_del, p2);
+        hgt_scan_u64(p2, p2, b.n_del, nullptr, nullptr, g->iv_scan.p, s);
+        k_iv_gen<<<nblk(b.n_del * 64), 256, 0, s>>>(b.del, b.n_del, g->st.h_off, g->st.h_len, g->st.h2v, nullptr,
+                                                    nullptr, p2, 0, vb, keys, cnt + ACC_T1, g->st.sc);
+    }
+    if (b.n_ins) {
+        k_c2<<<nblk(b.n_ins), 256, 0, s>>>(w.ins_card, b.n_ins, p2);
+        hgt_scan_u64(p2, p2, b.n_ins, nullptr, nullptr, g->iv_scan.p, s);
+        k_iv_gen<<<nblk(b.n_ins * 64), 256, 0, s>>>(nullptr, b.n_ins, nullptr, nullptr, nullptr, w.canon, w.ins_rel,
+                                                    p2, sum.del_pairs2, vb, keys, cnt + ACC_T1 + 1, g->st.sc);
+    }
+    ip.uniq = g->iv_uniq.as<uint64_t>() + 1;
+    ip.n_uniq = g->iv_uniq.as<uint64_t>();
+    if (nk == 0) {
+        hgt_fill_u64(ip.n_uniq, 0, 1, s);
+        return HGT_OK;
+    }
+    hgt_radix_sort_u64(keys, g->iv_alt.as<uint64_t>(), nk, nullptr, 2 * vb, g->iv_sort.p, s);
+    uint64_t* head = g->iv_head.as<uint64_t>();
+    k_uniq_heads<<<nblk(nk), 256, 0, s>>>(keys, nk, head);
+    hgt_scan_u64(head, head, nk, nullptr, ip.n_uniq, g->iv_scan.p, s);
+    k_uniq_write<<<nblk(nk), 256, 0, s>>>(keys, nk, head, vb, ip.uniq);
+    return HGT_OK;
+}
+
+void iv_phase(hgt_graph* g, const IvPlan& ip, bool minus, hipStream_t s) {
+    if (ip.n_keys == 0) return;
+    IvParams P{};
+    P.g = view_of(g);
+    P.pairs = ip.uniq;
+    P.n_pairs = ip.n_uniq;
+    P.pairs_cap = ip.n_keys;
+    P.out = g->counts.as<uint64_t>() + (minus ? ACC_IV_M : ACC_IV_P);
+    P.status = &g->st.sc->status;
+    triad_iv_launch(P, s);
+}
+
+__global__ void k_he_tmp_update(uint64_t* cnt) {
+    int i = threadIdx.x;
+    if (i < 30) cnt[CNT_HE + i] += cnt[ACC_HE_P + i] - cnt[ACC_HE_M + i];
+    if (i < 96) cnt[CNT_TMP + i] += cnt[ACC_TMP_P + i] - cnt[ACC_TMP_M + i];
+}
+
+// One batch.  check_order = 0 only for the build batch.
+int apply(hgt_graph* g, const uint32_t* del, uint64_t n_del, const uint64_t* ins_off, const uint32_t* ins_mem,
+          uint64_t n_mem, const int64_t* ins_ts, uint64_t n_ins, uint32_t* out_ids, hipStream_t s, int check_order) {
+    const bool tmp = g->track_mask & (1u << HGT_TRIAD_TEMPORAL);
+    if ((n_del && !del) || (n_ins && !ins_off) || (n_mem && !ins_mem)) return HGT_EINVAL;
+    if (tmp && n_ins && !ins_ts) return HGT_EINVAL;
+    if (n_ins > 0xfffffff0ull || n_del > 0xfffffff0ull) return HGT_EINVAL;
+    if (n_mem > n_ins * (uint64_t)HGT_MAX_CARD) return HGT_EINVAL;
+    if (n_del > g->n_live) {
+        g->sticky = g->sticky ? g->sticky : HGT_ENOENT;
+        return HGT_ENOENT;
+    }
+    g->last_stream = s;
+    int rc = ensure_id_cap(g, g->next_id + n_ins + 1, s);
+    if (rc) return rc;
+    g->st.next_id_host = g->next_id;
+    g->st.hb = bits_for(g->next_id + n_ins);
+    g->st.vb = bits_for(g->st.n_vertices ? g->st.n_vertices - 1 : 0);
+    if (g->st.hb + 1 + g->st.vb > 64) return HGT_EINVAL;
+    Sizes z{n_del, n_ins, n_mem, g->n_inc + n_mem, (g->next_id + 63) / 64 + 1};
+    PlanScratch w{};
+    rc = ensure_plan_scratch(g, z, w);
+    if (rc) return rc;
+    BatchIn b{del, n_del, ins_off, ins_mem, n_mem, ins_ts, n_ins, g->epoch + 1, g->epoch + 2, check_order};
+    g->epoch += 2;
+    uint64_t* cnt = g->counts.as<uint64_t>();
+    // planning (reads only)
+    store_batch_begin(g->st.sc, w.sum, s);
+    hgt_fill_u64(cnt + CNT_N, 0, ACC_N - CNT_N, s);
+    store_plan(g->st, b, w, s);
+    HIP_OK(hipMemcpyAsync(g->h_sum, w.sum, sizeof(BatchSummary), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipMemcpyAsync(g->h_sc, g->st.sc, sizeof(DevScalars), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    const BatchSummary sum = *g->h_sum;
+    if (sum.status != HGT_OK) {
+        if (!g->sticky) g->sticky = sum.status;
+        return sum.status;
+    }
+    // capacities for the commit
+    rc = ensure_pool(g->h2v, g->h_bump, sum.h2v_need, s);
+    if (!rc) rc = ensure_pool(g->v2h, g->v_bump, sum.v2h_need, s);
+    if (!rc) rc = ensure(g->s_staging, std::max<uint64_t>(sum.stage_words, 1) * 4);
+    if (rc) return rc;
+    refresh_view(g);
+    w.staging = g->s_staging.as<uint32_t>();
+    const bool do_iv = g->track_mask & (1u << HGT_TRIAD_INCIDENT_VERTEX);
+    IvPlan ip;
+    if (do_iv) {
+        rc = iv_prepare(g, b, w, sum, ip, s);
+        if (rc) return rc;
+    }
+    // step 2: deltas on the old graph
+    rc = run_he_phase(g, del, n_del, g->st.mark_del, b.epoch_del, sum.max_lh_del, true, s);
+    if (rc) return rc;
+    if (do_iv) iv_phase(g, ip, true, s);
+    // step 3: delete, then insert
+    store_commit(g->st, b, w, sum, g->h_bump, g->v_bump, g->next_seq, s);
+    if (out_ids && n_ins) HIP_OK(hipMemcpyAsync(out_ids, w.assigned, n_ins * 4, hipMemcpyDeviceToDevice, s));
+    // step 5: deltas on the new graph
+    rc = run_he_phase(g, w.assigned, n_ins, g->st.mark_ins, b.epoch_ins, sum.max_lh_ins, false, s);
+    if (rc) return rc;
+    if (do_iv) iv_phase(g, ip, false, s);
+    // step 6
+    k_he_tmp_update<<<1, 128, 0, s>>>(cnt);
+    if (do_iv) k_iv_update<<<1, 64, 0, s>>>(cnt, CNT_IV, ACC_IV_M, ACC_IV_P, ACC_T1);
+    HIP_OK(hipGetLastError());
+    // host mirrors
+    g->next_id = sum.next_id_new;
+    g->h_bump += sum.h2v_need;
+    g->v_bump += sum.v2h_need;
+    g->next_seq += n_ins;
+    g->n_live = g->n_live + n_ins - n_del;
+    g->n_inc = g->n_inc + n_mem - sum.del_members;
+    g->batches++;
+    return HGT_OK;
+}
+
+void destroy_graph(hgt_graph* g) {
+    if (!g) return;
+    DevBuf* all[] = {&g->h_off, &g->h_len, &g->h_cap, &g->h_ts, &g->h_seq, &g->free_bm, &g->mark_del, &g->mark_ins,
+                     &g->h2v, &g->v_off, &g->v_len, &g->v_cap, &g->v2h, &g->scal, &g->counts, &g->tabs,
+                     &g->s_sum, &g->s_del_bm, &g->s_del_card, &g->s_del_poff, &g->s_ins_rel, &g->s_ins_card,
+                     &g->s_canon, &g->s_big, &g->s_small, &g->s_popc, &g->s_scan, &g->s_assigned, &g->s_h_need,
+                     &g->s_h_rel, &g->s_keys, &g->s_keys_alt, &g->s_sort, &g->s_head, &g->s_is_ins, &g->s_tv,
+                     &g->s_tseg, &g->s_D, &g->s_I, &g->s_It, &g->s_vp, &g->s_staging, &g->s_dst, &g->t_ctr,
+                     &g->t_big_list, &g->t_big_rank, &g->t_big_scratch, &g->iv_keys, &g->iv_alt, &g->iv_sort,
+                     &g->iv_head, &g->iv_uniq, &g->iv_p2, &g->iv_scan};
+    for (DevBuf* b : all) dev_free(*b);
+    if (g->h_sum) (void)hipHostFree(g->h_sum);
+    if (g->h_sc) (void)hipHostFree(g->h_sc);
+    delete g;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char* hgt_status_str(int status) {
+    switch (status) {
+        case HGT_OK: return "ok";
+        case HGT_EINVAL: return "invalid argument or member list";
+        case HGT_ENOENT: return "deleted ID is not live";
+        case HGT_EDUP: return "ID repeated in a deletion list";
+        case HGT_EORDER: return "temporal insert out of order";
+        case HGT_ENOMEM: return "device memory exhausted";
+        case HGT_ENOTTRACKED: return "triad family or window not tracked";
+        case HGT_EDEVICE: return "HIP runtime failure";
+        default: return "unknown status";
+    }
+}
+
+int hgt_class_codes(int type, int32_t* out_host, uint32_t n) {
+    const ClassTables& t = tables();
+    const std::vector<int32_t>* v = type == HGT_TRIAD_HYPEREDGE ? &t.he_codes
+                                    : type == HGT_TRIAD_TEMPORAL ? &t.tmp_codes
+                                                                 : nullptr;
+    if (!v) return HGT_EINVAL;
+    if (out_host) {
+        if (n < v->size()) return HGT_EINVAL;
+        std::memcpy(out_host, v->data(), v->size() * 4);
+    }
+    return (int)v->size();
+}
+
+int hgt_build(const hgt_build_desc* d, hgt_graph** out) {
+    if (!d || !out) return HGT_EINVAL;
+    *out = nullptr;
+    if (d->n_vertices == 0 || d->n_vertices > 0x7fffffffu) return HGT_EINVAL;
+    if (d->n_edges && (!d->offsets || !d->members)) return HGT_EINVAL;
+    if (d->track_mask & ~7u) return HGT_EINVAL;
+    const bool tmp = d->track_mask & (1u << HGT_TRIAD_TEMPORAL);
+    if (tmp && d->n_edges && !d->timestamps) return HGT_EINVAL;
+    if (d->temporal_window < 0) return HGT_EINVAL;
+    if (d->n_edges > 0xfffffff0ull) return HGT_EINVAL;
+    hipStream_t s = (hipStream_t)d->stream;
+    hgt_graph* g = new (std::nothrow) hgt_graph();
+    if (!g) return HGT_ENOMEM;
+    g->track_mask = d->track_mask;
+    g->window = d->temporal_window;
+    g->last_stream = s;
+    int rc = HGT_OK;
+    do {
+        if (hipGetDevice(&g->device) != hipSuccess) { rc = HGT_EDEVICE; break; }
+        int ncu = 0;
+        if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, g->device) == hipSuccess && ncu > 0)
+            g->n_cu = ncu;
+        if (hipHostMalloc((void**)&g->h_sum, sizeof(BatchSummary), hipHostMallocDefault) != hipSuccess ||
+            hipHostMalloc((void**)&g->h_sc, sizeof(DevScalars), hipHostMallocDefault) != hipSuccess) {
+            rc = HGT_ENOMEM;
+            break;
+        }
+        g->st.n_vertices = d->n_vertices;
+        g->st.id_cap = 0;
+        uint64_t cap = std::max<uint64_t>(d->edge_capacity, d->n_edges + d->n_edges / 4 + 64);
+        if ((rc = ensure_id_cap(g, cap, s))) break;
+        uint64_t V = d->n_vertices;
+        if ((rc = dev_alloc(g->v_off, V * 8)) || (rc = dev_alloc(g->v_len, V * 4)) || (rc = dev_alloc(g->v_cap, V * 4)))
+            break;
+        if (hipMemsetAsync(g->v_off.p, 0, V * 8, s) != hipSuccess || hipMemsetAsync(g->v_len.p, 0, V * 4, s) != hipSuccess ||
+            hipMemsetAsync(g->v_cap.p, 0, V * 4, s) != hipSuccess) {
+            rc = HGT_EDEVICE;
+            break;
+        }
+        uint64_t pw = d->pool_words ? d->pool_words : 1 << 20;
+        if ((rc = dev_alloc(g->h2v, pw * 4)) || (rc = dev_alloc(g->v2h, pw * 4))) break;
+        if ((rc = dev_alloc(g->scal, sizeof(DevScalars))) || (rc = dev_alloc(g->counts, ACC_N * 8)) ||
+            (rc = dev_alloc(g->tabs, 256)))
+            break;
+        DevScalars z{};
+        z.last_ts = INT64_MIN;
+        const ClassTables& t = tables();
+        uint8_t tb[256];
+        std::memcpy(tb, t.he, 128);
+        std::memcpy(tb + 128, t.tmp, 128);
+        if (hipMemcpyAsync(g->scal.p, &z, sizeof z, hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipMemsetAsync(g->counts.p, 0, ACC_N * 8, s) != hipSuccess ||
+            hipMemcpyAsync(g->tabs.p, tb, 256, hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess) {
+            rc = HGT_EDEVICE;
+            break;
+        }
+        refresh_view(g);
+        if (d->n_edges) {
+            // build = insert every hyperedge into the empty graph; the inserted
+            // hyperedges' deltas are the initial counts
+            uint64_t first = 0, last = 0;
+            if (hipMemcpy(&first, d->offsets, 8, hipMemcpyDeviceToHost) != hipSuccess ||
+                hipMemcpy(&last, d->offsets + d->n_edges, 8, hipMemcpyDeviceToHost) != hipSuccess) {
+                rc = HGT_EDEVICE;
+                break;
+            }
+            if (last < first) { rc = HGT_EINVAL; break; }
+            if (tmp) store_max_ts(d->timestamps, d->n_edges, g->st.sc, s);
+            rc = apply(g, nullptr, 0, d->offsets, d->members, last - first, tmp ? d->timestamps : nullptr, d->n_edges,
+                       nullptr, s, 0);
+            if (rc) break;
+            if (hipStreamSynchronize(s) != hipSuccess) { rc = HGT_EDEVICE; break; }
+        }
+    } while (0);
+    if (rc) {
+        destroy_graph(g);
+        return rc;
+    }
+    g->sticky = HGT_OK;
+    *out = g;
+    return HGT_OK;
+}
+
+int hgt_apply_batch(hgt_graph* g, const uint32_t* del_ids, uint64_t n_del, const uint64_t* ins_offsets,
+                    const uint32_t* ins_members, uint64_t n_ins_members, const int64_t* ins_ts, uint64_t n_ins,
+                    uint32_t* out_ins_ids, void* stream) {
+    if (!g) return HGT_EINVAL;
+    if (n_del == 0 && n_ins == 0) return HGT_OK;
+    int rc = apply(g, del_ids, n_del, ins_offsets, ins_members, n_ins_members, ins_ts, n_ins, out_ins_ids,
+                   (hipStream_t)stream, 1);
+    if (rc && !g->sticky) g->sticky = rc;
+    return rc;
+}
+
+int hgt_sync(hgt_graph* g, int* status) {
+    if (!g) return HGT_EINVAL;
+    if (hipStreamSynchronize(g->last_stream) != hipSuccess) {
+        (void)hipGetLastError();
+        if (status) *status = HGT_EDEVICE;
+        return HGT_EDEVICE;
+    }
+    if (status) *status = g->sticky;
+    return HGT_OK;
+}
+
+int hgt_triad_counts(hgt_graph* g, int type, int64_t window, uint64_t* out_host, uint32_t n_out) {
+    if (!g || !out_host) return HGT_EINVAL;
+    int off, n;
+    switch (type) {
+        case HGT_TRIAD_HYPEREDGE: off = CNT_HE; n = 30; break;
+        case HGT_TRIAD_INCIDENT_VERTEX: off = CNT_IV; n = 3; break;
+        case HGT_TRIAD_TEMPORAL: off = CNT_TMP; n = 96; break;
+        default: return HGT_EINVAL;
+    }
+    if (n_out < (uint32_t)n) return HGT_EINVAL;
+    if (!(g->track_mask & (1u << type))) return HGT_ENOTTRACKED;
+    if (type == HGT_TRIAD_TEMPORAL ? window != g->window : window != 0) return HGT_ENOTTRACKED;
+    HIP_OK(hipMemcpyAsync(out_host, g->counts.as<uint64_t>() + off, n * 8, hipMemcpyDeviceToHost, g->last_stream));
+    HIP_OK(hipStreamSynchronize(g->last_stream));
+    return HGT_OK;
+}
+
+int hgt_destroy(hgt_graph* g) {
+    if (!g) return HGT_EINVAL;
+    (void)hipStreamSynchronize(g->last_stream);
+    destroy_graph(g);
+    return HGT_OK;
+}
+
+int hgt_get_info(hgt_graph* g, hgt_info* o) {
+    if (!g || !o) return HGT_EINVAL;
+    HIP_OK(hipStreamSynchronize(g->last_stream));
+    o->n_vertices = g->st.n_vertices;
+    o->track_mask = g->track_mask;
+    o->next_id = g->next_id;
+    o->n_live = g->n_live;
+    o->n_incidences = g->n_inc;
+    o->edge_capacity = g->st.id_cap;
+    o->h2v_pool_words = g->h2v.bytes / 4;
+    o->h2v_used_words = g->h_bump;
+    o->v2h_pool_words = g->v2h.bytes / 4;
+    o->v2h_used_words = g->v_bump;
+    o->temporal_window = g->window;
+    o->batches = g->batches;
+    return HGT_OK;
+}
+
+int hgt_export_h2v(hgt_graph* g, uint64_t* offsets_host, uint32_t* members_host, uint8_t* live_host) {
+    if (!g || !offsets_host || !members_host || !live_host) return HGT_EINVAL;
+    hipStream_t s = g->last_stream;
+    HIP_OK(hipStreamSynchronize(s));
+    uint64_t n = g->next_id;
+    std::vector<uint64_t> off(n), bm((n + 63) / 64 + 1);
+    std::vector<uint32_t> len(n), pool(g->h_bump);
+    if (n) {
+        HIP_OK(hipMemcpy(off.data(), g->h_off.p, n * 8, hipMemcpyDeviceToHost));
+        HIP_OK(hipMemcpy(len.data(), g->h_len.p, n * 4, hipMemcpyDeviceToHost));
+        HIP_OK(hipMemcpy(bm.data(), g->free_bm.p, ((n + 63) / 64) * 8, hipMemcpyDeviceToHost));
+    }
+    if (g->h_bump) HIP_OK(hipMemcpy(pool.data(), g->h2v.p, g->h_bump * 4, hipMemcpyDeviceToHost));
+    uint64_t k = 0;
+    for (uint64_t i = 0; i < n; i++) {
+        bool free_ = (bm[i >> 6] >> (i & 63)) & 1;
+        live_host[i] = free_ ? 0 : 1;
+        offsets_host[i] = k;
+        if (!free_) {
+            if (off[i] + len[i] > g->h_bump) return HGT_EDEVICE;
+            std::memcpy(members_host + k, pool.data() + off[i], len[i] * 4);
+            k += len[i];
+        }
+    }
+    offsets_host[n] = k;
+    return HGT_OK;
+}
+
+int hgt_export_v2h(hgt_graph* g, uint64_t* offsets_host, uint32_t* members_host) {
+    if (!g || !offsets_host || !members_host) return HGT_EINVAL;
+    HIP_OK(hipStreamSynchronize(g->last_stream));
+    uint64_t V = g->st.n_vertices;
+    std::vector<uint64_t> off(V);
+    std::vector<uint32_t> len(V), pool(g->v_bump);
+    HIP_OK(hipMemcpy(off.data(), g->v_off.p, V * 8, hipMemcpyDeviceToHost));
+    HIP_OK(hipMemcpy(len.data(), g->v_len.p, V * 4, hipMemcpyDeviceToHost));
+    if (g->v_bump) HIP_OK(hipMemcpy(pool.data(), g->v2h.p, g->v_bump * 4, hipMemcpyDeviceToHost));
+    uint64_t k = 0;
+    for (uint64_t v = 0; v < V; v++) {
+        offsets_host[v] = k;
+        if (len[v]) {
+            if (off[v] + len[v] > g->v_bump) return HGT_EDEVICE;
+            std::memcpy(members_host + k, pool.data() + off[v], len[v] * 4);
+            k += len[v];
+        }
+    }
+    offsets_host[V] = k;
+    return HGT_OK;
+}
+
+}  // extern "C"

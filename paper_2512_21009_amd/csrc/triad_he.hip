@@ -1,0 +1,630 @@
+// triad_he.hip -- hyperedge-based and temporal triad deltas (Alg. 3, steps 2 and 5).
+//
+// For a set of changed hyperedges C (the deleted ones on the old graph, or the
+// inserted ones on the new graph) the kernels count, per class, every triad
+// that contains at least one member of C, each exactly once: a triad is
+// counted at its member of C with the smallest batch rank.  This is the exact
+// form of Alg. 3's affected-region count; count_new - count_old over these
+// triads is the change of the full count.
+//
+// The triads that contain a centre h are {h,x,y} with
+//   (i)  x, y both line-graph neighbours of h, and
+//   (ii) x a neighbour of h, y a neighbour of x that is neither h nor meets h.
+// Work per centre h (one 256-thread workgroup):
+//   1. N(h) with c_x = |h & x| is built in an open-addressing hash from the
+//      incidence lists of h's members (coalesced segment reads).
+//   2. Pairs of type (i) are first all classified as if x and y were disjoint;
+//      for the hyperedge family this depends only on (c_x, |x| > c_x) of each
+//      side and on c_x + c_y < |h|, so a histogram over c gives every class
+//      count in O(|N(h)| + |h|).  The temporal family (window-limited, few
+//      pairs) enumerates these pairs directly.
+//   3. Each wave takes neighbours x and gathers the incidence lists of x's
+//      members into a wave-private LDS hash (y -> |x & y|, |h & x & y|).
+//      Every y found there is an intersecting pair: if y is in N(h) the pair's
+//      class from step 2 is replaced by its true class; otherwise {h,x,y} is a
+//      type (ii) path.
+// Class counts are accumulated in LDS (u64, modular) and flushed once per
+// workgroup.  Centres whose neighbourhood does not fit the LDS tables are
+// deferred to a second kernel that keeps the same tables in global scratch.
+#include "triad.h"
+
+namespace {
+
+constexpr int NWAVE = HGT_WG / HGT_WAVE;  // 4
+// small-centre (LDS) configuration
+constexpr uint32_t S_LH = 1024;        // max sum of member degrees
+constexpr uint32_t S_NH = 2048;        // N(h) hash slots
+constexpr uint32_t S_WAREA = 4096;     // u32 words shared area (per-wave hashes alias it)
+constexpr uint32_t WH_SLOTS = 512;     // per-wave 2-hop hash slots
+constexpr uint32_t WH_MAX_L = WH_SLOTS / 2;
+constexpr uint32_t CHUNK = 64;
+
+// meta word of a neighbour: c (14 bits) | len << 14 | eligible << 28 | in window << 29
+__device__ __forceinline__ uint32_t meta_c(uint32_t m) { return m & 0x3fffu; }
+__device__ __forceinline__ uint32_t meta_len(uint32_t m) { return (m >> 14) & 0x3fffu; }
+__device__ __forceinline__ bool meta_elig(uint32_t m) { return (m >> 28) & 1u; }
+__device__ __forceinline__ bool meta_win(uint32_t m) { return (m >> 29) & 1u; }
+
+__device__ __forceinline__ int venn_code(int na, int nb, int nc, int ab, int bc, int ca, int abc) {
+    int c = 0;
+    c |= (na - ab - ca + abc > 0) ? 1 : 0;
+    c |= (nb - ab - bc + abc > 0) ? 2 : 0;
+    c |= (nc - bc - ca + abc > 0) ? 4 : 0;
+    c |= (ab - abc > 0) ? 8 : 0;
+    c |= (bc - abc > 0) ? 16 : 0;
+    c |= (ca - abc > 0) ? 32 : 0;
+    c |= (abc > 0) ? 64 : 0;
+    return c;
+}
+
+__device__ __forceinline__ bool key_before(int64_t ta, uint64_t sa, int64_t tb, uint64_t sb) {
+    return ta < tb || (ta == tb && sa < sb);
+}
+
+// Venn code of the triple (h, x, y) relabelled in arrival order.
+__device__ __forceinline__ int time_code(int64_t th, uint64_t sh, int64_t tx, uint64_t sx, int64_t ty, uint64_t sy,
+                                         int nh, int nx, int ny, int hx, int xy, int hy, int hxy) {
+    // rank of each label in arrival order
+    int rh = (int)key_before(tx, sx, th, sh) + (int)key_before(ty, sy, th, sh);
+    int rx = (int)key_before(th, sh, tx, sx) + (int)key_before(ty, sy, tx, sx);
+    int lab[3];
+    lab[rh] = 0;
+    lab[rx] = 1;
+    lab[3 - rh - rx] = 2;
+    int n[3] = {nh, nx, ny};
+    // pairwise intersections indexed by label pair
+    auto pr = [&](int a, int b) -> int {
+        int s = a + b;  // {0,1}->1 hx, {1,2}->3 xy, {0,2}->2 hy
+        return s == 1 ? hx : (s == 3 ? xy : hy);
+    };
+    int a = lab[0], b = lab[1], c = lab[2];
+    return venn_code(n[a], n[b], n[c], pr(a, b), pr(b, c), pr(c, a), hxy);
+}
+
+__device__ __forceinline__ bool within(int64_t a, int64_t b, int64_t c, int64_t w) {
+    int64_t mx = a > b ? a : b, mn = a < b ? a : b;
+    mx = mx > c ? mx : c;
+    mn = mn < c ? mn : c;
+    return mx - mn <= w;
+}
+
+// ---- hashing --------------------------------------------------------------
+__device__ __forceinline__ void hash_add(uint32_t* keys, uint32_t* vals, uint32_t log_cap, uint32_t key, uint32_t inc) {
+    uint32_t mask = (1u << log_cap) - 1u;
+    uint32_t s = hash_slot(key, log_cap);
+    for (uint32_t probe = 0; probe <= mask; probe++) {
+        uint32_t k = __atomic_load_n(&keys[s], __ATOMIC_RELAXED);
+        if (k == HGT_EMPTY) {
+            uint32_t prev = atomicCAS(&keys[s], HGT_EMPTY, key);
+            if (prev == HGT_EMPTY || prev == key) { atomicAdd(&vals[s], inc); return; }
+        } else if (k == key) {
+            atomicAdd(&vals[s], inc);
+            return;
+        }
+        s = (s + 1) & mask;
+    }
+}
+
+// returns slot index or HGT_EMPTY
+__device__ __forceinline__ uint32_t hash_find(const uint32_t* keys, uint32_t log_cap, uint32_t key) {
+    uint32_t mask = (1u << log_cap) - 1u;
+    uint32_t s = hash_slot(key, log_cap);
+    for (uint32_t probe = 0; probe <= mask; probe++) {
+        uint32_t k = keys[s];
+        if (k == key) return s;
+        if (k == HGT_EMPTY) return HGT_EMPTY;
+        s = (s + 1) & mask;
+    }
+    return HGT_EMPTY;
+}
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// exclusive workgroup scan of one u32 per thread (all threads participate)
+__device__ __forceinline__ uint32_t wg_scan_u32(uint32_t v, uint32_t* ws, uint32_t* total) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t t = __shfl_up(x, o, 64);
+        if (lane >= o) x += t;
+    }
+    if (lane == 63) ws[wave] = x;
+    __syncthreads();
+    uint32_t pre = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < NWAVE; w++) {
+        uint32_t s = ws[w];
+        if (w < wave) pre += s;
+        tot += s;
+    }
+    __syncthreads();
+    *total = tot;
+    return pre + x - v;
+}
+
+struct Tables {
+    uint8_t he[128];
+    uint8_t tmp[128];
+};
+
+// Per-wave member info of the neighbour x being expanded.
+struct WaveMem {
+    uint32_t pre[CHUNK + 1];
+    uint64_t voff[CHUNK];
+    uint32_t inh[CHUNK];
+};
+
+// Storage of one workgroup (LDS for the small kernel, global for the big one).
+struct WgStore {
+    uint32_t* nh_keys;
+    uint32_t* nh_vals;
+    uint32_t* hm;      // members of h
+    uint32_t* nl_x;    // compacted N(h)
+    uint32_t* nl_meta;
+    uint32_t* warea;   // shared area
+    uint64_t warea_words;
+    uint32_t* wh;      // per-wave 2-hop hashes (NWAVE * 2 * WH_SLOTS words)
+};
+
+struct Shared {
+    uint32_t h, rank, hlen, lh, K, Kt, defer, stop;
+    uint64_t hoff;
+    int64_t th;
+    uint64_t sh;
+    uint32_t ws[NWAVE];
+    uint64_t g[8];
+};
+
+__device__ __forceinline__ void acc_add(uint64_t* acc, int cls, uint64_t v) {
+    if (cls < 255) atomicAdd((unsigned long long*)&acc[cls], (unsigned long long)v);
+}
+
+// classify the intersecting pair (x, y) found in x's 2-hop lists
+__device__ __forceinline__ void classify(const TriadParams& P, const Tables& T, const WgStore& S, const Shared& sh,
+                                         uint32_t nh_log, uint32_t x, uint32_t meta_x, int64_t tx, uint64_t sx,
+                                         uint32_t y, uint32_t cxy, uint32_t chxy, uint64_t* acc_he, uint64_t* acc_tmp) {
+    const int nh = (int)sh.hlen;
+    const int nx = (int)meta_len(meta_x), hx = (int)meta_c(meta_x);
+    uint32_t slot = hash_find(S.nh_keys, nh_log, y);
+    if (slot != HGT_EMPTY) {
+        // (i) both neighbours of h and intersecting: replace the disjoint-pair class
+        if (x > y) return;
+        uint32_t my = S.nh_vals[slot];
+        if (!meta_elig(my)) return;
+        const int ny = (int)meta_len(my), hy = (int)meta_c(my);
+        if (P.do_he) {
+            int ct = T.he[venn_code(nh, nx, ny, hx, (int)cxy, hy, (int)chxy)];
+            int cf = T.he[venn_code(nh, nx, ny, hx, 0, hy, 0)];
+            if (ct != cf) {
+                acc_add(acc_he, ct, 1);
+                acc_add(acc_he, cf, ~0ull);
+            }
+        }
+        if (P.do_tmp && meta_win(meta_x) && meta_win(my)) {
+            int64_t ty = P.g.h_ts[y];
+            if (within(sh.th, tx, ty, P.window)) {
+                uint64_t sy = P.g.h_seq[y];
+                int ct = T.tmp[time_code(sh.th, sh.sh, tx, sx, ty, sy, nh, nx, ny, hx, (int)cxy, hy, (int)chxy)];
+                int cf = T.tmp[time_code(sh.th, sh.sh, tx, sx, ty, sy, nh, nx, ny, hx, 0, hy, 0)];
+                if (ct != cf) {
+                    acc_add(acc_tmp, ct, 1);
+                    acc_add(acc_tmp, cf, ~0ull);
+                }
+            }
+        }
+        return;
+    }
+    // (ii) path h - x - y with y outside the closed neighbourhood of h
+    if (lower_ranked_member(P.mark[y], P.epoch, sh.rank)) return;
+    int64_t ty = 0;
+    if (P.do_tmp) {
+        ty = P.g.h_ts[y];
+        if (!P.do_he && !within(sh.th, tx, ty, P.window)) return;
+    }
+    const int ny = (int)P.g.h_len[y];
+    if (P.do_he) acc_add(acc_he, T.he[venn_code(nh, nx, ny, hx, (int)cxy, 0, 0)], 1);
+    if (P.do_tmp && meta_win(meta_x) && within(sh.th, tx, ty, P.window)) {
+        uint64_t sy = P.g.h_seq[y];
+        acc_add(acc_tmp, T.tmp[time_code(sh.th, sh.sh, tx, sx, ty, sy, nh, nx, ny, hx, (int)cxy, 0, 0)], 1);
+    }
+}
+
+// Expand neighbour x of the current centre (one wave).
+__device__ void expand_x(const TriadParams& P, const Tables& T, const WgStore& S, const Shared& sh, uint32_t nh_log,
+                         WaveMem& wm, uint32_t* wkeys, uint32_t* wvals, uint32_t x, uint32_t meta_x, uint64_t* acc_he,
+                         uint64_t* acc_tmp) {
+    const int lane = threadIdx.x & 63;
+    const uint32_t nx = meta_len(meta_x);
+    const uint64_t xoff = P.g.h_off[x];
+    int64_t tx = 0;
+    uint64_t sx = 0;
+    if (P.do_tmp) {
+        tx = P.g.h_ts[x];
+        sx = P.g.h_seq[x];
+    }
+    // total 2-hop length
+    uint32_t lx = 0;
+    for (uint32_t b = 0; b < nx; b += CHUNK) {
+        uint32_t d = 0;
+        if (b + lane < nx) d = P.g.v_len[P.g.h2v[xoff + b + lane]];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) d += __shfl_xor(d, o, 64);
+        lx += d;
+    }
+    if (lx <= WH_MAX_L) {
+        uint32_t log_cap = log2u64(pow2ceil64(2 * (uint64_t)lx < 64 ? 64 : 2 * (uint64_t)lx));
+        uint32_t cap = 1u << log_cap;
+        for (uint32_t s = lane; s < cap; s += 64) { wkeys[s] = HGT_EMPTY; wvals[s] = 0; }
+        wave_sync();
+        for (uint32_t b = 0; b < nx; b += CHUNK) {
+            uint32_t cnt = nx - b < CHUNK ? nx - b : CHUNK;
+            uint32_t d = 0;
+            if ((uint32_t)lane < cnt) {
+                uint32_t m = P.g.h2v[xoff + b + lane];
+                d = P.g.v_len[m];
+                wm.voff[lane] = P.g.v_off[m];
+                wm.inh[lane] = contains_u32(S.hm, sh.hlen, m) ? 1u : 0u;
+            }
+            uint32_t inc = d;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                uint32_t t = __shfl_up(inc, o, 64);
+                if (lane >= o) inc += t;
+            }
+            if ((uint32_t)lane < cnt) wm.pre[lane + 1] = inc;
+            if (lane == 0) wm.pre[0] = 0;
+            wave_sync();
+            uint32_t len = wm.pre[cnt];
+            for (uint32_t p = lane; p < len; p += 64) {
+                uint32_t k = seg_of<uint32_t>(wm.pre, cnt, p);
+                uint32_t y = P.g.v2h[wm.voff[k] + (p - wm.pre[k])];
+                if (y != x && y != sh.h) hash_add(wkeys, wvals, log_cap, y, 1u + (wm.inh[k] << 16));
+            }
+            wave_sync();
+        }
+        for (uint32_t s = lane; s < cap; s += 64) {
+            uint32_t y = wkeys[s];
+            if (y != HGT_EMPTY) {
+                uint32_t v = wvals[s];
+                classify(P, T, S, sh, nh_log, x, meta_x, tx, sx, y, v & 0xffffu, v >> 16, acc_he, acc_tmp);
+            }
+        }
+        wave_sync();
+        return;
+    }
+    // large 2-hop: a y is handled at the first member list (in member order)
+    // that holds it; its multiplicities come from binary searches in the other lists
+    for (uint32_t b = 0; b < nx; b += CHUNK) {
+        uint32_t cnt = nx - b < CHUNK ? nx - b : CHUNK;
+        uint32_t d = 0;
+        if ((uint32_t)lane < cnt) {
+            uint32_t m = P.g.h2v[xoff + b + lane];
+            d = P.g.v_len[m];
+            wm.voff[lane] = P.g.v_off[m];
+            wm.inh[lane] = contains_u32(S.hm, sh.hlen, m) ? 1u : 0u;
+        }
+        uint32_t inc = d;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            uint32_t t = __shfl_up(inc, o, 64);
+            if (lane >= o) inc += t;
+        }
+        if ((uint32_t)lane < cnt) wm.pre[lane + 1] = inc;
+        if (lane == 0) wm.pre[0] = 0;
+        wave_sync();
+        uint32_t len = wm.pre[cnt];
+        for (uint32_t p = lane; p < len; p += 64) {
+            uint32_t k = seg_of<uint32_t>(wm.pre, cnt, p);
+            uint32_t y = P.g.v2h[wm.voff[k] + (p - wm.pre[k])];
+            if (y == x || y == sh.h) continue;
+            uint32_t kg = b + k;
+            bool first = true;
+            uint32_t c = 1, ch = wm.inh[k];
+            for (uint32_t j = 0; j < nx; j++) {
+                if (j == kg) continue;
+                uint32_t mj = P.g.h2v[xoff + j];
+                const uint32_t* lst = P.g.v2h + P.g.v_off[mj];
+                if (contains_u32(lst, P.g.v_len[mj], y)) {
+                    if (j < kg) { first = false; break; }
+                    c++;
+                    ch += contains_u32(S.hm, sh.hlen, mj) ? 1u : 0u;
+                }
+            }
+            if (first) classify(P, T, S, sh, nh_log, x, meta_x, tx, sx, y, c, ch, acc_he, acc_tmp);
+        }
+        wave_sync();
+    }
+}
+
+// The whole per-centre computation; BIG selects global tables and no deferral.
+template <bool BIG>
+__device__ void run_centres(const TriadParams& P, const Tables& T, const WgStore& S, Shared& sh, WaveMem* wmem,
+                            uint64_t* acc_he, uint64_t* acc_tmp, uint32_t lh_limit, uint32_t hm_cap) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint32_t* list = BIG ? P.big_list : P.centres;
+    for (;;) {
+        if (tid == 0) {
+            uint64_t n = BIG ? (uint64_t)*P.big_count : P.n_centres;
+            uint32_t c = atomicAdd(BIG ? P.big_queue : P.queue, 1u);
+            sh.stop = c >= n;
+            if (!sh.stop) {
+                uint32_t h = list[c];
+                sh.h = h;
+                sh.rank = BIG ? P.big_rank[c] : c;
+                sh.hlen = P.g.h_len[h];
+                sh.hoff = P.g.h_off[h];
+                if (P.do_tmp) {
+                    sh.th = P.g.h_ts[h];
+                    sh.sh = P.g.h_seq[h];
+                }
+                sh.defer = (!BIG && sh.hlen > hm_cap) ? 1u : 0u;
+            }
+        }
+        __syncthreads();
+        if (sh.stop) break;
+        if (sh.defer) {
+            if (tid == 0) {
+                uint32_t q = atomicAdd(P.big_count, 1u);
+                P.big_list[q] = sh.h;
+                P.big_rank[q] = sh.rank;
+            }
+            __syncthreads();
+            continue;
+        }
+        const uint32_t hlen = sh.hlen, h = sh.h;
+        // members of h, their degrees and list offsets (prefix in warea)
+        uint32_t* pre = S.warea;                                  // hlen + 1 words
+        uint64_t* voff = (uint64_t*)(S.warea + ((hlen + 2) & ~1u));  // hlen u64, 8-byte aligned
+        uint32_t carry = 0;
+        for (uint32_t b = 0; b < hlen; b += HGT_WG) {
+            uint32_t i = b + tid, d = 0;
+            if (i < hlen) {
+                uint32_t m = P.g.h2v[sh.hoff + i];
+                S.hm[i] = m;
+                d = P.g.v_len[m];
+                voff[i] = P.g.v_off[m];
+            }
+            uint32_t tot;
+            uint32_t ex = wg_scan_u32(d, sh.ws, &tot);
+            if (i < hlen) pre[i] = carry + ex;
+            carry += tot;
+        }
+        if (tid == 0) {
+            pre[hlen] = carry;
+            sh.lh = carry;
+            sh.defer = (!BIG && carry > lh_limit) ? 1u : 0u;
+        }
+        __syncthreads();
+        if (sh.defer) {
+            if (tid == 0) {
+                uint32_t q = atomicAdd(P.big_count, 1u);
+                P.big_list[q] = h;
+                P.big_rank[q] = sh.rank;
+            }
+            __syncthreads();
+            continue;
+        }
+        const uint32_t lh = sh.lh;
+        uint32_t nh_log = log2u64(pow2ceil64(2 * (uint64_t)lh < 64 ? 64 : 2 * (uint64_t)lh));
+        uint32_t nh_cap = 1u << nh_log;
+        for (uint32_t s = tid; s < nh_cap; s += HGT_WG) { S.nh_keys[s] = HGT_EMPTY; S.nh_vals[s] = 0; }
+        if (tid == 0) { sh.K = 0; sh.Kt = 0; }
+        __syncthreads();
+        // 1. N(h) with c_x
+        for (uint32_t p = tid; p < lh; p += HGT_WG) {
+            uint32_t k = seg_of<uint32_t>(pre, hlen, p);
+            uint32_t x = P.g.v2h[voff[k] + (p - pre[k])];
+            if (x != h) hash_add(S.nh_keys, S.nh_vals, nh_log, x, 1u);
+        }
+        __syncthreads();
+        // compact, attaching |x|, eligibility and window flags
+        for (uint32_t s = tid; s < nh_cap; s += HGT_WG) {
+            uint32_t x = S.nh_keys[s];
+            if (x == HGT_EMPTY) continue;
+            uint32_t c = S.nh_vals[s];
+            uint32_t len = P.g.h_len[x];
+            bool elig = !lower_ranked_member(P.mark[x], P.epoch, sh.rank);
+            bool win = true;
+            if (P.do_tmp) {
+                int64_t d = P.g.h_ts[x] - sh.th;
+                win = d <= P.window && -d <= P.window;
+            }
+            uint32_t meta = c | (len << 14) | ((uint32_t)elig << 28) | ((uint32_t)win << 29);
+            S.nh_vals[s] = meta;
+            uint32_t q = atomicAdd(&sh.K, 1u);
+            S.nl_x[q] = x;
+            S.nl_meta[q] = meta;
+        }
+        __syncthreads();
+        const uint32_t K = sh.K;
+        // 2a. hyperedge family: every eligible pair of neighbours classified as disjoint
+        if (P.do_he) {
+            uint32_t* cnt = S.warea;  // cnt[f * (hlen + 1) + c]
+            const uint32_t W = hlen + 1;
+            for (uint32_t i = tid; i < 2 * W; i += HGT_WG) cnt[i] = 0;
+            if (tid < 8) sh.g[tid] = 0;
+            __syncthreads();
+            for (uint32_t i = tid; i < K; i += HGT_WG) {
+                uint32_t m = S.nl_meta[i];
+                if (!meta_elig(m)) continue;
+                uint32_t c = meta_c(m);
+                uint32_t f = meta_len(m) > c ? 1u : 0u;
+                atomicAdd(&cnt[f * W + c], 1u);
+            }
+            __syncthreads();
+            // exclusive prefix over c for each f (in place) -> number of x with c_x < k
+            for (uint32_t f = 0; f < 2; f++) {
+                uint32_t carry2 = 0;
+                for (uint32_t b = 0; b < W; b += HGT_WG) {
+                    uint32_t i = b + tid;
+                    uint32_t v = i < W ? cnt[f * W + i] : 0;
+                    uint32_t tot;
+                    uint32_t ex = wg_scan_u32(v, sh.ws, &tot);
+                    if (i < W) cnt[f * W + i] = carry2 + ex;
+                    carry2 += tot;
+                }
+                if (tid == 0) sh.g[6 + f] = carry2;  // N_f
+                __syncthreads();
+            }
+            const uint64_t N0 = sh.g[6], N1 = sh.g[7];
+            // S_f(k) = #{x in f : c_x >= k} = N_f - pre_f(k)
+            // G(f1,f2) = sum_c n_f1(c) * S_f2(hlen - c)
+            uint64_t g00 = 0, g01 = 0, g11 = 0, d0 = 0, d1 = 0;
+            for (uint32_t c = 1 + tid; c <= hlen; c += HGT_WG) {
+                uint64_t n0 = (uint64_t)((c + 1 < W ? cnt[c + 1] : (uint32_t)N0) - cnt[c]);
+                uint64_t n1 = (uint64_t)((c + 1 < W ? cnt[W + c + 1] : (uint32_t)N1) - cnt[W + c]);
+                uint32_t k = hlen - c;
+                uint64_t s0 = N0 - cnt[k], s1 = N1 - cnt[W + k];
+                g00 += n0 * s0;
+                g01 += n0 * s1;
+                g11 += n1 * s1;
+                if (2 * c >= hlen) { d0 += n0; d1 += n1; }
+            }
+            atomicAdd((unsigned long long*)&sh.g[0], (unsigned long long)g00);
+            atomicAdd((unsigned long long*)&sh.g[1], (unsigned long long)g01);
+            atomicAdd((unsigned long long*)&sh.g[2], (unsigned long long)g11);
+            atomicAdd((unsigned long long*)&sh.g[3], (unsigned long long)d0);
+            atomicAdd((unsigned long long*)&sh.g[4], (unsigned long long)d1);
+            __syncthreads();
+            if (tid == 0) {
+                uint64_t G00 = (sh.g[0] - sh.g[3]) / 2, G11 = (sh.g[2] - sh.g[4]) / 2, G01 = sh.g[1];
+                uint64_t T00 = N0 * (N0 - (N0 ? 1 : 0)) / 2, T11 = N1 * (N1 - (N1 ? 1 : 0)) / 2, T01 = N0 * N1;
+                // code bits: 1 h only, 2 x only, 4 y only, 8 h&x only, 32 h&y only
+                acc_add(acc_he, T.he[40 | 1], T00 - G00);
+                acc_add(acc_he, T.he[40], G00);
+                acc_add(acc_he, T.he[40 | 4 | 1], T01 - G01);
+                acc_add(acc_he, T.he[40 | 4], G01);
+                acc_add(acc_he, T.he[40 | 6 | 1], T11 - G11);
+                acc_add(acc_he, T.he[40 | 6], G11);
+            }
+            __syncthreads();
+        }
+        // 2b. temporal family: eligible in-window neighbour pairs enumerated directly
+        if (P.do_tmp) {
+            uint32_t* tl = S.warea;  // 4 words per entry: x, meta, t lo, t hi
+            for (uint32_t i = tid; i < K; i += HGT_WG) {
+                uint32_t m = S.nl_meta[i];
+                if (!meta_elig(m) || !meta_win(m)) continue;
+                uint32_t q = atomicAdd(&sh.Kt, 1u);
+                uint32_t x = S.nl_x[i];
+                int64_t t = P.g.h_ts[x];
+                tl[4 * q] = x;
+                tl[4 * q + 1] = m;
+                tl[4 * q + 2] = (uint32_t)(uint64_t)t;
+                tl[4 * q + 3] = (uint32_t)((uint64_t)t >> 32);
+            }
+            __syncthreads();
+            const uint32_t Kt = sh.Kt;
+            const uint64_t npairs = (uint64_t)Kt * (Kt - (Kt ? 1 : 0)) / 2;
+            for (uint64_t q = tid; q < npairs; q += HGT_WG) {
+                // row-major upper triangle: pair (i, j), i < j
+                uint32_t i = (uint32_t)((2.0 * Kt - 1.0 - sqrt((2.0 * Kt - 1.0) * (2.0 * Kt - 1.0) - 8.0 * (double)q)) / 2.0);
+                while (i > 0 && (uint64_t)i * (2ull * Kt - i - 1) / 2 > q) i--;
+                while ((uint64_t)(i + 1) * (2ull * Kt - i - 2) / 2 <= q) i++;
+                uint32_t j = (uint32_t)(q - (uint64_t)i * (2ull * Kt - i - 1) / 2) + i + 1;
+                int64_t ti = (int64_t)((uint64_t)tl[4 * i + 2] | ((uint64_t)tl[4 * i + 3] << 32));
+                int64_t tj = (int64_t)((uint64_t)tl[4 * j + 2] | ((uint64_t)tl[4 * j + 3] << 32));
+                if (!within(sh.th, ti, tj, P.window)) continue;
+                uint32_t mi = tl[4 * i + 1], mj = tl[4 * j + 1];
+                uint64_t si = P.g.h_seq[tl[4 * i]], sj = P.g.h_seq[tl[4 * j]];
+                int code = time_code(sh.th, sh.sh, ti, si, tj, sj, (int)hlen, (int)meta_len(mi), (int)meta_len(mj),
+                                     (int)meta_c(mi), 0, (int)meta_c(mj), 0);
+                acc_add(acc_tmp, T.tmp[code], 1);
+            }
+            __syncthreads();
+        }
+        // 3. intersecting pairs and paths through each neighbour
+        uint32_t* wk = S.wh + (uint64_t)wave * 2 * WH_SLOTS;
+        uint32_t* wv = wk + WH_SLOTS;
+        for (uint32_t i = wave; i < K; i += NWAVE) {
+            uint32_t x = S.nl_x[i];
+            uint32_t m = S.nl_meta[i];
+            if (!meta_elig(m)) continue;
+            if (!P.do_he && !meta_win(m)) continue;
+            expand_x(P, T, S, sh, nh_log, wmem[wave], wk, wv, x, m, acc_he, acc_tmp);
+        }
+        __syncthreads();
+        (void)lane;
+    }
+}
+
+__global__ void __launch_bounds__(HGT_WG) k_delta_small(TriadParams P) {
+    __shared__ uint32_t nh_keys[S_NH], nh_vals[S_NH];
+    __shared__ uint32_t hm[S_LH], nl_x[S_LH], nl_meta[S_LH];
+    __shared__ __attribute__((aligned(16))) uint32_t warea[S_WAREA];
+    __shared__ WaveMem wmem[NWAVE];
+    __shared__ Shared sh;
+    __shared__ Tables T;
+    __shared__ uint64_t acc_he[HGT_N_HE_CLASSES], acc_tmp[HGT_N_TEMPORAL_CLASSES];
+    if (*((volatile const int32_t*)P.status) != 0) return;
+    for (int i = threadIdx.x; i < 128; i += HGT_WG) { T.he[i] = P.he_tab[i]; T.tmp[i] = P.tmp_tab[i]; }
+    for (int i = threadIdx.x; i < HGT_N_HE_CLASSES; i += HGT_WG) acc_he[i] = 0;
+    for (int i = threadIdx.x; i < HGT_N_TEMPORAL_CLASSES; i += HGT_WG) acc_tmp[i] = 0;
+    __syncthreads();
+    WgStore S{nh_keys, nh_vals, hm, nl_x, nl_meta, warea, S_WAREA, warea};
+    run_centres<false>(P, T, S, sh, wmem, acc_he, acc_tmp, S_LH, S_LH);
+    __syncthreads();
+    for (int i = threadIdx.x; i < HGT_N_HE_CLASSES; i += HGT_WG)
+        if (acc_he[i]) atomicAdd((unsigned long long*)&P.out_he[i], (unsigned long long)acc_he[i]);
+    for (int i = threadIdx.x; i < HGT_N_TEMPORAL_CLASSES; i += HGT_WG)
+        if (acc_tmp[i]) atomicAdd((unsigned long long*)&P.out_tmp[i], (unsigned long long)acc_tmp[i]);
+}
+
+__global__ void __launch_bounds__(HGT_WG) k_delta_big(TriadParams P) {
+    __shared__ uint32_t wh[NWAVE * 2 * WH_SLOTS];
+    __shared__ WaveMem wmem[NWAVE];
+    __shared__ Shared sh;
+    __shared__ Tables T;
+    __shared__ uint64_t acc_he[HGT_N_HE_CLASSES], acc_tmp[HGT_N_TEMPORAL_CLASSES];
+    if (*((volatile const int32_t*)P.status) != 0) return;
+    for (int i = threadIdx.x; i < 128; i += HGT_WG) { T.he[i] = P.he_tab[i]; T.tmp[i] = P.tmp_tab[i]; }
+    for (int i = threadIdx.x; i < HGT_N_HE_CLASSES; i += HGT_WG) acc_he[i] = 0;
+    for (int i = threadIdx.x; i < HGT_N_TEMPORAL_CLASSES; i += HGT_WG) acc_tmp[i] = 0;
+    __syncthreads();
+    const BigLayout& L = P.big;
+    uint32_t* base = P.big_scratch + (uint64_t)blockIdx.x * L.words_per_wg;
+    WgStore S{base + L.nh_keys, base + L.nh_vals, base + L.hm, base + L.nl_x, base + L.nl_meta, base + L.warea,
+              L.warea_words, wh};
+    run_centres<true>(P, T, S, sh, wmem, acc_he, acc_tmp, 0xffffffffu, 0xffffffffu);
+    __syncthreads();
+    for (int i = threadIdx.x; i < HGT_N_HE_CLASSES; i += HGT_WG)
+        if (acc_he[i]) atomicAdd((unsigned long long*)&P.out_he[i], (unsigned long long)acc_he[i]);
+    for (int i = threadIdx.x; i < HGT_N_TEMPORAL_CLASSES; i += HGT_WG)
+        if (acc_tmp[i]) atomicAdd((unsigned long long*)&P.out_tmp[i], (unsigned long long)acc_tmp[i]);
+}
+
+}  // namespace
+
+BigLayout triad_big_layout(uint64_t max_lh, uint64_t max_card) {
+    BigLayout L{};
+    uint64_t nh = pow2ceil64(2 * (max_lh < 32 ? 32 : max_lh));
+    uint64_t off = 0;
+    auto take = [&](uint64_t words) { uint64_t o = off; off += (words + 3) & ~3ull; return o; };
+    L.nh_keys = take(nh);
+    L.nh_vals = take(nh);
+    L.hm = take(max_card);
+    L.nl_x = take(max_lh);
+    L.nl_meta = take(max_lh);
+    // shared area: prefix + offsets of h's members (3 words each + slack), histogram
+    // (2 * (card + 1)), temporal list (4 words per neighbour)
+    uint64_t wa = 3 * (max_card + 2) + 4;
+    if (2 * (max_card + 1) > wa) wa = 2 * (max_card + 1);
+    if (4 * max_lh > wa) wa = 4 * max_lh;
+    L.warea_words = wa;
+    L.warea = take(wa);
+    L.words_per_wg = off;
+    return L;
+}
+
+void triad_he_launch(TriadParams& P, unsigned grid_small, unsigned grid_big, hipStream_t s) {
+    hgt_fill_u32(P.queue, 0, 1, s);
+    hgt_fill_u32(P.big_queue, 0, 1, s);
+    hgt_fill_u32(P.big_count, 0, 1, s);
+    if (P.n_centres == 0) return;
+    k_delta_small<<<grid_small, HGT_WG, 0, s>>>(P);
+    k_delta_big<<<grid_big, HGT_WG, 0, s>>>(P);
+}

@@ -1,0 +1,258 @@
+"""Python binding of the HIP triad-count library (ctypes over include/hgt.h).
+
+Argument marshalling only: every step of the batch update and of the triad
+counting runs in the library's HIP kernels.  PyTorch supplies device memory
+(tensor data pointers) and the current HIP stream.  The library must be built
+(`python -m paper_2512_21009_amd.build`); loading fails loudly otherwise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import List, Optional, Sequence
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhgt.so")
+
+OK, EINVAL, ENOENT, EDUP, EORDER, ENOMEM, ENOTTRACKED, EDEVICE = 0, -1, -2, -3, -4, -5, -6, -7
+HYPEREDGE, INCIDENT_VERTEX, TEMPORAL = 0, 1, 2
+N_CLASSES = {HYPEREDGE: 30, INCIDENT_VERTEX: 3, TEMPORAL: 96}
+MAX_CARD = 8192
+_NAMES = {"hyperedge": HYPEREDGE, "incident_vertex": INCIDENT_VERTEX, "iv": INCIDENT_VERTEX, "temporal": TEMPORAL}
+
+
+class HgtError(RuntimeError):
+    def __init__(self, code: int, what: str = ""):
+        self.code = code
+        msg = _lib.hgt_status_str(code).decode() if _lib is not None else str(code)
+        super().__init__(f"{what}: {msg} ({code})" if what else f"{msg} ({code})")
+
+
+class BuildDesc(ctypes.Structure):
+    _fields_ = [
+        ("n_vertices", ctypes.c_uint32),
+        ("n_edges", ctypes.c_uint64),
+        ("offsets", ctypes.c_void_p),
+        ("members", ctypes.c_void_p),
+        ("timestamps", ctypes.c_void_p),
+        ("track_mask", ctypes.c_uint32),
+        ("temporal_window", ctypes.c_int64),
+        ("edge_capacity", ctypes.c_uint64),
+        ("pool_words", ctypes.c_uint64),
+        ("stream", ctypes.c_void_p),
+    ]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [
+        ("n_vertices", ctypes.c_uint32),
+        ("track_mask", ctypes.c_uint32),
+        ("next_id", ctypes.c_uint64),
+        ("n_live", ctypes.c_uint64),
+        ("n_incidences", ctypes.c_uint64),
+        ("edge_capacity", ctypes.c_uint64),
+        ("h2v_pool_words", ctypes.c_uint64),
+        ("h2v_used_words", ctypes.c_uint64),
+        ("v2h_pool_words", ctypes.c_uint64),
+        ("v2h_used_words", ctypes.c_uint64),
+        ("temporal_window", ctypes.c_int64),
+        ("batches", ctypes.c_uint64),
+    ]
+
+
+_lib = None
+
+EXPORTS = ["hgt_build", "hgt_apply_batch", "hgt_triad_counts", "hgt_sync", "hgt_destroy", "hgt_status_str",
+           "hgt_get_info", "hgt_export_h2v", "hgt_export_v2h", "hgt_class_codes"]
+
+
+def load(path: str = LIB_PATH):
+    """Load libhgt.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_2512_21009_amd.build`")
+    lib = ctypes.CDLL(path)
+    P, U64, U32, I64, I32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int64, ctypes.c_int
+    lib.hgt_build.argtypes = [ctypes.POINTER(BuildDesc), ctypes.POINTER(P)]
+    lib.hgt_apply_batch.argtypes = [P, P, U64, P, P, U64, P, U64, P, P]
+    lib.hgt_triad_counts.argtypes = [P, I32, I64, P, U32]
+    lib.hgt_sync.argtypes = [P, ctypes.POINTER(I32)]
+    lib.hgt_destroy.argtypes = [P]
+    lib.hgt_status_str.argtypes = [I32]
+    lib.hgt_status_str.restype = ctypes.c_char_p
+    lib.hgt_get_info.argtypes = [P, ctypes.POINTER(Info)]
+    lib.hgt_export_h2v.argtypes = [P, P, P, P]
+    lib.hgt_export_v2h.argtypes = [P, P, P]
+    lib.hgt_class_codes.argtypes = [I32, P, U32]
+    for name in EXPORTS:
+        getattr(lib, name).restype = getattr(lib, name).restype or ctypes.c_int
+    lib.hgt_status_str.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _stream(stream) -> int:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream) if hasattr(stream, "cuda_stream") else int(stream)
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return t.data_ptr() if t.numel() else None
+
+
+def _check_dtype(t, allowed, name):
+    if t is not None and t.dtype not in allowed:
+        raise TypeError(f"{name}: dtype {t.dtype} not in {allowed}")
+
+
+def _mask(track: Sequence) -> int:
+    m = 0
+    for t in track:
+        m |= 1 << (_NAMES[t] if isinstance(t, str) else int(t))
+    return m
+
+
+def class_codes(kind) -> List[int]:
+    lib = load()
+    k = _NAMES[kind] if isinstance(kind, str) else int(kind)
+    n = lib.hgt_class_codes(k, None, 0)
+    if n < 0:
+        raise HgtError(n, "class_codes")
+    arr = (ctypes.c_int32 * n)()
+    lib.hgt_class_codes(k, ctypes.cast(arr, ctypes.c_void_p), n)
+    return list(arr)
+
+
+class Graph:
+    """A hypergraph resident on the current GPU with incrementally maintained
+    triad counts (hyperedge 30 classes, incident-vertex 3 types, temporal 96)."""
+
+    def __init__(self, handle: int, window: int, track_mask: int):
+        self._h = ctypes.c_void_p(handle)
+        self.window = window
+        self.track_mask = track_mask
+
+    # ------------------------------------------------------------------ build
+    @classmethod
+    def build(cls, n_vertices: int, offsets, members, timestamps=None, track=("hyperedge",), window: int = 0,
+              edge_capacity: int = 0, pool_words: int = 0, stream=None) -> "Graph":
+        """offsets: int64 device tensor [E+1]; members: int32/uint32 device
+        tensor; timestamps: int64 device tensor [E] (temporal)."""
+        import torch
+        lib = load()
+        _check_dtype(offsets, (torch.int64, torch.uint64), "offsets")
+        _check_dtype(members, (torch.int32, torch.uint32), "members")
+        _check_dtype(timestamps, (torch.int64,), "timestamps")
+        d = BuildDesc()
+        d.n_vertices = int(n_vertices)
+        d.n_edges = int(offsets.numel() - 1)
+        d.offsets = _ptr(offsets)
+        d.members = _ptr(members)
+        d.timestamps = _ptr(timestamps)
+        d.track_mask = _mask(track)
+        d.temporal_window = int(window)
+        d.edge_capacity = int(edge_capacity)
+        d.pool_words = int(pool_words)
+        d.stream = _stream(stream)
+        out = ctypes.c_void_p()
+        rc = lib.hgt_build(ctypes.byref(d), ctypes.byref(out))
+        if rc != OK:
+            raise HgtError(rc, "hgt_build")
+        return cls(out.value, int(window), d.track_mask)
+
+    # ------------------------------------------------------------------ update
+    def apply_batch(self, del_ids=None, ins_offsets=None, ins_members=None, ins_ts=None, out_ids=None,
+                    stream=None, raise_on_error: bool = True):
+        """Delete del_ids (int32 device tensor), then insert the CSR batch.
+        Returns the int32 device tensor of assigned IDs (or (status, ids)
+        with raise_on_error=False)."""
+        import torch
+        lib = load()
+        n_del = 0 if del_ids is None else int(del_ids.numel())
+        n_ins = 0 if ins_offsets is None else int(ins_offsets.numel() - 1)
+        _check_dtype(del_ids, (torch.int32, torch.uint32), "del_ids")
+        _check_dtype(ins_offsets, (torch.int64, torch.uint64), "ins_offsets")
+        _check_dtype(ins_members, (torch.int32, torch.uint32), "ins_members")
+        _check_dtype(ins_ts, (torch.int64,), "ins_ts")
+        n_mem = 0 if ins_members is None else int(ins_members.numel())
+        if out_ids is None and n_ins:
+            dev = ins_offsets.device
+            out_ids = torch.empty(n_ins, dtype=torch.int32, device=dev)
+        rc = lib.hgt_apply_batch(self._h, _ptr(del_ids), n_del, _ptr(ins_offsets) if n_ins else None,
+                                 _ptr(ins_members), n_mem, _ptr(ins_ts), n_ins,
+                                 _ptr(out_ids) if n_ins else None, _stream(stream))
+        if raise_on_error:
+            if rc != OK:
+                raise HgtError(rc, "hgt_apply_batch")
+            return out_ids
+        return rc, out_ids
+
+    # ------------------------------------------------------------------ queries
+    def triad_counts(self, kind, window: Optional[int] = None) -> List[int]:
+        lib = load()
+        k = _NAMES[kind] if isinstance(kind, str) else int(kind)
+        n = N_CLASSES[k]
+        arr = (ctypes.c_uint64 * n)()
+        w = (self.window if window is None else int(window)) if k == TEMPORAL else 0
+        rc = lib.hgt_triad_counts(self._h, k, w, ctypes.cast(arr, ctypes.c_void_p), n)
+        if rc != OK:
+            raise HgtError(rc, "hgt_triad_counts")
+        return list(arr)
+
+    def sync(self) -> int:
+        st = ctypes.c_int(0)
+        rc = load().hgt_sync(self._h, ctypes.byref(st))
+        if rc != OK:
+            raise HgtError(rc, "hgt_sync")
+        return st.value
+
+    def info(self) -> dict:
+        inf = Info()
+        rc = load().hgt_get_info(self._h, ctypes.byref(inf))
+        if rc != OK:
+            raise HgtError(rc, "hgt_get_info")
+        return {f: getattr(inf, f) for f, _ in Info._fields_}
+
+    def export_h2v(self):
+        """(offsets, members, live) numpy arrays indexed by ID."""
+        import numpy as np
+        inf = self.info()
+        n = inf["next_id"]
+        off = np.zeros(n + 1, np.uint64)
+        mem = np.zeros(max(inf["n_incidences"], 1), np.uint32)
+        live = np.zeros(max(n, 1), np.uint8)
+        rc = load().hgt_export_h2v(self._h, off.ctypes.data, mem.ctypes.data, live.ctypes.data)
+        if rc != OK:
+            raise HgtError(rc, "hgt_export_h2v")
+        return off, mem[: int(off[-1])], live[:n]
+
+    def export_v2h(self):
+        import numpy as np
+        inf = self.info()
+        off = np.zeros(inf["n_vertices"] + 1, np.uint64)
+        mem = np.zeros(max(inf["n_incidences"], 1), np.uint32)
+        rc = load().hgt_export_v2h(self._h, off.ctypes.data, mem.ctypes.data)
+        if rc != OK:
+            raise HgtError(rc, "hgt_export_v2h")
+        return off, mem[: int(off[-1])]
+
+    def close(self):
+        if self._h and self._h.value:
+            load().hgt_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,61 @@
+"""CPU checks of the C ABI library: it loads, exports every function that
+include/hgt.h declares, and its host-side class tables agree with the
+oracle's (both built independently from the Venn-pattern definition)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+from oracle import oracle as orc
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hgt.h")
+
+
+def _lib_path():
+    from paper_2512_21009_amd import hgt
+    if not os.path.exists(hgt.LIB_PATH):
+        from paper_2512_21009_amd import build
+        build.build()
+    return hgt.LIB_PATH
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:int|const char\*)\s+(hgt_\w+)\s*\(", text, flags=re.M)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("hgt_build", "hgt_apply_batch", "hgt_triad_counts", "hgt_sync", "hgt_destroy"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    path = _lib_path()
+    out = subprocess.run(["nm", "-D", "--defined-only", path], capture_output=True, text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (hgt_\w+)", out))
+    missing = [n for n in declared_functions() if n not in exported]
+    assert not missing, missing
+    lib = ctypes.CDLL(path)
+    for n in declared_functions():
+        assert getattr(lib, n) is not None
+
+
+def test_class_tables_agree_with_oracle():
+    lib = ctypes.CDLL(_lib_path())
+    for kind, want in ((0, orc.he_class_codes()), (2, orc.tmp_class_codes())):
+        n = lib.hgt_class_codes(kind, None, 0)
+        arr = (ctypes.c_int32 * n)()
+        assert lib.hgt_class_codes(kind, ctypes.cast(arr, ctypes.c_void_p), n) == n
+        assert list(arr) == want.tolist()
+
+
+def test_status_strings():
+    lib = ctypes.CDLL(_lib_path())
+    lib.hgt_status_str.restype = ctypes.c_char_p
+    for code in range(0, -8, -1):
+        assert lib.hgt_status_str(code)
+    assert lib.hgt_apply_batch(None, None, 0, None, None, 0, None, 0, None, None) == -1

@@ -1,0 +1,189 @@
+#!/usr/bin/env python
+"""Hyperedge updates/s including the triad-count update, on one MI355X.
+
+A step is one batch through the whole hot path: validation and
+canonicalisation, the hyperedge-based and incident-vertex-based triad deltas
+on the old graph, the store delete/insert, the deltas on the new graph and the
+count update.  The default workload is the Medium configuration: 1M vertices,
+2M hyperedges, cardinality power law (exponent 2.5) on [2,64], vertex
+popularity (rank + 1e4)^-1.1, batches of 50k inserts + 50k deletions of
+uniformly chosen live hyperedges.  Inputs are synthetic and resident in HBM
+before timing starts.
+
+Prints one JSON line (rank 0).  Only one GPU is used.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=9)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--scale", type=float, default=1.0, help="workload scale (1.0 = the named configuration)")
+    ap.add_argument("--cpu-sample", type=int, default=2000, help="updates in the oracle's timed sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--quiet", action="store_true")
+    return ap.parse_args()
+
+
+def log(args, *a):
+    if not args.quiet:
+        print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}), flush=True)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_2512_21009_amd import hgt, workloads as W
+
+    hgt.load()
+    dev = torch.device("cuda:0")
+    n_b = args.warmup + args.steps
+    t0 = time.perf_counter()
+    st = W.medium(q=1.0e4, scale=args.scale, n_batches=n_b)
+    log(args, f"generated {st.initial.n} hyperedges, {n_b} batches in {time.perf_counter() - t0:.1f}s")
+
+    def d(a, dt):
+        return torch.from_numpy(np.ascontiguousarray(a).astype(dt)).to(dev)
+
+    ini = st.initial
+    off0, mem0 = d(ini.offsets, np.int64), d(ini.members, np.int32)
+    ins = [(d(b.ins.offsets, np.int64), d(b.ins.members, np.int32)) for b in st.batches]
+    # store-only pass to learn which IDs the deletions name (handles -> IDs)
+    g0 = hgt.Graph.build(st.n_vertices, off0, mem0, track=())
+    n_handles = ini.n + sum(b.ins.n for b in st.batches)
+    hid = np.full(n_handles, -1, np.int64)
+    hid[: ini.n] = np.arange(ini.n)
+    dels = []
+    for b, (io, im) in zip(st.batches, ins):
+        di = hid[b.del_handles]
+        assert (di >= 0).all()
+        dt = d(di, np.int32)
+        dels.append(dt)
+        out = g0.apply_batch(dt, io, im)
+        hid[b.ins_handles] = out.cpu().numpy()
+    g0.close()
+    del g0
+    torch.cuda.synchronize()
+    track = ("hyperedge", "incident_vertex")
+    t0 = time.perf_counter()
+    g = hgt.Graph.build(st.n_vertices, off0, mem0, track=track)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    log(args, f"build with initial counts: {build_s:.2f}s")
+    for k in range(args.warmup):
+        g.apply_batch(dels[k], *ins[k])
+    torch.cuda.synchronize()
+    g.profile(True)
+    lat = []
+    n_upd = 0
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for k in range(args.warmup, n_b):
+        tb = time.perf_counter()
+        g.apply_batch(dels[k], *ins[k])
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - tb)
+        n_upd += st.batches[k].n_updates
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    prof = g.profile_read()
+    status = g.sync()
+    assert status == hgt.OK, status
+    value = n_upd / elapsed
+    lat_ms = np.array(lat) * 1e3
+    log(args, f"{n_upd} updates in {elapsed:.3f}s -> {value:,.0f} updates/s")
+    for name, r in prof.items():
+        if r["launches"]:
+            gbs = r["algo_bytes"] / (r["total_ms"] * 1e6) if r["total_ms"] > 0 else 0.0
+            log(args, f"  {name:16s} launches={r['launches']:3d} total={r['total_ms']:9.2f}ms "
+                      f"algo={r['algo_bytes'] / 1e9:8.3f}GB ({gbs:7.1f} GB/s) events={r['events']} aux={r['aux']}")
+    # dominant kernel of the timed region
+    dom_name, dom = max(((n, r) for n, r in prof.items() if r["launches"]), key=lambda kv: kv[1]["total_ms"])
+    achieved = dom["algo_bytes"] / (dom["total_ms"] * 1e6) if dom["total_ms"] > 0 else 0.0
+    roofline = {"bound": "hbm", "kernel": dom_name, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+                "avg_launch_ms": round(dom["total_ms"] / dom["launches"], 4),
+                "algo_bytes_per_launch": int(dom["algo_bytes"] // dom["launches"])}
+    counts_he = g.triad_counts("hyperedge")
+    g.close()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(args, st, log)
+    out = {
+        "metric": "hyperedge updates/sec incl. triad-count update; p50/p99 batch latency",
+        "value": round(value, 1),
+        "unit": "updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(elapsed / max(args.steps, 1) * 1e3, 3),
+        "p50_ms": round(float(np.percentile(lat_ms, 50)), 3),
+        "p99_ms": round(float(np.percentile(lat_ms, 99)), 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": "medium: 1M vertices, 2M hyperedges, card power-law 2.5 on [2,64], popularity "
+                               "(rank+1e4)^-1.1, batches 50k ins + 50k del, hyperedge + incident-vertex triads",
+                   "scale": args.scale, "batch_updates": int(st.batches[-1].n_updates),
+                   "build_s": round(build_s, 3), "he_triads_total": int(sum(counts_he[i] for i in range(30)))},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(args, st, log):
+    """The oracle as it is, on the GPU machine's host: one sample batch (the first
+    timed batch's first n/2 deletions and n/2 inserts) applied by the oracle's
+    batch semantics, the hyperedge-triad delta counted by definition and the
+    incident-vertex counts recounted, timed together."""
+    import numpy as np
+    from oracle import oracle as orc
+    from paper_2512_21009_amd import workloads as W
+
+    lib = orc.lib()
+    threads = int(lib.orc_max_threads())
+    ini = st.initial
+    o = orc.OracleGraph(st.n_vertices, ini.offsets, ini.members)
+    b = st.batches[0]
+    half = max(1, args.cpu_sample // 2)
+    dels = b.del_handles[:half]  # the first batch deletes handles of the initial graph (= oracle IDs)
+    sub = b.ins.rows(np.arange(min(half, b.ins.n)))
+    t0 = time.perf_counter()
+    old = o.copy()
+    status, ids = o.apply_batch(dels, sub.offsets, sub.members)
+    assert status == orc.OK
+    dhe, _ = orc.delta_by_definition(old, o, dels, ids)
+    iv = o.iv_counts()
+    el = time.perf_counter() - t0
+    n = len(dels) + sub.n
+    log(args, f"cpu oracle: {n} updates in {el:.2f}s on {threads} threads")
+    del W
+    return {"value": round(n / el, 2), "unit": "updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"{len(dels)} deletions + {sub.n} inserts of the first batch; hyperedge delta by definition "
+                      f"+ incident-vertex recount; {el:.1f}s", "iv_total": int(sum(iv.tolist())),
+            "he_delta_classes_nonzero": int((dhe != 0).sum())}
+
+
+if __name__ == "__main__":
+    main()

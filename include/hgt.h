@@ -156,6 +156,30 @@ int hgt_export_h2v(hgt_graph* g, uint64_t* offsets_host, uint32_t* members_host,
  * offsets_host[0..n_vertices], members_host[0..n_incidences) (rows ascending). */
 int hgt_export_v2h(hgt_graph* g, uint64_t* offsets_host, uint32_t* members_host);
 
+/* ---- profiling (tools) ------------------------------------------------ */
+/* Per kernel group of the batch path: launches and summed duration (HIP events
+ * recorded on the batch stream around the group), and the algorithmic bytes
+ * the group moved: for the triad-delta kernels the incidence lists they gather
+ * (4 bytes per list entry read), for the store commit 16d+16 bytes per insert
+ * and 12d+8 per delete of cardinality d.  `events`/`aux`: neighbours expanded /
+ * expanded through the binary-search path (small-centre kernel) and centres
+ * deferred (large-centre kernel). */
+typedef struct {
+    char name[24];
+    uint64_t launches;
+    double total_ms;
+    uint64_t algo_bytes;
+    uint64_t events;
+    uint64_t aux;
+} hgt_kernel_time;
+
+/* Waits for the graph's work, resets the profile and switches it on (1) or off (0). */
+int hgt_profile(hgt_graph* g, int enable);
+
+/* Waits for the graph's work and copies up to n_max rows (host) ; *n_out
+ * receives the number of rows available. */
+int hgt_profile_read(hgt_graph* g, hgt_kernel_time* out_host, uint32_t n_max, uint32_t* n_out);
+
 /* Class codes of the hyperedge (30) or temporal (96) family, ascending;
  * host out[0..n).  Returns the number of classes or a negative status. */
 int hgt_class_codes(int type, int32_t* out_host, uint32_t n);

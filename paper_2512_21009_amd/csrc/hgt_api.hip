@@ -168,9 +168,47 @@ struct hgt_graph {
     uint64_t batches = 0;
     BatchSummary* h_sum = nullptr;  // pinned
     DevScalars* h_sc = nullptr;     // pinned
+    // profiling: HIP events around each kernel group, algorithmic-byte counters
+    bool prof = false;
+    struct Rec { int kind; hipEvent_t a, b; };
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    DevBuf stats;
+    uint64_t store_bytes = 0;
 };
 
 namespace {
+
+enum ProfKind { PK_PLAN = 0, PK_DELTA_SMALL, PK_DELTA_BIG, PK_IV_PREP, PK_IV_PAIRS, PK_COMMIT, PK_N };
+const char* kProfNames[PK_N] = {"store_plan", "tri_delta_small", "tri_delta_big", "iv_prepare", "iv_pairs",
+                                "store_commit"};
+
+hipEvent_t prof_event(hgt_graph* g) {
+    if (g->ev_used == g->ev_pool.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        g->ev_pool.push_back(e);
+    }
+    return g->ev_pool[g->ev_used++];
+}
+
+struct ProfScope {
+    hgt_graph* g;
+    int kind;
+    hipStream_t s;
+    hipEvent_t a = nullptr;
+    ProfScope(hgt_graph* g_, int k, hipStream_t s_) : g(g_), kind(k), s(s_) {
+        if (g->prof && (a = prof_event(g))) (void)hipEventRecord(a, s);
+    }
+    ~ProfScope() {
+        if (!a) return;
+        hipEvent_t b = prof_event(g);
+        if (!b) return;
+        (void)hipEventRecord(b, s);
+        g->recs.push_back({kind, a, b});
+    }
+};
 
 #define HIP_OK(expr)                          \
     do {                                      \
@@ -373,8 +411,17 @@ int run_he_phase(hgt_graph* g, const uint32_t* centres, uint64_t n, const uint64
     P.big_rank = g->t_big_rank.as<uint32_t>();
     P.big_scratch = g->t_big_scratch.as<uint32_t>();
     P.big = L;
+    P.stats = g->prof ? g->stats.as<uint64_t>() : nullptr;
     unsigned grid_small = (unsigned)std::min<uint64_t>((uint64_t)g->n_cu * 3, n);
-    triad_he_launch(P, grid_small, (unsigned)grid_big, s);
+    triad_he_prepare(P, s);
+    {
+        ProfScope ps(g, PK_DELTA_SMALL, s);
+        triad_he_launch_small(P, grid_small, s);
+    }
+    {
+        ProfScope ps(g, PK_DELTA_BIG, s);
+        triad_he_launch_big(P, (unsigned)grid_big, s);
+    }
     return HGT_OK;
 }
 
@@ -502,6 +549,8 @@ void iv_phase(hgt_graph* g, const IvPlan& ip, bool minus, hipStream_t s) {
     P.pairs_cap = ip.n_keys;
     P.out = g->counts.as<uint64_t>() + (minus ? ACC_IV_M : ACC_IV_P);
     P.status = &g->st.sc->status;
+    P.stats = g->prof ? g->stats.as<uint64_t>() : nullptr;
+    ProfScope ps(g, PK_IV_PAIRS, s);
     triad_iv_launch(P, s);
 }
 
@@ -540,7 +589,10 @@ int apply(hgt_graph* g, const uint32_t* del, uint64_t n_del, const uint64_t* ins
     // planning (reads only)
     store_batch_begin(g->st.sc, w.sum, s);
     hgt_fill_u64(cnt + CNT_N, 0, ACC_N - CNT_N, s);
-    store_plan(g->st, b, w, s);
+    {
+        ProfScope ps(g, PK_PLAN, s);
+        store_plan(g->st, b, w, s);
+    }
     HIP_OK(hipMemcpyAsync(g->h_sum, w.sum, sizeof(BatchSummary), hipMemcpyDeviceToHost, s));
     HIP_OK(hipMemcpyAsync(g->h_sc, g->st.sc, sizeof(DevScalars), hipMemcpyDeviceToHost, s));
     HIP_OK(hipStreamSynchronize(s));
@@ -559,6 +611,7 @@ int apply(hgt_graph* g, const uint32_t* del, uint64_t n_del, const uint64_t* ins
     const bool do_iv = g->track_mask & (1u << HGT_TRIAD_INCIDENT_VERTEX);
     IvPlan ip;
     if (do_iv) {
+        ProfScope ps(g, PK_IV_PREP, s);
         rc = iv_prepare(g, b, w, sum, ip, s);
         if (rc) return rc;
     }
@@ -567,7 +620,15 @@ int apply(hgt_graph* g, const uint32_t* del, uint64_t n_del, const uint64_t* ins
     if (rc) return rc;
     if (do_iv) iv_phase(g, ip, true, s);
     // step 3: delete, then insert
-    store_commit(g->st, b, w, sum, g->h_bump, g->v_bump, g->next_seq, s);
+    {
+        ProfScope ps(g, PK_COMMIT, s);
+        store_commit(g->st, b, w, sum, g->h_bump, g->v_bump, g->next_seq, s);
+    }
+    // algorithmic bytes of the store update: an insert of cardinality d reads its
+    // input (4d + 8) and writes its h2v block (4d) and v2h entries (4d, locating
+    // them reads 4d); a delete reads its h2v block (4d) and rewrites its v2h
+    // entries (8d)
+    if (g->prof) g->store_bytes += 16 * n_mem + 16 * n_ins + 12 * sum.del_members + 8 * n_del;
     if (out_ids && n_ins) HIP_OK(hipMemcpyAsync(out_ids, w.assigned, n_ins * 4, hipMemcpyDeviceToDevice, s));
     // step 5: deltas on the new graph
     rc = run_he_phase(g, w.assigned, n_ins, g->st.mark_ins, b.epoch_ins, sum.max_lh_ins, false, s);
@@ -599,6 +660,8 @@ void destroy_graph(hgt_graph* g) {
                      &g->t_big_list, &g->t_big_rank, &g->t_big_scratch, &g->iv_keys, &g->iv_alt, &g->iv_sort,
                      &g->iv_head, &g->iv_uniq, &g->iv_p2, &g->iv_scan};
     for (DevBuf* b : all) dev_free(*b);
+    dev_free(g->stats);
+    for (hipEvent_t e : g->ev_pool) (void)hipEventDestroy(e);
     if (g->h_sum) (void)hipHostFree(g->h_sum);
     if (g->h_sc) (void)hipHostFree(g->h_sc);
     delete g;
@@ -783,6 +846,45 @@ int hgt_get_info(hgt_graph* g, hgt_info* o) {
     o->v2h_used_words = g->v_bump;
     o->temporal_window = g->window;
     o->batches = g->batches;
+    return HGT_OK;
+}
+
+int hgt_profile(hgt_graph* g, int enable) {
+    if (!g) return HGT_EINVAL;
+    HIP_OK(hipStreamSynchronize(g->last_stream));
+    if (ensure(g->stats, ST_N * 8)) return HGT_ENOMEM;
+    HIP_OK(hipMemset(g->stats.p, 0, ST_N * 8));
+    g->recs.clear();
+    g->ev_used = 0;
+    g->store_bytes = 0;
+    g->prof = enable != 0;
+    return HGT_OK;
+}
+
+int hgt_profile_read(hgt_graph* g, hgt_kernel_time* out, uint32_t n_max, uint32_t* n_out) {
+    if (!g || (!out && n_max)) return HGT_EINVAL;
+    HIP_OK(hipStreamSynchronize(g->last_stream));
+    uint64_t st[ST_N] = {0};
+    if (g->stats.p) HIP_OK(hipMemcpy(st, g->stats.p, ST_N * 8, hipMemcpyDeviceToHost));
+    hgt_kernel_time rows[PK_N];
+    std::memset(rows, 0, sizeof rows);
+    for (int k = 0; k < PK_N; k++) std::snprintf(rows[k].name, sizeof rows[k].name, "%s", kProfNames[k]);
+    for (auto& r : g->recs) {
+        float ms = 0;
+        HIP_OK(hipEventElapsedTime(&ms, r.a, r.b));
+        rows[r.kind].launches++;
+        rows[r.kind].total_ms += ms;
+    }
+    rows[PK_DELTA_SMALL].algo_bytes = st[ST_BYTES_SMALL];
+    rows[PK_DELTA_BIG].algo_bytes = st[ST_BYTES_BIG];
+    rows[PK_IV_PAIRS].algo_bytes = st[ST_IV_BYTES];
+    rows[PK_COMMIT].algo_bytes = g->store_bytes;
+    rows[PK_DELTA_SMALL].events = st[ST_EXPANDED];
+    rows[PK_DELTA_SMALL].aux = st[ST_WITNESS];
+    rows[PK_DELTA_BIG].events = st[ST_DEFERRED];
+    uint32_t n = std::min<uint32_t>(n_max, PK_N);
+    for (uint32_t i = 0; i < n; i++) out[i] = rows[i];
+    if (n_out) *n_out = PK_N;
     return HGT_OK;
 }
 

@@ -28,10 +28,24 @@ struct TriadParams {
     uint32_t* big_rank;
     uint32_t* big_scratch;    // grid_big * big.words_per_wg words
     BigLayout big;
+    uint64_t* stats;          // optional counters (see TriadStat), NULL = off
+};
+
+// Counters accumulated by the triad kernels when TriadParams.stats is set.
+enum TriadStat {
+    ST_BYTES_SMALL = 0,  // algorithmic bytes gathered by the small-centre kernel
+    ST_BYTES_BIG = 1,    // ... by the large-centre kernel
+    ST_DEFERRED = 2,     // centres moved to the large-centre kernel
+    ST_WITNESS = 3,      // neighbours expanded through the binary-search path
+    ST_EXPANDED = 4,     // neighbours expanded
+    ST_IV_BYTES = 5,     // algorithmic bytes gathered by the incident-vertex kernel
+    ST_N = 8
 };
 
 BigLayout triad_big_layout(uint64_t max_lh, uint64_t max_card);
-void triad_he_launch(TriadParams& P, unsigned grid_small, unsigned grid_big, hipStream_t s);
+void triad_he_prepare(TriadParams& P, hipStream_t s);
+void triad_he_launch_small(TriadParams& P, unsigned grid, hipStream_t s);
+void triad_he_launch_big(TriadParams& P, unsigned grid, hipStream_t s);
 
 // incident-vertex family
 struct IvParams {
@@ -41,5 +55,6 @@ struct IvParams {
     uint64_t pairs_cap;
     uint64_t* out;            // u64[2]: sum_p m_p * w_p, sum over triangles with a touched pair of m m m
     const int32_t* status;
+    uint64_t* stats;          // optional, ST_IV_BYTES
 };
 void triad_iv_launch(IvParams& P, hipStream_t s);

@@ -236,7 +236,7 @@ __device__ __forceinline__ void classify(const TriadParams& P, const Tables& T, 
 // Expand neighbour x of the current centre (one wave).
 __device__ void expand_x(const TriadParams& P, const Tables& T, const WgStore& S, const Shared& sh, uint32_t nh_log,
                          WaveMem& wm, uint32_t* wkeys, uint32_t* wvals, uint32_t x, uint32_t meta_x, uint64_t* acc_he,
-                         uint64_t* acc_tmp) {
+                         uint64_t* acc_tmp, uint64_t* acc_st) {
     const int lane = threadIdx.x & 63;
     const uint32_t nx = meta_len(meta_x);
     const uint64_t xoff = P.g.h_off[x];
@@ -254,6 +254,11 @@ __device__ void expand_x(const TriadParams& P, const Tables& T, const WgStore& S
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) d += __shfl_xor(d, o, 64);
         lx += d;
+    }
+    if (lane == 0 && P.stats) {
+        atomicAdd((unsigned long long*)&acc_st[0], (unsigned long long)(4ull * (nx + lx)));
+        atomicAdd((unsigned long long*)&acc_st[3], 1ull);
+        if (lx > WH_MAX_L) atomicAdd((unsigned long long*)&acc_st[2], 1ull);
     }
     if (lx <= WH_MAX_L) {
         uint32_t log_cap = log2u64(pow2ceil64(2 * (uint64_t)lx < 64 ? 64 : 2 * (uint64_t)lx));
@@ -343,7 +348,7 @@ __device__ void expand_x(const TriadParams& P, const Tables& T, const WgStore& S
 // The whole per-centre computation; BIG selects global tables and no deferral.
 template <bool BIG>
 __device__ void run_centres(const TriadParams& P, const Tables& T, const WgStore& S, Shared& sh, WaveMem* wmem,
-                            uint64_t* acc_he, uint64_t* acc_tmp, uint32_t lh_limit, uint32_t hm_cap) {
+                            uint64_t* acc_he, uint64_t* acc_tmp, uint64_t* acc_st, uint32_t lh_limit, uint32_t hm_cap) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint32_t* list = BIG ? P.big_list : P.centres;
     for (;;) {
@@ -371,6 +376,7 @@ __device__ void run_centres(const TriadParams& P, const Tables& T, const WgStore
                 uint32_t q = atomicAdd(P.big_count, 1u);
                 P.big_list[q] = sh.h;
                 P.big_rank[q] = sh.rank;
+                if (P.stats) atomicAdd((unsigned long long*)&acc_st[1], 1ull);
             }
             __syncthreads();
             continue;
@@ -404,11 +410,13 @@ __device__ void run_centres(const TriadParams& P, const Tables& T, const WgStore
                 uint32_t q = atomicAdd(P.big_count, 1u);
                 P.big_list[q] = h;
                 P.big_rank[q] = sh.rank;
+                if (P.stats) atomicAdd((unsigned long long*)&acc_st[1], 1ull);
             }
             __syncthreads();
             continue;
         }
         const uint32_t lh = sh.lh;
+        if (tid == 0 && P.stats) atomicAdd((unsigned long long*)&acc_st[0], (unsigned long long)(4ull * (lh + hlen)));
         uint32_t nh_log = log2u64(pow2ceil64(2 * (uint64_t)lh < 64 ? 64 : 2 * (uint64_t)lh));
         uint32_t nh_cap = 1u << nh_log;
         for (uint32_t s = tid; s < nh_cap; s += HGT_WG) { S.nh_keys[s] = HGT_EMPTY; S.nh_vals[s] = 0; }
@@ -545,7 +553,7 @@ __device__ void run_centres(const TriadParams& P, const Tables& T, const WgStore
             uint32_t m = S.nl_meta[i];
             if (!meta_elig(m)) continue;
             if (!P.do_he && !meta_win(m)) continue;
-            expand_x(P, T, S, sh, nh_log, wmem[wave], wk, wv, x, m, acc_he, acc_tmp);
+            expand_x(P, T, S, sh, nh_log, wmem[wave], wk, wv, x, m, acc_he, acc_tmp, acc_st);
         }
         __syncthreads();
         (void)lane;
@@ -559,19 +567,26 @@ __global__ void __launch_bounds__(HGT_WG) k_delta_small(TriadParams P) {
     __shared__ WaveMem wmem[NWAVE];
     __shared__ Shared sh;
     __shared__ Tables T;
-    __shared__ uint64_t acc_he[HGT_N_HE_CLASSES], acc_tmp[HGT_N_TEMPORAL_CLASSES];
+    __shared__ uint64_t acc_he[HGT_N_HE_CLASSES], acc_tmp[HGT_N_TEMPORAL_CLASSES], acc_st[4];
     if (*((volatile const int32_t*)P.status) != 0) return;
     for (int i = threadIdx.x; i < 128; i += HGT_WG) { T.he[i] = P.he_tab[i]; T.tmp[i] = P.tmp_tab[i]; }
+    if (threadIdx.x < 4) acc_st[threadIdx.x] = 0;
     for (int i = threadIdx.x; i < HGT_N_HE_CLASSES; i += HGT_WG) acc_he[i] = 0;
     for (int i = threadIdx.x; i < HGT_N_TEMPORAL_CLASSES; i += HGT_WG) acc_tmp[i] = 0;
     __syncthreads();
     WgStore S{nh_keys, nh_vals, hm, nl_x, nl_meta, warea, S_WAREA, warea};
-    run_centres<false>(P, T, S, sh, wmem, acc_he, acc_tmp, S_LH, S_LH);
+    run_centres<false>(P, T, S, sh, wmem, acc_he, acc_tmp, acc_st, S_LH, S_LH);
     __syncthreads();
     for (int i = threadIdx.x; i < HGT_N_HE_CLASSES; i += HGT_WG)
         if (acc_he[i]) atomicAdd((unsigned long long*)&P.out_he[i], (unsigned long long)acc_he[i]);
     for (int i = threadIdx.x; i < HGT_N_TEMPORAL_CLASSES; i += HGT_WG)
         if (acc_tmp[i]) atomicAdd((unsigned long long*)&P.out_tmp[i], (unsigned long long)acc_tmp[i]);
+    if (P.stats && threadIdx.x == 0) {
+        atomicAdd((unsigned long long*)&P.stats[ST_BYTES_SMALL], (unsigned long long)acc_st[0]);
+        atomicAdd((unsigned long long*)&P.stats[ST_DEFERRED], (unsigned long long)acc_st[1]);
+        atomicAdd((unsigned long long*)&P.stats[ST_WITNESS], (unsigned long long)acc_st[2]);
+        atomicAdd((unsigned long long*)&P.stats[ST_EXPANDED], (unsigned long long)acc_st[3]);
+    }
 }
 
 __global__ void __launch_bounds__(HGT_WG) k_delta_big(TriadParams P) {
@@ -579,9 +594,10 @@ __global__ void __launch_bounds__(HGT_WG) k_delta_big(TriadParams P) {
     __shared__ WaveMem wmem[NWAVE];
     __shared__ Shared sh;
     __shared__ Tables T;
-    __shared__ uint64_t acc_he[HGT_N_HE_CLASSES], acc_tmp[HGT_N_TEMPORAL_CLASSES];
+    __shared__ uint64_t acc_he[HGT_N_HE_CLASSES], acc_tmp[HGT_N_TEMPORAL_CLASSES], acc_st[4];
     if (*((volatile const int32_t*)P.status) != 0) return;
     for (int i = threadIdx.x; i < 128; i += HGT_WG) { T.he[i] = P.he_tab[i]; T.tmp[i] = P.tmp_tab[i]; }
+    if (threadIdx.x < 4) acc_st[threadIdx.x] = 0;
     for (int i = threadIdx.x; i < HGT_N_HE_CLASSES; i += HGT_WG) acc_he[i] = 0;
     for (int i = threadIdx.x; i < HGT_N_TEMPORAL_CLASSES; i += HGT_WG) acc_tmp[i] = 0;
     __syncthreads();
@@ -589,12 +605,18 @@ __global__ void __launch_bounds__(HGT_WG) k_delta_big(TriadParams P) {
     uint32_t* base = P.big_scratch + (uint64_t)blockIdx.x * L.words_per_wg;
     WgStore S{base + L.nh_keys, base + L.nh_vals, base + L.hm, base + L.nl_x, base + L.nl_meta, base + L.warea,
               L.warea_words, wh};
-    run_centres<true>(P, T, S, sh, wmem, acc_he, acc_tmp, 0xffffffffu, 0xffffffffu);
+    run_centres<true>(P, T, S, sh, wmem, acc_he, acc_tmp, acc_st, 0xffffffffu, 0xffffffffu);
     __syncthreads();
     for (int i = threadIdx.x; i < HGT_N_HE_CLASSES; i += HGT_WG)
         if (acc_he[i]) atomicAdd((unsigned long long*)&P.out_he[i], (unsigned long long)acc_he[i]);
     for (int i = threadIdx.x; i < HGT_N_TEMPORAL_CLASSES; i += HGT_WG)
         if (acc_tmp[i]) atomicAdd((unsigned long long*)&P.out_tmp[i], (unsigned long long)acc_tmp[i]);
+    if (P.stats && threadIdx.x == 0) {
+        atomicAdd((unsigned long long*)&P.stats[ST_BYTES_BIG], (unsigned long long)acc_st[0]);
+        atomicAdd((unsigned long long*)&P.stats[ST_DEFERRED], (unsigned long long)acc_st[1]);
+        atomicAdd((unsigned long long*)&P.stats[ST_WITNESS], (unsigned long long)acc_st[2]);
+        atomicAdd((unsigned long long*)&P.stats[ST_EXPANDED], (unsigned long long)acc_st[3]);
+    }
 }
 
 }  // namespace
@@ -620,11 +642,14 @@ BigLayout triad_big_layout(uint64_t max_lh, uint64_t max_card) {
     return L;
 }
 
-void triad_he_launch(TriadParams& P, unsigned grid_small, unsigned grid_big, hipStream_t s) {
-    hgt_fill_u32(P.queue, 0, 1, s);
-    hgt_fill_u32(P.big_queue, 0, 1, s);
-    hgt_fill_u32(P.big_count, 0, 1, s);
-    if (P.n_centres == 0) return;
-    k_delta_small<<<grid_small, HGT_WG, 0, s>>>(P);
-    k_delta_big<<<grid_big, HGT_WG, 0, s>>>(P);
+void triad_he_prepare(TriadParams& P, hipStream_t s) {
+    hgt_fill_u32(P.queue, 0, 3, s);  // queue, big_queue, big_count
+}
+
+void triad_he_launch_small(TriadParams& P, unsigned grid, hipStream_t s) {
+    if (P.n_centres) k_delta_small<<<grid, HGT_WG, 0, s>>>(P);
+}
+
+void triad_he_launch_big(TriadParams& P, unsigned grid, hipStream_t s) {
+    if (P.n_centres) k_delta_big<<<grid, HGT_WG, 0, s>>>(P);
 }

@@ -61,7 +61,7 @@ __global__ void __launch_bounds__(HGT_WG) k_iv_pairs(IvParams P) {
     __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const uint64_t n = *P.n_pairs;
-    uint64_t s_sum = 0, t_sum = 0;
+    uint64_t s_sum = 0, t_sum = 0, bytes = 0;
     for (uint64_t q = (uint64_t)blockIdx.x * (HGT_WG / 64) + wave; q < n; q += (uint64_t)gridDim.x * (HGT_WG / 64)) {
         const uint64_t key = P.pairs[q];
         uint32_t a = (uint32_t)(key >> 32), b = (uint32_t)key;
@@ -81,7 +81,10 @@ __global__ void __launch_bounds__(HGT_WG) k_iv_pairs(IvParams P) {
             m += __shfl_xor(m, o, 64);
             w += __shfl_xor(w, o, 64);
         }
-        if (lane == 0) s_sum += m * w;
+        if (lane == 0) {
+            s_sum += m * w;
+            bytes += 4ull * la;
+        }
         if (m == 0) continue;
         // triangles {a, b, c}: c in a hyperedge of a, taken at its first one
         for (uint32_t base = 0; base < la; base += 64) {
@@ -109,6 +112,7 @@ __global__ void __launch_bounds__(HGT_WG) k_iv_pairs(IvParams P) {
                 if (c == a || c == b) continue;
                 const uint32_t* C = P.g.v2h + P.g.v_off[c];
                 uint32_t lc = P.g.v_len[c];
+                bytes += 4ull * (1 + lc);
                 uint32_t first;
                 uint32_t mac = inter_count_min(A, la, C, lc, &first);
                 if (first != hk) continue;  // c already met in an earlier hyperedge of a
@@ -122,6 +126,11 @@ __global__ void __launch_bounds__(HGT_WG) k_iv_pairs(IvParams P) {
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
             __builtin_amdgcn_wave_barrier();
         }
+    }
+    if (P.stats) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) bytes += __shfl_xor(bytes, o, 64);
+        if (lane == 0 && bytes) atomicAdd((unsigned long long*)&P.stats[ST_IV_BYTES], (unsigned long long)bytes);
     }
     if (s_sum) atomicAdd((unsigned long long*)&acc[0], (unsigned long long)s_sum);
     if (t_sum) atomicAdd((unsigned long long*)&acc[1], (unsigned long long)t_sum);

@@ -60,10 +60,22 @@ class Info(ctypes.Structure):
     ]
 
 
+class KernelTime(ctypes.Structure):
+    _fields_ = [
+        ("name", ctypes.c_char * 24),
+        ("launches", ctypes.c_uint64),
+        ("total_ms", ctypes.c_double),
+        ("algo_bytes", ctypes.c_uint64),
+        ("events", ctypes.c_uint64),
+        ("aux", ctypes.c_uint64),
+    ]
+
+
 _lib = None
 
 EXPORTS = ["hgt_build", "hgt_apply_batch", "hgt_triad_counts", "hgt_sync", "hgt_destroy", "hgt_status_str",
-           "hgt_get_info", "hgt_export_h2v", "hgt_export_v2h", "hgt_class_codes"]
+           "hgt_get_info", "hgt_export_h2v", "hgt_export_v2h", "hgt_class_codes", "hgt_profile",
+           "hgt_profile_read"]
 
 
 def load(path: str = LIB_PATH):
@@ -86,6 +98,8 @@ def load(path: str = LIB_PATH):
     lib.hgt_export_h2v.argtypes = [P, P, P, P]
     lib.hgt_export_v2h.argtypes = [P, P, P]
     lib.hgt_class_codes.argtypes = [I32, P, U32]
+    lib.hgt_profile.argtypes = [P, I32]
+    lib.hgt_profile_read.argtypes = [P, P, U32, ctypes.POINTER(U32)]
     for name in EXPORTS:
         getattr(lib, name).restype = getattr(lib, name).restype or ctypes.c_int
     lib.hgt_status_str.restype = ctypes.c_char_p
@@ -222,6 +236,25 @@ class Graph:
         if rc != OK:
             raise HgtError(rc, "hgt_get_info")
         return {f: getattr(inf, f) for f, _ in Info._fields_}
+
+    def profile(self, enable: bool = True):
+        """Reset the per-kernel-group profile and switch it on or off."""
+        rc = load().hgt_profile(self._h, 1 if enable else 0)
+        if rc != OK:
+            raise HgtError(rc, "hgt_profile")
+
+    def profile_read(self) -> dict:
+        """{group: {launches, total_ms, algo_bytes, events, aux}}"""
+        n = ctypes.c_uint32(0)
+        rows = (KernelTime * 16)()
+        rc = load().hgt_profile_read(self._h, ctypes.cast(rows, ctypes.c_void_p), 16, ctypes.byref(n))
+        if rc != OK:
+            raise HgtError(rc, "hgt_profile_read")
+        out = {}
+        for r in rows[: n.value]:
+            out[r.name.decode()] = dict(launches=r.launches, total_ms=r.total_ms, algo_bytes=r.algo_bytes,
+                                        events=r.events, aux=r.aux)
+        return out
 
     def export_h2v(self):
         """(offsets, members, live) numpy arrays indexed by ID."""

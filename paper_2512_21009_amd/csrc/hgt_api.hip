@@ -159,13 +159,16 @@ struct hgt_graph {
         s_assigned, s_h_need, s_h_rel, s_keys, s_keys_alt, s_sort, s_head, s_is_ins, s_tv, s_tseg, s_D, s_I, s_It,
         s_vp, s_staging, s_dst;
     // triad scratch
-    DevBuf t_ctr, t_big_list, t_big_rank, t_big_scratch;
+    DevBuf t_ctr, t_big_list, t_big_rank, t_big_scratch, t_list1, t_rank1, t_list2, t_rank2, t_garena;
+    // hyperedge-family histograms and batch-neighbour lists
+    DevBuf hpool, ent_x, ent_d, ent_pay, bl_cnt, bl_off, bl_cur, bl_d, bl_pay, nb_scratch, bl_scan;
     DevBuf iv_keys, iv_alt, iv_sort, iv_head, iv_uniq, iv_p2, iv_scan;
     // host mirrors (valid after each synchronisation)
     uint64_t next_id = 0, h_bump = 0, v_bump = 0, next_seq = 0, n_live = 0, n_inc = 0;
     uint32_t epoch = 0;
     int sticky = HGT_OK;
     uint64_t batches = 0;
+    int force_stage = 0;            // HGT_FORCE_STAGE (tests): see He2Params
     BatchSummary* h_sum = nullptr;  // pinned
     DevScalars* h_sc = nullptr;     // pinned
     // profiling: HIP events around each kernel group, algorithmic-byte counters
@@ -180,9 +183,10 @@ struct hgt_graph {
 
 namespace {
 
-enum ProfKind { PK_PLAN = 0, PK_DELTA_SMALL, PK_DELTA_BIG, PK_IV_PREP, PK_IV_PAIRS, PK_COMMIT, PK_N };
-const char* kProfNames[PK_N] = {"store_plan", "tri_delta_small", "tri_delta_big", "iv_prepare", "iv_pairs",
-                                "store_commit"};
+enum ProfKind { PK_PLAN = 0, PK_DELTA_SMALL, PK_DELTA_BIG, PK_IV_PREP, PK_IV_PAIRS, PK_COMMIT, PK_DELTA_MED,
+                PK_DELTA_GLOBAL, PK_NBR, PK_TMP, PK_N };
+const char* kProfNames[PK_N] = {"store_plan", "he_hist_lds72", "he_2hop", "iv_prepare", "iv_pairs", "store_commit",
+                                "he_hist_lds148", "he_hist_global", "he_nbr_pass", "temporal"};
 
 hipEvent_t prof_event(hgt_graph* g) {
     if (g->ev_used == g->ev_pool.size()) {
@@ -373,54 +377,164 @@ int ensure_plan_scratch(hgt_graph* g, const Sizes& z, PlanScratch& w) {
 }
 
 // ---- triad phases ---------------------------------------------------------
-int run_he_phase(hgt_graph* g, const uint32_t* centres, uint64_t n, const uint64_t* mark, uint32_t epoch,
-                 uint64_t max_lh, bool minus, hipStream_t s) {
+// Counter slots in t_ctr: 0-2 neighbour pass, 3 histogram kernel queue,
+// 4 its deferred count, 5 2-hop queue for the deferred centres, 6-8 temporal.
+int run_phase(hgt_graph* g, const uint32_t* centres, uint64_t n, const uint64_t* mark, uint32_t epoch,
+              uint64_t max_lh, uint64_t sum_lh, uint64_t n_ids, bool minus, bool full, hipStream_t s) {
     bool do_he = g->track_mask & (1u << HGT_TRIAD_HYPEREDGE);
     bool do_tmp = g->track_mask & (1u << HGT_TRIAD_TEMPORAL);
     if (!(do_he || do_tmp) || n == 0) return HGT_OK;
     int rc = 0;
-    rc |= ensure(g->t_ctr, 64);
+    rc |= ensure(g->t_ctr, 128);
     rc |= ensure(g->t_big_list, n * 4);
     rc |= ensure(g->t_big_rank, n * 4);
+    rc |= ensure(g->t_list1, n * 4);
+    rc |= ensure(g->t_rank1, n * 4);
+    rc |= ensure(g->t_list2, n * 4);
+    rc |= ensure(g->t_rank2, n * 4);
     if (rc) return HGT_ENOMEM;
-    uint64_t max_card = std::min<uint64_t>(HGT_MAX_CARD, std::max<uint64_t>(max_lh, 1));
-    BigLayout L = triad_big_layout(std::max<uint64_t>(max_lh, 1), max_card);
-    // at most ~1 GiB of global tables for the large-centre kernel
+    const uint64_t lhm = std::max<uint64_t>(max_lh, 1);
+    const uint64_t max_card = std::min<uint64_t>(HGT_MAX_CARD, lhm);
+    BigLayout L = triad_big_layout(lhm, max_card);
+    // at most ~1 GiB of global tables for the large-centre kernels
     uint64_t grid_big = std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)g->n_cu * 2, (1ull << 28) / L.words_per_wg));
     if (ensure(g->t_big_scratch, grid_big * L.words_per_wg * 4)) return HGT_ENOMEM;
+    uint32_t* ctr = g->t_ctr.as<uint32_t>();
+    uint64_t* cnt = g->counts.as<uint64_t>();
+    uint64_t* stats = g->prof ? g->stats.as<uint64_t>() : nullptr;
     TriadParams P{};
     P.g = view_of(g);
     P.centres = centres;
     P.n_centres = n;
     P.mark = mark;
     P.epoch = epoch;
-    P.do_he = do_he;
-    P.do_tmp = do_tmp;
     P.window = g->window;
-    uint64_t* cnt = g->counts.as<uint64_t>();
     P.out_he = cnt + (minus ? ACC_HE_M : ACC_HE_P);
     P.out_tmp = cnt + (minus ? ACC_TMP_M : ACC_TMP_P);
     P.he_tab = g->tabs.as<uint8_t>();
     P.tmp_tab = g->tabs.as<uint8_t>() + 128;
     P.status = &g->st.sc->status;
-    uint32_t* ctr = g->t_ctr.as<uint32_t>();
-    P.queue = ctr;
-    P.big_queue = ctr + 1;
-    P.big_count = ctr + 2;
     P.big_list = g->t_big_list.as<uint32_t>();
     P.big_rank = g->t_big_rank.as<uint32_t>();
     P.big_scratch = g->t_big_scratch.as<uint32_t>();
     P.big = L;
-    P.stats = g->prof ? g->stats.as<uint64_t>() : nullptr;
-    unsigned grid_small = (unsigned)std::min<uint64_t>((uint64_t)g->n_cu * 3, n);
-    triad_he_prepare(P, s);
-    {
-        ProfScope ps(g, PK_DELTA_SMALL, s);
-        triad_he_launch_small(P, grid_small, s);
+    P.stats = stats;
+    const unsigned grid_small = (unsigned)std::min<uint64_t>((uint64_t)g->n_cu * 2, n);
+    if (do_he) {
+        // neighbour pass: batch-neighbour entries; histogram updates for inserts
+        uint64_t ecap = std::max<uint64_t>(sum_lh, 1);
+        uint64_t nb_words = 2 * pow2ceil64(2 * std::max<uint64_t>(lhm, 32)) + 3 * max_card + 8;
+        uint64_t nb_grid = std::max<uint64_t>(1, std::min<uint64_t>(256, (1ull << 27) / nb_words));
+        uint64_t ids = std::max<uint64_t>(n_ids, 1);
+        rc |= ensure(g->ent_x, ecap * 4);
+        rc |= ensure(g->ent_d, ecap * 4);
+        rc |= ensure(g->ent_pay, ecap * 8);
+        rc |= ensure(g->bl_d, ecap * 4);
+        rc |= ensure(g->bl_pay, ecap * 8);
+        rc |= ensure(g->bl_cnt, ids * 8);
+        rc |= ensure(g->bl_off, ids * 8);
+        rc |= ensure(g->bl_cur, ids * 8);
+        rc |= ensure(g->bl_scan, hgt_scan_tmp_bytes(ids));
+        rc |= ensure(g->nb_scratch, nb_grid * nb_words * 4);
+        if (rc) return HGT_ENOMEM;
+        NbrParams N{};
+        N.g = P.g;
+        N.centres = centres;
+        N.n_centres = n;
+        N.inserting = minus ? 0 : 1;
+        N.mark_self = minus ? nullptr : mark;
+        N.epoch = epoch;
+        N.hpool = g->hpool.as<uint32_t>();
+        N.n_entries = (uint64_t*)(ctr + 10);  // 8-byte aligned slot
+        N.entries_cap = ecap;
+        N.ent_x = g->ent_x.as<uint32_t>();
+        N.ent_d = g->ent_d.as<uint32_t>();
+        N.ent_pay = g->ent_pay.as<uint64_t>();
+        N.queue = ctr;
+        N.big_queue = ctr + 1;
+        N.big_count = ctr + 2;
+        N.big_list = P.big_list;
+        N.big_rank = P.big_rank;
+        N.big_scratch = g->nb_scratch.as<uint32_t>();
+        N.big_words = nb_words;
+        N.status = P.status;
+        N.emit_entries = full ? 0 : 1;
+        {
+            ProfScope ps_nbr(g, PK_NBR, s);
+            he2_nbr_launch(N, grid_small, (unsigned)nb_grid, s);
+            if (!full)
+                he2_lists_build(N, ids, g->bl_cnt.as<uint64_t>(), g->bl_off.as<uint64_t>(), g->bl_cur.as<uint64_t>(),
+                                g->bl_d.as<uint32_t>(), g->bl_pay.as<uint64_t>(), g->bl_scan.p, s);
+        }
+        He2Params E{};
+        E.g = P.g;
+        E.centres = centres;
+        E.n_centres = n;
+        E.mark = mark;
+        E.epoch = epoch;
+        E.hpool = g->hpool.as<uint32_t>();
+        E.bl_off = g->bl_off.as<uint64_t>();
+        E.bl_cnt = g->bl_cnt.as<uint64_t>();
+        E.bl_d = g->bl_d.as<uint32_t>();
+        E.bl_pay = g->bl_pay.as<uint64_t>();
+        E.out_he = P.out_he;
+        E.he_tab = P.he_tab;
+        E.status = P.status;
+        // stages: ctr[16..18] queues, ctr[19..21] moved-on counts
+        E.queue = ctr + 16;
+        E.count = ctr + 19;
+        E.list[0] = g->t_list1.as<uint32_t>();
+        E.rank[0] = g->t_rank1.as<uint32_t>();
+        E.list[1] = g->t_list2.as<uint32_t>();
+        E.rank[1] = g->t_rank2.as<uint32_t>();
+        E.list[2] = P.big_list;
+        E.rank[2] = P.big_rank;
+        const uint64_t garena_words = 1ull << 18;  // 1 MB per workgroup
+        const unsigned grid_g = (unsigned)std::min<uint64_t>(128, n);
+        if (ensure(g->t_garena, (uint64_t)grid_g * garena_words * 4)) return HGT_ENOMEM;
+        E.garena = g->t_garena.as<uint32_t>();
+        E.garena_words = garena_words;
+        E.stats = stats;
+        E.force_stage = g->force_stage;
+        E.static_mode = full ? 1 : 0;
+        hgt_fill_u32(ctr + 16, 0, 6, s);
+        hgt_fill_u32(ctr + 5, 0, 1, s);
+        {
+            ProfScope ps(g, PK_DELTA_SMALL, s);
+            he2_launch_stage(E, 0, grid_small, s);
+        }
+        {
+            ProfScope ps(g, PK_DELTA_MED, s);
+            he2_launch_stage(E, 1, (unsigned)std::min<uint64_t>((uint64_t)g->n_cu, n), s);
+        }
+        {
+            ProfScope ps(g, PK_DELTA_GLOBAL, s);
+            he2_launch_stage(E, 2, grid_g, s);
+        }
+        // centres too large for the LDS arena: the 2-hop kernel
+        TriadParams B = P;
+        B.do_he = 1;
+        B.do_tmp = 0;
+        B.big_count = ctr + 21;
+        B.big_queue = ctr + 5;
+        B.static_he = full ? 1 : 0;
+        {
+            ProfScope ps(g, PK_DELTA_BIG, s);
+            triad_he_launch_big(B, (unsigned)grid_big, s);
+        }
+        if (minus) he2_remove_deleted(N, mark, epoch, s);
     }
-    {
-        ProfScope ps(g, PK_DELTA_BIG, s);
-        triad_he_launch_big(P, (unsigned)grid_big, s);
+    if (do_tmp) {
+        TriadParams Q = P;
+        Q.do_he = 0;
+        Q.do_tmp = 1;
+        Q.queue = ctr + 6;
+        Q.big_queue = ctr + 7;
+        Q.big_count = ctr + 8;
+        triad_he_prepare(Q, s);
+        ProfScope ps(g, PK_TMP, s);
+        triad_he_launch_small(Q, (unsigned)std::min<uint64_t>((uint64_t)g->n_cu * 3, n), s);
+        triad_he_launch_big(Q, (unsigned)grid_big, s);
     }
     return HGT_OK;
 }
@@ -603,6 +717,8 @@ int apply(hgt_graph* g, const uint32_t* del, uint64_t n_del, const uint64_t* ins
     }
     // capacities for the commit
     rc = ensure_pool(g->h2v, g->h_bump, sum.h2v_need, s);
+    if (!rc && (g->track_mask & (1u << HGT_TRIAD_HYPEREDGE)) && g->hpool.bytes < 2 * g->h2v.bytes)
+        rc = grow_keep(g->hpool, 2 * g->h2v.bytes, 2 * g->h_bump * 4, s);
     if (!rc) rc = ensure_pool(g->v2h, g->v_bump, sum.v2h_need, s);
     if (!rc) rc = ensure(g->s_staging, std::max<uint64_t>(sum.stage_words, 1) * 4);
     if (rc) return rc;
@@ -616,7 +732,8 @@ int apply(hgt_graph* g, const uint32_t* del, uint64_t n_del, const uint64_t* ins
         if (rc) return rc;
     }
     // step 2: deltas on the old graph
-    rc = run_he_phase(g, del, n_del, g->st.mark_del, b.epoch_del, sum.max_lh_del, true, s);
+    rc = run_phase(g, del, n_del, g->st.mark_del, b.epoch_del, sum.max_lh_del, sum.sum_lh_del, g->next_id, true,
+                   false, s);
     if (rc) return rc;
     if (do_iv) iv_phase(g, ip, true, s);
     // step 3: delete, then insert
@@ -631,7 +748,8 @@ int apply(hgt_graph* g, const uint32_t* del, uint64_t n_del, const uint64_t* ins
     if (g->prof) g->store_bytes += 16 * n_mem + 16 * n_ins + 12 * sum.del_members + 8 * n_del;
     if (out_ids && n_ins) HIP_OK(hipMemcpyAsync(out_ids, w.assigned, n_ins * 4, hipMemcpyDeviceToDevice, s));
     // step 5: deltas on the new graph
-    rc = run_he_phase(g, w.assigned, n_ins, g->st.mark_ins, b.epoch_ins, sum.max_lh_ins, false, s);
+    rc = run_phase(g, w.assigned, n_ins, g->st.mark_ins, b.epoch_ins, sum.max_lh_ins, sum.sum_lh_ins, sum.next_id_new,
+                   false, check_order == 0, s);
     if (rc) return rc;
     if (do_iv) iv_phase(g, ip, false, s);
     // step 6
@@ -657,8 +775,10 @@ void destroy_graph(hgt_graph* g) {
                      &g->s_canon, &g->s_big, &g->s_small, &g->s_popc, &g->s_scan, &g->s_assigned, &g->s_h_need,
                      &g->s_h_rel, &g->s_keys, &g->s_keys_alt, &g->s_sort, &g->s_head, &g->s_is_ins, &g->s_tv,
                      &g->s_tseg, &g->s_D, &g->s_I, &g->s_It, &g->s_vp, &g->s_staging, &g->s_dst, &g->t_ctr,
-                     &g->t_big_list, &g->t_big_rank, &g->t_big_scratch, &g->iv_keys, &g->iv_alt, &g->iv_sort,
-                     &g->iv_head, &g->iv_uniq, &g->iv_p2, &g->iv_scan};
+                     &g->t_big_list, &g->t_big_rank, &g->t_big_scratch, &g->t_list1, &g->t_rank1, &g->t_list2, &g->t_rank2, &g->t_garena, &g->iv_keys, &g->iv_alt, &g->iv_sort,
+                     &g->iv_head, &g->iv_uniq, &g->iv_p2, &g->iv_scan, &g->hpool, &g->ent_x, &g->ent_d,
+                     &g->ent_pay, &g->bl_cnt, &g->bl_off, &g->bl_cur, &g->bl_d, &g->bl_pay, &g->nb_scratch,
+                     &g->bl_scan};
     for (DevBuf* b : all) dev_free(*b);
     dev_free(g->stats);
     for (hipEvent_t e : g->ev_pool) (void)hipEventDestroy(e);
@@ -717,6 +837,7 @@ int hgt_build(const hgt_build_desc* d, hgt_graph** out) {
     g->track_mask = d->track_mask;
     g->window = d->temporal_window;
     g->last_stream = s;
+    if (const char* fs = std::getenv("HGT_FORCE_STAGE")) g->force_stage = std::atoi(fs);
     int rc = HGT_OK;
     do {
         if (hipGetDevice(&g->device) != hipSuccess) { rc = HGT_EDEVICE; break; }
@@ -742,6 +863,7 @@ int hgt_build(const hgt_build_desc* d, hgt_graph** out) {
         }
         uint64_t pw = d->pool_words ? d->pool_words : 1 << 20;
         if ((rc = dev_alloc(g->h2v, pw * 4)) || (rc = dev_alloc(g->v2h, pw * 4))) break;
+        if ((d->track_mask & (1u << HGT_TRIAD_HYPEREDGE)) && (rc = dev_alloc(g->hpool, pw * 8))) break;
         if ((rc = dev_alloc(g->scal, sizeof(DevScalars))) || (rc = dev_alloc(g->counts, ACC_N * 8)) ||
             (rc = dev_alloc(g->tabs, 256)))
             break;
@@ -867,6 +989,7 @@ int hgt_profile_read(hgt_graph* g, hgt_kernel_time* out, uint32_t n_max, uint32_
     uint64_t st[ST_N] = {0};
     if (g->stats.p) HIP_OK(hipMemcpy(st, g->stats.p, ST_N * 8, hipMemcpyDeviceToHost));
     hgt_kernel_time rows[PK_N];
+    static_assert(PK_N <= 16, "profile rows");
     std::memset(rows, 0, sizeof rows);
     for (int k = 0; k < PK_N; k++) std::snprintf(rows[k].name, sizeof rows[k].name, "%s", kProfNames[k]);
     for (auto& r : g->recs) {
@@ -879,9 +1002,9 @@ int hgt_profile_read(hgt_graph* g, hgt_kernel_time* out, uint32_t n_max, uint32_
     rows[PK_DELTA_BIG].algo_bytes = st[ST_BYTES_BIG];
     rows[PK_IV_PAIRS].algo_bytes = st[ST_IV_BYTES];
     rows[PK_COMMIT].algo_bytes = g->store_bytes;
-    rows[PK_DELTA_SMALL].events = st[ST_EXPANDED];
-    rows[PK_DELTA_SMALL].aux = st[ST_WITNESS];
-    rows[PK_DELTA_BIG].events = st[ST_DEFERRED];
+    rows[PK_DELTA_BIG].events = st[ST_DEFER0 + 2];
+    rows[PK_DELTA_SMALL].events = st[ST_DEFER0];
+    rows[PK_DELTA_SMALL].aux = st[ST_DEFER0 + 1];
     uint32_t n = std::min<uint32_t>(n_max, PK_N);
     for (uint32_t i = 0; i < n; i++) out[i] = rows[i];
     if (n_out) *n_out = PK_N;

@@ -39,7 +39,9 @@ struct BatchSummary {
     uint64_t max_lh_del;    // max over deleted h of sum_{u in h} deg(u) (old graph)
     uint64_t max_lh_ins;    // max over inserted h of sum_{u in h} deg(u) (new graph)
     uint64_t max_ins_card;
-    uint64_t pad[3];
+    uint64_t sum_lh_del;    // sum over deleted h of sum_{u in h} deg(u)
+    uint64_t sum_lh_ins;    // sum over inserted h (new graph)
+    uint64_t pad[1];
 };
 
 // Read-only view of the store used by the triad kernels.

@@ -61,6 +61,7 @@ __global__ void k_del_check(const uint32_t* __restrict__ del, uint64_t n_del, De
     const uint32_t* m = h2v + h_off[id];
     for (uint64_t k = 0; k < d; k++) lh += v_len[m[k]];
     atomicMax((unsigned long long*)&sum->max_lh_del, (unsigned long long)lh);
+    atomicAdd((unsigned long long*)&sum->sum_lh_del, (unsigned long long)lh);
 }
 
 // One thread per insert: CSR sanity, cardinality bounds, temporal order.
@@ -316,6 +317,7 @@ __global__ void k_lh_ins(const uint32_t* __restrict__ canon, const uint64_t* __r
         if (t < nt) lh += new_len[t];
     }
     atomicMax((unsigned long long*)&sum->max_lh_ins, (unsigned long long)lh);
+    atomicAdd((unsigned long long*)&sum->sum_lh_ins, (unsigned long long)lh);
 }
 
 __global__ void k_summary_finish(const DevScalars* sc, BatchSummary* sum, const uint64_t* n_free,

@@ -29,6 +29,7 @@ struct TriadParams {
     uint32_t* big_scratch;    // grid_big * big.words_per_wg words
     BigLayout big;
     uint64_t* stats;          // optional counters (see TriadStat), NULL = off
+    int static_he;            // hyperedge family as a full count (see He2Params::static_mode)
 };
 
 // Counters accumulated by the triad kernels when TriadParams.stats is set.
@@ -39,13 +40,72 @@ enum TriadStat {
     ST_WITNESS = 3,      // neighbours expanded through the binary-search path
     ST_EXPANDED = 4,     // neighbours expanded
     ST_IV_BYTES = 5,     // algorithmic bytes gathered by the incident-vertex kernel
-    ST_N = 8
+    ST_DEFER0 = 6,       // centres moved on by histogram-kernel stage 0, 1, 2
+    ST_N = 12
 };
 
 BigLayout triad_big_layout(uint64_t max_lh, uint64_t max_card);
 void triad_he_prepare(TriadParams& P, hipStream_t s);
 void triad_he_launch_small(TriadParams& P, unsigned grid, hipStream_t s);
 void triad_he_launch_big(TriadParams& P, unsigned grid, hipStream_t s);
+
+// hyperedge family through neighbour histograms (triad_he2.hip)
+struct NbrParams {
+    GraphView g;
+    const uint32_t* centres;
+    uint64_t n_centres;
+    int inserting;               // 1: rebuild the centres' histograms and add them to their neighbours'
+    const uint64_t* mark_self;   // this phase's marks: neighbours that are centres too get no increment
+    uint32_t epoch;
+    uint32_t* hpool;             // histograms, 2 words per h2v word
+    uint64_t* n_entries;         // batch-neighbour entries written
+    uint64_t entries_cap;
+    uint32_t* ent_x;
+    uint32_t* ent_d;
+    uint64_t* ent_pay;           // rank << 32 | k << 1 | [|d| > k]
+    uint32_t* queue;             // queue, big_queue, big_count (consecutive)
+    uint32_t* big_queue;
+    uint32_t* big_count;
+    uint32_t* big_list;
+    uint32_t* big_rank;
+    uint32_t* big_scratch;
+    uint64_t big_words;
+    const int32_t* status;
+    int emit_entries;            // 0: histograms only (build)
+};
+
+struct He2Params {
+    GraphView g;
+    const uint32_t* centres;
+    uint64_t n_centres;
+    const uint64_t* mark;
+    uint32_t epoch;
+    const uint32_t* hpool;
+    const uint64_t* bl_off;      // per ID: batch-neighbour list of x
+    const uint64_t* bl_cnt;
+    const uint32_t* bl_d;
+    const uint64_t* bl_pay;
+    uint64_t* out_he;
+    const uint8_t* he_tab;
+    const int32_t* status;
+    uint32_t* queue;             // per stage (3 consecutive counters)
+    uint32_t* count;             // centres moved on by each stage (3 consecutive)
+    uint32_t* list[3];           // list[s]: centres stage s could not fit; list[2] feeds
+    uint32_t* rank[3];           // the 2-hop kernel (k_delta_big)
+    uint32_t* garena;            // stage-2 tables: garena_words per workgroup
+    uint64_t garena_words;
+    uint64_t* stats;
+    int force_stage;             // test knob: stages below it move every centre on
+    int static_mode;             // full count (build): no batch ranks, no open paths through
+                                 // neighbours; open triples at their centre, closed ones at the
+                                 // smallest-ID centre
+};
+
+void he2_nbr_launch(NbrParams& P, unsigned grid_small, unsigned grid_big, hipStream_t s);
+void he2_lists_build(NbrParams& P, uint64_t n_ids, uint64_t* bl_cnt, uint64_t* bl_off, uint64_t* bl_cur,
+                     uint32_t* bl_d, uint64_t* bl_pay, void* scan_tmp, hipStream_t s);
+void he2_remove_deleted(NbrParams& P, const uint64_t* mark_del, uint32_t epoch_del, hipStream_t s);
+void he2_launch_stage(He2Params& P, int stage, unsigned grid, hipStream_t s);
 
 // incident-vertex family
 struct IvParams {

@@ -1,0 +1,686 @@
+// triad_he2.hip -- hyperedge-family triad deltas without 2-hop expansion.
+//
+// Every live hyperedge x carries a histogram H_x over its line-graph
+// neighbours y: H_x[k][f] = #{y : |x & y| = k, [|y| > k] = f} (2|x| u32
+// counters, stored beside its h2v block).  A changed hyperedge adds or removes
+// one neighbour of each x in N(h), so the histograms are kept exact with one
+// atomic per (h, x) pair.
+//
+// For a centre h and a neighbour x, the triads {h, x, y} with y outside the
+// closed neighbourhood of h (open paths h - x - y) have the class
+//   h only  = |h| > c_x,  x only = |x| - c_x - |x & y| > 0,  y only = |y| > |x & y|,
+//   plus the regions h&x and x&y,
+// so they are counted from H_x with one threshold (|x & y| < |x| - c_x), minus
+// the y that do meet h (y = h, and the neighbours of h that meet x) and minus
+// the batch members that rank below h (read from x's batch-neighbour list).
+// Neighbour pairs {x, y} of h that intersect are found by grouping the member
+// vertices of all neighbours of h by vertex in LDS (work sum_{x in N(h)} |x|),
+// each pair counted at its smallest common vertex; they get their true class in
+// place of the disjoint-pair class that the histogram pass gave them.
+#include "triad_common.h"
+
+namespace {
+
+using namespace tri;
+
+constexpr uint32_t ARENA_S = 18432;   // 72 KB of LDS: two workgroups per CU
+constexpr uint32_t ARENA_M = 37888;   // 148 KB of LDS: one workgroup per CU
+constexpr uint32_t K_MAX = 0x3fffu;   // neighbours with 14 bits
+// entry key: vertex << 15 | [vertex in h] << 14 | neighbour index (14 bits)
+
+// open-addressing tables of any capacity: slot = multiply-shift hash scaled to cap
+__device__ __forceinline__ uint32_t fr_slot(uint32_t key, uint32_t cap) {
+    return (uint32_t)(((uint64_t)(key * 2654435761u) * cap) >> 32);
+}
+__device__ __forceinline__ uint32_t fr_next(uint32_t s, uint32_t cap) { return s + 1 == cap ? 0 : s + 1; }
+__device__ __forceinline__ uint32_t hash_cap(uint32_t n) { return n + n / 2 + 32; }  // load <= 2/3
+
+__device__ __forceinline__ void fr_add(uint32_t* keys, uint32_t* vals, uint32_t cap, uint32_t key, uint32_t inc) {
+    uint32_t s = fr_slot(key, cap);
+    for (uint32_t probe = 0; probe < cap; probe++) {
+        uint32_t k = __atomic_load_n(&keys[s], __ATOMIC_RELAXED);
+        if (k == HGT_EMPTY) {
+            uint32_t prev = atomicCAS(&keys[s], HGT_EMPTY, key);
+            if (prev == HGT_EMPTY || prev == key) { atomicAdd(&vals[s], inc); return; }
+        } else if (k == key) {
+            atomicAdd(&vals[s], inc);
+            return;
+        }
+        s = fr_next(s, cap);
+    }
+}
+
+__device__ __forceinline__ uint32_t fr_find(const uint32_t* keys, uint32_t cap, uint32_t key) {
+    uint32_t s = fr_slot(key, cap);
+    for (uint32_t probe = 0; probe < cap; probe++) {
+        uint32_t k = keys[s];
+        if (k == key) return s;
+        if (k == HGT_EMPTY) return HGT_EMPTY;
+        s = fr_next(s, cap);
+    }
+    return HGT_EMPTY;
+}
+
+// Ascending bitonic sort of n keys in place by the whole workgroup.  The merge
+// steps compare i with its mirror in the block, then with i ^ stride, always
+// putting the smaller key first, so absent keys past n behave as +infinity and
+// their comparisons are skipped: no padding to a power of two is stored.
+__device__ __forceinline__ void sort_keys(uint64_t* k, uint32_t n) {
+    if (n < 2) return;
+    const uint32_t N = (uint32_t)pow2ceil64(n);
+    for (uint32_t size = 2; size <= N; size <<= 1) {
+        for (uint32_t i = threadIdx.x; i < n; i += HGT_WG) {
+            uint32_t p = i ^ (size - 1);
+            if (p > i && p < n) {
+                uint64_t a = k[i], b = k[p];
+                if (b < a) { k[i] = b; k[p] = a; }
+            }
+        }
+        __syncthreads();
+        for (uint32_t stride = size >> 2; stride > 0; stride >>= 1) {
+            for (uint32_t i = threadIdx.x; i < n; i += HGT_WG) {
+                uint32_t p = i ^ stride;
+                if (p > i && p < n) {
+                    uint64_t a = k[i], b = k[p];
+                    if (b < a) { k[i] = b; k[p] = a; }
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+struct Sh2 {
+    uint32_t h, rank, hlen, lh, K, W, defer, stop;
+    uint64_t hoff;
+    uint32_t ncap;
+    uint32_t o_nh, o_ent;  // arena word offsets
+    uint32_t ws[NWAVE];
+    uint64_t g[8];
+};
+
+__device__ __forceinline__ void acc_sub(uint64_t* acc, int cls) { acc_add(acc, cls, ~0ull); }
+__device__ __forceinline__ void acc32_add(uint32_t* acc, int cls, uint32_t v) {
+    if (cls < 255) atomicAdd(&acc[cls], v);
+}
+
+
+// ---- per-centre neighbourhood (shared by the neighbour pass and the delta kernel)
+// Builds N(h) -> c_x in the hash at keys/vals (already cleared), reading the
+// incidence lists of h's members through pre/voff.
+__device__ __forceinline__ void build_nh(const GraphView& G, uint32_t h, uint32_t hlen, uint32_t lh, const uint32_t* pre,
+                                         const uint64_t* voff, uint32_t* keys, uint32_t* vals, uint32_t cap) {
+    for (uint32_t p = threadIdx.x; p < lh; p += HGT_WG) {
+        uint32_t k = seg_of<uint32_t>(pre, hlen, p);
+        uint32_t x = G.v2h[voff[k] + (p - pre[k])];
+        if (x != h) fr_add(keys, vals, cap, x, 1u);
+    }
+}
+
+// prefix of member degrees and their list offsets; returns lh (all threads)
+__device__ __forceinline__ uint32_t member_prefix(const GraphView& G, uint64_t hoff, uint32_t hlen, uint32_t* pre,
+                                                  uint64_t* voff, uint32_t* ws) {
+    uint32_t carry = 0;
+    for (uint32_t b = 0; b < hlen; b += HGT_WG) {
+        uint32_t i = b + threadIdx.x, d = 0;
+        if (i < hlen) {
+            uint32_t m = G.h2v[hoff + i];
+            d = G.v_len[m];
+            voff[i] = G.v_off[m];
+        }
+        uint32_t tot;
+        uint32_t ex = wg_scan_u32(d, ws, &tot);
+        if (i < hlen) pre[i] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) pre[hlen] = carry;
+    __syncthreads();
+    return carry;
+}
+
+// ===========================================================================
+// neighbour pass: batch-neighbour entries (x, d, k = |x & d|, [|d| > k]) and,
+// for inserted hyperedges, the histogram updates
+// ===========================================================================
+template <bool BIG>
+__device__ void nbr_pass_body(const NbrParams& P, uint32_t* arena, uint64_t arena_words) {
+    __shared__ Sh2 sh;
+    const int tid = threadIdx.x;
+    for (;;) {
+        if (tid == 0) {
+            uint64_t n = BIG ? (uint64_t)*P.big_count : P.n_centres;
+            uint32_t c = atomicAdd(BIG ? P.big_queue : P.queue, 1u);
+            sh.stop = c >= n;
+            if (!sh.stop) {
+                uint32_t h = BIG ? P.big_list[c] : P.centres[c];
+                sh.h = h;
+                sh.rank = BIG ? P.big_rank[c] : c;
+                sh.hlen = P.g.h_len[h];
+                sh.hoff = P.g.h_off[h];
+                // prefix + offsets must fit at the arena end
+                sh.defer = (!BIG && 3ull * sh.hlen + 4 > arena_words / 2) ? 1u : 0u;
+            }
+        }
+        __syncthreads();
+        if (sh.stop) break;
+        if (!sh.defer) {
+            const uint32_t hlen = sh.hlen;
+            uint32_t* pre = arena + arena_words - (3 * hlen + 4);
+            uint64_t* voff = (uint64_t*)(pre + ((hlen + 2) & ~1u));
+            if (((uintptr_t)voff & 7) != 0) voff = (uint64_t*)((uint32_t*)voff + 1);
+            uint32_t lh = member_prefix(P.g, sh.hoff, hlen, pre, voff, sh.ws);
+            uint32_t cap = hash_cap(lh);
+            if (tid == 0) {
+                sh.lh = lh;
+                sh.ncap = cap;
+                sh.defer = (!BIG && 2ull * cap + 3ull * hlen + 4 > arena_words) ? 1u : 0u;
+            }
+            __syncthreads();
+        }
+        if (sh.defer) {
+            if (tid == 0) {
+                uint32_t q = atomicAdd(P.big_count, 1u);
+                P.big_list[q] = sh.h;
+                P.big_rank[q] = sh.rank;
+            }
+            __syncthreads();
+            continue;
+        }
+        const uint32_t h = sh.h, hlen = sh.hlen, lh = sh.lh, cap = sh.ncap;
+        uint32_t* keys = arena;
+        uint32_t* vals = arena + cap;
+        uint32_t* pre = arena + arena_words - (3 * hlen + 4);
+        uint64_t* voff = (uint64_t*)(pre + ((hlen + 2) & ~1u));
+        if (((uintptr_t)voff & 7) != 0) voff = (uint64_t*)((uint32_t*)voff + 1);
+        for (uint32_t s = tid; s < cap; s += HGT_WG) { keys[s] = HGT_EMPTY; vals[s] = 0; }
+        __syncthreads();
+        build_nh(P.g, h, hlen, lh, pre, voff, keys, vals, cap);
+        __syncthreads();
+        uint32_t* hd = P.hpool ? P.hpool + 2 * sh.hoff : nullptr;
+        for (uint32_t s = tid; s < cap; s += HGT_WG) {
+            uint32_t x = keys[s];
+            if (x == HGT_EMPTY) continue;
+            uint32_t c = vals[s];
+            uint32_t fd = hlen > c ? 1u : 0u;
+            if (P.emit_entries) {
+                uint64_t q = atomicAdd((unsigned long long*)P.n_entries, 1ull);
+                if (q < P.entries_cap) {
+                    P.ent_x[q] = x;
+                    P.ent_d[q] = h;
+                    P.ent_pay[q] = ((uint64_t)sh.rank << 32) | ((uint64_t)c << 1) | fd;
+                }
+            }
+            if (P.inserting) {
+                uint32_t lx = P.g.h_len[x];
+                atomicAdd(&hd[2 * (c - 1) + (lx > c ? 1u : 0u)], 1u);
+                if (!P.mark_self || (uint32_t)(P.mark_self[x] >> 32) != P.epoch)
+                    atomicAdd(&P.hpool[2 * P.g.h_off[x] + 2 * (c - 1) + fd], 1u);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void __launch_bounds__(HGT_WG) k_nbr_small(NbrParams P) {
+    __shared__ __attribute__((aligned(16))) uint32_t arena[ARENA_S];
+    if (*((volatile const int32_t*)P.status) != 0) return;
+    nbr_pass_body<false>(P, arena, ARENA_S);
+}
+
+__global__ void __launch_bounds__(HGT_WG) k_nbr_big(NbrParams P) {
+    if (*((volatile const int32_t*)P.status) != 0) return;
+    nbr_pass_body<true>(P, P.big_scratch + (uint64_t)blockIdx.x * P.big_words, P.big_words);
+}
+
+// clear the histograms of the inserted hyperedges (their blocks may be reused)
+__global__ void k_h_clear(const uint32_t* __restrict__ ids, uint64_t n, const uint64_t* __restrict__ h_off,
+                          const uint32_t* __restrict__ h_len, uint32_t* hpool, const int32_t* status) {
+    if (*status) return;
+    const int lane = threadIdx.x & 63;
+    uint64_t j = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (j >= n) return;
+    uint32_t id = ids[j];
+    uint32_t* hb = hpool + 2 * h_off[id];
+    uint32_t w = 2 * h_len[id];
+    for (uint32_t i = lane; i < w; i += 64) hb[i] = 0;
+}
+
+// remove the deleted hyperedges from their surviving neighbours' histograms
+__global__ void k_h_remove(const uint64_t* n_entries_p, uint64_t cap, const uint32_t* __restrict__ ent_x,
+                           const uint64_t* __restrict__ ent_pay, const uint64_t* __restrict__ mark_del,
+                           uint32_t epoch_del, const uint64_t* __restrict__ h_off, uint32_t* hpool,
+                           const int32_t* status) {
+    if (*status) return;
+    uint64_t n = *n_entries_p;
+    if (n > cap) n = cap;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+        uint32_t x = ent_x[i];
+        if ((uint32_t)(mark_del[x] >> 32) == epoch_del) continue;  // x is deleted too
+        uint64_t p = ent_pay[i];
+        uint32_t k = (uint32_t)(p >> 1) & 0x7fffffffu, f = (uint32_t)p & 1u;
+        atomicSub(&hpool[2 * h_off[x] + 2 * (k - 1) + f], 1u);
+    }
+}
+
+// counting sort of the entries by x: per-ID counts, then scatter
+__global__ void k_bl_count(const uint64_t* n_entries_p, uint64_t cap, const uint32_t* __restrict__ ent_x,
+                           uint64_t* bl_cnt, const int32_t* status) {
+    if (*status) return;
+    uint64_t n = *n_entries_p;
+    if (n > cap) n = cap;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        atomicAdd((unsigned long long*)&bl_cnt[ent_x[i]], 1ull);
+}
+
+__global__ void k_bl_scatter(const uint64_t* n_entries_p, uint64_t cap, const uint32_t* __restrict__ ent_x,
+                             const uint32_t* __restrict__ ent_d, const uint64_t* __restrict__ ent_pay,
+                             uint64_t* bl_cur, uint32_t* out_d, uint64_t* out_pay, const int32_t* status) {
+    if (*status) return;
+    uint64_t n = *n_entries_p;
+    if (n > cap) n = cap;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+        uint64_t pos = atomicAdd((unsigned long long*)&bl_cur[ent_x[i]], 1ull);
+        out_d[pos] = ent_d[i];
+        out_pay[pos] = ent_pay[i];
+    }
+}
+
+__global__ void k_entries_check(const uint64_t* n_entries_p, uint64_t cap, int32_t* status) {
+    if (threadIdx.x == 0 && blockIdx.x == 0 && *n_entries_p > cap) atomicCAS(status, 0, HGT_EDEVICE);
+}
+
+// ===========================================================================
+// the delta kernel
+// ===========================================================================
+// Stage s takes its centres from the batch (s = 0) or from list s-1 and moves
+// the centres whose tables do not fit its arena to list s; list 2 feeds the
+// 2-hop kernel.  Stages 0 and 1 keep the arena in LDS (72 KB, 148 KB), stage 2
+// in a 1 MB slice of global memory per workgroup.
+template <int STAGE>
+__device__ void he2_body(const He2Params& P, uint32_t* arena, const uint32_t ARENA_WORDS, Sh2& sh, const Tables& T,
+                         uint64_t* acc_all, uint32_t* acc32_all, uint64_t* st) {
+    const int tid = threadIdx.x;
+    uint64_t* myacc = acc_all + (tid >> 6) * HGT_N_HE_CLASSES;
+    uint32_t* myacc32 = acc32_all + (tid >> 6) * HGT_N_HE_CLASSES;
+    for (;;) {
+        if (tid == 0) {
+            uint32_t c = atomicAdd(&P.queue[STAGE], 1u);
+            sh.stop = c >= (STAGE == 0 ? P.n_centres : (uint64_t)P.count[STAGE - 1]);
+            if (!sh.stop) {
+                uint32_t h = STAGE == 0 ? P.centres[c] : P.list[STAGE - 1][c];
+                sh.h = h;
+                sh.rank = STAGE == 0 ? c : P.rank[STAGE - 1][c];
+                sh.hlen = P.g.h_len[h];
+                sh.hoff = P.g.h_off[h];
+                sh.defer = (3ull * sh.hlen + 4 > ARENA_WORDS / 2 || STAGE < P.force_stage) ? 1u : 0u;
+            }
+        }
+        __syncthreads();
+        if (sh.stop) break;
+        const uint32_t h = sh.h, hlen = sh.hlen;
+        // --- members of h: degree prefix and list offsets at the arena end
+        uint32_t* pre = arena + ARENA_WORDS - (3 * hlen + 4);
+        uint64_t* voff = (uint64_t*)(pre + ((hlen + 2) & ~1u));
+        if (((uintptr_t)voff & 7) != 0) voff = (uint64_t*)((uint32_t*)voff + 1);
+        if (!sh.defer) {
+            uint32_t lh = member_prefix(P.g, sh.hoff, hlen, pre, voff, sh.ws);
+            uint32_t cap = hash_cap(lh);
+            if (tid == 0) {
+                sh.lh = lh;
+                sh.ncap = cap;
+                sh.o_nh = 0;
+                uint64_t a = 2ull * cap + 3ull * hlen + 4, b = 2ull * cap + 4ull * lh + 1 + hlen + 2;
+                sh.defer = ((a > b ? a : b) > ARENA_WORDS) ? 1u : 0u;
+            }
+            __syncthreads();
+        }
+        if (sh.defer) {
+            if (tid == 0) {
+                uint32_t q = atomicAdd(&P.count[STAGE], 1u);
+                P.list[STAGE][q] = h;
+                P.rank[STAGE][q] = sh.rank;
+                atomicAdd((unsigned long long*)&st[0], 1ull);
+            }
+            __syncthreads();
+            continue;
+        }
+        const uint32_t lh = sh.lh, ncap = sh.ncap;
+        uint32_t* nkeys = arena;
+        uint32_t* nvals = arena + ncap;
+        for (uint32_t s = tid; s < ncap; s += HGT_WG) { nkeys[s] = HGT_EMPTY; nvals[s] = 0; }
+        if (tid == 0) sh.K = 0;
+        __syncthreads();
+        build_nh(P.g, h, hlen, lh, pre, voff, nkeys, nvals, ncap);
+        __syncthreads();
+        // --- compact N(h): x, meta (c | len | eligible), member offsets later
+        uint32_t* nl_x = arena + 2 * ncap;
+        uint32_t* nl_meta = nl_x + lh;
+        uint32_t* nl_mo = nl_meta + lh;  // lh + 1 words
+        uint32_t* nl_msh = nl_mo + lh + 1;  // members shared with another neighbour
+        for (uint32_t s = tid; s < ncap; s += HGT_WG) {
+            uint32_t x = nkeys[s];
+            if (x == HGT_EMPTY) continue;
+            uint32_t c = nvals[s];
+            uint32_t len = P.g.h_len[x];
+            bool elig = P.static_mode || !lower_ranked_member(P.mark[x], P.epoch, sh.rank);
+            uint32_t meta = c | (len << 14) | ((uint32_t)elig << 28);
+            nvals[s] = meta;
+            uint32_t q = atomicAdd(&sh.K, 1u);
+            nl_x[q] = x;
+            nl_meta[q] = meta;
+        }
+        __syncthreads();
+        const uint32_t K = sh.K;
+        // member offsets of the neighbours in the entry array
+        uint32_t* hm = nl_msh + lh;  // members of h
+        {
+            uint32_t carry = 0;
+            for (uint32_t b = 0; b < K; b += HGT_WG) {
+                uint32_t i = b + tid;
+                uint32_t v = i < K ? meta_len(nl_meta[i]) : 0;
+                uint32_t tot;
+                uint32_t ex = wg_scan_u32(v, sh.ws, &tot);
+                if (i < K) nl_mo[i] = carry + ex;
+                carry += tot;
+            }
+            if (tid == 0) {
+                nl_mo[K] = carry;
+                sh.W = carry;
+                uint64_t o_ent = (uint64_t)(hm + hlen - arena);
+                o_ent = (o_ent + 1) & ~1ull;
+                uint64_t need = 2ull * carry > 2ull * hlen + 2 ? 2ull * carry : 2ull * hlen + 2;
+                sh.o_ent = (uint32_t)o_ent;
+                sh.defer = (K > K_MAX || o_ent + need > ARENA_WORDS) ? 1u : 0u;
+            }
+            __syncthreads();
+        }
+        if (sh.defer) {
+            if (tid == 0) {
+                uint32_t q = atomicAdd(&P.count[STAGE], 1u);
+                P.list[STAGE][q] = h;
+                P.rank[STAGE][q] = sh.rank;
+                atomicAdd((unsigned long long*)&st[0], 1ull);
+            }
+            __syncthreads();
+            continue;
+        }
+        const uint32_t W = sh.W;
+        uint64_t* keys = (uint64_t*)(arena + sh.o_ent);
+        for (uint32_t i = tid; i < hlen; i += HGT_WG) hm[i] = P.g.h2v[sh.hoff + i];
+        // --- disjoint-pair classes of all eligible neighbour pairs (histogram over c)
+        {
+            uint32_t* cnt = (uint32_t*)keys;  // 2 (hlen + 1) words, free until the entries are written
+            const uint32_t Wc = hlen + 1;
+            for (uint32_t i = tid; i < 2 * Wc; i += HGT_WG) cnt[i] = 0;
+            if (tid < 8) sh.g[tid] = 0;
+            __syncthreads();
+            for (uint32_t i = tid; i < K; i += HGT_WG) {
+                uint32_t m = nl_meta[i];
+                if (!meta_elig(m)) continue;
+                uint32_t c = meta_c(m);
+                atomicAdd(&cnt[(meta_len(m) > c ? Wc : 0) + c], 1u);
+            }
+            __syncthreads();
+            for (uint32_t f = 0; f < 2; f++) {
+                uint32_t carry2 = 0;
+                for (uint32_t b = 0; b < Wc; b += HGT_WG) {
+                    uint32_t i = b + tid;
+                    uint32_t v = i < Wc ? cnt[f * Wc + i] : 0;
+                    uint32_t tot;
+                    uint32_t ex = wg_scan_u32(v, sh.ws, &tot);
+                    if (i < Wc) cnt[f * Wc + i] = carry2 + ex;
+                    carry2 += tot;
+                }
+                if (tid == 0) sh.g[6 + f] = carry2;
+                __syncthreads();
+            }
+            const uint64_t N0 = sh.g[6], N1 = sh.g[7];
+            uint64_t g00 = 0, g01 = 0, g11 = 0, d0 = 0, d1 = 0;
+            for (uint32_t c = 1 + tid; c <= hlen; c += HGT_WG) {
+                uint64_t n0 = (uint64_t)((c + 1 < Wc ? cnt[c + 1] : (uint32_t)N0) - cnt[c]);
+                uint64_t n1 = (uint64_t)((c + 1 < Wc ? cnt[Wc + c + 1] : (uint32_t)N1) - cnt[Wc + c]);
+                uint32_t k = hlen - c;
+                uint64_t s0 = N0 - cnt[k], s1 = N1 - cnt[Wc + k];
+                g00 += n0 * s0;
+                g01 += n0 * s1;
+                g11 += n1 * s1;
+                if (2 * c >= hlen) { d0 += n0; d1 += n1; }
+            }
+            atomicAdd((unsigned long long*)&sh.g[0], (unsigned long long)g00);
+            atomicAdd((unsigned long long*)&sh.g[1], (unsigned long long)g01);
+            atomicAdd((unsigned long long*)&sh.g[2], (unsigned long long)g11);
+            atomicAdd((unsigned long long*)&sh.g[3], (unsigned long long)d0);
+            atomicAdd((unsigned long long*)&sh.g[4], (unsigned long long)d1);
+            __syncthreads();
+            if (tid == 0) {
+                uint64_t G00 = (sh.g[0] - sh.g[3]) / 2, G11 = (sh.g[2] - sh.g[4]) / 2, G01 = sh.g[1];
+                uint64_t T00 = N0 * (N0 - (N0 ? 1 : 0)) / 2, T11 = N1 * (N1 - (N1 ? 1 : 0)) / 2, T01 = N0 * N1;
+                acc_add(myacc, T.he[40 | 1], T00 - G00);
+                acc_add(myacc, T.he[40], G00);
+                acc_add(myacc, T.he[40 | 4 | 1], T01 - G01);
+                acc_add(myacc, T.he[40 | 4], G01);
+                acc_add(myacc, T.he[40 | 6 | 1], T11 - G11);
+                acc_add(myacc, T.he[40 | 6], G11);
+            }
+            __syncthreads();
+        }
+        // --- entries: (vertex, v in h, neighbour) for every member of every neighbour,
+        // sorted by vertex so that the neighbours meeting at a vertex are contiguous
+        for (uint32_t i = tid; i < K; i += HGT_WG) nl_msh[i] = 0;
+        for (uint32_t p = tid; p < W; p += HGT_WG) {
+            uint32_t xi = seg_of<uint32_t>(nl_mo, K, p);
+            uint32_t x = nl_x[xi];
+            uint32_t v = P.g.h2v[P.g.h_off[x] + (p - nl_mo[xi])];
+            uint64_t inh = contains_u32(hm, hlen, v) ? 1ull : 0ull;
+            keys[p] = ((uint64_t)v << 15) | (inh << 14) | xi;
+        }
+        __syncthreads();
+        sort_keys(keys, W);
+        // vertices met by two or more neighbours; per neighbour, how many it has
+        for (uint32_t i = tid; i < W; i += HGT_WG) {
+            uint64_t v = keys[i] >> 15;
+            bool shared = (i > 0 && (keys[i - 1] >> 15) == v) || (i + 1 < W && (keys[i + 1] >> 15) == v);
+            if (shared) atomicAdd(&nl_msh[keys[i] & K_MAX], 1u);
+        }
+        __syncthreads();
+        // --- open paths h - x - y through the histograms, per eligible neighbour
+        for (uint32_t i = P.static_mode ? K : tid; i < K; i += HGT_WG) {
+            uint32_t m = nl_meta[i];
+            if (!meta_elig(m)) continue;
+            uint32_t x = nl_x[i];
+            uint32_t c = meta_c(m), lx = meta_len(m);
+            uint32_t thr = lx - c;  // k < thr  <=>  x has a vertex outside h and y
+            uint32_t base = (hlen > c ? 1u : 0u) | 24u;
+            const uint32_t* H = P.hpool + 2 * P.g.h_off[x];
+            // a_f: neighbours y with |x & y| < thr (x keeps a private vertex), b_f: the rest
+            uint64_t a0 = 0, a1 = 0, b0 = 0, b1 = 0;
+            for (uint32_t k = 1; k <= lx; k++) {
+                uint32_t h0 = H[2 * (k - 1)], h1 = H[2 * (k - 1) + 1];
+                if (k < thr) { a0 += h0; a1 += h1; }
+                else { b0 += h0; b1 += h1; }
+            }
+            // the histogram holds h itself: k = c, y only = |h| > c
+            if (c < thr) { if (hlen > c) a1--; else a0--; }
+            else { if (hlen > c) b1--; else b0--; }
+            // lower-ranked batch members adjacent to x but not to h
+            uint64_t bo = P.bl_off[x], bn = P.bl_cnt[x];
+            for (uint64_t e = 0; e < bn; e++) {
+                uint64_t pay = P.bl_pay[bo + e];
+                if ((uint32_t)(pay >> 32) >= sh.rank) continue;
+                uint32_t d = P.bl_d[bo + e];
+                if (fr_find(nkeys, ncap, d) != HGT_EMPTY) continue;  // meets h: an intersecting pair
+                uint32_t k = (uint32_t)(pay >> 1) & 0x7fffffffu, f = (uint32_t)pay & 1u;
+                if (k < thr) { if (f) a1--; else a0--; }
+                else { if (f) b1--; else b0--; }
+            }
+            acc_add(myacc, T.he[base | 2], a0);
+            acc_add(myacc, T.he[base | 2 | 4], a1);
+            acc_add(myacc, T.he[base], b0);
+            acc_add(myacc, T.he[base | 4], b1);
+        }
+        // --- intersecting neighbour pairs, each at its smallest common vertex.  When
+        // one side has a single shared member the pair meets only at this vertex.
+        for (uint32_t i = tid; i + 1 < W; i += HGT_WG) {
+            const uint64_t ki = keys[i];
+            const uint64_t v = ki >> 15;
+            if ((keys[i + 1] >> 15) != v) continue;
+            const uint32_t xi = (uint32_t)ki & K_MAX;
+            const uint32_t vin = (uint32_t)(ki >> 14) & 1u;
+            const uint32_t mx = nl_meta[xi];
+            const uint32_t xl = meta_len(mx), xsh = nl_msh[xi], cx = meta_c(mx);
+            const bool ex = meta_elig(mx);
+            for (uint32_t j = i + 1; j < W; j++) {
+                const uint64_t kj = keys[j];
+                if ((kj >> 15) != v) break;
+                const uint32_t yi = (uint32_t)kj & K_MAX;
+                const uint32_t my = nl_meta[yi];
+                const uint32_t yl = meta_len(my);
+                uint32_t s = 1, shh = vin;
+                bool at_first = true;
+                if (xsh > 1 && nl_msh[yi] > 1) {
+                    // both have other shared members: merge the member lists
+                    const uint32_t* X = P.g.h2v + P.g.h_off[nl_x[xi]];
+                    const uint32_t* Y = P.g.h2v + P.g.h_off[nl_x[yi]];
+                    uint32_t a = 0, b = 0, first = HGT_EMPTY;
+                    s = 0;
+                    shh = 0;
+                    while (a < xl && b < yl) {
+                        uint32_t va = X[a], vb = Y[b];
+                        if (va < vb) a++;
+                        else if (va > vb) b++;
+                        else {
+                            if (s == 0) first = va;
+                            s++;
+                            shh += contains_u32(hm, hlen, va) ? 1u : 0u;
+                            a++;
+                            b++;
+                        }
+                    }
+                    at_first = (uint64_t)first == v;
+                }
+                if (!at_first) continue;
+                const uint32_t cy = meta_c(my);
+                if (P.static_mode) {
+                    // closed triple: counted at its smallest-ID centre only
+                    acc32_add(myacc32, T.he[venn_code((int)hlen, (int)xl, (int)yl, (int)cx, 0, (int)cy, 0)], ~0u);
+                    if (h < nl_x[xi] && h < nl_x[yi])
+                        acc32_add(myacc32, T.he[venn_code((int)hlen, (int)xl, (int)yl, (int)cx, (int)s, (int)cy, (int)shh)],
+                                  1u);
+                } else {
+                    const bool ey = meta_elig(my);
+                    if (ex) {
+                        uint32_t base = (hlen > cx ? 1u : 0u) | 24u;
+                        acc32_add(myacc32, T.he[base | (xl - cx > s ? 2u : 0u) | (yl > s ? 4u : 0u)], ~0u);
+                    }
+                    if (ey) {
+                        uint32_t base = (hlen > cy ? 1u : 0u) | 24u;
+                        acc32_add(myacc32, T.he[base | (yl - cy > s ? 2u : 0u) | (xl > s ? 4u : 0u)], ~0u);
+                    }
+                    if (ex && ey) {
+                        int ct = T.he[venn_code((int)hlen, (int)xl, (int)yl, (int)cx, (int)s, (int)cy, (int)shh)];
+                        int cf = T.he[venn_code((int)hlen, (int)xl, (int)yl, (int)cx, 0, (int)cy, 0)];
+                        if (ct != cf) {
+                            acc32_add(myacc32, ct, 1u);
+                            acc32_add(myacc32, cf, ~0u);
+                        }
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        // fold the per-centre 32-bit pair counters (signed) into the 64-bit ones
+        for (uint32_t i = tid; i < NWAVE * HGT_N_HE_CLASSES; i += HGT_WG) {
+            int32_t v = (int32_t)acc32_all[i];
+            if (v) {
+                atomicAdd((unsigned long long*)&acc_all[i], (unsigned long long)(int64_t)v);
+                acc32_all[i] = 0;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <int STAGE>
+__device__ void he2_flush(const He2Params& P, uint64_t (*acc)[HGT_N_HE_CLASSES], const uint64_t* st) {
+    __syncthreads();
+    for (int i = threadIdx.x; i < HGT_N_HE_CLASSES; i += HGT_WG) {
+        uint64_t s = 0;
+        for (int w = 0; w < NWAVE; w++) s += acc[w][i];
+        if (s) atomicAdd((unsigned long long*)&P.out_he[i], (unsigned long long)s);
+    }
+    if (P.stats && threadIdx.x == 0 && st[0])
+        atomicAdd((unsigned long long*)&P.stats[ST_DEFER0 + STAGE], (unsigned long long)st[0]);
+}
+
+#define HE2_PROLOGUE                                                                   \
+    __shared__ Sh2 sh;                                                                 \
+    __shared__ Tables T;                                                               \
+    __shared__ uint64_t acc[NWAVE][HGT_N_HE_CLASSES];                                  \
+    __shared__ uint32_t acc32[NWAVE][HGT_N_HE_CLASSES];                                \
+    __shared__ uint64_t st[2];                                                         \
+    if (*((volatile const int32_t*)P.status) != 0) return;                             \
+    for (int i = threadIdx.x; i < 128; i += HGT_WG) T.he[i] = P.he_tab[i];             \
+    for (int i = threadIdx.x; i < NWAVE * HGT_N_HE_CLASSES; i += HGT_WG) {             \
+        (&acc[0][0])[i] = 0;                                                           \
+        (&acc32[0][0])[i] = 0;                                                         \
+    }                                                                                  \
+    if (threadIdx.x < 2) st[threadIdx.x] = 0;                                          \
+    __syncthreads();
+
+__global__ void __launch_bounds__(HGT_WG) k_he2_s0(He2Params P) {
+    __shared__ __attribute__((aligned(16))) uint32_t arena[ARENA_S];
+    HE2_PROLOGUE
+    he2_body<0>(P, arena, ARENA_S, sh, T, &acc[0][0], &acc32[0][0], st);
+    he2_flush<0>(P, acc, st);
+}
+
+__global__ void __launch_bounds__(HGT_WG) k_he2_s1(He2Params P) {
+    __shared__ __attribute__((aligned(16))) uint32_t arena[ARENA_M];
+    HE2_PROLOGUE
+    he2_body<1>(P, arena, ARENA_M, sh, T, &acc[0][0], &acc32[0][0], st);
+    he2_flush<1>(P, acc, st);
+}
+
+__global__ void __launch_bounds__(HGT_WG) k_he2_s2(He2Params P) {
+    HE2_PROLOGUE
+    he2_body<2>(P, P.garena + (uint64_t)blockIdx.x * P.garena_words, (uint32_t)P.garena_words, sh, T, &acc[0][0],
+                &acc32[0][0], st);
+    he2_flush<2>(P, acc, st);
+}
+
+}  // namespace
+
+void he2_nbr_launch(NbrParams& P, unsigned grid_small, unsigned grid_big, hipStream_t s) {
+    hgt_fill_u32(P.queue, 0, 3, s);
+    hgt_fill_u64(P.n_entries, 0, 1, s);
+    if (P.n_centres == 0) return;
+    if (P.inserting && P.hpool)
+        k_h_clear<<<(unsigned)((P.n_centres * 64 + 255) / 256), 256, 0, s>>>(P.centres, P.n_centres, P.g.h_off,
+                                                                            P.g.h_len, P.hpool, P.status);
+    k_nbr_small<<<grid_small, HGT_WG, 0, s>>>(P);
+    k_nbr_big<<<grid_big, HGT_WG, 0, s>>>(P);
+    k_entries_check<<<1, 64, 0, s>>>(P.n_entries, P.entries_cap, const_cast<int32_t*>(P.status));
+}
+
+void he2_lists_build(NbrParams& P, uint64_t n_ids, uint64_t* bl_cnt, uint64_t* bl_off, uint64_t* bl_cur,
+                     uint32_t* bl_d, uint64_t* bl_pay, void* scan_tmp, hipStream_t s) {
+    hgt_fill_u64(bl_cnt, 0, n_ids, s);
+    unsigned g = 2048;
+    k_bl_count<<<g, 256, 0, s>>>(P.n_entries, P.entries_cap, P.ent_x, bl_cnt, P.status);
+    hgt_scan_u64(bl_cnt, bl_off, n_ids, nullptr, nullptr, scan_tmp, s);
+    (void)hipMemcpyAsync(bl_cur, bl_off, n_ids * 8, hipMemcpyDeviceToDevice, s);
+    k_bl_scatter<<<g, 256, 0, s>>>(P.n_entries, P.entries_cap, P.ent_x, P.ent_d, P.ent_pay, bl_cur, bl_d, bl_pay,
+                                   P.status);
+}
+
+void he2_remove_deleted(NbrParams& P, const uint64_t* mark_del, uint32_t epoch_del, hipStream_t s) {
+    k_h_remove<<<2048, 256, 0, s>>>(P.n_entries, P.entries_cap, P.ent_x, P.ent_pay, mark_del, epoch_del, P.g.h_off,
+                                    P.hpool, P.status);
+}
+
+void he2_launch_stage(He2Params& P, int stage, unsigned grid, hipStream_t s) {
+    if (!P.n_centres) return;
+    if (stage == 0) k_he2_s0<<<grid, HGT_WG, 0, s>>>(P);
+    else if (stage == 1) k_he2_s1<<<grid, HGT_WG, 0, s>>>(P);
+    else k_he2_s2<<<grid, HGT_WG, 0, s>>>(P);
+}

@@ -165,3 +165,26 @@ def test_errors_leave_state_unchanged(gpu_lib):
         assert after == before
     assert g.sync() != hgt.OK  # sticky status reports the first error
     p.close()
+
+
+@pytest.mark.parametrize("stage", [1, 2, 3])
+def test_every_kernel_path(gpu_lib, monkeypatch, stage):
+    """Force every centre past the first `stage` stages of the histogram kernel
+    (1: 148 KB LDS arena, 2: global-memory arena, 3: 2-hop kernel) and check
+    the same results."""
+    monkeypatch.setenv("HGT_FORCE_STAGE", str(stage))
+    st = _random_stream(3000 + stage, n_edges=250, nv=90, n_batches=2, n_ins=50, n_del=60, temporal=False,
+                        card=(1, 9))
+    p = Pair(st, track=("hyperedge",))
+    compare_counts(p.g, p.o, p.track, f"stage {stage} build")
+    for k, b in enumerate(st.batches):
+        p.apply(b, f"stage {stage} batch {k}")
+        compare_counts(p.g, p.o, p.track, f"stage {stage} batch {k}")
+    p.close()
+    st = W.medium(scale=0.0005, n_batches=2)
+    p = Pair(st, track=("hyperedge",))
+    compare_counts(p.g, p.o, p.track, f"stage {stage} medium build")
+    for k, b in enumerate(st.batches):
+        p.apply(b, f"stage {stage} medium batch {k}")
+        compare_counts(p.g, p.o, p.track, f"stage {stage} medium batch {k}")
+    p.close()

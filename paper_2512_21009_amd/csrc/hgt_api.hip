@@ -162,7 +162,7 @@ struct hgt_graph {
     DevBuf t_ctr, t_big_list, t_big_rank, t_big_scratch, t_list1, t_rank1, t_list2, t_rank2, t_garena;
     // hyperedge-family histograms and batch-neighbour lists
     DevBuf hpool, ent_x, ent_d, ent_pay, bl_cnt, bl_off, bl_cur, bl_d, bl_pay, nb_scratch, bl_scan;
-    DevBuf iv_keys, iv_alt, iv_sort, iv_head, iv_uniq, iv_p2, iv_scan;
+    DevBuf iv_keys, iv_alt, iv_sort, iv_head, iv_uniq, iv_p2, iv_scan, iv_tab, iv_owner, iv_ctr, iv_list, iv_garena;
     // host mirrors (valid after each synchronisation)
     uint64_t next_id = 0, h_bump = 0, v_bump = 0, next_seq = 0, n_live = 0, n_inc = 0;
     uint32_t epoch = 0;
@@ -607,6 +607,7 @@ struct IvPlan {
     uint64_t n_keys = 0;
     uint64_t* uniq = nullptr;
     uint64_t* n_uniq = nullptr;
+    uint64_t tab_slots = 0;
 };
 
 int iv_prepare(hgt_graph* g, const BatchIn& b, const PlanScratch& w, const BatchSummary& sum, IvPlan& ip,
@@ -651,21 +652,42 @@ int iv_prepare(hgt_graph* g, const BatchIn& b, const PlanScratch& w, const Batch
     k_uniq_heads<<<nblk(nk), 256, 0, s>>>(keys, nk, head);
     hgt_scan_u64(head, head, nk, nullptr, ip.n_uniq, g->iv_scan.p, s);
     k_uniq_write<<<nblk(nk), 256, 0, s>>>(keys, nk, head, vb, ip.uniq);
+    // hash of the touched pairs and the owner (first vertex) segments
+    ip.tab_slots = pow2ceil64(2 * nk + 64);
+    if (ensure(g->iv_tab, ip.tab_slots * 8) || ensure(g->iv_owner, (nk + 2) * 8) || ensure(g->iv_ctr, 64))
+        return HGT_ENOMEM;
+    uint64_t* ictr = g->iv_ctr.as<uint64_t>();
+    iv_touched_build(ip.uniq, ip.n_uniq, g->iv_tab.as<uint64_t>(), ip.tab_slots, head, g->iv_owner.as<uint64_t>(),
+                     ictr, nk, g->iv_scan.p, s);
     return HGT_OK;
 }
 
-void iv_phase(hgt_graph* g, const IvPlan& ip, bool minus, hipStream_t s) {
-    if (ip.n_keys == 0) return;
+int iv_phase(hgt_graph* g, const IvPlan& ip, bool minus, hipStream_t s) {
+    if (ip.n_keys == 0) return HGT_OK;
+    const uint64_t gwords = 1ull << 22;  // 16 MB per workgroup of the global stage
+    const unsigned grid_g = 32;
+    if (ensure(g->iv_list, (ip.n_keys + 1) * 4) || ensure(g->iv_garena, (uint64_t)grid_g * gwords * 4))
+        return HGT_ENOMEM;
     IvParams P{};
     P.g = view_of(g);
     P.pairs = ip.uniq;
     P.n_pairs = ip.n_uniq;
-    P.pairs_cap = ip.n_keys;
+    uint64_t* ictr = g->iv_ctr.as<uint64_t>();
+    P.n_owners = ictr;
+    P.owner_start = g->iv_owner.as<uint64_t>();
+    P.tab = g->iv_tab.as<uint64_t>();
+    P.tab_mask = ip.tab_slots - 1;
     P.out = g->counts.as<uint64_t>() + (minus ? ACC_IV_M : ACC_IV_P);
     P.status = &g->st.sc->status;
+    P.queue = (uint32_t*)(ictr + 2);
+    P.count = P.queue + 2;
+    P.list = g->iv_list.as<uint32_t>();
+    P.garena = g->iv_garena.as<uint32_t>();
+    P.garena_words = gwords;
     P.stats = g->prof ? g->stats.as<uint64_t>() : nullptr;
     ProfScope ps(g, PK_IV_PAIRS, s);
-    triad_iv_launch(P, s);
+    triad_iv_launch(P, (unsigned)std::min<uint64_t>((uint64_t)g->n_cu * 2, ip.n_keys), grid_g, s);
+    return HGT_OK;
 }
 
 __global__ void k_he_tmp_update(uint64_t* cnt) {
@@ -735,7 +757,7 @@ int apply(hgt_graph* g, const uint32_t* del, uint64_t n_del, const uint64_t* ins
     rc = run_phase(g, del, n_del, g->st.mark_del, b.epoch_del, sum.max_lh_del, sum.sum_lh_del, g->next_id, true,
                    false, s);
     if (rc) return rc;
-    if (do_iv) iv_phase(g, ip, true, s);
+    if (do_iv && (rc = iv_phase(g, ip, true, s))) return rc;
     // step 3: delete, then insert
     {
         ProfScope ps(g, PK_COMMIT, s);
@@ -751,7 +773,7 @@ int apply(hgt_graph* g, const uint32_t* del, uint64_t n_del, const uint64_t* ins
     rc = run_phase(g, w.assigned, n_ins, g->st.mark_ins, b.epoch_ins, sum.max_lh_ins, sum.sum_lh_ins, sum.next_id_new,
                    false, check_order == 0, s);
     if (rc) return rc;
-    if (do_iv) iv_phase(g, ip, false, s);
+    if (do_iv && (rc = iv_phase(g, ip, false, s))) return rc;
     // step 6
     k_he_tmp_update<<<1, 128, 0, s>>>(cnt);
     if (do_iv) k_iv_update<<<1, 64, 0, s>>>(cnt, CNT_IV, ACC_IV_M, ACC_IV_P, ACC_T1);
@@ -776,7 +798,8 @@ void destroy_graph(hgt_graph* g) {
                      &g->s_h_rel, &g->s_keys, &g->s_keys_alt, &g->s_sort, &g->s_head, &g->s_is_ins, &g->s_tv,
                      &g->s_tseg, &g->s_D, &g->s_I, &g->s_It, &g->s_vp, &g->s_staging, &g->s_dst, &g->t_ctr,
                      &g->t_big_list, &g->t_big_rank, &g->t_big_scratch, &g->t_list1, &g->t_rank1, &g->t_list2, &g->t_rank2, &g->t_garena, &g->iv_keys, &g->iv_alt, &g->iv_sort,
-                     &g->iv_head, &g->iv_uniq, &g->iv_p2, &g->iv_scan, &g->hpool, &g->ent_x, &g->ent_d,
+                     &g->iv_head, &g->iv_uniq, &g->iv_p2, &g->iv_scan, &g->iv_tab, &g->iv_owner, &g->iv_ctr,
+                     &g->iv_list, &g->iv_garena, &g->hpool, &g->ent_x, &g->ent_d,
                      &g->ent_pay, &g->bl_cnt, &g->bl_off, &g->bl_cur, &g->bl_d, &g->bl_pay, &g->nb_scratch,
                      &g->bl_scan};
     for (DevBuf* b : all) dev_free(*b);

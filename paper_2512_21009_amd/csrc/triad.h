@@ -110,11 +110,22 @@ void he2_launch_stage(He2Params& P, int stage, unsigned grid, hipStream_t s);
 // incident-vertex family
 struct IvParams {
     GraphView g;
-    const uint64_t* pairs;    // unique touched vertex pairs u << 32 | v, ascending
-    const uint64_t* n_pairs;  // device count
-    uint64_t pairs_cap;
-    uint64_t* out;            // u64[2]: sum_p m_p * w_p, sum over triangles with a touched pair of m m m
+    const uint64_t* pairs;       // unique touched vertex pairs u << 32 | v (u < v), ascending
+    const uint64_t* n_pairs;     // device count
+    const uint64_t* owner_start; // first pair of every distinct u, plus the end
+    const uint64_t* n_owners;
+    const uint64_t* tab;         // open-addressing hash of the touched pairs (empty = ~0)
+    uint64_t tab_mask;
+    uint64_t* out;               // u64[2]: sum_p m_p * w_p, sum over triangles with a touched pair of m m m
     const int32_t* status;
-    uint64_t* stats;          // optional, ST_IV_BYTES
+    uint32_t* queue;             // per stage
+    uint32_t* count;             // owners moved to the global-memory stage
+    uint32_t* list;
+    uint32_t* garena;
+    uint64_t garena_words;
+    uint64_t* stats;             // optional, ST_IV_BYTES
 };
-void triad_iv_launch(IvParams& P, hipStream_t s);
+void iv_touched_build(const uint64_t* pairs, const uint64_t* n_pairs, uint64_t* tab, uint64_t tab_slots,
+                      uint64_t* head, uint64_t* owner_start, uint64_t* n_owners, uint64_t pairs_cap, void* scan_tmp,
+                      hipStream_t s);
+void triad_iv_launch(IvParams& P, unsigned grid_lds, unsigned grid_global, hipStream_t s);

@@ -11,18 +11,77 @@
 //   sum_p m_p w_p             by its value over the touched pairs, and
 //   the triangle sum          by its value over triangles with a touched pair.
 // Both are evaluated on the old graph (before the batch) and on the new graph
-// (after it); the difference is the delta.  A triangle with several touched
-// pairs is counted at the smallest one.
+// (after it); the difference is the delta.
 //
-// One wave per touched pair (a, b): the lanes walk the members w of the
-// hyperedges incident to the endpoint with the shorter incidence list; a w is
-// taken at the first such hyperedge that contains it (found as the smallest
-// common element of the two incidence lists, which also gives m_aw).
-#include "triad.h"
+// A workgroup takes a touched vertex a and builds its weighted clique map
+// M_a : w -> (m_aw, w_aw) in LDS from the hyperedges that contain a.  For each
+// touched pair (a, b) with a < b, m_ab and w_ab are read from the map, and the
+// triangles through (a, b) contribute
+//   m_ab * sum_{h' containing b} sum_{w in h', w != a, b} M_a[w].m
+// (the inner double sum counts w with multiplicity m_bw).  A triangle with
+// several touched pairs is counted at its lexicographically smallest one: the
+// triangle {a, b, w} is skipped at (a, b) when {a, w} is touched and w < b, or
+// {b, w} is touched and w < a (a global hash of the touched pairs answers).
+#include "triad_common.h"
 
 namespace {
 
-// |A & B| and the smallest common element of two ascending lists
+using namespace tri;
+
+constexpr uint32_t IV_ARENA = 16384;  // 64 KB of LDS per workgroup
+
+__device__ __forceinline__ uint64_t mix64(uint64_t k) {
+    k ^= k >> 33;
+    k *= 0xff51afd7ed558ccdull;
+    k ^= k >> 33;
+    k *= 0xc4ceb9fe1a85ec53ull;
+    k ^= k >> 33;
+    return k;
+}
+
+__device__ __forceinline__ bool touched(const uint64_t* tab, uint64_t mask, uint32_t x, uint32_t y) {
+    uint64_t k = x < y ? ((uint64_t)x << 32 | y) : ((uint64_t)y << 32 | x);
+    uint64_t s = mix64(k) & mask;
+    for (uint64_t probe = 0; probe <= mask; probe++) {
+        uint64_t t = tab[s];
+        if (t == k) return true;
+        if (t == ~0ull) return false;
+        s = (s + 1) & mask;
+    }
+    return false;
+}
+
+__global__ void k_iv_hash_build(const uint64_t* __restrict__ pairs, const uint64_t* n_p, uint64_t* tab, uint64_t mask) {
+    uint64_t n = *n_p;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+        uint64_t k = pairs[i];
+        uint64_t s = mix64(k) & mask;
+        for (uint64_t probe = 0; probe <= mask; probe++) {
+            unsigned long long prev = atomicCAS((unsigned long long*)&tab[s], ~0ull, (unsigned long long)k);
+            if (prev == ~0ull || prev == k) break;
+            s = (s + 1) & mask;
+        }
+    }
+}
+
+// owners: first pair index of every distinct first vertex
+__global__ void k_iv_owner_heads(const uint64_t* __restrict__ pairs, const uint64_t* n_p, uint64_t* head) {
+    uint64_t n = *n_p;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        head[i] = (i == 0 || (pairs[i] >> 32) != (pairs[i - 1] >> 32)) ? 1 : 0;
+}
+
+__global__ void k_iv_owner_list(const uint64_t* __restrict__ pairs, const uint64_t* n_p, const uint64_t* __restrict__ pos,
+                                uint64_t* owner_start, const uint64_t* n_owner) {
+    uint64_t n = *n_p;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        if (i == 0 || (pairs[i] >> 32) != (pairs[i - 1] >> 32)) owner_start[pos[i]] = i;
+    if (blockIdx.x == 0 && threadIdx.x == 0) owner_start[*n_owner] = n;
+}
+
+// ---- memory-free fallback for vertices whose map does not fit: per pair,
+// m_ab from binary searches and every triangle vertex c from a's hyperedges
+// (taken at the first of them that holds c), m_ac and m_bc by list intersection.
 __device__ __forceinline__ uint32_t inter_count_min(const uint32_t* A, uint32_t na, const uint32_t* B, uint32_t nb,
                                                     uint32_t* mn) {
     if (na > nb) {
@@ -41,109 +100,274 @@ __device__ __forceinline__ uint32_t inter_count_min(const uint32_t* A, uint32_t 
     return c;
 }
 
-__device__ __forceinline__ bool pair_touched_before(const uint64_t* pairs, uint64_t n, uint32_t x, uint32_t y,
-                                                    uint64_t key_p) {
-    uint64_t k = x < y ? ((uint64_t)x << 32 | y) : ((uint64_t)y << 32 | x);
-    if (k >= key_p) return false;
-    uint64_t lo = 0, hi = n;
-    while (lo < hi) {
-        uint64_t mid = (lo + hi) >> 1;
-        if (pairs[mid] < k) lo = mid + 1; else hi = mid;
+// one wave: returns (lane 0) m_ab * w_ab in *s_out and the attributed triangle sum in *t_out
+__device__ void iv_pair_direct(const IvParams& P, uint32_t a, uint32_t b, uint32_t* pre, uint64_t* s_out,
+                               uint64_t* t_out) {
+    const int lane = threadIdx.x & 63;
+    uint32_t la = P.g.v_len[a], lb = P.g.v_len[b];
+    if (lb < la) { uint32_t t = a; a = b; b = t; t = la; la = lb; lb = t; }
+    const uint32_t lo = a < b ? a : b, hi = a < b ? b : a;
+    const uint32_t* A = P.g.v2h + P.g.v_off[a];
+    const uint32_t* B = P.g.v2h + P.g.v_off[b];
+    uint64_t m = 0, w = 0;
+    for (uint32_t i = lane; i < la; i += 64) {
+        uint32_t h = A[i];
+        uint32_t d = P.g.h_len[h];
+        if (contains_u32(P.g.h2v + P.g.h_off[h], d, b)) { m++; w += d - 2; }
     }
-    return lo < n && pairs[lo] == k;
-}
-
-__global__ void __launch_bounds__(HGT_WG) k_iv_pairs(IvParams P) {
-    __shared__ uint64_t acc[2];
-    __shared__ uint32_t pre[HGT_WG / 64][65];
-    if (*((volatile const int32_t*)P.status) != 0) return;
-    if (threadIdx.x < 2) acc[threadIdx.x] = 0;
-    __syncthreads();
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const uint64_t n = *P.n_pairs;
-    uint64_t s_sum = 0, t_sum = 0, bytes = 0;
-    for (uint64_t q = (uint64_t)blockIdx.x * (HGT_WG / 64) + wave; q < n; q += (uint64_t)gridDim.x * (HGT_WG / 64)) {
-        const uint64_t key = P.pairs[q];
-        uint32_t a = (uint32_t)(key >> 32), b = (uint32_t)key;
-        uint32_t la = P.g.v_len[a], lb = P.g.v_len[b];
-        if (lb < la) { uint32_t t = a; a = b; b = t; t = la; la = lb; lb = t; }
-        const uint32_t* A = P.g.v2h + P.g.v_off[a];
-        const uint32_t* B = P.g.v2h + P.g.v_off[b];
-        // m_ab and w_ab: hyperedges of a that contain b
-        uint64_t m = 0, w = 0;
-        for (uint32_t i = lane; i < la; i += 64) {
-            uint32_t h = A[i];
-            uint32_t d = P.g.h_len[h];
-            if (contains_u32(P.g.h2v + P.g.h_off[h], d, b)) { m++; w += d - 2; }
-        }
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-            m += __shfl_xor(m, o, 64);
-            w += __shfl_xor(w, o, 64);
-        }
-        if (lane == 0) {
-            s_sum += m * w;
-            bytes += 4ull * la;
-        }
-        if (m == 0) continue;
-        // triangles {a, b, c}: c in a hyperedge of a, taken at its first one
+    for (int o = 32; o > 0; o >>= 1) {
+        m += __shfl_xor(m, o, 64);
+        w += __shfl_xor(w, o, 64);
+    }
+    *s_out = m * w;
+    uint64_t t_sum = 0;
+    if (m) {
         for (uint32_t base = 0; base < la; base += 64) {
             uint32_t cnt = la - base < 64 ? la - base : 64;
-            uint32_t h = 0, d = 0;
-            if ((uint32_t)lane < cnt) {
-                h = A[base + lane];
-                d = P.g.h_len[h];
-            }
+            uint32_t d = 0;
+            if ((uint32_t)lane < cnt) d = P.g.h_len[A[base + lane]];
             uint32_t inc = d;
 #pragma unroll
             for (int o = 1; o < 64; o <<= 1) {
                 uint32_t t = __shfl_up(inc, o, 64);
                 if (lane >= o) inc += t;
             }
-            if ((uint32_t)lane < cnt) pre[wave][lane + 1] = inc;
-            if (lane == 0) pre[wave][0] = 0;
+            if ((uint32_t)lane < cnt) pre[lane + 1] = inc;
+            if (lane == 0) pre[0] = 0;
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
             __builtin_amdgcn_wave_barrier();
-            uint32_t tot = pre[wave][cnt];
+            uint32_t tot = pre[cnt];
             for (uint32_t p = lane; p < tot; p += 64) {
-                uint32_t k = seg_of<uint32_t>(pre[wave], cnt, p);
+                uint32_t k = seg_of<uint32_t>(pre, cnt, p);
                 uint32_t hk = A[base + k];
-                uint32_t c = P.g.h2v[P.g.h_off[hk] + (p - pre[wave][k])];
+                uint32_t c = P.g.h2v[P.g.h_off[hk] + (p - pre[k])];
                 if (c == a || c == b) continue;
                 const uint32_t* C = P.g.v2h + P.g.v_off[c];
                 uint32_t lc = P.g.v_len[c];
-                bytes += 4ull * (1 + lc);
                 uint32_t first;
                 uint32_t mac = inter_count_min(A, la, C, lc, &first);
-                if (first != hk) continue;  // c already met in an earlier hyperedge of a
+                if (first != hk) continue;
                 uint32_t dummy;
                 uint32_t mbc = inter_count_min(B, lb, C, lc, &dummy);
                 if (mbc == 0) continue;
-                if (pair_touched_before(P.pairs, n, a, c, key)) continue;
-                if (pair_touched_before(P.pairs, n, b, c, key)) continue;
+                if (c < hi && touched(P.tab, P.tab_mask, lo, c)) continue;
+                if (c < lo && touched(P.tab, P.tab_mask, hi, c)) continue;
                 t_sum += m * (uint64_t)mac * (uint64_t)mbc;
             }
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
             __builtin_amdgcn_wave_barrier();
         }
     }
-    if (P.stats) {
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) bytes += __shfl_xor(bytes, o, 64);
-        if (lane == 0 && bytes) atomicAdd((unsigned long long*)&P.stats[ST_IV_BYTES], (unsigned long long)bytes);
+    for (int o = 32; o > 0; o >>= 1) t_sum += __shfl_xor(t_sum, o, 64);
+    *t_out = t_sum;
+}
+
+struct IvSh {
+    uint32_t a, la, L, cap, defer, stop, idx;
+    uint64_t off_a, p0, p1;
+    uint32_t ws[NWAVE];
+};
+
+// map slot layout: key | m | w lo | w hi  (4 words)
+__device__ __forceinline__ uint32_t map_find(const uint32_t* mp, uint32_t cap, uint32_t key) {
+    uint32_t s = (uint32_t)(((uint64_t)(key * 2654435761u) * cap) >> 32);
+    for (uint32_t probe = 0; probe < cap; probe++) {
+        uint32_t k = mp[4 * s];
+        if (k == key) return s;
+        if (k == HGT_EMPTY) return HGT_EMPTY;
+        s = s + 1 == cap ? 0 : s + 1;
     }
-    if (s_sum) atomicAdd((unsigned long long*)&acc[0], (unsigned long long)s_sum);
-    if (t_sum) atomicAdd((unsigned long long*)&acc[1], (unsigned long long)t_sum);
+    return HGT_EMPTY;
+}
+
+__device__ __forceinline__ void map_add(uint32_t* mp, uint32_t cap, uint32_t key, uint32_t w) {
+    uint32_t s = (uint32_t)(((uint64_t)(key * 2654435761u) * cap) >> 32);
+    for (uint32_t probe = 0; probe < cap; probe++) {
+        uint32_t k = __atomic_load_n(&mp[4 * s], __ATOMIC_RELAXED);
+        if (k == HGT_EMPTY) {
+            uint32_t prev = atomicCAS(&mp[4 * s], HGT_EMPTY, key);
+            if (prev == HGT_EMPTY || prev == key) break;
+        } else if (k == key) {
+            break;
+        }
+        s = s + 1 == cap ? 0 : s + 1;
+    }
+    atomicAdd(&mp[4 * s + 1], 1u);
+    atomicAdd((unsigned long long*)&mp[4 * s + 2], (unsigned long long)w);
+}
+
+template <int STAGE>
+__device__ void iv_body(const IvParams& P, uint32_t* arena, uint32_t arena_words, IvSh& sh, uint64_t* acc) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    __shared__ uint32_t wpre[NWAVE][65];
+    const uint64_t n_pairs = *P.n_pairs;
+    uint64_t s_sum = 0, t_sum = 0, bytes = 0;
+    for (;;) {
+        if (tid == 0) {
+            uint32_t q = atomicAdd(&P.queue[STAGE], 1u);
+            uint64_t n = STAGE == 0 ? *P.n_owners : (uint64_t)P.count[0];
+            sh.stop = q >= n;
+            if (!sh.stop) {
+                uint32_t oi = STAGE == 0 ? q : P.list[q];
+                sh.idx = oi;
+                sh.p0 = P.owner_start[oi];
+                sh.p1 = P.owner_start[oi + 1];
+                uint32_t a = (uint32_t)(P.pairs[sh.p0] >> 32);
+                sh.a = a;
+                sh.la = P.g.v_len[a];
+                sh.off_a = P.g.v_off[a];
+            }
+        }
+        __syncthreads();
+        if (sh.stop) break;
+        const uint32_t a = sh.a, la = sh.la;
+        const uint32_t* A = P.g.v2h + sh.off_a;
+        // L = sum of the cardinalities of a's hyperedges
+        uint32_t part = 0;
+        for (uint32_t i = tid; i < la; i += HGT_WG) part += P.g.h_len[A[i]];
+        uint32_t L;
+        wg_scan_u32(part, sh.ws, &L);
+        if (tid == 0) {
+            sh.L = L;
+            sh.cap = L + L / 2 + 32;
+            sh.defer = (4ull * sh.cap > arena_words) ? 1u : 0u;
+        }
+        __syncthreads();
+        if (sh.defer && STAGE == 0) {
+            if (tid == 0) P.list[atomicAdd(&P.count[0], 1u)] = sh.idx;
+            __syncthreads();
+            continue;
+        }
+        if (sh.defer) {
+            // too large for any map: pair by pair without one
+            for (uint64_t q = sh.p0 + wave; q < sh.p1; q += NWAVE) {
+                uint64_t so, to;
+                iv_pair_direct(P, a, (uint32_t)P.pairs[q], wpre[wave], &so, &to);
+                if (lane == 0) {
+                    s_sum += so;
+                    t_sum += to;
+                }
+            }
+            __syncthreads();
+            continue;
+        }
+        const uint32_t cap = sh.cap;
+        uint32_t* mp = arena;
+        for (uint32_t s = tid; s < cap; s += HGT_WG) {
+            mp[4 * s] = HGT_EMPTY;
+            mp[4 * s + 1] = 0;
+            mp[4 * s + 2] = 0;
+            mp[4 * s + 3] = 0;
+        }
+        __syncthreads();
+        // M_a from a's hyperedges: one wave per hyperedge, lanes over members
+        for (uint32_t i = wave; i < la; i += NWAVE) {
+            uint32_t h = A[i];
+            uint32_t d = P.g.h_len[h];
+            const uint32_t* M = P.g.h2v + P.g.h_off[h];
+            for (uint32_t k = lane; k < d; k += 64) {
+                uint32_t w = M[k];
+                if (w != a) map_add(mp, cap, w, d - 2);
+            }
+        }
+        __syncthreads();
+        if (lane == 0 && P.stats) bytes += 4ull * (la + L) / NWAVE;
+        // touched pairs (a, b), b > a: one wave each
+        for (uint64_t q = sh.p0 + wave; q < sh.p1; q += NWAVE) {
+            const uint32_t b = (uint32_t)P.pairs[q];
+            uint32_t sb = map_find(mp, cap, b);
+            uint64_t m_ab = 0, w_ab = 0;
+            if (sb != HGT_EMPTY) {
+                m_ab = mp[4 * sb + 1];
+                w_ab = (uint64_t)mp[4 * sb + 2] | ((uint64_t)mp[4 * sb + 3] << 32);
+            }
+            if (lane == 0) s_sum += m_ab * w_ab;
+            if (m_ab == 0) continue;
+            const uint32_t lb = P.g.v_len[b];
+            const uint32_t* B = P.g.v2h + P.g.v_off[b];
+            uint64_t sum = 0;
+            for (uint32_t base = 0; base < lb; base += 64) {
+                uint32_t cnt = lb - base < 64 ? lb - base : 64;
+                uint32_t d = 0;
+                if ((uint32_t)lane < cnt) d = P.g.h_len[B[base + lane]];
+                uint32_t inc = d;
+#pragma unroll
+                for (int o = 1; o < 64; o <<= 1) {
+                    uint32_t t = __shfl_up(inc, o, 64);
+                    if (lane >= o) inc += t;
+                }
+                if ((uint32_t)lane < cnt) wpre[wave][lane + 1] = inc;
+                if (lane == 0) wpre[wave][0] = 0;
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+                __builtin_amdgcn_wave_barrier();
+                const uint32_t tot = wpre[wave][cnt];
+                if (P.stats && lane == 0) bytes += 4ull * (cnt + tot);
+                for (uint32_t p = lane; p < tot; p += 64) {
+                    uint32_t k = seg_of<uint32_t>(wpre[wave], cnt, p);
+                    uint32_t hk = B[base + k];
+                    uint32_t w = P.g.h2v[P.g.h_off[hk] + (p - wpre[wave][k])];
+                    if (w == a || w == b) continue;
+                    uint32_t sw = map_find(mp, cap, w);
+                    if (sw == HGT_EMPTY) continue;
+                    if (w < b && touched(P.tab, P.tab_mask, a, w)) continue;
+                    if (w < a && touched(P.tab, P.tab_mask, b, w)) continue;
+                    sum += mp[4 * sw + 1];
+                }
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+                __builtin_amdgcn_wave_barrier();
+            }
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
+            if (lane == 0) t_sum += m_ab * sum;
+        }
+        __syncthreads();
+    }
+    if (lane == 0) {
+        if (s_sum) atomicAdd((unsigned long long*)&acc[0], (unsigned long long)s_sum);
+        if (t_sum) atomicAdd((unsigned long long*)&acc[1], (unsigned long long)t_sum);
+        if (bytes && P.stats) atomicAdd((unsigned long long*)&P.stats[ST_IV_BYTES], (unsigned long long)bytes);
+    }
+}
+
+__global__ void __launch_bounds__(HGT_WG) k_iv_lds(IvParams P) {
+    __shared__ __attribute__((aligned(16))) uint32_t arena[IV_ARENA];
+    __shared__ IvSh sh;
+    __shared__ uint64_t acc[2];
+    if (*((volatile const int32_t*)P.status) != 0) return;
+    if (threadIdx.x < 2) acc[threadIdx.x] = 0;
+    __syncthreads();
+    iv_body<0>(P, arena, IV_ARENA, sh, acc);
+    __syncthreads();
+    if (threadIdx.x < 2 && acc[threadIdx.x]) atomicAdd((unsigned long long*)&P.out[threadIdx.x], (unsigned long long)acc[threadIdx.x]);
+}
+
+__global__ void __launch_bounds__(HGT_WG) k_iv_global(IvParams P) {
+    __shared__ IvSh sh;
+    __shared__ uint64_t acc[2];
+    if (*((volatile const int32_t*)P.status) != 0) return;
+    if (threadIdx.x < 2) acc[threadIdx.x] = 0;
+    __syncthreads();
+    iv_body<1>(P, P.garena + (uint64_t)blockIdx.x * P.garena_words, (uint32_t)P.garena_words, sh, acc);
     __syncthreads();
     if (threadIdx.x < 2 && acc[threadIdx.x]) atomicAdd((unsigned long long*)&P.out[threadIdx.x], (unsigned long long)acc[threadIdx.x]);
 }
 
 }  // namespace
 
-void triad_iv_launch(IvParams& P, hipStream_t s) {
-    uint64_t waves = P.pairs_cap;
-    uint64_t blocks = (waves + 3) / 4;
-    if (blocks > 8192) blocks = 8192;
-    if (blocks == 0) return;
-    k_iv_pairs<<<(unsigned)blocks, HGT_WG, 0, s>>>(P);
+void iv_touched_build(const uint64_t* pairs, const uint64_t* n_pairs, uint64_t* tab, uint64_t tab_slots,
+                      uint64_t* head, uint64_t* owner_start, uint64_t* n_owners, uint64_t pairs_cap, void* scan_tmp,
+                      hipStream_t s) {
+    hgt_fill_u64(tab, ~0ull, tab_slots, s);
+    k_iv_hash_build<<<2048, 256, 0, s>>>(pairs, n_pairs, tab, tab_slots - 1);
+    k_iv_owner_heads<<<2048, 256, 0, s>>>(pairs, n_pairs, head);
+    hgt_scan_u64(head, head, pairs_cap, n_pairs, n_owners, scan_tmp, s);
+    k_iv_owner_list<<<2048, 256, 0, s>>>(pairs, n_pairs, head, owner_start, n_owners);
+}
+
+void triad_iv_launch(IvParams& P, unsigned grid_lds, unsigned grid_global, hipStream_t s) {
+    hgt_fill_u32(P.queue, 0, 4, s);  // queues of both stages and the moved-on count
+    k_iv_lds<<<grid_lds, HGT_WG, 0, s>>>(P);
+    k_iv_global<<<grid_global, HGT_WG, 0, s>>>(P);
 }

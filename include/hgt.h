@@ -115,6 +115,35 @@ int hgt_apply_batch(hgt_graph* g, const uint32_t* del_ids, uint64_t n_del,
                     uint64_t n_ins_members, const int64_t* ins_ts, uint64_t n_ins,
                     uint32_t* out_ins_ids, void* stream);
 
+/* ---- batched form ------------------------------------------------------ */
+/* One graph's batch for hgt_apply_batches: the arguments of hgt_apply_batch,
+ * plus its result. */
+typedef struct {
+    hgt_graph* graph;
+    const uint32_t* del_ids;        /* device */
+    uint64_t n_del;
+    const uint64_t* ins_offsets;    /* device */
+    const uint32_t* ins_members;    /* device */
+    uint64_t n_ins_members;
+    const int64_t* ins_ts;          /* device */
+    uint64_t n_ins;
+    uint32_t* out_ins_ids;          /* device, may be NULL */
+    int32_t status;                 /* out: this batch's result */
+    int32_t pad0;
+} hgt_batch;
+
+/* Applies batches[i] to batches[i].graph for every i, with the same semantics
+ * and the same results as n separate hgt_apply_batch calls.  The graphs must
+ * be distinct and live on the current device.  Their planning passes are
+ * queued together and the call waits once for all of their summaries; the
+ * triad phases of all graphs then share one launch per kernel, whose workgroups
+ * take (graph, hyperedge) work items from one device queue.  A batch that
+ * fails validation is rejected alone (its status says why); the others are
+ * applied.  The first graph's triad scratch serves the whole call, so calls
+ * that share a graph must not overlap.  Returns HGT_OK when every batch was
+ * applied, else the first failing batch's status. */
+int hgt_apply_batches(hgt_batch* batches, uint32_t n, void* stream);
+
 /* ---- queries ---------------------------------------------------------- */
 /* Copies the maintained counts of family `type` to out_host[0..n_out) (host).
  * n_out must be at least 30 / 3 / 96.  `window` must be 0 for the hyperedge

@@ -144,6 +144,19 @@ constexpr int ACC_HE_M = 129, ACC_HE_P = 159, ACC_TMP_M = 189, ACC_TMP_P = 285, 
 
 }  // namespace
 
+// Scratch of the hyperedge/temporal triad phases.  A plain batch uses its own
+// graph's; a batched call uses the first graph's for all of its graphs.
+struct PhaseCtx {
+    DevBuf t_ctr, t_big_list, t_big_rank, t_big_scratch, t_list1, t_rank1, t_list2, t_rank2, t_garena;
+    DevBuf ent_x, ent_d, ent_pay, bl_cnt, bl_off, bl_cur, bl_d, bl_pay, nb_scratch, bl_scan;
+    // per-graph phase descriptors: device copies and their pinned staging, one
+    // slot per (phase, family) so no upload overwrites one still in flight
+    DevBuf desc;
+    char* desc_host = nullptr;
+    uint64_t desc_cap = 0;       // graphs per slot
+    hipEvent_t desc_ev[4] = {nullptr, nullptr, nullptr, nullptr};
+};
+
 struct hgt_graph {
     int device = 0;
     int n_cu = 256;
@@ -158,10 +171,10 @@ struct hgt_graph {
     DevBuf s_sum, s_del_bm, s_del_card, s_del_poff, s_ins_rel, s_ins_card, s_canon, s_big, s_small, s_popc, s_scan,
         s_assigned, s_h_need, s_h_rel, s_keys, s_keys_alt, s_sort, s_head, s_is_ins, s_tv, s_tseg, s_D, s_I, s_It,
         s_vp, s_staging, s_dst;
-    // triad scratch
-    DevBuf t_ctr, t_big_list, t_big_rank, t_big_scratch, t_list1, t_rank1, t_list2, t_rank2, t_garena;
-    // hyperedge-family histograms and batch-neighbour lists
-    DevBuf hpool, ent_x, ent_d, ent_pay, bl_cnt, bl_off, bl_cur, bl_d, bl_pay, nb_scratch, bl_scan;
+    // hyperedge-family neighbour histograms (2 words per h2v word)
+    DevBuf hpool;
+    // scratch of the triad phases (also lent to batched calls led by this graph)
+    PhaseCtx ph;
     DevBuf iv_keys, iv_alt, iv_sort, iv_head, iv_uniq, iv_p2, iv_scan, iv_tab, iv_owner, iv_ctr, iv_list, iv_garena;
     // host mirrors (valid after each synchronisation)
     uint64_t next_id = 0, h_bump = 0, v_bump = 0, next_seq = 0, n_live = 0, n_inc = 0;
@@ -377,164 +390,258 @@ int ensure_plan_scratch(hgt_graph* g, const Sizes& z, PlanScratch& w) {
 }
 
 // ---- triad phases ---------------------------------------------------------
-// Counter slots in t_ctr: 0-2 neighbour pass, 3 histogram kernel queue,
-// 4 its deferred count, 5 2-hop queue for the deferred centres, 6-8 temporal.
-int run_phase(hgt_graph* g, const uint32_t* centres, uint64_t n, const uint64_t* mark, uint32_t epoch,
-              uint64_t max_lh, uint64_t sum_lh, uint64_t n_ids, bool minus, bool full, hipStream_t s) {
-    bool do_he = g->track_mask & (1u << HGT_TRIAD_HYPEREDGE);
-    bool do_tmp = g->track_mask & (1u << HGT_TRIAD_TEMPORAL);
-    if (!(do_he || do_tmp) || n == 0) return HGT_OK;
-    int rc = 0;
-    rc |= ensure(g->t_ctr, 128);
-    rc |= ensure(g->t_big_list, n * 4);
-    rc |= ensure(g->t_big_rank, n * 4);
-    rc |= ensure(g->t_list1, n * 4);
-    rc |= ensure(g->t_rank1, n * 4);
-    rc |= ensure(g->t_list2, n * 4);
-    rc |= ensure(g->t_rank2, n * 4);
-    if (rc) return HGT_ENOMEM;
-    const uint64_t lhm = std::max<uint64_t>(max_lh, 1);
-    const uint64_t max_card = std::min<uint64_t>(HGT_MAX_CARD, lhm);
-    BigLayout L = triad_big_layout(lhm, max_card);
-    // at most ~1 GiB of global tables for the large-centre kernels
-    uint64_t grid_big = std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)g->n_cu * 2, (1ull << 28) / L.words_per_wg));
-    if (ensure(g->t_big_scratch, grid_big * L.words_per_wg * 4)) return HGT_ENOMEM;
-    uint32_t* ctr = g->t_ctr.as<uint32_t>();
-    uint64_t* cnt = g->counts.as<uint64_t>();
-    uint64_t* stats = g->prof ? g->stats.as<uint64_t>() : nullptr;
-    TriadParams P{};
-    P.g = view_of(g);
-    P.centres = centres;
-    P.n_centres = n;
-    P.mark = mark;
-    P.epoch = epoch;
-    P.window = g->window;
-    P.out_he = cnt + (minus ? ACC_HE_M : ACC_HE_P);
-    P.out_tmp = cnt + (minus ? ACC_TMP_M : ACC_TMP_P);
-    P.he_tab = g->tabs.as<uint8_t>();
-    P.tmp_tab = g->tabs.as<uint8_t>() + 128;
-    P.status = &g->st.sc->status;
-    P.big_list = g->t_big_list.as<uint32_t>();
-    P.big_rank = g->t_big_rank.as<uint32_t>();
-    P.big_scratch = g->t_big_scratch.as<uint32_t>();
-    P.big = L;
-    P.stats = stats;
-    const unsigned grid_small = (unsigned)std::min<uint64_t>((uint64_t)g->n_cu * 2, n);
-    if (do_he) {
-        // neighbour pass: batch-neighbour entries; histogram updates for inserts
-        uint64_t ecap = std::max<uint64_t>(sum_lh, 1);
-        uint64_t nb_words = 2 * pow2ceil64(2 * std::max<uint64_t>(lhm, 32)) + 3 * max_card + 8;
-        uint64_t nb_grid = std::max<uint64_t>(1, std::min<uint64_t>(256, (1ull << 27) / nb_words));
-        uint64_t ids = std::max<uint64_t>(n_ids, 1);
-        rc |= ensure(g->ent_x, ecap * 4);
-        rc |= ensure(g->ent_d, ecap * 4);
-        rc |= ensure(g->ent_pay, ecap * 8);
-        rc |= ensure(g->bl_d, ecap * 4);
-        rc |= ensure(g->bl_pay, ecap * 8);
-        rc |= ensure(g->bl_cnt, ids * 8);
-        rc |= ensure(g->bl_off, ids * 8);
-        rc |= ensure(g->bl_cur, ids * 8);
-        rc |= ensure(g->bl_scan, hgt_scan_tmp_bytes(ids));
-        rc |= ensure(g->nb_scratch, nb_grid * nb_words * 4);
-        if (rc) return HGT_ENOMEM;
-        NbrParams N{};
-        N.g = P.g;
-        N.centres = centres;
-        N.n_centres = n;
-        N.inserting = minus ? 0 : 1;
-        N.mark_self = minus ? nullptr : mark;
-        N.epoch = epoch;
-        N.hpool = g->hpool.as<uint32_t>();
-        N.n_entries = (uint64_t*)(ctr + 10);  // 8-byte aligned slot
-        N.entries_cap = ecap;
-        N.ent_x = g->ent_x.as<uint32_t>();
-        N.ent_d = g->ent_d.as<uint32_t>();
-        N.ent_pay = g->ent_pay.as<uint64_t>();
-        N.queue = ctr;
-        N.big_queue = ctr + 1;
-        N.big_count = ctr + 2;
-        N.big_list = P.big_list;
-        N.big_rank = P.big_rank;
-        N.big_scratch = g->nb_scratch.as<uint32_t>();
-        N.big_words = nb_words;
-        N.status = P.status;
-        N.emit_entries = full ? 0 : 1;
-        {
-            ProfScope ps_nbr(g, PK_NBR, s);
-            he2_nbr_launch(N, grid_small, (unsigned)nb_grid, s);
-            if (!full)
-                he2_lists_build(N, ids, g->bl_cnt.as<uint64_t>(), g->bl_off.as<uint64_t>(), g->bl_cur.as<uint64_t>(),
-                                g->bl_d.as<uint32_t>(), g->bl_pay.as<uint64_t>(), g->bl_scan.p, s);
-        }
-        He2Params E{};
-        E.g = P.g;
-        E.centres = centres;
-        E.n_centres = n;
-        E.mark = mark;
-        E.epoch = epoch;
-        E.hpool = g->hpool.as<uint32_t>();
-        E.bl_off = g->bl_off.as<uint64_t>();
-        E.bl_cnt = g->bl_cnt.as<uint64_t>();
-        E.bl_d = g->bl_d.as<uint32_t>();
-        E.bl_pay = g->bl_pay.as<uint64_t>();
-        E.out_he = P.out_he;
-        E.he_tab = P.he_tab;
-        E.status = P.status;
-        // stages: ctr[16..18] queues, ctr[19..21] moved-on counts
-        E.queue = ctr + 16;
-        E.count = ctr + 19;
-        E.list[0] = g->t_list1.as<uint32_t>();
-        E.rank[0] = g->t_rank1.as<uint32_t>();
-        E.list[1] = g->t_list2.as<uint32_t>();
-        E.rank[1] = g->t_rank2.as<uint32_t>();
-        E.list[2] = P.big_list;
-        E.rank[2] = P.big_rank;
-        const uint64_t garena_words = 1ull << 18;  // 1 MB per workgroup
-        const unsigned grid_g = (unsigned)std::min<uint64_t>(128, n);
-        if (ensure(g->t_garena, (uint64_t)grid_g * garena_words * 4)) return HGT_ENOMEM;
-        E.garena = g->t_garena.as<uint32_t>();
-        E.garena_words = garena_words;
-        E.stats = stats;
-        E.force_stage = g->force_stage;
-        E.static_mode = full ? 1 : 0;
-        hgt_fill_u32(ctr + 16, 0, 6, s);
-        hgt_fill_u32(ctr + 5, 0, 1, s);
-        {
-            ProfScope ps(g, PK_DELTA_SMALL, s);
-            he2_launch_stage(E, 0, grid_small, s);
-        }
-        {
-            ProfScope ps(g, PK_DELTA_MED, s);
-            he2_launch_stage(E, 1, (unsigned)std::min<uint64_t>((uint64_t)g->n_cu, n), s);
-        }
-        {
-            ProfScope ps(g, PK_DELTA_GLOBAL, s);
-            he2_launch_stage(E, 2, grid_g, s);
-        }
-        // centres too large for the LDS arena: the 2-hop kernel
-        TriadParams B = P;
-        B.do_he = 1;
-        B.do_tmp = 0;
-        B.big_count = ctr + 21;
-        B.big_queue = ctr + 5;
-        B.static_he = full ? 1 : 0;
-        {
-            ProfScope ps(g, PK_DELTA_BIG, s);
-            triad_he_launch_big(B, (unsigned)grid_big, s);
-        }
-        if (minus) he2_remove_deleted(N, mark, epoch, s);
+void phase_ctx_free(PhaseCtx& c) {
+    DevBuf* all[] = {&c.t_ctr, &c.t_big_list, &c.t_big_rank, &c.t_big_scratch, &c.t_list1, &c.t_rank1, &c.t_list2,
+                     &c.t_rank2, &c.t_garena, &c.ent_x, &c.ent_d, &c.ent_pay, &c.bl_cnt, &c.bl_off, &c.bl_cur,
+                     &c.bl_d, &c.bl_pay, &c.nb_scratch, &c.bl_scan, &c.desc};
+    for (DevBuf* b : all) dev_free(*b);
+    for (hipEvent_t& e : c.desc_ev) {
+        if (e) (void)hipEventSynchronize(e);
+        if (e) (void)hipEventDestroy(e);
+        e = nullptr;
     }
-    if (do_tmp) {
-        TriadParams Q = P;
-        Q.do_he = 0;
-        Q.do_tmp = 1;
-        Q.queue = ctr + 6;
-        Q.big_queue = ctr + 7;
-        Q.big_count = ctr + 8;
-        triad_he_prepare(Q, s);
-        ProfScope ps(g, PK_TMP, s);
-        triad_he_launch_small(Q, (unsigned)std::min<uint64_t>((uint64_t)g->n_cu * 3, n), s);
-        triad_he_launch_big(Q, (unsigned)grid_big, s);
+    if (c.desc_host) (void)hipHostFree(c.desc_host);
+    c.desc_host = nullptr;
+    c.desc_cap = 0;
+}
+
+// One graph's share of a phase.
+struct PhaseJob {
+    hgt_graph* g;
+    const uint32_t* centres;  // device, n entries; the index is the batch rank
+    uint64_t n;
+    const uint64_t* mark;
+    uint32_t epoch;
+    uint64_t max_lh, sum_lh;  // over the centres (see BatchSummary)
+    uint64_t n_ids;           // IDs in use during the phase
+};
+
+inline size_t desc_slot_bytes(uint64_t cap) { return cap * sizeof(HeGraph) + 2 * (cap + 1) * 8; }
+
+// Uploads the descriptors of `G` into slot `slot` and fills M's device pointers.
+int upload_multi(PhaseCtx& c, int slot, const std::vector<HeGraph>& G, const std::vector<uint64_t>& base,
+                 const std::vector<uint64_t>& id_base, Multi& M, hipStream_t s) {
+    const uint64_t n = G.size();
+    if (n > c.desc_cap) {
+        for (hipEvent_t e : c.desc_ev)
+            if (e) HIP_OK(hipEventSynchronize(e));
+        HIP_OK(hipStreamSynchronize(s));
+        uint64_t cap = std::max<uint64_t>(n, 2 * c.desc_cap);
+        cap = std::max<uint64_t>(cap, 4);
+        if (c.desc_host) (void)hipHostFree(c.desc_host);
+        c.desc_host = nullptr;
+        c.desc_cap = 0;
+        if (hipHostMalloc((void**)&c.desc_host, 4 * desc_slot_bytes(cap), hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            c.desc_host = nullptr;
+            return HGT_ENOMEM;
+        }
+        dev_free(c.desc);
+        if (dev_alloc(c.desc, 4 * desc_slot_bytes(cap))) return HGT_ENOMEM;
+        c.desc_cap = cap;
+    }
+    if (!c.desc_ev[slot] && hipEventCreateWithFlags(&c.desc_ev[slot], hipEventDisableTiming) != hipSuccess) {
+        c.desc_ev[slot] = nullptr;
+        return HGT_EDEVICE;
+    }
+    HIP_OK(hipEventSynchronize(c.desc_ev[slot]));  // the slot's previous upload has been read
+    const size_t sb = desc_slot_bytes(c.desc_cap);
+    char* h = c.desc_host + slot * sb;
+    char* d = (char*)c.desc.p + slot * sb;
+    std::memcpy(h, G.data(), n * sizeof(HeGraph));
+    std::memcpy(h + n * sizeof(HeGraph), base.data(), (n + 1) * 8);
+    std::memcpy(h + n * sizeof(HeGraph) + (n + 1) * 8, id_base.data(), (n + 1) * 8);
+    const size_t bytes = n * sizeof(HeGraph) + 2 * (n + 1) * 8;
+    HIP_OK(hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, s));
+    HIP_OK(hipEventRecord(c.desc_ev[slot], s));
+    M.graphs = (const HeGraph*)d;
+    M.base = (const uint64_t*)(d + n * sizeof(HeGraph));
+    M.id_base = (const uint64_t*)(d + n * sizeof(HeGraph) + (n + 1) * 8);
+    M.n_graphs = (uint32_t)n;
+    M.total = base[n];
+    M.total_ids = id_base[n];
+    return HGT_OK;
+}
+
+// Builds the descriptors of the jobs whose graph tracks `family`.
+void collect(const PhaseJob* jobs, uint32_t nj, int family, bool minus, std::vector<HeGraph>& G,
+             std::vector<uint64_t>& base, std::vector<uint64_t>& id_base, uint64_t& max_lh, uint64_t& sum_lh) {
+    G.clear();
+    base.assign(1, 0);
+    id_base.assign(1, 0);
+    max_lh = sum_lh = 0;
+    for (uint32_t j = 0; j < nj; j++) {
+        const PhaseJob& J = jobs[j];
+        hgt_graph* g = J.g;
+        if (J.n == 0 || !(g->track_mask & (1u << family))) continue;
+        HeGraph h{};
+        h.g = view_of(g);
+        h.centres = J.centres;
+        h.n_centres = J.n;
+        h.mark = J.mark;
+        h.epoch = J.epoch;
+        h.window = g->window;
+        h.status = &g->st.sc->status;
+        uint64_t* cnt = g->counts.as<uint64_t>();
+        h.out_he = cnt + (minus ? ACC_HE_M : ACC_HE_P);
+        h.out_tmp = cnt + (minus ? ACC_TMP_M : ACC_TMP_P);
+        h.hpool = g->hpool.as<uint32_t>();
+        h.id_base = id_base.back();
+        G.push_back(h);
+        base.push_back(base.back() + J.n);
+        id_base.push_back(id_base.back() + std::max<uint64_t>(J.n_ids, 1));
+        max_lh = std::max(max_lh, J.max_lh);
+        sum_lh += J.sum_lh;
+    }
+}
+
+// One phase (deltas of the deleted hyperedges on the old graphs, or of the
+// inserted ones on the new graphs) for every job, in one launch per kernel.
+// Counter slots in t_ctr: 0-2 neighbour pass, 5 2-hop queue for the centres the
+// histogram stages pass on, 6-8 temporal, 10-11 entry count, 16-18 stage queues,
+// 19-21 stage hand-over counts.
+int run_phase(hgt_graph* owner, const PhaseJob* jobs, uint32_t nj, bool minus, bool full, hipStream_t s) {
+    PhaseCtx& c = owner->ph;
+    uint64_t* stats = owner->prof ? owner->stats.as<uint64_t>() : nullptr;
+    const uint64_t n_cu = (uint64_t)owner->n_cu;
+    std::vector<HeGraph> G;
+    std::vector<uint64_t> base, id_base;
+    for (int family : {HGT_TRIAD_HYPEREDGE, HGT_TRIAD_TEMPORAL}) {
+        uint64_t max_lh, sum_lh;
+        collect(jobs, nj, family, minus, G, base, id_base, max_lh, sum_lh);
+        const uint64_t n = base.back();
+        if (n == 0) continue;
+        if (id_base.back() > 0xfffffff0ull) return HGT_EINVAL;  // entry slots are u32
+        int rc = 0;
+        rc |= ensure(c.t_ctr, 128);
+        rc |= ensure(c.t_big_list, n * 8);
+        rc |= ensure(c.t_big_rank, n * 4);
+        rc |= ensure(c.t_list1, n * 8);
+        rc |= ensure(c.t_rank1, n * 4);
+        rc |= ensure(c.t_list2, n * 8);
+        rc |= ensure(c.t_rank2, n * 4);
+        if (rc) return HGT_ENOMEM;
+        const uint64_t lhm = std::max<uint64_t>(max_lh, 1);
+        const uint64_t max_card = std::min<uint64_t>(HGT_MAX_CARD, lhm);
+        BigLayout L = triad_big_layout(lhm, max_card);
+        // at most ~1 GiB of global tables for the large-centre kernels
+        uint64_t grid_big = std::max<uint64_t>(1, std::min<uint64_t>(n_cu * 2, (1ull << 28) / L.words_per_wg));
+        if (ensure(c.t_big_scratch, grid_big * L.words_per_wg * 4)) return HGT_ENOMEM;
+        Multi M{};
+        rc = upload_multi(c, (minus ? 0 : 2) + (family == HGT_TRIAD_TEMPORAL ? 1 : 0), G, base, id_base, M, s);
+        if (rc) return rc;
+        uint32_t* ctr = c.t_ctr.as<uint32_t>();
+        TriadParams P{};
+        P.M = M;
+        P.he_tab = owner->tabs.as<uint8_t>();
+        P.tmp_tab = owner->tabs.as<uint8_t>() + 128;
+        P.big_list = c.t_big_list.as<uint64_t>();
+        P.big_rank = c.t_big_rank.as<uint32_t>();
+        P.big_scratch = c.t_big_scratch.as<uint32_t>();
+        P.big = L;
+        P.stats = stats;
+        const unsigned grid_small = (unsigned)std::min<uint64_t>(n_cu * 2, n);
+        if (family == HGT_TRIAD_HYPEREDGE) {
+            // neighbour pass: batch-neighbour entries; histogram updates for inserts
+            uint64_t ecap = std::max<uint64_t>(sum_lh, 1);
+            uint64_t nb_words = 2 * pow2ceil64(2 * std::max<uint64_t>(lhm, 32)) + 3 * max_card + 8;
+            uint64_t nb_grid = std::max<uint64_t>(1, std::min<uint64_t>(256, (1ull << 27) / nb_words));
+            uint64_t ids = M.total_ids;
+            rc |= ensure(c.ent_x, ecap * 4);
+            rc |= ensure(c.ent_d, ecap * 4);
+            rc |= ensure(c.ent_pay, ecap * 8);
+            rc |= ensure(c.bl_d, ecap * 4);
+            rc |= ensure(c.bl_pay, ecap * 8);
+            rc |= ensure(c.bl_cnt, ids * 8);
+            rc |= ensure(c.bl_off, ids * 8);
+            rc |= ensure(c.bl_cur, ids * 8);
+            rc |= ensure(c.bl_scan, hgt_scan_tmp_bytes(ids));
+            rc |= ensure(c.nb_scratch, nb_grid * nb_words * 4);
+            if (rc) return HGT_ENOMEM;
+            NbrParams N{};
+            N.M = M;
+            N.inserting = minus ? 0 : 1;
+            N.emit_entries = full ? 0 : 1;
+            N.n_entries = (uint64_t*)(ctr + 10);  // 8-byte aligned slot
+            N.entries_cap = ecap;
+            N.ent_x = c.ent_x.as<uint32_t>();
+            N.ent_d = c.ent_d.as<uint32_t>();
+            N.ent_pay = c.ent_pay.as<uint64_t>();
+            N.queue = ctr;
+            N.big_queue = ctr + 1;
+            N.big_count = ctr + 2;
+            N.big_list = P.big_list;
+            N.big_rank = P.big_rank;
+            N.big_scratch = c.nb_scratch.as<uint32_t>();
+            N.big_words = nb_words;
+            {
+                ProfScope ps_nbr(owner, PK_NBR, s);
+                he2_nbr_launch(N, grid_small, (unsigned)nb_grid, s);
+                if (!full)
+                    he2_lists_build(N, c.bl_cnt.as<uint64_t>(), c.bl_off.as<uint64_t>(), c.bl_cur.as<uint64_t>(),
+                                    c.bl_d.as<uint32_t>(), c.bl_pay.as<uint64_t>(), c.bl_scan.p, s);
+            }
+            He2Params E{};
+            E.M = M;
+            E.he_tab = P.he_tab;
+            E.bl_off = c.bl_off.as<uint64_t>();
+            E.bl_cnt = c.bl_cnt.as<uint64_t>();
+            E.bl_d = c.bl_d.as<uint32_t>();
+            E.bl_pay = c.bl_pay.as<uint64_t>();
+            E.queue = ctr + 16;
+            E.count = ctr + 19;
+            E.list[0] = c.t_list1.as<uint64_t>();
+            E.rank[0] = c.t_rank1.as<uint32_t>();
+            E.list[1] = c.t_list2.as<uint64_t>();
+            E.rank[1] = c.t_rank2.as<uint32_t>();
+            E.list[2] = P.big_list;
+            E.rank[2] = P.big_rank;
+            const uint64_t garena_words = 1ull << 18;  // 1 MB per workgroup
+            const unsigned grid_g = (unsigned)std::min<uint64_t>(128, n);
+            if (ensure(c.t_garena, (uint64_t)grid_g * garena_words * 4)) return HGT_ENOMEM;
+            E.garena = c.t_garena.as<uint32_t>();
+            E.garena_words = garena_words;
+            E.stats = stats;
+            E.force_stage = owner->force_stage;
+            E.static_mode = full ? 1 : 0;
+            hgt_fill_u32(ctr + 16, 0, 6, s);
+            hgt_fill_u32(ctr + 5, 0, 1, s);
+            {
+                ProfScope ps(owner, PK_DELTA_SMALL, s);
+                he2_launch_stage(E, 0, grid_small, s);
+            }
+            {
+                ProfScope ps(owner, PK_DELTA_MED, s);
+                he2_launch_stage(E, 1, (unsigned)std::min<uint64_t>(n_cu, n), s);
+            }
+            {
+                ProfScope ps(owner, PK_DELTA_GLOBAL, s);
+                he2_launch_stage(E, 2, grid_g, s);
+            }
+            // centres too large for every arena: the 2-hop kernel
+            TriadParams B = P;
+            B.do_he = 1;
+            B.do_tmp = 0;
+            B.big_count = ctr + 21;
+            B.big_queue = ctr + 5;
+            B.static_he = full ? 1 : 0;
+            {
+                ProfScope ps(owner, PK_DELTA_BIG, s);
+                triad_he_launch_big(B, (unsigned)grid_big, s);
+            }
+            if (minus) he2_remove_deleted(N, s);
+        } else {
+            TriadParams Q = P;
+            Q.do_he = 0;
+            Q.do_tmp = 1;
+            Q.queue = ctr + 6;
+            Q.big_queue = ctr + 7;
+            Q.big_count = ctr + 8;
+            triad_he_prepare(Q, s);
+            ProfScope ps(owner, PK_TMP, s);
+            triad_he_launch_small(Q, (unsigned)std::min<uint64_t>(n_cu * 3, n), s);
+            triad_he_launch_big(Q, (unsigned)grid_big, s);
+        }
     }
     return HGT_OK;
 }
@@ -696,18 +803,30 @@ __global__ void k_he_tmp_update(uint64_t* cnt) {
     if (i < 96) cnt[CNT_TMP + i] += cnt[ACC_TMP_P + i] - cnt[ACC_TMP_M + i];
 }
 
-// One batch.  check_order = 0 only for the build batch.
-int apply(hgt_graph* g, const uint32_t* del, uint64_t n_del, const uint64_t* ins_off, const uint32_t* ins_mem,
-          uint64_t n_mem, const int64_t* ins_ts, uint64_t n_ins, uint32_t* out_ids, hipStream_t s, int check_order) {
+// A batch in flight: the steps before and after the one host synchronisation.
+struct Pending {
+    hgt_graph* g = nullptr;
+    BatchIn b{};
+    PlanScratch w{};
+    BatchSummary sum{};
+    IvPlan ip;
+    uint64_t n_mem = 0;
+    uint32_t* out_ids = nullptr;
+    int check_order = 1;
+    int rc = HGT_OK;  // this batch's result so far
+};
+
+// Host checks, scratch, and the non-mutating planning pass; the summary is
+// copied to pinned memory, read after the caller synchronises.
+int plan_begin(Pending& p, const uint32_t* del, uint64_t n_del, const uint64_t* ins_off, const uint32_t* ins_mem,
+               uint64_t n_mem, const int64_t* ins_ts, uint64_t n_ins, hipStream_t s) {
+    hgt_graph* g = p.g;
     const bool tmp = g->track_mask & (1u << HGT_TRIAD_TEMPORAL);
     if ((n_del && !del) || (n_ins && !ins_off) || (n_mem && !ins_mem)) return HGT_EINVAL;
     if (tmp && n_ins && !ins_ts) return HGT_EINVAL;
     if (n_ins > 0xfffffff0ull || n_del > 0xfffffff0ull) return HGT_EINVAL;
     if (n_mem > n_ins * (uint64_t)HGT_MAX_CARD) return HGT_EINVAL;
-    if (n_del > g->n_live) {
-        g->sticky = g->sticky ? g->sticky : HGT_ENOENT;
-        return HGT_ENOENT;
-    }
+    if (n_del > g->n_live) return HGT_ENOENT;
     g->last_stream = s;
     int rc = ensure_id_cap(g, g->next_id + n_ins + 1, s);
     if (rc) return rc;
@@ -716,77 +835,136 @@ int apply(hgt_graph* g, const uint32_t* del, uint64_t n_del, const uint64_t* ins
     g->st.vb = bits_for(g->st.n_vertices ? g->st.n_vertices - 1 : 0);
     if (g->st.hb + 1 + g->st.vb > 64) return HGT_EINVAL;
     Sizes z{n_del, n_ins, n_mem, g->n_inc + n_mem, (g->next_id + 63) / 64 + 1};
-    PlanScratch w{};
-    rc = ensure_plan_scratch(g, z, w);
+    rc = ensure_plan_scratch(g, z, p.w);
     if (rc) return rc;
-    BatchIn b{del, n_del, ins_off, ins_mem, n_mem, ins_ts, n_ins, g->epoch + 1, g->epoch + 2, check_order};
+    p.b = BatchIn{del, n_del, ins_off, ins_mem, n_mem, ins_ts, n_ins, g->epoch + 1, g->epoch + 2, p.check_order};
+    p.n_mem = n_mem;
     g->epoch += 2;
     uint64_t* cnt = g->counts.as<uint64_t>();
-    // planning (reads only)
-    store_batch_begin(g->st.sc, w.sum, s);
+    store_batch_begin(g->st.sc, p.w.sum, s);
     hgt_fill_u64(cnt + CNT_N, 0, ACC_N - CNT_N, s);
     {
         ProfScope ps(g, PK_PLAN, s);
-        store_plan(g->st, b, w, s);
+        store_plan(g->st, p.b, p.w, s);
     }
-    HIP_OK(hipMemcpyAsync(g->h_sum, w.sum, sizeof(BatchSummary), hipMemcpyDeviceToHost, s));
-    HIP_OK(hipMemcpyAsync(g->h_sc, g->st.sc, sizeof(DevScalars), hipMemcpyDeviceToHost, s));
-    HIP_OK(hipStreamSynchronize(s));
-    const BatchSummary sum = *g->h_sum;
-    if (sum.status != HGT_OK) {
-        if (!g->sticky) g->sticky = sum.status;
-        return sum.status;
-    }
-    // capacities for the commit
-    rc = ensure_pool(g->h2v, g->h_bump, sum.h2v_need, s);
+    HIP_OK(hipMemcpyAsync(g->h_sum, p.w.sum, sizeof(BatchSummary), hipMemcpyDeviceToHost, s));
+    return HGT_OK;
+}
+
+// After the synchronisation: the batch's verdict, then capacities for the commit
+// and the incident-vertex pair list.
+int plan_end(Pending& p, hipStream_t s) {
+    hgt_graph* g = p.g;
+    p.sum = *g->h_sum;
+    if (p.sum.status != HGT_OK) return p.sum.status;
+    const BatchSummary& sum = p.sum;
+    int rc = ensure_pool(g->h2v, g->h_bump, sum.h2v_need, s);
     if (!rc && (g->track_mask & (1u << HGT_TRIAD_HYPEREDGE)) && g->hpool.bytes < 2 * g->h2v.bytes)
         rc = grow_keep(g->hpool, 2 * g->h2v.bytes, 2 * g->h_bump * 4, s);
     if (!rc) rc = ensure_pool(g->v2h, g->v_bump, sum.v2h_need, s);
     if (!rc) rc = ensure(g->s_staging, std::max<uint64_t>(sum.stage_words, 1) * 4);
     if (rc) return rc;
     refresh_view(g);
-    w.staging = g->s_staging.as<uint32_t>();
-    const bool do_iv = g->track_mask & (1u << HGT_TRIAD_INCIDENT_VERTEX);
-    IvPlan ip;
-    if (do_iv) {
+    p.w.staging = g->s_staging.as<uint32_t>();
+    if (g->track_mask & (1u << HGT_TRIAD_INCIDENT_VERTEX)) {
         ProfScope ps(g, PK_IV_PREP, s);
-        rc = iv_prepare(g, b, w, sum, ip, s);
+        rc = iv_prepare(g, p.b, p.w, sum, p.ip, s);
         if (rc) return rc;
     }
-    // step 2: deltas on the old graph
-    rc = run_phase(g, del, n_del, g->st.mark_del, b.epoch_del, sum.max_lh_del, sum.sum_lh_del, g->next_id, true,
-                   false, s);
-    if (rc) return rc;
-    if (do_iv && (rc = iv_phase(g, ip, true, s))) return rc;
-    // step 3: delete, then insert
-    {
-        ProfScope ps(g, PK_COMMIT, s);
-        store_commit(g->st, b, w, sum, g->h_bump, g->v_bump, g->next_seq, s);
-    }
-    // algorithmic bytes of the store update: an insert of cardinality d reads its
-    // input (4d + 8) and writes its h2v block (4d) and v2h entries (4d, locating
-    // them reads 4d); a delete reads its h2v block (4d) and rewrites its v2h
-    // entries (8d)
-    if (g->prof) g->store_bytes += 16 * n_mem + 16 * n_ins + 12 * sum.del_members + 8 * n_del;
-    if (out_ids && n_ins) HIP_OK(hipMemcpyAsync(out_ids, w.assigned, n_ins * 4, hipMemcpyDeviceToDevice, s));
-    // step 5: deltas on the new graph
-    rc = run_phase(g, w.assigned, n_ins, g->st.mark_ins, b.epoch_ins, sum.max_lh_ins, sum.sum_lh_ins, sum.next_id_new,
-                   false, check_order == 0, s);
-    if (rc) return rc;
-    if (do_iv && (rc = iv_phase(g, ip, false, s))) return rc;
-    // step 6
-    k_he_tmp_update<<<1, 128, 0, s>>>(cnt);
-    if (do_iv) k_iv_update<<<1, 64, 0, s>>>(cnt, CNT_IV, ACC_IV_M, ACC_IV_P, ACC_T1);
-    HIP_OK(hipGetLastError());
-    // host mirrors
-    g->next_id = sum.next_id_new;
-    g->h_bump += sum.h2v_need;
-    g->v_bump += sum.v2h_need;
-    g->next_seq += n_ins;
-    g->n_live = g->n_live + n_ins - n_del;
-    g->n_inc = g->n_inc + n_mem - sum.del_members;
-    g->batches++;
     return HGT_OK;
+}
+
+PhaseJob job_minus(const Pending& p) {
+    hgt_graph* g = p.g;
+    return PhaseJob{g, p.b.del, p.b.n_del, g->st.mark_del, p.b.epoch_del, p.sum.max_lh_del, p.sum.sum_lh_del,
+                    g->next_id};
+}
+
+PhaseJob job_plus(const Pending& p) {
+    hgt_graph* g = p.g;
+    return PhaseJob{g, p.w.assigned, p.b.n_ins, g->st.mark_ins, p.b.epoch_ins, p.sum.max_lh_ins, p.sum.sum_lh_ins,
+                    p.sum.next_id_new};
+}
+
+// Applies the planned batches of `ps` (all with rc == 0) on stream s: deltas on
+// the old graphs, delete + insert, deltas on the new graphs, count update.  The
+// hyperedge and temporal phases of all graphs share one launch per kernel.
+int apply_planned(hgt_graph* owner, std::vector<Pending*>& ps, hipStream_t s) {
+    std::vector<PhaseJob> jobs;
+    jobs.reserve(ps.size());
+    for (Pending* p : ps) jobs.push_back(job_minus(*p));
+    bool full = !ps.empty() && ps[0]->check_order == 0;
+    // step 2: deltas on the old graph
+    int rc = run_phase(owner, jobs.data(), (uint32_t)jobs.size(), true, false, s);
+    if (rc) return rc;
+    for (Pending* p : ps)
+        if ((p->g->track_mask & (1u << HGT_TRIAD_INCIDENT_VERTEX)) && (rc = iv_phase(p->g, p->ip, true, s)))
+            return rc;
+    // step 3: delete, then insert
+    for (Pending* p : ps) {
+        hgt_graph* g = p->g;
+        {
+            ProfScope sc(g, PK_COMMIT, s);
+            store_commit(g->st, p->b, p->w, p->sum, g->h_bump, g->v_bump, g->next_seq, s);
+        }
+        // algorithmic bytes of the store update: an insert of cardinality d reads its
+        // input (4d + 8) and writes its h2v block (4d) and v2h entries (4d, locating
+        // them reads 4d); a delete reads its h2v block (4d) and rewrites its v2h
+        // entries (8d)
+        if (g->prof) g->store_bytes += 16 * p->n_mem + 16 * p->b.n_ins + 12 * p->sum.del_members + 8 * p->b.n_del;
+        if (p->out_ids && p->b.n_ins)
+            HIP_OK(hipMemcpyAsync(p->out_ids, p->w.assigned, p->b.n_ins * 4, hipMemcpyDeviceToDevice, s));
+    }
+    // step 5: deltas on the new graph
+    jobs.clear();
+    for (Pending* p : ps) jobs.push_back(job_plus(*p));
+    rc = run_phase(owner, jobs.data(), (uint32_t)jobs.size(), false, full, s);
+    if (rc) return rc;
+    for (Pending* p : ps)
+        if ((p->g->track_mask & (1u << HGT_TRIAD_INCIDENT_VERTEX)) && (rc = iv_phase(p->g, p->ip, false, s)))
+            return rc;
+    // step 6
+    for (Pending* p : ps) {
+        hgt_graph* g = p->g;
+        uint64_t* cnt = g->counts.as<uint64_t>();
+        k_he_tmp_update<<<1, 128, 0, s>>>(cnt);
+        if (g->track_mask & (1u << HGT_TRIAD_INCIDENT_VERTEX))
+            k_iv_update<<<1, 64, 0, s>>>(cnt, CNT_IV, ACC_IV_M, ACC_IV_P, ACC_T1);
+        // host mirrors
+        g->next_id = p->sum.next_id_new;
+        g->h_bump += p->sum.h2v_need;
+        g->v_bump += p->sum.v2h_need;
+        g->next_seq += p->b.n_ins;
+        g->n_live = g->n_live + p->b.n_ins - p->b.n_del;
+        g->n_inc = g->n_inc + p->n_mem - p->sum.del_members;
+        g->batches++;
+    }
+    HIP_OK(hipGetLastError());
+    return HGT_OK;
+}
+
+void set_sticky(hgt_graph* g, int rc) {
+    if (rc && !g->sticky) g->sticky = rc;
+}
+
+// One batch.  check_order = 0 only for the build batch.
+int apply(hgt_graph* g, const uint32_t* del, uint64_t n_del, const uint64_t* ins_off, const uint32_t* ins_mem,
+          uint64_t n_mem, const int64_t* ins_ts, uint64_t n_ins, uint32_t* out_ids, hipStream_t s, int check_order) {
+    Pending p;
+    p.g = g;
+    p.out_ids = out_ids;
+    p.check_order = check_order;
+    int rc = plan_begin(p, del, n_del, ins_off, ins_mem, n_mem, ins_ts, n_ins, s);
+    if (rc == HGT_ENOENT) set_sticky(g, rc);
+    if (rc) return rc;
+    HIP_OK(hipStreamSynchronize(s));
+    rc = plan_end(p, s);
+    if (rc) {
+        set_sticky(g, rc);
+        return rc;
+    }
+    std::vector<Pending*> ps{&p};
+    return apply_planned(g, ps, s);
 }
 
 void destroy_graph(hgt_graph* g) {
@@ -796,13 +974,11 @@ void destroy_graph(hgt_graph* g) {
                      &g->s_sum, &g->s_del_bm, &g->s_del_card, &g->s_del_poff, &g->s_ins_rel, &g->s_ins_card,
                      &g->s_canon, &g->s_big, &g->s_small, &g->s_popc, &g->s_scan, &g->s_assigned, &g->s_h_need,
                      &g->s_h_rel, &g->s_keys, &g->s_keys_alt, &g->s_sort, &g->s_head, &g->s_is_ins, &g->s_tv,
-                     &g->s_tseg, &g->s_D, &g->s_I, &g->s_It, &g->s_vp, &g->s_staging, &g->s_dst, &g->t_ctr,
-                     &g->t_big_list, &g->t_big_rank, &g->t_big_scratch, &g->t_list1, &g->t_rank1, &g->t_list2, &g->t_rank2, &g->t_garena, &g->iv_keys, &g->iv_alt, &g->iv_sort,
+                     &g->s_tseg, &g->s_D, &g->s_I, &g->s_It, &g->s_vp, &g->s_staging, &g->s_dst, &g->iv_keys, &g->iv_alt, &g->iv_sort,
                      &g->iv_head, &g->iv_uniq, &g->iv_p2, &g->iv_scan, &g->iv_tab, &g->iv_owner, &g->iv_ctr,
-                     &g->iv_list, &g->iv_garena, &g->hpool, &g->ent_x, &g->ent_d,
-                     &g->ent_pay, &g->bl_cnt, &g->bl_off, &g->bl_cur, &g->bl_d, &g->bl_pay, &g->nb_scratch,
-                     &g->bl_scan};
+                     &g->iv_list, &g->iv_garena, &g->hpool};
     for (DevBuf* b : all) dev_free(*b);
+    phase_ctx_free(g->ph);
     dev_free(g->stats);
     for (hipEvent_t e : g->ev_pool) (void)hipEventDestroy(e);
     if (g->h_sum) (void)hipHostFree(g->h_sum);
@@ -941,6 +1117,54 @@ int hgt_apply_batch(hgt_graph* g, const uint32_t* del_ids, uint64_t n_del, const
     return rc;
 }
 
+int hgt_apply_batches(hgt_batch* bs, uint32_t n, void* stream) {
+    if (n == 0) return HGT_OK;
+    if (!bs) return HGT_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    {
+        std::vector<hgt_graph*> gs;
+        for (uint32_t i = 0; i < n; i++) {
+            if (!bs[i].graph) return HGT_EINVAL;
+            gs.push_back(bs[i].graph);
+        }
+        std::sort(gs.begin(), gs.end());
+        if (std::adjacent_find(gs.begin(), gs.end()) != gs.end()) return HGT_EINVAL;
+    }
+    std::vector<Pending> P(n);
+    bool any = false;
+    for (uint32_t i = 0; i < n; i++) {
+        hgt_batch& b = bs[i];
+        b.status = HGT_OK;
+        P[i].g = b.graph;
+        P[i].out_ids = b.out_ins_ids;
+        P[i].rc = 1;  // nothing to apply
+        if (b.n_del == 0 && b.n_ins == 0) continue;
+        P[i].rc = plan_begin(P[i], b.del_ids, b.n_del, b.ins_offsets, b.ins_members, b.n_ins_members, b.ins_ts,
+                             b.n_ins, s);
+        if (P[i].rc == HGT_OK) any = true;
+    }
+    if (any) HIP_OK(hipStreamSynchronize(s));
+    std::vector<Pending*> act;
+    for (uint32_t i = 0; i < n; i++) {
+        if (P[i].rc != HGT_OK) continue;
+        P[i].rc = plan_end(P[i], s);
+        if (P[i].rc == HGT_OK) act.push_back(&P[i]);
+    }
+    if (!act.empty()) {
+        int rc = apply_planned(act[0]->g, act, s);
+        if (rc)
+            for (Pending* p : act) p->rc = rc;
+    }
+    int first = HGT_OK;
+    for (uint32_t i = 0; i < n; i++) {
+        int rc = P[i].rc == 1 ? HGT_OK : P[i].rc;
+        bs[i].status = rc;
+        set_sticky(bs[i].graph, rc);
+        if (rc && first == HGT_OK) first = rc;
+    }
+    return first;
+}
+
 int hgt_sync(hgt_graph* g, int* status) {
     if (!g) return HGT_EINVAL;
     if (hipStreamSynchronize(g->last_stream) != hipSuccess) {
@@ -1021,11 +1245,13 @@ int hgt_profile_read(hgt_graph* g, hgt_kernel_time* out, uint32_t n_max, uint32_
         rows[r.kind].launches++;
         rows[r.kind].total_ms += ms;
     }
-    rows[PK_DELTA_SMALL].algo_bytes = st[ST_BYTES_SMALL];
     rows[PK_DELTA_BIG].algo_bytes = st[ST_BYTES_BIG];
     rows[PK_IV_PAIRS].algo_bytes = st[ST_IV_BYTES];
     rows[PK_COMMIT].algo_bytes = g->store_bytes;
     rows[PK_DELTA_BIG].events = st[ST_DEFER0 + 2];
+    rows[PK_DELTA_SMALL].algo_bytes = st[ST_HEB0];
+    rows[PK_DELTA_MED].algo_bytes = st[ST_HEB0 + 1];
+    rows[PK_DELTA_GLOBAL].algo_bytes = st[ST_HEB0 + 2];
     rows[PK_DELTA_SMALL].events = st[ST_DEFER0];
     rows[PK_DELTA_SMALL].aux = st[ST_DEFER0 + 1];
     uint32_t n = std::min<uint32_t>(n_max, PK_N);

@@ -8,23 +8,54 @@ struct BigLayout {
     uint64_t nh_keys, nh_vals, hm, nl_x, nl_meta, warea, warea_words, words_per_wg;
 };
 
-struct TriadParams {
+// Per-graph inputs of one phase of the hyperedge/temporal kernels.  The
+// kernels take an array of these, so one launch serves one graph or many.
+struct HeGraph {
     GraphView g;
     const uint32_t* centres;  // changed hyperedge IDs; the index is the batch rank
     uint64_t n_centres;
     const uint64_t* mark;     // epoch-tagged batch rank per ID of this phase
     uint32_t epoch;
-    int do_he, do_tmp;
+    uint32_t pad0;
     int64_t window;
+    const int32_t* status;    // the graph's batch status: work is skipped unless 0
     uint64_t* out_he;         // u64[30] phase accumulators
     uint64_t* out_tmp;        // u64[96]
+    uint32_t* hpool;          // neighbour histograms, 2 words per h2v word
+    uint64_t id_base;         // first slot of this graph's IDs in the shared per-ID arrays
+};
+
+// The graphs of one launch: work item q belongs to the graph g with
+// base[g] <= q < base[g+1] and is that graph's centre q - base[g].
+struct Multi {
+    const HeGraph* graphs;
+    const uint64_t* base;     // n_graphs + 1 entries
+    const uint64_t* id_base;  // n_graphs + 1 entries: graph g owns slots [id_base[g], id_base[g+1])
+    uint32_t n_graphs;
+    uint32_t pad0;
+    uint64_t total;           // base[n_graphs]
+    uint64_t total_ids;       // id_base[n_graphs]
+};
+
+__device__ __forceinline__ uint32_t multi_graph_of(const Multi& M, uint64_t q) {
+    return M.n_graphs == 1 ? 0u : seg_of<uint64_t>(M.base, M.n_graphs, q);
+}
+__device__ __forceinline__ uint32_t multi_graph_of_id(const Multi& M, uint64_t slot) {
+    return M.n_graphs == 1 ? 0u : seg_of<uint64_t>(M.id_base, M.n_graphs, slot);
+}
+
+// Deferred work items name their graph: graph << 32 | hyperedge ID.
+__device__ __forceinline__ uint64_t item_of(uint32_t g, uint32_t h) { return ((uint64_t)g << 32) | h; }
+
+struct TriadParams {
+    Multi M;
+    int do_he, do_tmp;
     const uint8_t* he_tab;    // [128] class index of a Venn code (255 = not a triad)
     const uint8_t* tmp_tab;   // [128]
-    const int32_t* status;
     uint32_t* queue;          // work counters, cleared by the launcher
     uint32_t* big_queue;
     uint32_t* big_count;
-    uint32_t* big_list;       // centres deferred to the large kernel (capacity n_centres)
+    uint64_t* big_list;       // items deferred to the large kernel (capacity: all centres)
     uint32_t* big_rank;
     uint32_t* big_scratch;    // grid_big * big.words_per_wg words
     BigLayout big;
@@ -41,7 +72,8 @@ enum TriadStat {
     ST_EXPANDED = 4,     // neighbours expanded
     ST_IV_BYTES = 5,     // algorithmic bytes gathered by the incident-vertex kernel
     ST_DEFER0 = 6,       // centres moved on by histogram-kernel stage 0, 1, 2
-    ST_N = 12
+    ST_HEB0 = 9,         // algorithmic bytes gathered by histogram-kernel stage 0, 1, 2
+    ST_N = 16
 };
 
 BigLayout triad_big_layout(uint64_t max_lh, uint64_t max_card);
@@ -51,46 +83,33 @@ void triad_he_launch_big(TriadParams& P, unsigned grid, hipStream_t s);
 
 // hyperedge family through neighbour histograms (triad_he2.hip)
 struct NbrParams {
-    GraphView g;
-    const uint32_t* centres;
-    uint64_t n_centres;
+    Multi M;
     int inserting;               // 1: rebuild the centres' histograms and add them to their neighbours'
-    const uint64_t* mark_self;   // this phase's marks: neighbours that are centres too get no increment
-    uint32_t epoch;
-    uint32_t* hpool;             // histograms, 2 words per h2v word
-    uint64_t* n_entries;         // batch-neighbour entries written
+    int emit_entries;            // 0: histograms only (build)
+    uint64_t* n_entries;         // batch-neighbour entries written (all graphs)
     uint64_t entries_cap;
-    uint32_t* ent_x;
+    uint32_t* ent_x;             // id_base + x
     uint32_t* ent_d;
     uint64_t* ent_pay;           // rank << 32 | k << 1 | [|d| > k]
     uint32_t* queue;             // queue, big_queue, big_count (consecutive)
     uint32_t* big_queue;
     uint32_t* big_count;
-    uint32_t* big_list;
+    uint64_t* big_list;
     uint32_t* big_rank;
     uint32_t* big_scratch;
     uint64_t big_words;
-    const int32_t* status;
-    int emit_entries;            // 0: histograms only (build)
 };
 
 struct He2Params {
-    GraphView g;
-    const uint32_t* centres;
-    uint64_t n_centres;
-    const uint64_t* mark;
-    uint32_t epoch;
-    const uint32_t* hpool;
-    const uint64_t* bl_off;      // per ID: batch-neighbour list of x
+    Multi M;
+    const uint8_t* he_tab;
+    const uint64_t* bl_off;      // per ID slot: batch-neighbour list of x
     const uint64_t* bl_cnt;
     const uint32_t* bl_d;
     const uint64_t* bl_pay;
-    uint64_t* out_he;
-    const uint8_t* he_tab;
-    const int32_t* status;
     uint32_t* queue;             // per stage (3 consecutive counters)
-    uint32_t* count;             // centres moved on by each stage (3 consecutive)
-    uint32_t* list[3];           // list[s]: centres stage s could not fit; list[2] feeds
+    uint32_t* count;             // items moved on by each stage (3 consecutive)
+    uint64_t* list[3];           // list[s]: items stage s could not fit; list[2] feeds
     uint32_t* rank[3];           // the 2-hop kernel (k_delta_big)
     uint32_t* garena;            // stage-2 tables: garena_words per workgroup
     uint64_t garena_words;
@@ -102,9 +121,11 @@ struct He2Params {
 };
 
 void he2_nbr_launch(NbrParams& P, unsigned grid_small, unsigned grid_big, hipStream_t s);
-void he2_lists_build(NbrParams& P, uint64_t n_ids, uint64_t* bl_cnt, uint64_t* bl_off, uint64_t* bl_cur,
-                     uint32_t* bl_d, uint64_t* bl_pay, void* scan_tmp, hipStream_t s);
-void he2_remove_deleted(NbrParams& P, const uint64_t* mark_del, uint32_t epoch_del, hipStream_t s);
+// per-ID batch-neighbour lists over all graphs of P.M (M.total_ids slots)
+void he2_lists_build(NbrParams& P, uint64_t* bl_cnt, uint64_t* bl_off, uint64_t* bl_cur, uint32_t* bl_d,
+                     uint64_t* bl_pay, void* scan_tmp, hipStream_t s);
+// after the deletion phase: take the deleted hyperedges out of their neighbours' histograms
+void he2_remove_deleted(NbrParams& P, hipStream_t s);
 void he2_launch_stage(He2Params& P, int stage, unsigned grid, hipStream_t s);
 
 // incident-vertex family

@@ -60,6 +60,7 @@ struct WgStore {
 
 struct Shared {
     uint32_t h, rank, hlen, lh, K, Kt, defer, stop;
+    uint32_t gi, cur_g, skip;
     uint64_t hoff;
     int64_t th;
     uint64_t sh;
@@ -68,7 +69,8 @@ struct Shared {
 };
 
 // classify the intersecting pair (x, y) found in x's 2-hop lists
-__device__ __forceinline__ void classify(const TriadParams& P, const Tables& T, const WgStore& S, const Shared& sh,
+__device__ __forceinline__ void classify(const TriadParams& P, const HeGraph& G, const Tables& T, const WgStore& S,
+                                         const Shared& sh,
                                          uint32_t nh_log, uint32_t x, uint32_t meta_x, int64_t tx, uint64_t sx,
                                          uint32_t y, uint32_t cxy, uint32_t chxy, uint64_t* acc_he, uint64_t* acc_tmp) {
     const int nh = (int)sh.hlen;
@@ -93,9 +95,9 @@ __device__ __forceinline__ void classify(const TriadParams& P, const Tables& T, 
             }
         }
         if (P.do_tmp && meta_win(meta_x) && meta_win(my)) {
-            int64_t ty = P.g.h_ts[y];
-            if (within(sh.th, tx, ty, P.window)) {
-                uint64_t sy = P.g.h_seq[y];
+            int64_t ty = G.g.h_ts[y];
+            if (within(sh.th, tx, ty, G.window)) {
+                uint64_t sy = G.g.h_seq[y];
                 int ct = T.tmp[time_code(sh.th, sh.sh, tx, sx, ty, sy, nh, nx, ny, hx, (int)cxy, hy, (int)chxy)];
                 int cf = T.tmp[time_code(sh.th, sh.sh, tx, sx, ty, sy, nh, nx, ny, hx, 0, hy, 0)];
                 if (ct != cf) {
@@ -108,38 +110,39 @@ __device__ __forceinline__ void classify(const TriadParams& P, const Tables& T, 
     }
     // (ii) path h - x - y with y outside the closed neighbourhood of h (its centre is x)
     if (P.static_he) return;
-    if (lower_ranked_member(P.mark[y], P.epoch, sh.rank)) return;
+    if (lower_ranked_member(G.mark[y], G.epoch, sh.rank)) return;
     int64_t ty = 0;
     if (P.do_tmp) {
-        ty = P.g.h_ts[y];
-        if (!P.do_he && !within(sh.th, tx, ty, P.window)) return;
+        ty = G.g.h_ts[y];
+        if (!P.do_he && !within(sh.th, tx, ty, G.window)) return;
     }
-    const int ny = (int)P.g.h_len[y];
+    const int ny = (int)G.g.h_len[y];
     if (P.do_he) acc_add(acc_he, T.he[venn_code(nh, nx, ny, hx, (int)cxy, 0, 0)], 1);
-    if (P.do_tmp && meta_win(meta_x) && within(sh.th, tx, ty, P.window)) {
-        uint64_t sy = P.g.h_seq[y];
+    if (P.do_tmp && meta_win(meta_x) && within(sh.th, tx, ty, G.window)) {
+        uint64_t sy = G.g.h_seq[y];
         acc_add(acc_tmp, T.tmp[time_code(sh.th, sh.sh, tx, sx, ty, sy, nh, nx, ny, hx, (int)cxy, 0, 0)], 1);
     }
 }
 
 // Expand neighbour x of the current centre (one wave).
-__device__ void expand_x(const TriadParams& P, const Tables& T, const WgStore& S, const Shared& sh, uint32_t nh_log,
+__device__ void expand_x(const TriadParams& P, const HeGraph& G, const Tables& T, const WgStore& S, const Shared& sh,
+                         uint32_t nh_log,
                          WaveMem& wm, uint32_t* wkeys, uint32_t* wvals, uint32_t x, uint32_t meta_x, uint64_t* acc_he,
                          uint64_t* acc_tmp, uint64_t* acc_st) {
     const int lane = threadIdx.x & 63;
     const uint32_t nx = meta_len(meta_x);
-    const uint64_t xoff = P.g.h_off[x];
+    const uint64_t xoff = G.g.h_off[x];
     int64_t tx = 0;
     uint64_t sx = 0;
     if (P.do_tmp) {
-        tx = P.g.h_ts[x];
-        sx = P.g.h_seq[x];
+        tx = G.g.h_ts[x];
+        sx = G.g.h_seq[x];
     }
     // total 2-hop length
     uint32_t lx = 0;
     for (uint32_t b = 0; b < nx; b += CHUNK) {
         uint32_t d = 0;
-        if (b + lane < nx) d = P.g.v_len[P.g.h2v[xoff + b + lane]];
+        if (b + lane < nx) d = G.g.v_len[G.g.h2v[xoff + b + lane]];
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) d += __shfl_xor(d, o, 64);
         lx += d;
@@ -158,9 +161,9 @@ __device__ void expand_x(const TriadParams& P, const Tables& T, const WgStore& S
             uint32_t cnt = nx - b < CHUNK ? nx - b : CHUNK;
             uint32_t d = 0;
             if ((uint32_t)lane < cnt) {
-                uint32_t m = P.g.h2v[xoff + b + lane];
-                d = P.g.v_len[m];
-                wm.voff[lane] = P.g.v_off[m];
+                uint32_t m = G.g.h2v[xoff + b + lane];
+                d = G.g.v_len[m];
+                wm.voff[lane] = G.g.v_off[m];
                 wm.inh[lane] = contains_u32(S.hm, sh.hlen, m) ? 1u : 0u;
             }
             uint32_t inc = d;
@@ -175,7 +178,7 @@ __device__ void expand_x(const TriadParams& P, const Tables& T, const WgStore& S
             uint32_t len = wm.pre[cnt];
             for (uint32_t p = lane; p < len; p += 64) {
                 uint32_t k = seg_of<uint32_t>(wm.pre, cnt, p);
-                uint32_t y = P.g.v2h[wm.voff[k] + (p - wm.pre[k])];
+                uint32_t y = G.g.v2h[wm.voff[k] + (p - wm.pre[k])];
                 if (y != x && y != sh.h) hash_add(wkeys, wvals, log_cap, y, 1u + (wm.inh[k] << 16));
             }
             wave_sync();
@@ -184,7 +187,7 @@ __device__ void expand_x(const TriadParams& P, const Tables& T, const WgStore& S
             uint32_t y = wkeys[s];
             if (y != HGT_EMPTY) {
                 uint32_t v = wvals[s];
-                classify(P, T, S, sh, nh_log, x, meta_x, tx, sx, y, v & 0xffffu, v >> 16, acc_he, acc_tmp);
+                classify(P, G, T, S, sh, nh_log, x, meta_x, tx, sx, y, v & 0xffffu, v >> 16, acc_he, acc_tmp);
             }
         }
         wave_sync();
@@ -196,9 +199,9 @@ __device__ void expand_x(const TriadParams& P, const Tables& T, const WgStore& S
         uint32_t cnt = nx - b < CHUNK ? nx - b : CHUNK;
         uint32_t d = 0;
         if ((uint32_t)lane < cnt) {
-            uint32_t m = P.g.h2v[xoff + b + lane];
-            d = P.g.v_len[m];
-            wm.voff[lane] = P.g.v_off[m];
+            uint32_t m = G.g.h2v[xoff + b + lane];
+            d = G.g.v_len[m];
+            wm.voff[lane] = G.g.v_off[m];
             wm.inh[lane] = contains_u32(S.hm, sh.hlen, m) ? 1u : 0u;
         }
         uint32_t inc = d;
@@ -213,25 +216,41 @@ __device__ void expand_x(const TriadParams& P, const Tables& T, const WgStore& S
         uint32_t len = wm.pre[cnt];
         for (uint32_t p = lane; p < len; p += 64) {
             uint32_t k = seg_of<uint32_t>(wm.pre, cnt, p);
-            uint32_t y = P.g.v2h[wm.voff[k] + (p - wm.pre[k])];
+            uint32_t y = G.g.v2h[wm.voff[k] + (p - wm.pre[k])];
             if (y == x || y == sh.h) continue;
             uint32_t kg = b + k;
             bool first = true;
             uint32_t c = 1, ch = wm.inh[k];
             for (uint32_t j = 0; j < nx; j++) {
                 if (j == kg) continue;
-                uint32_t mj = P.g.h2v[xoff + j];
-                const uint32_t* lst = P.g.v2h + P.g.v_off[mj];
-                if (contains_u32(lst, P.g.v_len[mj], y)) {
+                uint32_t mj = G.g.h2v[xoff + j];
+                const uint32_t* lst = G.g.v2h + G.g.v_off[mj];
+                if (contains_u32(lst, G.g.v_len[mj], y)) {
                     if (j < kg) { first = false; break; }
                     c++;
                     ch += contains_u32(S.hm, sh.hlen, mj) ? 1u : 0u;
                 }
             }
-            if (first) classify(P, T, S, sh, nh_log, x, meta_x, tx, sx, y, c, ch, acc_he, acc_tmp);
+            if (first) classify(P, G, T, S, sh, nh_log, x, meta_x, tx, sx, y, c, ch, acc_he, acc_tmp);
         }
         wave_sync();
     }
+}
+
+// Adds the workgroup's counts to graph g's phase accumulators and clears them.
+__device__ void flush_counts(const TriadParams& P, uint32_t g, uint64_t* acc_he, uint64_t* acc_tmp) {
+    __syncthreads();
+    if (g != 0xffffffffu) {
+        const HeGraph& G = P.M.graphs[g];
+        for (int i = threadIdx.x; i < HGT_N_HE_CLASSES; i += HGT_WG)
+            if (acc_he[i]) atomicAdd((unsigned long long*)&G.out_he[i], (unsigned long long)acc_he[i]);
+        for (int i = threadIdx.x; i < HGT_N_TEMPORAL_CLASSES; i += HGT_WG)
+            if (acc_tmp[i]) atomicAdd((unsigned long long*)&G.out_tmp[i], (unsigned long long)acc_tmp[i]);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < HGT_N_HE_CLASSES; i += HGT_WG) acc_he[i] = 0;
+    for (int i = threadIdx.x; i < HGT_N_TEMPORAL_CLASSES; i += HGT_WG) acc_tmp[i] = 0;
+    __syncthreads();
 }
 
 // The whole per-centre computation; BIG selects global tables and no deferral.
@@ -239,31 +258,53 @@ template <bool BIG>
 __device__ void run_centres(const TriadParams& P, const Tables& T, const WgStore& S, Shared& sh, WaveMem* wmem,
                             uint64_t* acc_he, uint64_t* acc_tmp, uint64_t* acc_st, uint32_t lh_limit, uint32_t hm_cap) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const uint32_t* list = BIG ? P.big_list : P.centres;
     for (;;) {
         if (tid == 0) {
-            uint64_t n = BIG ? (uint64_t)*P.big_count : P.n_centres;
+            uint64_t n = BIG ? (uint64_t)*P.big_count : P.M.total;
             uint32_t c = atomicAdd(BIG ? P.big_queue : P.queue, 1u);
             sh.stop = c >= n;
             if (!sh.stop) {
-                uint32_t h = list[c];
+                uint32_t gi, h, rank;
+                if (BIG) {
+                    uint64_t it = P.big_list[c];
+                    gi = (uint32_t)(it >> 32);
+                    h = (uint32_t)it;
+                    rank = P.big_rank[c];
+                } else {
+                    gi = multi_graph_of(P.M, c);
+                    rank = (uint32_t)(c - P.M.base[gi]);
+                    h = P.M.graphs[gi].centres[rank];
+                }
+                const HeGraph& Gq = P.M.graphs[gi];
+                sh.gi = gi;
                 sh.h = h;
-                sh.rank = BIG ? P.big_rank[c] : c;
-                sh.hlen = P.g.h_len[h];
-                sh.hoff = P.g.h_off[h];
+                sh.rank = rank;
+                sh.skip = *((volatile const int32_t*)Gq.status) != 0;
+                sh.hlen = Gq.g.h_len[h];
+                sh.hoff = Gq.g.h_off[h];
                 if (P.do_tmp) {
-                    sh.th = P.g.h_ts[h];
-                    sh.sh = P.g.h_seq[h];
+                    sh.th = Gq.g.h_ts[h];
+                    sh.sh = Gq.g.h_seq[h];
                 }
                 sh.defer = (!BIG && sh.hlen > hm_cap) ? 1u : 0u;
             }
         }
         __syncthreads();
         if (sh.stop) break;
+        if (sh.gi != sh.cur_g) {  // results so far belong to the previous graph
+            flush_counts(P, sh.cur_g, acc_he, acc_tmp);
+            if (tid == 0) sh.cur_g = sh.gi;
+            __syncthreads();
+        }
+        if (sh.skip) {
+            __syncthreads();
+            continue;
+        }
+        const HeGraph& G = P.M.graphs[sh.gi];
         if (sh.defer) {
             if (tid == 0) {
                 uint32_t q = atomicAdd(P.big_count, 1u);
-                P.big_list[q] = sh.h;
+                P.big_list[q] = item_of(sh.gi, sh.h);
                 P.big_rank[q] = sh.rank;
                 if (P.stats) atomicAdd((unsigned long long*)&acc_st[1], 1ull);
             }
@@ -278,10 +319,10 @@ __device__ void run_centres(const TriadParams& P, const Tables& T, const WgStore
         for (uint32_t b = 0; b < hlen; b += HGT_WG) {
             uint32_t i = b + tid, d = 0;
             if (i < hlen) {
-                uint32_t m = P.g.h2v[sh.hoff + i];
+                uint32_t m = G.g.h2v[sh.hoff + i];
                 S.hm[i] = m;
-                d = P.g.v_len[m];
-                voff[i] = P.g.v_off[m];
+                d = G.g.v_len[m];
+                voff[i] = G.g.v_off[m];
             }
             uint32_t tot;
             uint32_t ex = wg_scan_u32(d, sh.ws, &tot);
@@ -297,7 +338,7 @@ __device__ void run_centres(const TriadParams& P, const Tables& T, const WgStore
         if (sh.defer) {
             if (tid == 0) {
                 uint32_t q = atomicAdd(P.big_count, 1u);
-                P.big_list[q] = h;
+                P.big_list[q] = item_of(sh.gi, h);
                 P.big_rank[q] = sh.rank;
                 if (P.stats) atomicAdd((unsigned long long*)&acc_st[1], 1ull);
             }
@@ -314,7 +355,7 @@ __device__ void run_centres(const TriadParams& P, const Tables& T, const WgStore
         // 1. N(h) with c_x
         for (uint32_t p = tid; p < lh; p += HGT_WG) {
             uint32_t k = seg_of<uint32_t>(pre, hlen, p);
-            uint32_t x = P.g.v2h[voff[k] + (p - pre[k])];
+            uint32_t x = G.g.v2h[voff[k] + (p - pre[k])];
             if (x != h) hash_add(S.nh_keys, S.nh_vals, nh_log, x, 1u);
         }
         __syncthreads();
@@ -323,12 +364,12 @@ __device__ void run_centres(const TriadParams& P, const Tables& T, const WgStore
             uint32_t x = S.nh_keys[s];
             if (x == HGT_EMPTY) continue;
             uint32_t c = S.nh_vals[s];
-            uint32_t len = P.g.h_len[x];
-            bool elig = P.static_he || !lower_ranked_member(P.mark[x], P.epoch, sh.rank);
+            uint32_t len = G.g.h_len[x];
+            bool elig = P.static_he || !lower_ranked_member(G.mark[x], G.epoch, sh.rank);
             bool win = true;
             if (P.do_tmp) {
-                int64_t d = P.g.h_ts[x] - sh.th;
-                win = d <= P.window && -d <= P.window;
+                int64_t d = G.g.h_ts[x] - sh.th;
+                win = d <= G.window && -d <= G.window;
             }
             uint32_t meta = c | (len << 14) | ((uint32_t)elig << 28) | ((uint32_t)win << 29);
             S.nh_vals[s] = meta;
@@ -408,7 +449,7 @@ __device__ void run_centres(const TriadParams& P, const Tables& T, const WgStore
                 if (!meta_elig(m) || !meta_win(m)) continue;
                 uint32_t q = atomicAdd(&sh.Kt, 1u);
                 uint32_t x = S.nl_x[i];
-                int64_t t = P.g.h_ts[x];
+                int64_t t = G.g.h_ts[x];
                 tl[4 * q] = x;
                 tl[4 * q + 1] = m;
                 tl[4 * q + 2] = (uint32_t)(uint64_t)t;
@@ -425,9 +466,9 @@ __device__ void run_centres(const TriadParams& P, const Tables& T, const WgStore
                 uint32_t j = (uint32_t)(q - (uint64_t)i * (2ull * Kt - i - 1) / 2) + i + 1;
                 int64_t ti = (int64_t)((uint64_t)tl[4 * i + 2] | ((uint64_t)tl[4 * i + 3] << 32));
                 int64_t tj = (int64_t)((uint64_t)tl[4 * j + 2] | ((uint64_t)tl[4 * j + 3] << 32));
-                if (!within(sh.th, ti, tj, P.window)) continue;
+                if (!within(sh.th, ti, tj, G.window)) continue;
                 uint32_t mi = tl[4 * i + 1], mj = tl[4 * j + 1];
-                uint64_t si = P.g.h_seq[tl[4 * i]], sj = P.g.h_seq[tl[4 * j]];
+                uint64_t si = G.g.h_seq[tl[4 * i]], sj = G.g.h_seq[tl[4 * j]];
                 int code = time_code(sh.th, sh.sh, ti, si, tj, sj, (int)hlen, (int)meta_len(mi), (int)meta_len(mj),
                                      (int)meta_c(mi), 0, (int)meta_c(mj), 0);
                 acc_add(acc_tmp, T.tmp[code], 1);
@@ -442,7 +483,7 @@ __device__ void run_centres(const TriadParams& P, const Tables& T, const WgStore
             uint32_t m = S.nl_meta[i];
             if (!meta_elig(m)) continue;
             if (!P.do_he && !meta_win(m)) continue;
-            expand_x(P, T, S, sh, nh_log, wmem[wave], wk, wv, x, m, acc_he, acc_tmp, acc_st);
+            expand_x(P, G, T, S, sh, nh_log, wmem[wave], wk, wv, x, m, acc_he, acc_tmp, acc_st);
         }
         __syncthreads();
         (void)lane;
@@ -457,19 +498,15 @@ __global__ void __launch_bounds__(HGT_WG) k_delta_small(TriadParams P) {
     __shared__ Shared sh;
     __shared__ Tables T;
     __shared__ uint64_t acc_he[HGT_N_HE_CLASSES], acc_tmp[HGT_N_TEMPORAL_CLASSES], acc_st[4];
-    if (*((volatile const int32_t*)P.status) != 0) return;
     for (int i = threadIdx.x; i < 128; i += HGT_WG) { T.he[i] = P.he_tab[i]; T.tmp[i] = P.tmp_tab[i]; }
+    if (threadIdx.x == 0) sh.cur_g = 0xffffffffu;
     if (threadIdx.x < 4) acc_st[threadIdx.x] = 0;
     for (int i = threadIdx.x; i < HGT_N_HE_CLASSES; i += HGT_WG) acc_he[i] = 0;
     for (int i = threadIdx.x; i < HGT_N_TEMPORAL_CLASSES; i += HGT_WG) acc_tmp[i] = 0;
     __syncthreads();
     WgStore S{nh_keys, nh_vals, hm, nl_x, nl_meta, warea, S_WAREA, warea};
     run_centres<false>(P, T, S, sh, wmem, acc_he, acc_tmp, acc_st, S_LH, S_LH);
-    __syncthreads();
-    for (int i = threadIdx.x; i < HGT_N_HE_CLASSES; i += HGT_WG)
-        if (acc_he[i]) atomicAdd((unsigned long long*)&P.out_he[i], (unsigned long long)acc_he[i]);
-    for (int i = threadIdx.x; i < HGT_N_TEMPORAL_CLASSES; i += HGT_WG)
-        if (acc_tmp[i]) atomicAdd((unsigned long long*)&P.out_tmp[i], (unsigned long long)acc_tmp[i]);
+    flush_counts(P, sh.cur_g, acc_he, acc_tmp);
     if (P.stats && threadIdx.x == 0) {
         atomicAdd((unsigned long long*)&P.stats[ST_BYTES_SMALL], (unsigned long long)acc_st[0]);
         atomicAdd((unsigned long long*)&P.stats[ST_DEFERRED], (unsigned long long)acc_st[1]);
@@ -484,8 +521,8 @@ __global__ void __launch_bounds__(HGT_WG) k_delta_big(TriadParams P) {
     __shared__ Shared sh;
     __shared__ Tables T;
     __shared__ uint64_t acc_he[HGT_N_HE_CLASSES], acc_tmp[HGT_N_TEMPORAL_CLASSES], acc_st[4];
-    if (*((volatile const int32_t*)P.status) != 0) return;
     for (int i = threadIdx.x; i < 128; i += HGT_WG) { T.he[i] = P.he_tab[i]; T.tmp[i] = P.tmp_tab[i]; }
+    if (threadIdx.x == 0) sh.cur_g = 0xffffffffu;
     if (threadIdx.x < 4) acc_st[threadIdx.x] = 0;
     for (int i = threadIdx.x; i < HGT_N_HE_CLASSES; i += HGT_WG) acc_he[i] = 0;
     for (int i = threadIdx.x; i < HGT_N_TEMPORAL_CLASSES; i += HGT_WG) acc_tmp[i] = 0;
@@ -495,11 +532,7 @@ __global__ void __launch_bounds__(HGT_WG) k_delta_big(TriadParams P) {
     WgStore S{base + L.nh_keys, base + L.nh_vals, base + L.hm, base + L.nl_x, base + L.nl_meta, base + L.warea,
               L.warea_words, wh};
     run_centres<true>(P, T, S, sh, wmem, acc_he, acc_tmp, acc_st, 0xffffffffu, 0xffffffffu);
-    __syncthreads();
-    for (int i = threadIdx.x; i < HGT_N_HE_CLASSES; i += HGT_WG)
-        if (acc_he[i]) atomicAdd((unsigned long long*)&P.out_he[i], (unsigned long long)acc_he[i]);
-    for (int i = threadIdx.x; i < HGT_N_TEMPORAL_CLASSES; i += HGT_WG)
-        if (acc_tmp[i]) atomicAdd((unsigned long long*)&P.out_tmp[i], (unsigned long long)acc_tmp[i]);
+    flush_counts(P, sh.cur_g, acc_he, acc_tmp);
     if (P.stats && threadIdx.x == 0) {
         atomicAdd((unsigned long long*)&P.stats[ST_BYTES_BIG], (unsigned long long)acc_st[0]);
         atomicAdd((unsigned long long*)&P.stats[ST_DEFERRED], (unsigned long long)acc_st[1]);
@@ -536,9 +569,9 @@ void triad_he_prepare(TriadParams& P, hipStream_t s) {
 }
 
 void triad_he_launch_small(TriadParams& P, unsigned grid, hipStream_t s) {
-    if (P.n_centres) k_delta_small<<<grid, HGT_WG, 0, s>>>(P);
+    if (P.M.total) k_delta_small<<<grid, HGT_WG, 0, s>>>(P);
 }
 
 void triad_he_launch_big(TriadParams& P, unsigned grid, hipStream_t s) {
-    if (P.n_centres) k_delta_big<<<grid, HGT_WG, 0, s>>>(P);
+    if (P.M.total) k_delta_big<<<grid, HGT_WG, 0, s>>>(P);
 }

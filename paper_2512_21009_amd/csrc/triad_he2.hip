@@ -92,6 +92,7 @@ __device__ __forceinline__ void sort_keys(uint64_t* k, uint32_t n) {
 
 struct Sh2 {
     uint32_t h, rank, hlen, lh, K, W, defer, stop;
+    uint32_t gi, cur_g, skip;
     uint64_t hoff;
     uint32_t ncap;
     uint32_t o_nh, o_ent;  // arena word offsets
@@ -148,27 +149,45 @@ __device__ void nbr_pass_body(const NbrParams& P, uint32_t* arena, uint64_t aren
     const int tid = threadIdx.x;
     for (;;) {
         if (tid == 0) {
-            uint64_t n = BIG ? (uint64_t)*P.big_count : P.n_centres;
+            uint64_t n = BIG ? (uint64_t)*P.big_count : P.M.total;
             uint32_t c = atomicAdd(BIG ? P.big_queue : P.queue, 1u);
             sh.stop = c >= n;
             if (!sh.stop) {
-                uint32_t h = BIG ? P.big_list[c] : P.centres[c];
+                uint32_t gi, h, rank;
+                if (BIG) {
+                    uint64_t it = P.big_list[c];
+                    gi = (uint32_t)(it >> 32);
+                    h = (uint32_t)it;
+                    rank = P.big_rank[c];
+                } else {
+                    gi = multi_graph_of(P.M, c);
+                    rank = (uint32_t)(c - P.M.base[gi]);
+                    h = P.M.graphs[gi].centres[rank];
+                }
+                const HeGraph& Gq = P.M.graphs[gi];
+                sh.gi = gi;
                 sh.h = h;
-                sh.rank = BIG ? P.big_rank[c] : c;
-                sh.hlen = P.g.h_len[h];
-                sh.hoff = P.g.h_off[h];
+                sh.rank = rank;
+                sh.skip = *((volatile const int32_t*)Gq.status) != 0;
+                sh.hlen = Gq.g.h_len[h];
+                sh.hoff = Gq.g.h_off[h];
                 // prefix + offsets must fit at the arena end
                 sh.defer = (!BIG && 3ull * sh.hlen + 4 > arena_words / 2) ? 1u : 0u;
             }
         }
         __syncthreads();
         if (sh.stop) break;
+        if (sh.skip) {
+            __syncthreads();
+            continue;
+        }
+        const HeGraph& G = P.M.graphs[sh.gi];
         if (!sh.defer) {
             const uint32_t hlen = sh.hlen;
             uint32_t* pre = arena + arena_words - (3 * hlen + 4);
             uint64_t* voff = (uint64_t*)(pre + ((hlen + 2) & ~1u));
             if (((uintptr_t)voff & 7) != 0) voff = (uint64_t*)((uint32_t*)voff + 1);
-            uint32_t lh = member_prefix(P.g, sh.hoff, hlen, pre, voff, sh.ws);
+            uint32_t lh = member_prefix(G.g, sh.hoff, hlen, pre, voff, sh.ws);
             uint32_t cap = hash_cap(lh);
             if (tid == 0) {
                 sh.lh = lh;
@@ -180,7 +199,7 @@ __device__ void nbr_pass_body(const NbrParams& P, uint32_t* arena, uint64_t aren
         if (sh.defer) {
             if (tid == 0) {
                 uint32_t q = atomicAdd(P.big_count, 1u);
-                P.big_list[q] = sh.h;
+                P.big_list[q] = item_of(sh.gi, sh.h);
                 P.big_rank[q] = sh.rank;
             }
             __syncthreads();
@@ -194,9 +213,9 @@ __device__ void nbr_pass_body(const NbrParams& P, uint32_t* arena, uint64_t aren
         if (((uintptr_t)voff & 7) != 0) voff = (uint64_t*)((uint32_t*)voff + 1);
         for (uint32_t s = tid; s < cap; s += HGT_WG) { keys[s] = HGT_EMPTY; vals[s] = 0; }
         __syncthreads();
-        build_nh(P.g, h, hlen, lh, pre, voff, keys, vals, cap);
+        build_nh(G.g, h, hlen, lh, pre, voff, keys, vals, cap);
         __syncthreads();
-        uint32_t* hd = P.hpool ? P.hpool + 2 * sh.hoff : nullptr;
+        uint32_t* hd = G.hpool + 2 * sh.hoff;
         for (uint32_t s = tid; s < cap; s += HGT_WG) {
             uint32_t x = keys[s];
             if (x == HGT_EMPTY) continue;
@@ -205,16 +224,17 @@ __device__ void nbr_pass_body(const NbrParams& P, uint32_t* arena, uint64_t aren
             if (P.emit_entries) {
                 uint64_t q = atomicAdd((unsigned long long*)P.n_entries, 1ull);
                 if (q < P.entries_cap) {
-                    P.ent_x[q] = x;
+                    P.ent_x[q] = (uint32_t)(G.id_base + x);
                     P.ent_d[q] = h;
                     P.ent_pay[q] = ((uint64_t)sh.rank << 32) | ((uint64_t)c << 1) | fd;
                 }
             }
             if (P.inserting) {
-                uint32_t lx = P.g.h_len[x];
+                uint32_t lx = G.g.h_len[x];
                 atomicAdd(&hd[2 * (c - 1) + (lx > c ? 1u : 0u)], 1u);
-                if (!P.mark_self || (uint32_t)(P.mark_self[x] >> 32) != P.epoch)
-                    atomicAdd(&P.hpool[2 * P.g.h_off[x] + 2 * (c - 1) + fd], 1u);
+                // an inserted neighbour builds its own histogram, this one included
+                if ((uint32_t)(G.mark[x] >> 32) != G.epoch)
+                    atomicAdd(&G.hpool[2 * G.g.h_off[x] + 2 * (c - 1) + fd], 1u);
             }
         }
         __syncthreads();
@@ -223,49 +243,47 @@ __device__ void nbr_pass_body(const NbrParams& P, uint32_t* arena, uint64_t aren
 
 __global__ void __launch_bounds__(HGT_WG) k_nbr_small(NbrParams P) {
     __shared__ __attribute__((aligned(16))) uint32_t arena[ARENA_S];
-    if (*((volatile const int32_t*)P.status) != 0) return;
     nbr_pass_body<false>(P, arena, ARENA_S);
 }
 
 __global__ void __launch_bounds__(HGT_WG) k_nbr_big(NbrParams P) {
-    if (*((volatile const int32_t*)P.status) != 0) return;
     nbr_pass_body<true>(P, P.big_scratch + (uint64_t)blockIdx.x * P.big_words, P.big_words);
 }
 
-// clear the histograms of the inserted hyperedges (their blocks may be reused)
-__global__ void k_h_clear(const uint32_t* __restrict__ ids, uint64_t n, const uint64_t* __restrict__ h_off,
-                          const uint32_t* __restrict__ h_len, uint32_t* hpool, const int32_t* status) {
-    if (*status) return;
+// clear the histograms of the inserted hyperedges (their blocks may be reused); a wave per centre
+__global__ void k_h_clear(Multi M) {
     const int lane = threadIdx.x & 63;
-    uint64_t j = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    if (j >= n) return;
-    uint32_t id = ids[j];
-    uint32_t* hb = hpool + 2 * h_off[id];
-    uint32_t w = 2 * h_len[id];
+    uint64_t q = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (q >= M.total) return;
+    uint32_t gi = multi_graph_of(M, q);
+    const HeGraph& G = M.graphs[gi];
+    if (*G.status) return;
+    uint32_t id = G.centres[q - M.base[gi]];
+    uint32_t* hb = G.hpool + 2 * G.g.h_off[id];
+    uint32_t w = 2 * G.g.h_len[id];
     for (uint32_t i = lane; i < w; i += 64) hb[i] = 0;
 }
 
 // remove the deleted hyperedges from their surviving neighbours' histograms
-__global__ void k_h_remove(const uint64_t* n_entries_p, uint64_t cap, const uint32_t* __restrict__ ent_x,
-                           const uint64_t* __restrict__ ent_pay, const uint64_t* __restrict__ mark_del,
-                           uint32_t epoch_del, const uint64_t* __restrict__ h_off, uint32_t* hpool,
-                           const int32_t* status) {
-    if (*status) return;
+__global__ void k_h_remove(Multi M, const uint64_t* n_entries_p, uint64_t cap, const uint32_t* __restrict__ ent_x,
+                           const uint64_t* __restrict__ ent_pay) {
     uint64_t n = *n_entries_p;
     if (n > cap) n = cap;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
-        uint32_t x = ent_x[i];
-        if ((uint32_t)(mark_del[x] >> 32) == epoch_del) continue;  // x is deleted too
+        uint32_t slot = ent_x[i];
+        const HeGraph& G = M.graphs[multi_graph_of_id(M, slot)];
+        if (*G.status) continue;
+        uint32_t x = (uint32_t)(slot - G.id_base);
+        if ((uint32_t)(G.mark[x] >> 32) == G.epoch) continue;  // x is deleted too
         uint64_t p = ent_pay[i];
         uint32_t k = (uint32_t)(p >> 1) & 0x7fffffffu, f = (uint32_t)p & 1u;
-        atomicSub(&hpool[2 * h_off[x] + 2 * (k - 1) + f], 1u);
+        atomicSub(&G.hpool[2 * G.g.h_off[x] + 2 * (k - 1) + f], 1u);
     }
 }
 
-// counting sort of the entries by x: per-ID counts, then scatter
+// counting sort of the entries by ID slot: per-slot counts, then scatter
 __global__ void k_bl_count(const uint64_t* n_entries_p, uint64_t cap, const uint32_t* __restrict__ ent_x,
-                           uint64_t* bl_cnt, const int32_t* status) {
-    if (*status) return;
+                           uint64_t* bl_cnt) {
     uint64_t n = *n_entries_p;
     if (n > cap) n = cap;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
@@ -274,8 +292,7 @@ __global__ void k_bl_count(const uint64_t* n_entries_p, uint64_t cap, const uint
 
 __global__ void k_bl_scatter(const uint64_t* n_entries_p, uint64_t cap, const uint32_t* __restrict__ ent_x,
                              const uint32_t* __restrict__ ent_d, const uint64_t* __restrict__ ent_pay,
-                             uint64_t* bl_cur, uint32_t* out_d, uint64_t* out_pay, const int32_t* status) {
-    if (*status) return;
+                             uint64_t* bl_cur, uint32_t* out_d, uint64_t* out_pay) {
     uint64_t n = *n_entries_p;
     if (n > cap) n = cap;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
@@ -285,8 +302,11 @@ __global__ void k_bl_scatter(const uint64_t* n_entries_p, uint64_t cap, const ui
     }
 }
 
-__global__ void k_entries_check(const uint64_t* n_entries_p, uint64_t cap, int32_t* status) {
-    if (threadIdx.x == 0 && blockIdx.x == 0 && *n_entries_p > cap) atomicCAS(status, 0, HGT_EDEVICE);
+// the entry buffer is sized for the worst case; overflow is an internal error of every graph
+__global__ void k_entries_check(Multi M, const uint64_t* n_entries_p, uint64_t cap) {
+    if (*n_entries_p <= cap) return;
+    for (uint32_t g = threadIdx.x; g < M.n_graphs; g += blockDim.x)
+        atomicCAS(const_cast<int32_t*>(M.graphs[g].status), 0, HGT_EDEVICE);
 }
 
 // ===========================================================================
@@ -296,6 +316,22 @@ __global__ void k_entries_check(const uint64_t* n_entries_p, uint64_t cap, int32
 // the centres whose tables do not fit its arena to list s; list 2 feeds the
 // 2-hop kernel.  Stages 0 and 1 keep the arena in LDS (72 KB, 148 KB), stage 2
 // in a 1 MB slice of global memory per workgroup.
+// Adds the per-wave counts to graph g's phase accumulators and clears them.
+__device__ void he2_flush_graph(const He2Params& P, uint32_t g, uint64_t* acc_all) {
+    __syncthreads();
+    if (g != 0xffffffffu) {
+        const HeGraph& G = P.M.graphs[g];
+        for (int i = threadIdx.x; i < HGT_N_HE_CLASSES; i += HGT_WG) {
+            uint64_t s = 0;
+            for (int w = 0; w < NWAVE; w++) s += acc_all[w * HGT_N_HE_CLASSES + i];
+            if (s) atomicAdd((unsigned long long*)&G.out_he[i], (unsigned long long)s);
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < NWAVE * HGT_N_HE_CLASSES; i += HGT_WG) acc_all[i] = 0;
+    __syncthreads();
+}
+
 template <int STAGE>
 __device__ void he2_body(const He2Params& P, uint32_t* arena, const uint32_t ARENA_WORDS, Sh2& sh, const Tables& T,
                          uint64_t* acc_all, uint32_t* acc32_all, uint64_t* st) {
@@ -305,25 +341,48 @@ __device__ void he2_body(const He2Params& P, uint32_t* arena, const uint32_t ARE
     for (;;) {
         if (tid == 0) {
             uint32_t c = atomicAdd(&P.queue[STAGE], 1u);
-            sh.stop = c >= (STAGE == 0 ? P.n_centres : (uint64_t)P.count[STAGE - 1]);
+            sh.stop = c >= (STAGE == 0 ? P.M.total : (uint64_t)P.count[STAGE - 1]);
             if (!sh.stop) {
-                uint32_t h = STAGE == 0 ? P.centres[c] : P.list[STAGE - 1][c];
+                uint32_t gi, h, rank;
+                if (STAGE == 0) {
+                    gi = multi_graph_of(P.M, c);
+                    rank = (uint32_t)(c - P.M.base[gi]);
+                    h = P.M.graphs[gi].centres[rank];
+                } else {
+                    uint64_t it = P.list[STAGE - 1][c];
+                    gi = (uint32_t)(it >> 32);
+                    h = (uint32_t)it;
+                    rank = P.rank[STAGE - 1][c];
+                }
+                const HeGraph& Gq = P.M.graphs[gi];
+                sh.gi = gi;
                 sh.h = h;
-                sh.rank = STAGE == 0 ? c : P.rank[STAGE - 1][c];
-                sh.hlen = P.g.h_len[h];
-                sh.hoff = P.g.h_off[h];
+                sh.rank = rank;
+                sh.skip = *((volatile const int32_t*)Gq.status) != 0;
+                sh.hlen = Gq.g.h_len[h];
+                sh.hoff = Gq.g.h_off[h];
                 sh.defer = (3ull * sh.hlen + 4 > ARENA_WORDS / 2 || STAGE < P.force_stage) ? 1u : 0u;
             }
         }
         __syncthreads();
         if (sh.stop) break;
+        if (sh.gi != sh.cur_g) {  // the counts so far belong to the previous graph
+            he2_flush_graph(P, sh.cur_g, acc_all);
+            if (tid == 0) sh.cur_g = sh.gi;
+            __syncthreads();
+        }
+        if (sh.skip) {
+            __syncthreads();
+            continue;
+        }
+        const HeGraph& G = P.M.graphs[sh.gi];
         const uint32_t h = sh.h, hlen = sh.hlen;
         // --- members of h: degree prefix and list offsets at the arena end
         uint32_t* pre = arena + ARENA_WORDS - (3 * hlen + 4);
         uint64_t* voff = (uint64_t*)(pre + ((hlen + 2) & ~1u));
         if (((uintptr_t)voff & 7) != 0) voff = (uint64_t*)((uint32_t*)voff + 1);
         if (!sh.defer) {
-            uint32_t lh = member_prefix(P.g, sh.hoff, hlen, pre, voff, sh.ws);
+            uint32_t lh = member_prefix(G.g, sh.hoff, hlen, pre, voff, sh.ws);
             uint32_t cap = hash_cap(lh);
             if (tid == 0) {
                 sh.lh = lh;
@@ -337,7 +396,7 @@ __device__ void he2_body(const He2Params& P, uint32_t* arena, const uint32_t ARE
         if (sh.defer) {
             if (tid == 0) {
                 uint32_t q = atomicAdd(&P.count[STAGE], 1u);
-                P.list[STAGE][q] = h;
+                P.list[STAGE][q] = item_of(sh.gi, h);
                 P.rank[STAGE][q] = sh.rank;
                 atomicAdd((unsigned long long*)&st[0], 1ull);
             }
@@ -350,7 +409,7 @@ __device__ void he2_body(const He2Params& P, uint32_t* arena, const uint32_t ARE
         for (uint32_t s = tid; s < ncap; s += HGT_WG) { nkeys[s] = HGT_EMPTY; nvals[s] = 0; }
         if (tid == 0) sh.K = 0;
         __syncthreads();
-        build_nh(P.g, h, hlen, lh, pre, voff, nkeys, nvals, ncap);
+        build_nh(G.g, h, hlen, lh, pre, voff, nkeys, nvals, ncap);
         __syncthreads();
         // --- compact N(h): x, meta (c | len | eligible), member offsets later
         uint32_t* nl_x = arena + 2 * ncap;
@@ -361,8 +420,8 @@ __device__ void he2_body(const He2Params& P, uint32_t* arena, const uint32_t ARE
             uint32_t x = nkeys[s];
             if (x == HGT_EMPTY) continue;
             uint32_t c = nvals[s];
-            uint32_t len = P.g.h_len[x];
-            bool elig = P.static_mode || !lower_ranked_member(P.mark[x], P.epoch, sh.rank);
+            uint32_t len = G.g.h_len[x];
+            bool elig = P.static_mode || !lower_ranked_member(G.mark[x], G.epoch, sh.rank);
             uint32_t meta = c | (len << 14) | ((uint32_t)elig << 28);
             nvals[s] = meta;
             uint32_t q = atomicAdd(&sh.K, 1u);
@@ -386,6 +445,10 @@ __device__ void he2_body(const He2Params& P, uint32_t* arena, const uint32_t ARE
             if (tid == 0) {
                 nl_mo[K] = carry;
                 sh.W = carry;
+                // h's row and its members' incidence lists, each neighbour's row and metadata
+                if (P.stats)
+                    atomicAdd((unsigned long long*)&st[1],
+                              (unsigned long long)(4ull * (hlen + lh) + 20ull * K + 4ull * carry));
                 uint64_t o_ent = (uint64_t)(hm + hlen - arena);
                 o_ent = (o_ent + 1) & ~1ull;
                 uint64_t need = 2ull * carry > 2ull * hlen + 2 ? 2ull * carry : 2ull * hlen + 2;
@@ -397,7 +460,7 @@ __device__ void he2_body(const He2Params& P, uint32_t* arena, const uint32_t ARE
         if (sh.defer) {
             if (tid == 0) {
                 uint32_t q = atomicAdd(&P.count[STAGE], 1u);
-                P.list[STAGE][q] = h;
+                P.list[STAGE][q] = item_of(sh.gi, h);
                 P.rank[STAGE][q] = sh.rank;
                 atomicAdd((unsigned long long*)&st[0], 1ull);
             }
@@ -406,7 +469,7 @@ __device__ void he2_body(const He2Params& P, uint32_t* arena, const uint32_t ARE
         }
         const uint32_t W = sh.W;
         uint64_t* keys = (uint64_t*)(arena + sh.o_ent);
-        for (uint32_t i = tid; i < hlen; i += HGT_WG) hm[i] = P.g.h2v[sh.hoff + i];
+        for (uint32_t i = tid; i < hlen; i += HGT_WG) hm[i] = G.g.h2v[sh.hoff + i];
         // --- disjoint-pair classes of all eligible neighbour pairs (histogram over c)
         {
             uint32_t* cnt = (uint32_t*)keys;  // 2 (hlen + 1) words, free until the entries are written
@@ -470,7 +533,7 @@ __device__ void he2_body(const He2Params& P, uint32_t* arena, const uint32_t ARE
         for (uint32_t p = tid; p < W; p += HGT_WG) {
             uint32_t xi = seg_of<uint32_t>(nl_mo, K, p);
             uint32_t x = nl_x[xi];
-            uint32_t v = P.g.h2v[P.g.h_off[x] + (p - nl_mo[xi])];
+            uint32_t v = G.g.h2v[G.g.h_off[x] + (p - nl_mo[xi])];
             uint64_t inh = contains_u32(hm, hlen, v) ? 1ull : 0ull;
             keys[p] = ((uint64_t)v << 15) | (inh << 14) | xi;
         }
@@ -491,7 +554,10 @@ __device__ void he2_body(const He2Params& P, uint32_t* arena, const uint32_t ARE
             uint32_t c = meta_c(m), lx = meta_len(m);
             uint32_t thr = lx - c;  // k < thr  <=>  x has a vertex outside h and y
             uint32_t base = (hlen > c ? 1u : 0u) | 24u;
-            const uint32_t* H = P.hpool + 2 * P.g.h_off[x];
+            const uint32_t* H = G.hpool + 2 * G.g.h_off[x];
+            const uint64_t xs = G.id_base + x;
+            if (P.stats)  // x's histogram, list bounds and batch-neighbour entries
+                atomicAdd((unsigned long long*)&st[1], (unsigned long long)(8ull * lx + 16 + 12ull * P.bl_cnt[xs]));
             // a_f: neighbours y with |x & y| < thr (x keeps a private vertex), b_f: the rest
             uint64_t a0 = 0, a1 = 0, b0 = 0, b1 = 0;
             for (uint32_t k = 1; k <= lx; k++) {
@@ -503,7 +569,7 @@ __device__ void he2_body(const He2Params& P, uint32_t* arena, const uint32_t ARE
             if (c < thr) { if (hlen > c) a1--; else a0--; }
             else { if (hlen > c) b1--; else b0--; }
             // lower-ranked batch members adjacent to x but not to h
-            uint64_t bo = P.bl_off[x], bn = P.bl_cnt[x];
+            uint64_t bo = P.bl_off[xs], bn = P.bl_cnt[xs];
             for (uint64_t e = 0; e < bn; e++) {
                 uint64_t pay = P.bl_pay[bo + e];
                 if ((uint32_t)(pay >> 32) >= sh.rank) continue;
@@ -539,8 +605,8 @@ __device__ void he2_body(const He2Params& P, uint32_t* arena, const uint32_t ARE
                 bool at_first = true;
                 if (xsh > 1 && nl_msh[yi] > 1) {
                     // both have other shared members: merge the member lists
-                    const uint32_t* X = P.g.h2v + P.g.h_off[nl_x[xi]];
-                    const uint32_t* Y = P.g.h2v + P.g.h_off[nl_x[yi]];
+                    const uint32_t* X = G.g.h2v + G.g.h_off[nl_x[xi]];
+                    const uint32_t* Y = G.g.h2v + G.g.h_off[nl_x[yi]];
                     uint32_t a = 0, b = 0, first = HGT_EMPTY;
                     s = 0;
                     shh = 0;
@@ -601,15 +667,11 @@ __device__ void he2_body(const He2Params& P, uint32_t* arena, const uint32_t ARE
 }
 
 template <int STAGE>
-__device__ void he2_flush(const He2Params& P, uint64_t (*acc)[HGT_N_HE_CLASSES], const uint64_t* st) {
-    __syncthreads();
-    for (int i = threadIdx.x; i < HGT_N_HE_CLASSES; i += HGT_WG) {
-        uint64_t s = 0;
-        for (int w = 0; w < NWAVE; w++) s += acc[w][i];
-        if (s) atomicAdd((unsigned long long*)&P.out_he[i], (unsigned long long)s);
-    }
+__device__ void he2_flush_stats(const He2Params& P, const uint64_t* st) {
     if (P.stats && threadIdx.x == 0 && st[0])
         atomicAdd((unsigned long long*)&P.stats[ST_DEFER0 + STAGE], (unsigned long long)st[0]);
+    if (P.stats && threadIdx.x == 0 && st[1])
+        atomicAdd((unsigned long long*)&P.stats[ST_HEB0 + STAGE], (unsigned long long)st[1]);
 }
 
 #define HE2_PROLOGUE                                                                   \
@@ -618,7 +680,7 @@ __device__ void he2_flush(const He2Params& P, uint64_t (*acc)[HGT_N_HE_CLASSES],
     __shared__ uint64_t acc[NWAVE][HGT_N_HE_CLASSES];                                  \
     __shared__ uint32_t acc32[NWAVE][HGT_N_HE_CLASSES];                                \
     __shared__ uint64_t st[2];                                                         \
-    if (*((volatile const int32_t*)P.status) != 0) return;                             \
+    if (threadIdx.x == 0) sh.cur_g = 0xffffffffu;                                      \
     for (int i = threadIdx.x; i < 128; i += HGT_WG) T.he[i] = P.he_tab[i];             \
     for (int i = threadIdx.x; i < NWAVE * HGT_N_HE_CLASSES; i += HGT_WG) {             \
         (&acc[0][0])[i] = 0;                                                           \
@@ -631,21 +693,24 @@ __global__ void __launch_bounds__(HGT_WG) k_he2_s0(He2Params P) {
     __shared__ __attribute__((aligned(16))) uint32_t arena[ARENA_S];
     HE2_PROLOGUE
     he2_body<0>(P, arena, ARENA_S, sh, T, &acc[0][0], &acc32[0][0], st);
-    he2_flush<0>(P, acc, st);
+    he2_flush_graph(P, sh.cur_g, &acc[0][0]);
+    he2_flush_stats<0>(P, st);
 }
 
 __global__ void __launch_bounds__(HGT_WG) k_he2_s1(He2Params P) {
     __shared__ __attribute__((aligned(16))) uint32_t arena[ARENA_M];
     HE2_PROLOGUE
     he2_body<1>(P, arena, ARENA_M, sh, T, &acc[0][0], &acc32[0][0], st);
-    he2_flush<1>(P, acc, st);
+    he2_flush_graph(P, sh.cur_g, &acc[0][0]);
+    he2_flush_stats<1>(P, st);
 }
 
 __global__ void __launch_bounds__(HGT_WG) k_he2_s2(He2Params P) {
     HE2_PROLOGUE
     he2_body<2>(P, P.garena + (uint64_t)blockIdx.x * P.garena_words, (uint32_t)P.garena_words, sh, T, &acc[0][0],
                 &acc32[0][0], st);
-    he2_flush<2>(P, acc, st);
+    he2_flush_graph(P, sh.cur_g, &acc[0][0]);
+    he2_flush_stats<2>(P, st);
 }
 
 }  // namespace
@@ -653,33 +718,31 @@ __global__ void __launch_bounds__(HGT_WG) k_he2_s2(He2Params P) {
 void he2_nbr_launch(NbrParams& P, unsigned grid_small, unsigned grid_big, hipStream_t s) {
     hgt_fill_u32(P.queue, 0, 3, s);
     hgt_fill_u64(P.n_entries, 0, 1, s);
-    if (P.n_centres == 0) return;
-    if (P.inserting && P.hpool)
-        k_h_clear<<<(unsigned)((P.n_centres * 64 + 255) / 256), 256, 0, s>>>(P.centres, P.n_centres, P.g.h_off,
-                                                                            P.g.h_len, P.hpool, P.status);
+    if (P.M.total == 0) return;
+    if (P.inserting) k_h_clear<<<(unsigned)((P.M.total * 64 + 255) / 256), 256, 0, s>>>(P.M);
     k_nbr_small<<<grid_small, HGT_WG, 0, s>>>(P);
     k_nbr_big<<<grid_big, HGT_WG, 0, s>>>(P);
-    k_entries_check<<<1, 64, 0, s>>>(P.n_entries, P.entries_cap, const_cast<int32_t*>(P.status));
+    k_entries_check<<<1, 256, 0, s>>>(P.M, P.n_entries, P.entries_cap);
 }
 
-void he2_lists_build(NbrParams& P, uint64_t n_ids, uint64_t* bl_cnt, uint64_t* bl_off, uint64_t* bl_cur,
-                     uint32_t* bl_d, uint64_t* bl_pay, void* scan_tmp, hipStream_t s) {
+void he2_lists_build(NbrParams& P, uint64_t* bl_cnt, uint64_t* bl_off, uint64_t* bl_cur, uint32_t* bl_d,
+                     uint64_t* bl_pay, void* scan_tmp, hipStream_t s) {
+    const uint64_t n_ids = P.M.total_ids;
     hgt_fill_u64(bl_cnt, 0, n_ids, s);
     unsigned g = 2048;
-    k_bl_count<<<g, 256, 0, s>>>(P.n_entries, P.entries_cap, P.ent_x, bl_cnt, P.status);
+    k_bl_count<<<g, 256, 0, s>>>(P.n_entries, P.entries_cap, P.ent_x, bl_cnt);
     hgt_scan_u64(bl_cnt, bl_off, n_ids, nullptr, nullptr, scan_tmp, s);
     (void)hipMemcpyAsync(bl_cur, bl_off, n_ids * 8, hipMemcpyDeviceToDevice, s);
-    k_bl_scatter<<<g, 256, 0, s>>>(P.n_entries, P.entries_cap, P.ent_x, P.ent_d, P.ent_pay, bl_cur, bl_d, bl_pay,
-                                   P.status);
+    k_bl_scatter<<<g, 256, 0, s>>>(P.n_entries, P.entries_cap, P.ent_x, P.ent_d, P.ent_pay, bl_cur, bl_d, bl_pay);
 }
 
-void he2_remove_deleted(NbrParams& P, const uint64_t* mark_del, uint32_t epoch_del, hipStream_t s) {
-    k_h_remove<<<2048, 256, 0, s>>>(P.n_entries, P.entries_cap, P.ent_x, P.ent_pay, mark_del, epoch_del, P.g.h_off,
-                                    P.hpool, P.status);
+void he2_remove_deleted(NbrParams& P, hipStream_t s) {
+    if (P.M.total == 0) return;
+    k_h_remove<<<2048, 256, 0, s>>>(P.M, P.n_entries, P.entries_cap, P.ent_x, P.ent_pay);
 }
 
 void he2_launch_stage(He2Params& P, int stage, unsigned grid, hipStream_t s) {
-    if (!P.n_centres) return;
+    if (!P.M.total) return;
     if (stage == 0) k_he2_s0<<<grid, HGT_WG, 0, s>>>(P);
     else if (stage == 1) k_he2_s1<<<grid, HGT_WG, 0, s>>>(P);
     else k_he2_s2<<<grid, HGT_WG, 0, s>>>(P);

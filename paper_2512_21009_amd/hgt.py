@@ -71,9 +71,25 @@ class KernelTime(ctypes.Structure):
     ]
 
 
+class Batch(ctypes.Structure):
+    _fields_ = [
+        ("graph", ctypes.c_void_p),
+        ("del_ids", ctypes.c_void_p),
+        ("n_del", ctypes.c_uint64),
+        ("ins_offsets", ctypes.c_void_p),
+        ("ins_members", ctypes.c_void_p),
+        ("n_ins_members", ctypes.c_uint64),
+        ("ins_ts", ctypes.c_void_p),
+        ("n_ins", ctypes.c_uint64),
+        ("out_ins_ids", ctypes.c_void_p),
+        ("status", ctypes.c_int32),
+        ("pad0", ctypes.c_int32),
+    ]
+
+
 _lib = None
 
-EXPORTS = ["hgt_build", "hgt_apply_batch", "hgt_triad_counts", "hgt_sync", "hgt_destroy", "hgt_status_str",
+EXPORTS = ["hgt_build", "hgt_apply_batch", "hgt_apply_batches", "hgt_triad_counts", "hgt_sync", "hgt_destroy", "hgt_status_str",
            "hgt_get_info", "hgt_export_h2v", "hgt_export_v2h", "hgt_class_codes", "hgt_profile",
            "hgt_profile_read"]
 
@@ -89,6 +105,7 @@ def load(path: str = LIB_PATH):
     P, U64, U32, I64, I32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int64, ctypes.c_int
     lib.hgt_build.argtypes = [ctypes.POINTER(BuildDesc), ctypes.POINTER(P)]
     lib.hgt_apply_batch.argtypes = [P, P, U64, P, P, U64, P, U64, P, P]
+    lib.hgt_apply_batches.argtypes = [P, U32, P]
     lib.hgt_triad_counts.argtypes = [P, I32, I64, P, U32]
     lib.hgt_sync.argtypes = [P, ctypes.POINTER(I32)]
     lib.hgt_destroy.argtypes = [P]
@@ -145,6 +162,52 @@ def class_codes(kind) -> List[int]:
     arr = (ctypes.c_int32 * n)()
     lib.hgt_class_codes(k, ctypes.cast(arr, ctypes.c_void_p), n)
     return list(arr)
+
+
+def _batch_args(del_ids, ins_offsets, ins_members, ins_ts):
+    import torch
+    _check_dtype(del_ids, (torch.int32, torch.uint32), "del_ids")
+    _check_dtype(ins_offsets, (torch.int64, torch.uint64), "ins_offsets")
+    _check_dtype(ins_members, (torch.int32, torch.uint32), "ins_members")
+    _check_dtype(ins_ts, (torch.int64,), "ins_ts")
+    n_del = 0 if del_ids is None else int(del_ids.numel())
+    n_ins = 0 if ins_offsets is None else int(ins_offsets.numel() - 1)
+    n_mem = 0 if ins_members is None else int(ins_members.numel())
+    return n_del, n_ins, n_mem
+
+
+def apply_batches(items, stream=None, raise_on_error: bool = True):
+    """Batched form: items = [(graph, del_ids, ins_offsets, ins_members, ins_ts), ...]
+    with distinct graphs.  Applies all of them in one call (one wait, shared
+    triad launches).  Returns the list of assigned-ID tensors (or, with
+    raise_on_error=False, (first_status, [status...], [ids...]))."""
+    import torch
+    lib = load()
+    n = len(items)
+    arr = (Batch * max(n, 1))()
+    outs = []
+    for i, it in enumerate(items):
+        g, del_ids, ins_offsets, ins_members, ins_ts = (list(it) + [None] * 5)[:5]
+        n_del, n_ins, n_mem = _batch_args(del_ids, ins_offsets, ins_members, ins_ts)
+        out = torch.empty(n_ins, dtype=torch.int32, device=ins_offsets.device) if n_ins else None
+        outs.append(out)
+        b = arr[i]
+        b.graph = g._h.value
+        b.del_ids = _ptr(del_ids)
+        b.n_del = n_del
+        b.ins_offsets = _ptr(ins_offsets) if n_ins else None
+        b.ins_members = _ptr(ins_members)
+        b.n_ins_members = n_mem
+        b.ins_ts = _ptr(ins_ts)
+        b.n_ins = n_ins
+        b.out_ins_ids = _ptr(out) if n_ins else None
+    rc = lib.hgt_apply_batches(ctypes.cast(arr, ctypes.c_void_p), n, _stream(stream))
+    status = [arr[i].status for i in range(n)]
+    if raise_on_error:
+        if rc != OK:
+            raise HgtError(rc, f"hgt_apply_batches (statuses {status})")
+        return outs
+    return rc, status, outs
 
 
 class Graph:

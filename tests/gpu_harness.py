@@ -81,29 +81,56 @@ class Pair:
         self.gid = {h: h for h in range(n0)}  # handle -> device ID
         self.oid = {h: h for h in range(n0)}  # handle -> oracle ID
 
-    def apply(self, batch, where=""):
-        import torch
+    def prepare(self, batch, where=""):
+        """Device arguments of `batch` (del_ids, ins_offsets, ins_members, ins_ts)
+        and a function that takes the assigned-ID tensor, applies the batch to
+        the oracle and checks the IDs."""
         temporal = "temporal" in self.track
         gd = np.array([self.gid[h] for h in batch.del_handles], dtype=np.int64)
-        od = np.array([self.oid[h] for h in batch.del_handles], dtype=np.int64)
         ins = batch.ins
         ts = ins.ts if temporal else None
-        out = self.g.apply_batch(dev(gd, np.int32) if len(gd) else None,
-                                 dev(ins.offsets, np.int64) if ins.n else None,
-                                 dev(ins.members, np.int32) if ins.n else None,
-                                 dev(ts, np.int64) if (ts is not None and ins.n) else None)
+        args = (dev(gd, np.int32) if len(gd) else None,
+                dev(ins.offsets, np.int64) if ins.n else None,
+                dev(ins.members, np.int32) if ins.n else None,
+                dev(ts, np.int64) if (ts is not None and ins.n) else None)
+
+        def finish(out):
+            od = np.array([self.oid[h] for h in batch.del_handles], dtype=np.int64)
+            st, oids = self.o.apply_batch(od, ins.offsets, ins.members, ts)
+            assert st == orc.OK, f"{where}: oracle rejected the batch ({st})"
+            gids = out.cpu().numpy().astype(np.uint32) if out is not None else np.zeros(0, np.uint32)
+            assert gids.tolist() == oids.tolist(), f"{where}: assigned IDs differ"
+            for h, a, b in zip(batch.ins_handles, gids, oids):
+                self.gid[int(h)] = int(a)
+                self.oid[int(h)] = int(b)
+            for h in batch.del_handles:
+                self.gid.pop(int(h), None)
+                self.oid.pop(int(h), None)
+            return gids
+        return args, finish
+
+    def apply(self, batch, where=""):
+        import torch
+        args, finish = self.prepare(batch, where)
+        out = self.g.apply_batch(*args)
         torch.cuda.synchronize()
-        st, oids = self.o.apply_batch(od, ins.offsets, ins.members, ts)
-        assert st == orc.OK, f"{where}: oracle rejected the batch ({st})"
-        gids = out.cpu().numpy().astype(np.uint32) if out is not None else np.zeros(0, np.uint32)
-        assert gids.tolist() == oids.tolist(), f"{where}: assigned IDs differ"
-        for h, a, b in zip(batch.ins_handles, gids, oids):
-            self.gid[int(h)] = int(a)
-            self.oid[int(h)] = int(b)
-        for h in batch.del_handles:
-            self.gid.pop(int(h), None)
-            self.oid.pop(int(h), None)
-        return gids
+        return finish(out)
 
     def close(self):
         self.g.close()
+
+
+def apply_many(pairs, batches, where=""):
+    """Applies batches[i] to pairs[i] through the batched entry point (one call)
+    and to each oracle; checks the assigned IDs."""
+    import torch
+    from paper_2512_21009_amd import hgt
+    items, fins = [], []
+    for k, (p, b) in enumerate(zip(pairs, batches)):
+        args, fin = p.prepare(b, f"{where} graph {k}")
+        items.append((p.g,) + args)
+        fins.append(fin)
+    outs = hgt.apply_batches(items)
+    torch.cuda.synchronize()
+    for fin, out in zip(fins, outs):
+        fin(out)

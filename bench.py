@@ -2,15 +2,24 @@
 """Hyperedge updates/s including the triad-count update, on one MI355X.
 
 A step is one batch through the whole hot path: validation and
-canonicalisation, the hyperedge-based and incident-vertex-based triad deltas
-on the old graph, the store delete/insert, the deltas on the new graph and the
-count update.  The default workload is the Medium configuration: 1M vertices,
-2M hyperedges, cardinality power law (exponent 2.5) on [2,64], vertex
-popularity (rank + 1e4)^-1.1, batches of 50k inserts + 50k deletions of
-uniformly chosen live hyperedges.  Inputs are synthetic and resident in HBM
-before timing starts.
+canonicalisation, the triad deltas on the old graph, the store delete/insert,
+the deltas on the new graph and the count update.  Inputs are synthetic and
+resident in HBM before timing starts.  Workloads (--config):
 
-Prints one JSON line (rank 0).  Only one GPU is used.
+  medium   (default) 1M vertices, 2M hyperedges, cardinality power law 2.5 on
+           [2,64], vertex popularity (rank + 1e4)^-1.1, batches of 50k inserts
+           + 50k deletions of uniformly chosen live hyperedges; hyperedge and
+           incident-vertex triads.
+  temporal 500k vertices, 4M hyperedges, cardinality power law 2.2 on [2,128],
+           Poisson arrivals at 1e3/s, batches of 200k arrivals with expiry of
+           hyperedges older than 3600 s; temporal triads within 600 s.
+  batched  256 graphs, |E| log-uniform in [1k,200k], |V| = |E|/2, cardinality
+           power law 2.5 on [2,256], per-graph batches log-uniform in [10,50k]
+           (60% inserts); hyperedge triads.  Every round is timed twice on
+           identical copies: one hgt_apply_batch call per graph (plain) and one
+           hgt_apply_batches call for all graphs (batched).
+
+Prints one JSON line.  Only one GPU is used.
 """
 import argparse
 import json
@@ -23,6 +32,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+METRIC = "hyperedge updates/sec incl. triad-count update; p50/p99 batch latency"
 
 
 def parse():
@@ -30,8 +40,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=9)
     ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", choices=("medium", "temporal", "batched"), default="medium")
     ap.add_argument("--scale", type=float, default=1.0, help="workload scale (1.0 = the named configuration)")
-    ap.add_argument("--cpu-sample", type=int, default=1000, help="updates in the oracle's timed sample")
+    ap.add_argument("--cpu-sample", type=int, default=600, help="updates in the oracle's timed sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quiet", action="store_true")
     return ap.parse_args()
@@ -42,31 +53,57 @@ def log(args, *a):
         print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
-                          "n_gpus": args.gpus}), flush=True)
-        sys.exit(2)
+def to_dev(a, dt):
     import numpy as np
     import torch
-    from paper_2512_21009_amd import hgt, workloads as W
+    return torch.from_numpy(np.ascontiguousarray(a).astype(dt)).to("cuda:0")
 
-    hgt.load()
-    dev = torch.device("cuda:0")
-    n_b = args.warmup + args.steps
-    t0 = time.perf_counter()
-    st = W.medium(q=1.0e4, scale=args.scale, n_batches=n_b)
-    log(args, f"generated {st.initial.n} hyperedges, {n_b} batches in {time.perf_counter() - t0:.1f}s")
 
-    def d(a, dt):
-        return torch.from_numpy(np.ascontiguousarray(a).astype(dt)).to(dev)
+def roofline_of(prof):
+    """Dominant kernel group of the timed region: its algorithmic bytes per
+    launch over its average launch duration (HIP events on the launch stream)."""
+    live = [(n, r) for n, r in prof.items() if r["launches"]]
+    dom_name, dom = max(live, key=lambda kv: kv[1]["total_ms"])
+    achieved = dom["algo_bytes"] / (dom["total_ms"] * 1e6) if dom["total_ms"] > 0 else 0.0
+    return {"bound": "hbm", "kernel": dom_name, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+            "avg_launch_ms": round(dom["total_ms"] / dom["launches"], 4),
+            "algo_bytes_per_launch": int(dom["algo_bytes"] // dom["launches"])}
 
+
+def log_profile(args, prof):
+    for name, r in prof.items():
+        if r["launches"]:
+            gbs = r["algo_bytes"] / (r["total_ms"] * 1e6) if r["total_ms"] > 0 else 0.0
+            log(args, f"  {name:16s} launches={r['launches']:5d} total={r['total_ms']:9.2f}ms "
+                      f"algo={r['algo_bytes'] / 1e9:8.3f}GB ({gbs:7.1f} GB/s) events={r['events']} aux={r['aux']}")
+
+
+def add_profiles(acc, prof):
+    for k, r in prof.items():
+        a = acc.setdefault(k, dict(launches=0, total_ms=0.0, algo_bytes=0, events=0, aux=0))
+        for f in a:
+            a[f] += r[f]
+    return acc
+
+
+def calibration_copy():
+    """A plain device copy of known size (256 MiB read + 256 MiB written), run
+    outside the timed region: profiler byte counters are scaled by it."""
+    import torch
+    calib = torch.empty(1 << 26, dtype=torch.int32, device="cuda:0")
+    calib.fill_(1)
+    calib.clone()
+    torch.cuda.synchronize()
+
+
+def ids_of_stream(hgt, st, ins):
+    """Deletion IDs of every batch: a store-only replay (no triad families)
+    gives the IDs the library assigns, the same as in any tracked copy."""
+    import numpy as np
+    import torch
     ini = st.initial
-    off0, mem0 = d(ini.offsets, np.int64), d(ini.members, np.int32)
-    ins = [(d(b.ins.offsets, np.int64), d(b.ins.members, np.int32)) for b in st.batches]
-    # store-only pass to learn which IDs the deletions name (handles -> IDs)
-    g0 = hgt.Graph.build(st.n_vertices, off0, mem0, track=())
+    g0 = hgt.Graph.build(st.n_vertices, to_dev(ini.offsets, np.int64), to_dev(ini.members, np.int32), track=())
     n_handles = ini.n + sum(b.ins.n for b in st.batches)
     hid = np.full(n_handles, -1, np.int64)
     hid[: ini.n] = np.arange(ini.n)
@@ -74,30 +111,45 @@ def main():
     for b, (io, im) in zip(st.batches, ins):
         di = hid[b.del_handles]
         assert (di >= 0).all()
-        dt = d(di, np.int32)
+        dt = to_dev(di, np.int32) if len(di) else None
         dels.append(dt)
         out = g0.apply_batch(dt, io, im)
-        hid[b.ins_handles] = out.cpu().numpy()
+        if out is not None:
+            hid[b.ins_handles] = out.cpu().numpy()
     g0.close()
-    del g0
     torch.cuda.synchronize()
-    track = ("hyperedge", "incident_vertex")
+    return dels
+
+
+def bench_single(args, st, track, name, workload):
+    """One graph, one hgt_apply_batch call per step."""
+    import numpy as np
+    import torch
+    from paper_2512_21009_amd import hgt
+    temporal = "temporal" in track
+    ini = st.initial
+    off0, mem0 = to_dev(ini.offsets, np.int64), to_dev(ini.members, np.int32)
+    ts0 = to_dev(ini.ts, np.int64) if temporal else None
+    ins = [(to_dev(b.ins.offsets, np.int64) if b.ins.n else None, to_dev(b.ins.members, np.int32) if b.ins.n else None)
+           for b in st.batches]
+    its = [to_dev(b.ins.ts, np.int64) if (temporal and b.ins.n) else None for b in st.batches]
+    dels = ids_of_stream(hgt, st, ins)
     t0 = time.perf_counter()
-    g = hgt.Graph.build(st.n_vertices, off0, mem0, track=track)
+    g = hgt.Graph.build(st.n_vertices, off0, mem0, ts0, track=track, window=st.window)
     torch.cuda.synchronize()
     build_s = time.perf_counter() - t0
     log(args, f"build with initial counts: {build_s:.2f}s")
+    n_b = len(st.batches)
     for k in range(args.warmup):
-        g.apply_batch(dels[k], *ins[k])
+        g.apply_batch(dels[k], *ins[k], its[k])
     torch.cuda.synchronize()
     g.profile(True)
-    lat = []
-    n_upd = 0
+    lat, n_upd = [], 0
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for k in range(args.warmup, n_b):
         tb = time.perf_counter()
-        g.apply_batch(dels[k], *ins[k])
+        g.apply_batch(dels[k], *ins[k], its[k])
         torch.cuda.synchronize()
         lat.append(time.perf_counter() - tb)
         n_upd += st.batches[k].n_updates
@@ -107,88 +159,177 @@ def main():
     status = g.sync()
     assert status == hgt.OK, status
     value = n_upd / elapsed
-    lat_ms = np.array(lat) * 1e3
     log(args, f"{n_upd} updates in {elapsed:.3f}s -> {value:,.0f} updates/s")
-    for name, r in prof.items():
-        if r["launches"]:
-            gbs = r["algo_bytes"] / (r["total_ms"] * 1e6) if r["total_ms"] > 0 else 0.0
-            log(args, f"  {name:16s} launches={r['launches']:3d} total={r['total_ms']:9.2f}ms "
-                      f"algo={r['algo_bytes'] / 1e9:8.3f}GB ({gbs:7.1f} GB/s) events={r['events']} aux={r['aux']}")
-    # dominant kernel of the timed region
-    dom_name, dom = max(((n, r) for n, r in prof.items() if r["launches"]), key=lambda kv: kv[1]["total_ms"])
-    achieved = dom["algo_bytes"] / (dom["total_ms"] * 1e6) if dom["total_ms"] > 0 else 0.0
-    roofline = {"bound": "hbm", "kernel": dom_name, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
-                "avg_launch_ms": round(dom["total_ms"] / dom["launches"], 4),
-                "algo_bytes_per_launch": int(dom["algo_bytes"] // dom["launches"])}
-    counts_he = g.triad_counts("hyperedge")
+    log_profile(args, prof)
+    totals = {k: int(sum(g.triad_counts(k))) for k in track}
     g.close()
-    # a plain device copy of known size (256 MiB read + 256 MiB written), outside
-    # the timed region: profiler byte counters are calibrated against it
-    calib = torch.empty(1 << 26, dtype=torch.int32, device=dev)
-    calib.fill_(1)
-    calib.clone()
-    torch.cuda.synchronize()
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        cpu = cpu_baseline(args, st, log)
-    out = {
-        "metric": "hyperedge updates/sec incl. triad-count update; p50/p99 batch latency",
-        "value": round(value, 1),
-        "unit": "updates/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(elapsed / max(args.steps, 1) * 1e3, 3),
-        "p50_ms": round(float(np.percentile(lat_ms, 50)), 3),
-        "p99_ms": round(float(np.percentile(lat_ms, 99)), 3),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "u64",
-        "data": "synthetic",
-        "config": {"workload": "medium: 1M vertices, 2M hyperedges, card power-law 2.5 on [2,64], popularity "
-                               "(rank+1e4)^-1.1, batches 50k ins + 50k del, hyperedge + incident-vertex triads",
-                   "scale": args.scale, "batch_updates": int(st.batches[-1].n_updates),
-                   "build_s": round(build_s, 3), "he_triads_total": int(sum(counts_he[i] for i in range(30)))},
-        "roofline": roofline,
-        "cpu_baseline": cpu,
+    calibration_copy()
+    lat_ms = np.array(lat) * 1e3
+    return {
+        "metric": METRIC, "value": round(value, 1), "unit": "updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(elapsed / max(args.steps, 1) * 1e3, 3),
+        "p50_ms": round(float(np.percentile(lat_ms, 50)), 3), "p99_ms": round(float(np.percentile(lat_ms, 99)), 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": workload, "scale": args.scale, "batch_updates": int(st.batches[-1].n_updates),
+                   "build_s": round(build_s, 3), "triads_total": totals},
+        "roofline": roofline_of(prof),
     }
-    print(json.dumps(out), flush=True)
 
 
-def cpu_baseline(args, st, log):
-    """The oracle as it is, on the GPU machine's host: one sample batch (the first
-    timed batch's first n/2 deletions and n/2 inserts) applied by the oracle's
-    batch semantics, the hyperedge-triad delta counted by definition and the
-    incident-vertex counts recounted, timed together."""
+def bench_batched(args):
+    """256 graphs; each round applies every graph's next batch, first with one
+    call per graph (plain), then, on an identical copy, with one call for all."""
+    import numpy as np
+    import torch
+    from paper_2512_21009_amd import hgt
+    from paper_2512_21009_amd import workloads as W
+    n_b = args.warmup + args.steps
+    t0 = time.perf_counter()
+    sc = args.scale
+    sts = W.batched(n_batches=n_b, e_lo=max(100.0, 1e3 * sc), e_hi=max(1e3, 2e5 * sc), b_hi=max(20.0, 5e4 * sc))
+    log(args, f"generated {len(sts)} graphs, {sum(s.initial.n for s in sts)} hyperedges, "
+              f"{sum(s.batches[0].n_updates for s in sts)} updates per round in {time.perf_counter() - t0:.1f}s")
+    ins = [[(to_dev(b.ins.offsets, np.int64) if b.ins.n else None, to_dev(b.ins.members, np.int32) if b.ins.n else None)
+            for b in st.batches] for st in sts]
+    dels = [ids_of_stream(hgt, st, i) for st, i in zip(sts, ins)]
+    track = ("hyperedge",)
+
+    def build_all():
+        out = []
+        for st in sts:
+            ini = st.initial
+            out.append(hgt.Graph.build(st.n_vertices, to_dev(ini.offsets, np.int64), to_dev(ini.members, np.int32),
+                                       track=track))
+        torch.cuda.synchronize()
+        return out
+
+    t0 = time.perf_counter()
+    plain = build_all()
+    build_s = time.perf_counter() - t0
+    batch = build_all()
+    log(args, f"built 2 x {len(sts)} graphs ({build_s:.2f}s per copy)")
+    ups = [sum(st.batches[k].n_updates for st in sts) for k in range(n_b)]
+    # plain: one call per graph
+    lat_p = []
+    for k in range(n_b):
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        for gi, g in enumerate(plain):
+            g.apply_batch(dels[gi][k], *ins[gi][k])
+        torch.cuda.synchronize()
+        if k >= args.warmup:
+            lat_p.append(time.perf_counter() - tb)
+    # batched: one call per round
+    lat_b = []
+    for k in range(n_b):
+        if k == args.warmup:
+            for g in batch:
+                g.profile(True)
+        items = [(g, dels[gi][k]) + ins[gi][k] for gi, g in enumerate(batch)]
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        hgt.apply_batches(items)
+        torch.cuda.synchronize()
+        if k >= args.warmup:
+            lat_b.append(time.perf_counter() - tb)
+    prof = {}
+    for g in batch:
+        add_profiles(prof, g.profile_read())
+    same = all(a.triad_counts("hyperedge") == b.triad_counts("hyperedge") for a, b in zip(plain, batch))
+    assert same, "batched and plain counts differ"
+    total = sum(sum(g.triad_counts("hyperedge")) for g in batch)
+    for g in plain + batch:
+        assert g.sync() == hgt.OK
+        g.close()
+    calibration_copy()
+    n_upd = sum(ups[args.warmup:])
+    v_b = n_upd / sum(lat_b)
+    v_p = n_upd / sum(lat_p)
+    log(args, f"plain {v_p:,.0f} updates/s, batched {v_b:,.0f} updates/s ({v_b / v_p:.2f}x)")
+    log_profile(args, prof)
+    lb, lp = np.array(lat_b) * 1e3, np.array(lat_p) * 1e3
+    return {
+        "metric": METRIC, "value": round(v_b, 1), "unit": "updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(float(lb.mean()), 3),
+        "p50_ms": round(float(np.percentile(lb, 50)), 3), "p99_ms": round(float(np.percentile(lb, 99)), 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": "batched: 256 graphs, |E| log-uniform [1k,200k], |V|=|E|/2, card power-law 2.5 on "
+                               "[2,256], batches log-uniform [10,50k] (60% inserts), hyperedge triads",
+                   "scale": sc, "round_updates": int(np.mean(ups[args.warmup:])), "build_s_per_copy": round(build_s, 3),
+                   "he_triads_total": int(total)},
+        "plain": {"value": round(v_p, 1), "p50_ms": round(float(np.percentile(lp, 50)), 3),
+                  "p99_ms": round(float(np.percentile(lp, 99)), 3)},
+        "speedup_vs_plain": round(v_b / v_p, 3),
+        "roofline": roofline_of(prof),
+    }, sts
+
+
+def cpu_baseline(args, st, families):
+    """The oracle as it is, on this host: one sample batch (the first batch's
+    first n/2 deletions and n/2 inserts) applied by the oracle's batch
+    semantics, the hyperedge-triad delta counted by definition and the other
+    tracked families recounted, timed together."""
     import numpy as np
     from oracle import oracle as orc
-    from paper_2512_21009_amd import workloads as W
 
     lib = orc.lib()
     threads = int(lib.orc_max_threads())
     ini = st.initial
-    o = orc.OracleGraph(st.n_vertices, ini.offsets, ini.members)
+    temporal = "temporal" in families
+    o = orc.OracleGraph(st.n_vertices, ini.offsets, ini.members, ts=ini.ts if temporal else None, window=st.window)
     b = st.batches[0]
     half = max(1, args.cpu_sample // 2)
     dels = b.del_handles[:half]  # the first batch deletes handles of the initial graph (= oracle IDs)
     sub = b.ins.rows(np.arange(min(half, b.ins.n)))
     t0 = time.perf_counter()
     old = o.copy()
-    status, ids = o.apply_batch(dels, sub.offsets, sub.members)
+    status, ids = o.apply_batch(dels, sub.offsets, sub.members, sub.ts if temporal else None)
     assert status == orc.OK
-    dhe, _ = orc.delta_by_definition(old, o, dels, ids)
-    iv = o.iv_counts()
+    what = []
+    if "hyperedge" in families or temporal:
+        orc.delta_by_definition(old, o, dels, ids)
+        what.append("hyperedge and temporal deltas by definition")
+    if "incident_vertex" in families:
+        o.iv_counts()
+        what.append("incident-vertex recount")
     el = time.perf_counter() - t0
     n = len(dels) + sub.n
     log(args, f"cpu oracle: {n} updates in {el:.2f}s on {threads} threads")
-    del W
     return {"value": round(n / el, 2), "unit": "updates/s", "cores": threads, "kind": "oracle",
-            "sample": f"{len(dels)} deletions + {sub.n} inserts of the first batch; hyperedge delta by definition "
-                      f"+ incident-vertex recount; {el:.1f}s", "iv_total": int(sum(iv.tolist())),
-            "he_delta_classes_nonzero": int((dhe != 0).sum())}
+            "sample": f"{len(dels)} deletions + {sub.n} inserts of the first batch of {st.name}; " + " + ".join(what)
+                      + f"; {el:.1f}s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1", "n_gpus": args.gpus}),
+              flush=True)
+        sys.exit(2)
+    from paper_2512_21009_amd import hgt, workloads as W
+
+    hgt.load()
+    n_b = args.warmup + args.steps
+    t0 = time.perf_counter()
+    if args.config == "batched":
+        out, sts = bench_batched(args)
+        cpu_st, fam = sorted(sts, key=lambda s: s.initial.n)[len(sts) // 2], ("hyperedge",)
+    else:
+        if args.config == "medium":
+            st = W.medium(q=1.0e4, scale=args.scale, n_batches=n_b)
+            track = ("hyperedge", "incident_vertex")
+            wl = ("medium: 1M vertices, 2M hyperedges, card power-law 2.5 on [2,64], popularity (rank+1e4)^-1.1, "
+                  "batches 50k ins + 50k del, hyperedge + incident-vertex triads")
+        else:
+            st = W.temporal(scale=args.scale, n_batches=n_b)
+            track = ("temporal",)
+            wl = ("temporal: 500k vertices, 4M hyperedges, card power-law 2.2 on [2,128], Poisson arrivals 1e3/s, "
+                  "batches of 200k arrivals, expiry 3600 s, temporal triads within 600 s")
+        log(args, f"generated {st.initial.n} hyperedges, {n_b} batches in {time.perf_counter() - t0:.1f}s")
+        out = bench_single(args, st, track, args.config, wl)
+        cpu_st, fam = st, track
+    out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline(args, cpu_st, fam)
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

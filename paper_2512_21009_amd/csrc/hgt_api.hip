@@ -4,6 +4,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -11,6 +12,35 @@
 #include "triad.h"
 
 namespace {
+
+// HGT_DEBUG=1 in the environment prints every failing HIP call to stderr.
+bool debug_on() {
+    static const bool on = [] {
+        const char* e = std::getenv("HGT_DEBUG");
+        return e && *e && *e != '0';
+    }();
+    return on;
+}
+
+bool hip_failed(hipError_t e, const char* what, int line) {
+    if (e == hipSuccess) return false;
+    (void)hipGetLastError();
+    if (debug_on()) std::fprintf(stderr, "hgt: %s failed at hgt_api.hip:%d: %s\n", what, line, hipGetErrorString(e));
+    return true;
+}
+
+// inside a do { ... } while (0) block that sets rc
+#define HIP_BRK(expr)                                    \
+    if (hip_failed((expr), #expr, __LINE__)) {           \
+        rc = HGT_EDEVICE;                                \
+        break;                                           \
+    }
+
+#define HIP_OK(expr)                                       \
+    do {                                                   \
+        if (hip_failed((expr), #expr, __LINE__)) return HGT_EDEVICE; \
+    } while (0)
+
 
 // ---------------------------------------------------------------------------
 // class tables: Venn pattern code -> class index (built from the definitions)
@@ -86,10 +116,7 @@ struct DevBuf {
 int dev_alloc(DevBuf& b, size_t bytes) {
     if (bytes == 0) bytes = 256;
     void* p = nullptr;
-    if (hipMalloc(&p, bytes) != hipSuccess) {
-        (void)hipGetLastError();
-        return HGT_ENOMEM;
-    }
+    if (hip_failed(hipMalloc(&p, bytes), "hipMalloc", __LINE__)) return HGT_ENOMEM;
     b.p = p;
     b.bytes = bytes;
     return HGT_OK;
@@ -117,11 +144,9 @@ int grow_keep(DevBuf& b, size_t bytes, size_t keep, hipStream_t s) {
     int rc = dev_alloc(nb, (bytes + 4095) & ~(size_t)4095);
     if (rc) return rc;
     if (keep && b.p) {
-        if (hipMemcpyAsync(nb.p, b.p, std::min(keep, b.bytes), hipMemcpyDeviceToDevice, s) != hipSuccess) {
-            dev_free(nb);
-            return HGT_EDEVICE;
-        }
-        if (hipStreamSynchronize(s) != hipSuccess) {
+        if (hip_failed(hipMemcpyAsync(nb.p, b.p, std::min(keep, b.bytes), hipMemcpyDeviceToDevice, s),
+                       "grow copy", __LINE__) ||
+            hip_failed(hipStreamSynchronize(s), "grow sync", __LINE__)) {
             dev_free(nb);
             return HGT_EDEVICE;
         }
@@ -144,9 +169,15 @@ constexpr int ACC_HE_M = 129, ACC_HE_P = 159, ACC_TMP_M = 189, ACC_TMP_P = 285, 
 
 }  // namespace
 
-// Scratch of the hyperedge/temporal triad phases.  A plain batch uses its own
-// graph's; a batched call uses the first graph's for all of its graphs.
+// Scratch of the triad phases, one per device, shared by every graph on it:
+// work of one call holds the lock while it queues its phases, and each call's
+// stream first waits for the previous user's (ordered reuse across streams).
 struct PhaseCtx {
+    std::mutex mu;
+    int device = 0;
+    int refs = 0;                 // graphs that use it
+    hipEvent_t done = nullptr;    // recorded after the last user's phases
+    DevBuf iv_list, iv_garena;    // incident-vertex stage scratch
     DevBuf t_ctr, t_big_list, t_big_rank, t_big_scratch, t_list1, t_rank1, t_list2, t_rank2, t_garena;
     DevBuf ent_x, ent_d, ent_pay, bl_cnt, bl_off, bl_cur, bl_d, bl_pay, nb_scratch, bl_scan;
     // per-graph phase descriptors: device copies and their pinned staging, one
@@ -173,9 +204,8 @@ struct hgt_graph {
         s_vp, s_staging, s_dst;
     // hyperedge-family neighbour histograms (2 words per h2v word)
     DevBuf hpool;
-    // scratch of the triad phases (also lent to batched calls led by this graph)
-    PhaseCtx ph;
-    DevBuf iv_keys, iv_alt, iv_sort, iv_head, iv_uniq, iv_p2, iv_scan, iv_tab, iv_owner, iv_ctr, iv_list, iv_garena;
+    PhaseCtx* ph = nullptr;  // the device's shared phase scratch
+    DevBuf iv_keys, iv_alt, iv_sort, iv_head, iv_uniq, iv_p2, iv_scan, iv_tab, iv_owner, iv_ctr;
     // host mirrors (valid after each synchronisation)
     uint64_t next_id = 0, h_bump = 0, v_bump = 0, next_seq = 0, n_live = 0, n_inc = 0;
     uint32_t epoch = 0;
@@ -226,14 +256,6 @@ struct ProfScope {
         g->recs.push_back({kind, a, b});
     }
 };
-
-#define HIP_OK(expr)                          \
-    do {                                      \
-        if ((expr) != hipSuccess) {           \
-            (void)hipGetLastError();          \
-            return HGT_EDEVICE;               \
-        }                                     \
-    } while (0)
 
 void refresh_view(hgt_graph* g) {
     StoreDev& s = g->st;
@@ -393,7 +415,7 @@ int ensure_plan_scratch(hgt_graph* g, const Sizes& z, PlanScratch& w) {
 void phase_ctx_free(PhaseCtx& c) {
     DevBuf* all[] = {&c.t_ctr, &c.t_big_list, &c.t_big_rank, &c.t_big_scratch, &c.t_list1, &c.t_rank1, &c.t_list2,
                      &c.t_rank2, &c.t_garena, &c.ent_x, &c.ent_d, &c.ent_pay, &c.bl_cnt, &c.bl_off, &c.bl_cur,
-                     &c.bl_d, &c.bl_pay, &c.nb_scratch, &c.bl_scan, &c.desc};
+                     &c.bl_d, &c.bl_pay, &c.nb_scratch, &c.bl_scan, &c.desc, &c.iv_list, &c.iv_garena};
     for (DevBuf* b : all) dev_free(*b);
     for (hipEvent_t& e : c.desc_ev) {
         if (e) (void)hipEventSynchronize(e);
@@ -403,6 +425,39 @@ void phase_ctx_free(PhaseCtx& c) {
     if (c.desc_host) (void)hipHostFree(c.desc_host);
     c.desc_host = nullptr;
     c.desc_cap = 0;
+    if (c.done) (void)hipEventDestroy(c.done);
+    c.done = nullptr;
+}
+
+std::mutex g_ctx_mu;
+std::vector<PhaseCtx*> g_ctx;  // by device
+
+PhaseCtx* phase_ctx_acquire(int device) {
+    std::lock_guard<std::mutex> lk(g_ctx_mu);
+    if ((int)g_ctx.size() <= device) g_ctx.resize(device + 1, nullptr);
+    PhaseCtx*& c = g_ctx[device];
+    if (!c) {
+        c = new (std::nothrow) PhaseCtx();
+        if (!c) return nullptr;
+        c->device = device;
+        if (hipEventCreateWithFlags(&c->done, hipEventDisableTiming) != hipSuccess) {
+            delete c;
+            c = nullptr;
+            return nullptr;
+        }
+    }
+    c->refs++;
+    return c;
+}
+
+// The last graph of a device frees the scratch.
+void phase_ctx_release(PhaseCtx* c) {
+    std::lock_guard<std::mutex> lk(g_ctx_mu);
+    if (--c->refs > 0) return;
+    (void)hipEventSynchronize(c->done);
+    phase_ctx_free(*c);
+    g_ctx[c->device] = nullptr;
+    delete c;
 }
 
 // One graph's share of a phase.
@@ -501,7 +556,7 @@ void collect(const PhaseJob* jobs, uint32_t nj, int family, bool minus, std::vec
 // histogram stages pass on, 6-8 temporal, 10-11 entry count, 16-18 stage queues,
 // 19-21 stage hand-over counts.
 int run_phase(hgt_graph* owner, const PhaseJob* jobs, uint32_t nj, bool minus, bool full, hipStream_t s) {
-    PhaseCtx& c = owner->ph;
+    PhaseCtx& c = *owner->ph;
     uint64_t* stats = owner->prof ? owner->stats.as<uint64_t>() : nullptr;
     const uint64_t n_cu = (uint64_t)owner->n_cu;
     std::vector<HeGraph> G;
@@ -773,7 +828,8 @@ int iv_phase(hgt_graph* g, const IvPlan& ip, bool minus, hipStream_t s) {
     if (ip.n_keys == 0) return HGT_OK;
     const uint64_t gwords = 1ull << 22;  // 16 MB per workgroup of the global stage
     const unsigned grid_g = 32;
-    if (ensure(g->iv_list, (ip.n_keys + 1) * 4) || ensure(g->iv_garena, (uint64_t)grid_g * gwords * 4))
+    PhaseCtx& c = *g->ph;
+    if (ensure(c.iv_list, (ip.n_keys + 1) * 4) || ensure(c.iv_garena, (uint64_t)grid_g * gwords * 4))
         return HGT_ENOMEM;
     IvParams P{};
     P.g = view_of(g);
@@ -788,8 +844,8 @@ int iv_phase(hgt_graph* g, const IvPlan& ip, bool minus, hipStream_t s) {
     P.status = &g->st.sc->status;
     P.queue = (uint32_t*)(ictr + 2);
     P.count = P.queue + 2;
-    P.list = g->iv_list.as<uint32_t>();
-    P.garena = g->iv_garena.as<uint32_t>();
+    P.list = c.iv_list.as<uint32_t>();
+    P.garena = c.iv_garena.as<uint32_t>();
     P.garena_words = gwords;
     P.stats = g->prof ? g->stats.as<uint64_t>() : nullptr;
     ProfScope ps(g, PK_IV_PAIRS, s);
@@ -889,13 +945,14 @@ PhaseJob job_plus(const Pending& p) {
 // Applies the planned batches of `ps` (all with rc == 0) on stream s: deltas on
 // the old graphs, delete + insert, deltas on the new graphs, count update.  The
 // hyperedge and temporal phases of all graphs share one launch per kernel.
-int apply_planned(hgt_graph* owner, std::vector<Pending*>& ps, hipStream_t s) {
+int apply_locked(hgt_graph* owner, std::vector<Pending*>& ps, hipStream_t s) {
+    int rc;
     std::vector<PhaseJob> jobs;
     jobs.reserve(ps.size());
     for (Pending* p : ps) jobs.push_back(job_minus(*p));
     bool full = !ps.empty() && ps[0]->check_order == 0;
     // step 2: deltas on the old graph
-    int rc = run_phase(owner, jobs.data(), (uint32_t)jobs.size(), true, false, s);
+    rc = run_phase(owner, jobs.data(), (uint32_t)jobs.size(), true, false, s);
     if (rc) return rc;
     for (Pending* p : ps)
         if ((p->g->track_mask & (1u << HGT_TRIAD_INCIDENT_VERTEX)) && (rc = iv_phase(p->g, p->ip, true, s)))
@@ -943,6 +1000,15 @@ int apply_planned(hgt_graph* owner, std::vector<Pending*>& ps, hipStream_t s) {
     return HGT_OK;
 }
 
+int apply_planned(hgt_graph* owner, std::vector<Pending*>& ps, hipStream_t s) {
+    PhaseCtx& c = *owner->ph;
+    std::lock_guard<std::mutex> lk(c.mu);
+    HIP_OK(hipStreamWaitEvent(s, c.done, 0));
+    int rc = apply_locked(owner, ps, s);
+    if (hipEventRecord(c.done, s) != hipSuccess && rc == HGT_OK) rc = HGT_EDEVICE;
+    return rc;
+}
+
 void set_sticky(hgt_graph* g, int rc) {
     if (rc && !g->sticky) g->sticky = rc;
 }
@@ -976,9 +1042,9 @@ void destroy_graph(hgt_graph* g) {
                      &g->s_h_rel, &g->s_keys, &g->s_keys_alt, &g->s_sort, &g->s_head, &g->s_is_ins, &g->s_tv,
                      &g->s_tseg, &g->s_D, &g->s_I, &g->s_It, &g->s_vp, &g->s_staging, &g->s_dst, &g->iv_keys, &g->iv_alt, &g->iv_sort,
                      &g->iv_head, &g->iv_uniq, &g->iv_p2, &g->iv_scan, &g->iv_tab, &g->iv_owner, &g->iv_ctr,
-                     &g->iv_list, &g->iv_garena, &g->hpool};
+                     &g->hpool};
     for (DevBuf* b : all) dev_free(*b);
-    phase_ctx_free(g->ph);
+    if (g->ph) phase_ctx_release(g->ph);
     dev_free(g->stats);
     for (hipEvent_t e : g->ev_pool) (void)hipEventDestroy(e);
     if (g->h_sum) (void)hipHostFree(g->h_sum);
@@ -1039,7 +1105,8 @@ int hgt_build(const hgt_build_desc* d, hgt_graph** out) {
     if (const char* fs = std::getenv("HGT_FORCE_STAGE")) g->force_stage = std::atoi(fs);
     int rc = HGT_OK;
     do {
-        if (hipGetDevice(&g->device) != hipSuccess) { rc = HGT_EDEVICE; break; }
+        HIP_BRK(hipGetDevice(&g->device));
+        if (!(g->ph = phase_ctx_acquire(g->device))) { rc = HGT_ENOMEM; break; }
         int ncu = 0;
         if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, g->device) == hipSuccess && ncu > 0)
             g->n_cu = ncu;
@@ -1055,11 +1122,9 @@ int hgt_build(const hgt_build_desc* d, hgt_graph** out) {
         uint64_t V = d->n_vertices;
         if ((rc = dev_alloc(g->v_off, V * 8)) || (rc = dev_alloc(g->v_len, V * 4)) || (rc = dev_alloc(g->v_cap, V * 4)))
             break;
-        if (hipMemsetAsync(g->v_off.p, 0, V * 8, s) != hipSuccess || hipMemsetAsync(g->v_len.p, 0, V * 4, s) != hipSuccess ||
-            hipMemsetAsync(g->v_cap.p, 0, V * 4, s) != hipSuccess) {
-            rc = HGT_EDEVICE;
-            break;
-        }
+        HIP_BRK(hipMemsetAsync(g->v_off.p, 0, V * 8, s));
+        HIP_BRK(hipMemsetAsync(g->v_len.p, 0, V * 4, s));
+        HIP_BRK(hipMemsetAsync(g->v_cap.p, 0, V * 4, s));
         uint64_t pw = d->pool_words ? d->pool_words : 1 << 20;
         if ((rc = dev_alloc(g->h2v, pw * 4)) || (rc = dev_alloc(g->v2h, pw * 4))) break;
         if ((d->track_mask & (1u << HGT_TRIAD_HYPEREDGE)) && (rc = dev_alloc(g->hpool, pw * 8))) break;
@@ -1072,29 +1137,23 @@ int hgt_build(const hgt_build_desc* d, hgt_graph** out) {
         uint8_t tb[256];
         std::memcpy(tb, t.he, 128);
         std::memcpy(tb + 128, t.tmp, 128);
-        if (hipMemcpyAsync(g->scal.p, &z, sizeof z, hipMemcpyHostToDevice, s) != hipSuccess ||
-            hipMemsetAsync(g->counts.p, 0, ACC_N * 8, s) != hipSuccess ||
-            hipMemcpyAsync(g->tabs.p, tb, 256, hipMemcpyHostToDevice, s) != hipSuccess ||
-            hipStreamSynchronize(s) != hipSuccess) {
-            rc = HGT_EDEVICE;
-            break;
-        }
+        HIP_BRK(hipMemcpyAsync(g->scal.p, &z, sizeof z, hipMemcpyHostToDevice, s));
+        HIP_BRK(hipMemsetAsync(g->counts.p, 0, ACC_N * 8, s));
+        HIP_BRK(hipMemcpyAsync(g->tabs.p, tb, 256, hipMemcpyHostToDevice, s));
+        HIP_BRK(hipStreamSynchronize(s));
         refresh_view(g);
         if (d->n_edges) {
             // build = insert every hyperedge into the empty graph; the inserted
             // hyperedges' deltas are the initial counts
             uint64_t first = 0, last = 0;
-            if (hipMemcpy(&first, d->offsets, 8, hipMemcpyDeviceToHost) != hipSuccess ||
-                hipMemcpy(&last, d->offsets + d->n_edges, 8, hipMemcpyDeviceToHost) != hipSuccess) {
-                rc = HGT_EDEVICE;
-                break;
-            }
+            HIP_BRK(hipMemcpy(&first, d->offsets, 8, hipMemcpyDeviceToHost));
+            HIP_BRK(hipMemcpy(&last, d->offsets + d->n_edges, 8, hipMemcpyDeviceToHost));
             if (last < first) { rc = HGT_EINVAL; break; }
             if (tmp) store_max_ts(d->timestamps, d->n_edges, g->st.sc, s);
             rc = apply(g, nullptr, 0, d->offsets, d->members, last - first, tmp ? d->timestamps : nullptr, d->n_edges,
                        nullptr, s, 0);
             if (rc) break;
-            if (hipStreamSynchronize(s) != hipSuccess) { rc = HGT_EDEVICE; break; }
+            HIP_BRK(hipStreamSynchronize(s));
         }
     } while (0);
     if (rc) {
@@ -1124,7 +1183,7 @@ int hgt_apply_batches(hgt_batch* bs, uint32_t n, void* stream) {
     {
         std::vector<hgt_graph*> gs;
         for (uint32_t i = 0; i < n; i++) {
-            if (!bs[i].graph) return HGT_EINVAL;
+            if (!bs[i].graph || bs[i].graph->device != bs[0].graph->device) return HGT_EINVAL;
             gs.push_back(bs[i].graph);
         }
         std::sort(gs.begin(), gs.end());

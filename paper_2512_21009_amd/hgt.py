@@ -101,6 +101,9 @@ def load(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it with `python -m paper_2512_21009_amd.build`")
+    # torch first: the library then binds to the HIP runtime torch has loaded,
+    # so torch's streams and allocations belong to the runtime it calls
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     P, U64, U32, I64, I32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int64, ctypes.c_int
     lib.hgt_build.argtypes = [ctypes.POINTER(BuildDesc), ctypes.POINTER(P)]

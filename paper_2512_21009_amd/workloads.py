@@ -100,11 +100,17 @@ def draw_members(rng: np.random.Generator, cards: np.ndarray, pop: Popularity) -
         rows = order[:n_rows]
         vals = pop.draw(rng, n_rows)
         pending = np.arange(n_rows)
+        cols = np.arange(c, dtype=np.int64)
         while True:
-            bad = np.zeros(len(pending), dtype=bool)
             base = offsets[rows[pending]]
-            for p in range(c):
-                bad |= out[base + p] == vals[pending]
+            if c == 0:
+                bad = np.zeros(len(pending), dtype=bool)
+            else:
+                bad = np.zeros(len(pending), dtype=bool)
+                step = max(1, (1 << 22) // c)  # bound the temporary (rows x columns) array
+                for a in range(0, len(pending), step):
+                    blk = slice(a, a + step)
+                    bad[blk] = (out[base[blk, None] + cols] == vals[pending[blk], None]).any(axis=1)
             if not bad.any():
                 out[base + c] = vals[pending]
                 break
@@ -286,10 +292,10 @@ def log_uniform_int(rng: np.random.Generator, lo: float, hi: float, size=None) -
 
 
 def batched(seed: int = SEED_BASE + 4, n_graphs: int = 256, e_lo: float = 1e3, e_hi: float = 2e5,
-            b_lo: float = 10, b_hi: float = 5e4, card_hi: int = 256) -> List[Stream]:
+            b_lo: float = 10, b_hi: float = 5e4, card_hi: int = 256, n_batches: int = 1) -> List[Stream]:
     """n_graphs independent hypergraphs, |E_g| log-uniform in [e_lo, e_hi],
     |V_g| = |E_g| / 2, card power law 2.5 on [2, card_hi], uniform popularity;
-    each with one batch of log-uniform size in [b_lo, b_hi] (60% inserts)."""
+    each with batches of one log-uniform size in [b_lo, b_hi] (60% inserts)."""
     rng = np.random.default_rng(seed)
     sizes = log_uniform_int(rng, e_lo, e_hi, n_graphs)
     bsz = log_uniform_int(rng, b_lo, b_hi, n_graphs)
@@ -301,5 +307,5 @@ def batched(seed: int = SEED_BASE + 4, n_graphs: int = 256, e_lo: float = 1e3, e
         n_i = int(round(0.6 * n_b))
         n_d = n_b - n_i
         out.append(plain_stream(f"batched[{g}]", nv, ne, ("power", 2.5, 2, card_hi), 0.0, 0.0,
-                                1, n_i, n_d, seed * 1000 + g))
+                                n_batches, n_i, n_d, seed * 1000 + g))
     return out

@@ -144,6 +144,88 @@ typedef struct {
  * applied, else the first failing batch's status. */
 int hgt_apply_batches(hgt_batch* batches, uint32_t n, void* stream);
 
+/* ---- served form ------------------------------------------------------- */
+/* A request server over many resident hypergraphs ("tenants").  Clients
+ * submit update batches from host memory at any time; a server thread merges
+ * the admitted requests of distinct tenants into rounds, each applied like
+ * one hgt_apply_batches call, and starts a new round while earlier ones are
+ * still on the GPU (continuous batching).  Per tenant, requests are applied
+ * in submission order, one at a time, so each result equals that of applying
+ * the tenant's requests alone with hgt_apply_batch.
+ * Admission: a request's inputs, assigned IDs and result counts live in a
+ * device arena (with a pinned host mirror) of desc.arena_bytes; it is
+ * admitted when its arena range fits and the footprint estimate of all
+ * admitted requests (inputs + batch scratch, from the request sizes and the
+ * tenant's mean cardinality) stays within desc.hbm_budget_bytes.  A request
+ * whose footprint alone exceeds the budget runs in a round of its own. */
+typedef struct hgt_server hgt_server;
+
+typedef struct {
+    uint64_t hbm_budget_bytes;  /* footprint limit of the admitted requests     */
+    uint64_t arena_bytes;       /* device arena for request buffers (0: 256 MiB) */
+    uint32_t max_round;         /* most requests merged into one round (0: 256) */
+    uint32_t max_inflight;      /* rounds on the GPU at once, 1 or 2 (0: 2)      */
+} hgt_server_desc;
+
+/* One update request (host buffers, copied by hgt_server_submit): the
+ * arguments of hgt_apply_batch.  out_ins_ids_host (may be NULL) receives the
+ * assigned IDs and must stay valid until hgt_server_wait returns. */
+typedef struct {
+    const uint32_t* del_ids;
+    uint64_t n_del;
+    const uint64_t* ins_offsets;
+    const uint32_t* ins_members;
+    uint64_t n_ins_members;
+    const int64_t* ins_ts;
+    uint64_t n_ins;
+    uint32_t* out_ins_ids_host;
+} hgt_request;
+
+/* Result of a request: its status, the tenant's counts after it (families the
+ * tenant does not track are 0) and its times in ns of a monotonic clock. */
+typedef struct {
+    int32_t status;
+    uint32_t tenant;
+    uint64_t he[30];
+    uint64_t iv[3];
+    uint64_t temporal[96];
+    uint64_t t_submit_ns, t_admit_ns, t_done_ns;
+    uint64_t round;             /* the round that applied it                   */
+    uint32_t round_size;        /* requests in that round                      */
+    uint32_t pad0;
+} hgt_result;
+
+typedef struct {
+    uint64_t rounds, requests_done, requests_pending, requests_running;
+    uint64_t footprint_in_use, arena_in_use;
+    uint64_t max_round_size, max_inflight_seen;
+} hgt_server_info;
+
+/* Creates a server on the current device and starts its thread. */
+int hgt_server_create(const hgt_server_desc* d, hgt_server** out);
+
+/* Builds a tenant (as hgt_build, on the server's stream) and returns its index. */
+int hgt_server_add_tenant(hgt_server* s, const hgt_build_desc* d, uint32_t* tenant);
+
+/* The tenant's graph, for queries while the server holds none of its requests. */
+int hgt_server_tenant_graph(hgt_server* s, uint32_t tenant, hgt_graph** out);
+
+/* Copies the request and queues it; *ticket names it.  HGT_ENOMEM when it
+ * can never fit the arena, HGT_EINVAL for bad arguments. */
+int hgt_server_submit(hgt_server* s, uint32_t tenant, const hgt_request* r, uint64_t* ticket);
+
+/* Waits until the request is done and fills *out (may be NULL); the ticket is
+ * then released.  Returns the request's status. */
+int hgt_server_wait(hgt_server* s, uint64_t ticket, hgt_result* out);
+
+/* *done = 1 when the request has completed (non-blocking). */
+int hgt_server_query(hgt_server* s, uint64_t ticket, int* done);
+
+int hgt_server_get_info(hgt_server* s, hgt_server_info* out);
+
+/* Waits for all submitted requests, stops the thread and destroys the tenants. */
+int hgt_server_destroy(hgt_server* s);
+
 /* ---- queries ---------------------------------------------------------- */
 /* Copies the maintained counts of family `type` to out_host[0..n_out) (host).
  * n_out must be at least 30 / 3 / 96.  `window` must be 0 for the hyperedge

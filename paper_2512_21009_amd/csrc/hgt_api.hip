@@ -8,6 +8,7 @@
 #include <new>
 #include <vector>
 
+#include "internal.h"
 #include "store.h"
 #include "triad.h"
 
@@ -1053,6 +1054,23 @@ void destroy_graph(hgt_graph* g) {
 }
 
 }  // namespace
+
+// ---- hooks for the request server (internal.h) -----------------------------
+int hgt_counts_async(hgt_graph* g, uint64_t* dst, hipStream_t s) {
+    static_assert(CNT_N == HGT_COUNT_WORDS, "count layout");
+    HIP_OK(hipMemcpyAsync(dst, g->counts.p, CNT_N * 8, hipMemcpyDeviceToHost, s));
+    return HGT_OK;
+}
+
+HgtSizes hgt_sizes(hgt_graph* g) {
+    HgtSizes z;
+    z.n_vertices = g->st.n_vertices;
+    z.track_mask = g->track_mask;
+    z.n_live = g->n_live;
+    z.n_inc = g->n_inc;
+    z.device = g->device;
+    return z;
+}
 
 // ===========================================================================
 // C ABI

@@ -87,11 +87,56 @@ class Batch(ctypes.Structure):
     ]
 
 
+class ServerDesc(ctypes.Structure):
+    _fields_ = [
+        ("hbm_budget_bytes", ctypes.c_uint64),
+        ("arena_bytes", ctypes.c_uint64),
+        ("max_round", ctypes.c_uint32),
+        ("max_inflight", ctypes.c_uint32),
+    ]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [
+        ("del_ids", ctypes.c_void_p),
+        ("n_del", ctypes.c_uint64),
+        ("ins_offsets", ctypes.c_void_p),
+        ("ins_members", ctypes.c_void_p),
+        ("n_ins_members", ctypes.c_uint64),
+        ("ins_ts", ctypes.c_void_p),
+        ("n_ins", ctypes.c_uint64),
+        ("out_ins_ids_host", ctypes.c_void_p),
+    ]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int32),
+        ("tenant", ctypes.c_uint32),
+        ("he", ctypes.c_uint64 * 30),
+        ("iv", ctypes.c_uint64 * 3),
+        ("temporal", ctypes.c_uint64 * 96),
+        ("t_submit_ns", ctypes.c_uint64),
+        ("t_admit_ns", ctypes.c_uint64),
+        ("t_done_ns", ctypes.c_uint64),
+        ("round", ctypes.c_uint64),
+        ("round_size", ctypes.c_uint32),
+        ("pad0", ctypes.c_uint32),
+    ]
+
+
+class ServerInfo(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_uint64) for f in ("rounds", "requests_done", "requests_pending", "requests_running",
+                                               "footprint_in_use", "arena_in_use", "max_round_size",
+                                               "max_inflight_seen")]
+
+
 _lib = None
 
 EXPORTS = ["hgt_build", "hgt_apply_batch", "hgt_apply_batches", "hgt_triad_counts", "hgt_sync", "hgt_destroy", "hgt_status_str",
            "hgt_get_info", "hgt_export_h2v", "hgt_export_v2h", "hgt_class_codes", "hgt_profile",
-           "hgt_profile_read"]
+           "hgt_profile_read", "hgt_server_create", "hgt_server_add_tenant", "hgt_server_tenant_graph",
+           "hgt_server_submit", "hgt_server_wait", "hgt_server_query", "hgt_server_get_info", "hgt_server_destroy"]
 
 
 def load(path: str = LIB_PATH):
@@ -120,6 +165,14 @@ def load(path: str = LIB_PATH):
     lib.hgt_class_codes.argtypes = [I32, P, U32]
     lib.hgt_profile.argtypes = [P, I32]
     lib.hgt_profile_read.argtypes = [P, P, U32, ctypes.POINTER(U32)]
+    lib.hgt_server_create.argtypes = [ctypes.POINTER(ServerDesc), ctypes.POINTER(P)]
+    lib.hgt_server_add_tenant.argtypes = [P, ctypes.POINTER(BuildDesc), ctypes.POINTER(U32)]
+    lib.hgt_server_tenant_graph.argtypes = [P, U32, ctypes.POINTER(P)]
+    lib.hgt_server_submit.argtypes = [P, U32, ctypes.POINTER(Request), ctypes.POINTER(U64)]
+    lib.hgt_server_wait.argtypes = [P, U64, ctypes.POINTER(Result)]
+    lib.hgt_server_query.argtypes = [P, U64, ctypes.POINTER(I32)]
+    lib.hgt_server_get_info.argtypes = [P, ctypes.POINTER(ServerInfo)]
+    lib.hgt_server_destroy.argtypes = [P]
     for name in EXPORTS:
         getattr(lib, name).restype = getattr(lib, name).restype or ctypes.c_int
     lib.hgt_status_str.restype = ctypes.c_char_p
@@ -213,6 +266,24 @@ def apply_batches(items, stream=None, raise_on_error: bool = True):
     return rc, status, outs
 
 
+def _build_desc(n_vertices, offsets, members, timestamps, track, window, edge_capacity, pool_words):
+    import torch
+    _check_dtype(offsets, (torch.int64, torch.uint64), "offsets")
+    _check_dtype(members, (torch.int32, torch.uint32), "members")
+    _check_dtype(timestamps, (torch.int64,), "timestamps")
+    d = BuildDesc()
+    d.n_vertices = int(n_vertices)
+    d.n_edges = int(offsets.numel() - 1)
+    d.offsets = _ptr(offsets)
+    d.members = _ptr(members)
+    d.timestamps = _ptr(timestamps)
+    d.track_mask = _mask(track)
+    d.temporal_window = int(window)
+    d.edge_capacity = int(edge_capacity)
+    d.pool_words = int(pool_words)
+    return d
+
+
 class Graph:
     """A hypergraph resident on the current GPU with incrementally maintained
     triad counts (hyperedge 30 classes, incident-vertex 3 types, temporal 96)."""
@@ -228,21 +299,8 @@ class Graph:
               edge_capacity: int = 0, pool_words: int = 0, stream=None) -> "Graph":
         """offsets: int64 device tensor [E+1]; members: int32/uint32 device
         tensor; timestamps: int64 device tensor [E] (temporal)."""
-        import torch
         lib = load()
-        _check_dtype(offsets, (torch.int64, torch.uint64), "offsets")
-        _check_dtype(members, (torch.int32, torch.uint32), "members")
-        _check_dtype(timestamps, (torch.int64,), "timestamps")
-        d = BuildDesc()
-        d.n_vertices = int(n_vertices)
-        d.n_edges = int(offsets.numel() - 1)
-        d.offsets = _ptr(offsets)
-        d.members = _ptr(members)
-        d.timestamps = _ptr(timestamps)
-        d.track_mask = _mask(track)
-        d.temporal_window = int(window)
-        d.edge_capacity = int(edge_capacity)
-        d.pool_words = int(pool_words)
+        d = _build_desc(n_vertices, offsets, members, timestamps, track, window, edge_capacity, pool_words)
         d.stream = _stream(stream)
         out = ctypes.c_void_p()
         rc = lib.hgt_build(ctypes.byref(d), ctypes.byref(out))
@@ -348,6 +406,108 @@ class Graph:
     def close(self):
         if self._h and self._h.value:
             load().hgt_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """The served form: resident tenants, requests submitted from host arrays
+    (copied at submit), applied in continuous-batching rounds by the
+    library's server thread."""
+
+    def __init__(self, hbm_budget_bytes: int = 8 << 30, arena_bytes: int = 0, max_round: int = 0,
+                 max_inflight: int = 0):
+        lib = load()
+        d = ServerDesc(int(hbm_budget_bytes), int(arena_bytes), int(max_round), int(max_inflight))
+        out = ctypes.c_void_p()
+        rc = lib.hgt_server_create(ctypes.byref(d), ctypes.byref(out))
+        if rc != OK:
+            raise HgtError(rc, "hgt_server_create")
+        self._h = out
+        self._ids = {}      # ticket -> (numpy out-ID buffer, keep-alive inputs)
+        self._track = {}
+
+    def add_tenant(self, n_vertices: int, offsets, members, timestamps=None, track=("hyperedge",), window: int = 0,
+                   edge_capacity: int = 0, pool_words: int = 0) -> int:
+        d = _build_desc(n_vertices, offsets, members, timestamps, track, window, edge_capacity, pool_words)
+        t = ctypes.c_uint32()
+        rc = load().hgt_server_add_tenant(self._h, ctypes.byref(d), ctypes.byref(t))
+        if rc != OK:
+            raise HgtError(rc, "hgt_server_add_tenant")
+        self._track[t.value] = (d.track_mask, int(window))
+        return t.value
+
+    def tenant_graph(self, tenant: int) -> "Graph":
+        """A non-owning Graph view of the tenant (for queries while it is idle)."""
+        out = ctypes.c_void_p()
+        rc = load().hgt_server_tenant_graph(self._h, int(tenant), ctypes.byref(out))
+        if rc != OK:
+            raise HgtError(rc, "hgt_server_tenant_graph")
+        g = Graph(out.value, self._track[tenant][1], self._track[tenant][0])
+        g.close = lambda: None  # the server owns it
+        return g
+
+    def submit(self, tenant: int, del_ids=None, ins_offsets=None, ins_members=None, ins_ts=None) -> int:
+        """Host numpy arrays (del_ids u32, ins_offsets u64 [n+1], ins_members u32,
+        ins_ts i64).  Returns the ticket."""
+        import numpy as np
+        r = Request()
+        keep = []
+
+        def arr(a, dt):
+            if a is None:
+                return None, 0
+            a = np.ascontiguousarray(np.asarray(a).astype(dt, copy=False))
+            keep.append(a)
+            return (a.ctypes.data if a.size else None), a.size
+        r.del_ids, r.n_del = arr(del_ids, np.uint32)
+        off, n_off = arr(ins_offsets, np.uint64)
+        r.n_ins = max(n_off - 1, 0)
+        r.ins_offsets = off if r.n_ins else None
+        r.ins_members, r.n_ins_members = arr(ins_members, np.uint32)
+        r.ins_ts, _ = arr(ins_ts, np.int64)
+        ids = np.zeros(max(r.n_ins, 1), np.uint32)
+        r.out_ins_ids_host = ids.ctypes.data if r.n_ins else None
+        t = ctypes.c_uint64()
+        rc = load().hgt_server_submit(self._h, int(tenant), ctypes.byref(r), ctypes.byref(t))
+        if rc != OK:
+            raise HgtError(rc, "hgt_server_submit")
+        self._ids[t.value] = (ids[: r.n_ins], keep)
+        return t.value
+
+    def wait(self, ticket: int) -> dict:
+        res = Result()
+        rc = load().hgt_server_wait(self._h, int(ticket), ctypes.byref(res))
+        ids, _ = self._ids.pop(ticket, (None, None))
+        if rc == EINVAL and res.t_submit_ns == 0:
+            raise HgtError(rc, "hgt_server_wait")
+        return {"status": res.status, "tenant": res.tenant, "hyperedge": list(res.he),
+                "incident_vertex": list(res.iv), "temporal": list(res.temporal), "ids": ids,
+                "t_submit_ns": res.t_submit_ns, "t_admit_ns": res.t_admit_ns, "t_done_ns": res.t_done_ns,
+                "round": res.round, "round_size": res.round_size}
+
+    def query(self, ticket: int) -> bool:
+        d = ctypes.c_int(0)
+        rc = load().hgt_server_query(self._h, int(ticket), ctypes.byref(d))
+        if rc != OK:
+            raise HgtError(rc, "hgt_server_query")
+        return bool(d.value)
+
+    def info(self) -> dict:
+        inf = ServerInfo()
+        rc = load().hgt_server_get_info(self._h, ctypes.byref(inf))
+        if rc != OK:
+            raise HgtError(rc, "hgt_server_get_info")
+        return {f: getattr(inf, f) for f, _ in ServerInfo._fields_}
+
+    def close(self):
+        if self._h and self._h.value:
+            load().hgt_server_destroy(self._h)
             self._h = ctypes.c_void_p()
 
     def __del__(self):

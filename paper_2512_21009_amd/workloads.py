@@ -309,3 +309,85 @@ def batched(seed: int = SEED_BASE + 4, n_graphs: int = 256, e_lo: float = 1e3, e
         out.append(plain_stream(f"batched[{g}]", nv, ne, ("power", 2.5, 2, card_hi), 0.0, 0.0,
                                 n_batches, n_i, n_d, seed * 1000 + g))
     return out
+
+
+@dataclass
+class Served:
+    """Tenants (one Stream each; its batches are the tenant's requests in
+    order) and the arrival sequence: (arrival time in us, tenant, index of the
+    request in the tenant's stream, reported family)."""
+    tenants: List[Stream]
+    arrivals: List[tuple]
+
+
+FAMILIES = ("hyperedge", "incident_vertex", "temporal")
+
+
+def tenant_stream(name: str, n_vertices: int, n_edges: int, alpha: float, card_hi: int, pop_s: float, pop_q: float,
+                  sizes: List[tuple], mean_gap_us: float, window_us: int, seed: int) -> Stream:
+    """A tenant: n_edges initial hyperedges with Poisson timestamps, then one
+    batch per (n_ins, n_del) in `sizes`: n_del deletions uniform over the live
+    hyperedges and n_ins new ones from the same distribution, stamped after
+    every earlier hyperedge of the tenant."""
+    rng = np.random.default_rng(seed)
+    pop = Popularity(n_vertices, pop_s, pop_q, rng)
+    hi = min(card_hi, n_vertices)
+    c0 = power_law_cards(rng, n_edges, alpha, 2, hi)
+    ts0 = poisson_times(rng, n_edges, mean_gap_us)
+    initial = _csr(c0, draw_members(rng, c0, pop), ts0)
+    st = Stream(name, n_vertices, initial, window=int(window_us),
+                params=dict(n_edges=n_edges, alpha=alpha, card_hi=card_hi, pop_s=pop_s, pop_q=pop_q, seed=seed))
+    live = np.arange(n_edges, dtype=np.int64)
+    next_handle = n_edges
+    t_last = int(ts0[-1]) if n_edges else 0
+    for n_ins, n_del in sizes:
+        k = min(int(n_del), len(live))
+        pick = rng.choice(len(live), size=k, replace=False)
+        dels = live[pick]
+        keep = np.ones(len(live), dtype=bool)
+        keep[pick] = False
+        ci = power_law_cards(rng, int(n_ins), alpha, 2, hi)
+        ts = poisson_times(rng, int(n_ins), mean_gap_us, t_last)
+        if n_ins:
+            t_last = int(ts[-1])
+        ins = _csr(ci, draw_members(rng, ci, pop), ts)
+        ih = np.arange(next_handle, next_handle + int(n_ins), dtype=np.int64)
+        next_handle += int(n_ins)
+        live = np.concatenate([live[keep], ih])
+        st.batches.append(Batch(dels.astype(np.int64), ins, ih))
+    return st
+
+
+def served(seed: int = SEED_BASE + 5, n_tenants: int = 64, total_edges: float = 20e6, n_requests: int = 256,
+           rate_per_s: float = 1000.0, req_lo: float = 1, req_hi: float = 1e5, card_hi: int = 4096,
+           pop_q: float = 3.0e3, size_lo: float = 1e4, size_hi: float = 1e6,
+           window_us: int = 600_000_000) -> Served:
+    """64 tenants with sizes log-uniform in [size_lo, size_hi] rescaled to
+    total_edges hyperedges, |V_t| = |E_t| / 2, cardinality power law 2.0 on
+    [2, card_hi], popularity (rank + pop_q)^-1.3, Poisson timestamps (1e3/s,
+    us) and window 600 s; n_requests requests with Poisson arrivals at
+    rate_per_s, tenant uniform, size log-uniform in [req_lo, req_hi] (half
+    inserts, half deletions), reported family uniform."""
+    rng = np.random.default_rng(seed)
+    w = np.exp(rng.uniform(np.log(size_lo), np.log(size_hi), n_tenants))
+    n_e = np.maximum(np.round(w / w.sum() * total_edges).astype(np.int64), 64)
+    tenant_of = rng.integers(0, n_tenants, n_requests)
+    sizes = log_uniform_int(rng, req_lo, req_hi, n_requests)
+    fam = rng.integers(0, 3, n_requests)
+    gaps = rng.exponential(1e6 / rate_per_s, n_requests)
+    t_arr = np.cumsum(gaps)
+    per = [[] for _ in range(n_tenants)]
+    arrivals = []
+    for r in range(n_requests):
+        t = int(tenant_of[r])
+        n = int(sizes[r])
+        n_ins = (n + 1) // 2
+        per[t].append((n_ins, n - n_ins))
+        arrivals.append((float(t_arr[r]), t, len(per[t]) - 1, FAMILIES[int(fam[r])]))
+    tenants = []
+    for t in range(n_tenants):
+        ne = int(n_e[t])
+        nv = max(64, ne // 2)
+        tenants.append(tenant_stream(f"served[{t}]", nv, ne, 2.0, card_hi, 1.3, pop_q, per[t], 1000.0,
+                                     window_us, seed * 1000 + t))
+    return Served(tenants, arrivals)

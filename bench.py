@@ -18,6 +18,14 @@ resident in HBM before timing starts.  Workloads (--config):
            (60% inserts); hyperedge triads.  Every round is timed twice on
            identical copies: one hgt_apply_batch call per graph (plain) and one
            hgt_apply_batches call for all graphs (batched).
+  served   64 tenants totalling 20M hyperedges (|V_t| = |E_t|/2), cardinality
+           power law 2.0 on [2,256], popularity (rank + 3e3)^-1.3, Poisson
+           timestamps, every family tracked (temporal window 600 s); requests
+           of log-uniform size in [1,1e5] (half inserts) for uniform tenants.
+           All requests are first applied one at a time with hgt_apply_batch
+           on one copy of the tenants (plain), then submitted together to a
+           request server holding another copy (served); every request's
+           counts must agree.  p50/p99 are per request, submission to completion.
 
 Prints one JSON line.  Only one GPU is used.
 """
@@ -40,7 +48,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=9)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", choices=("medium", "temporal", "batched"), default="medium")
+    ap.add_argument("--config", choices=("medium", "temporal", "batched", "served"), default="medium")
+    ap.add_argument("--requests", type=int, default=256, help="served: number of requests")
     ap.add_argument("--scale", type=float, default=1.0, help="workload scale (1.0 = the named configuration)")
     ap.add_argument("--cpu-sample", type=int, default=600, help="updates in the oracle's timed sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -264,6 +273,102 @@ def bench_batched(args):
     }, sts
 
 
+def bench_served(args):
+    import numpy as np
+    import torch
+    from paper_2512_21009_amd import hgt
+    from paper_2512_21009_amd import workloads as W
+    fams = W.FAMILIES
+    t0 = time.perf_counter()
+    sc = args.scale
+    sv = W.served(total_edges=20e6 * sc, n_requests=args.requests, req_hi=max(10.0, 1e5 * sc), card_hi=256)
+    n_req = len(sv.arrivals)
+    log(args, f"generated {len(sv.tenants)} tenants, {sum(t.initial.n for t in sv.tenants)} hyperedges, "
+              f"{n_req} requests in {time.perf_counter() - t0:.1f}s")
+    # deletion IDs: a store-only replay of each tenant's requests in order
+    ins = [[(to_dev(b.ins.offsets, np.int64) if b.ins.n else None, to_dev(b.ins.members, np.int32) if b.ins.n else None)
+            for b in st.batches] for st in sv.tenants]
+    dels = [ids_of_stream(hgt, st, i) for st, i in zip(sv.tenants, ins)]
+    log(args, "deletion IDs replayed")
+    del_host = [[d.cpu().numpy().astype(np.uint32) if d is not None else np.zeros(0, np.uint32) for d in dl]
+                for dl in dels]
+    its = [[to_dev(b.ins.ts, np.int64) if b.ins.n else None for b in st.batches] for st in sv.tenants]
+
+    def build_args(st):
+        ini = st.initial
+        return (st.n_vertices, to_dev(ini.offsets, np.int64), to_dev(ini.members, np.int32), to_dev(ini.ts, np.int64))
+
+    t0 = time.perf_counter()
+    plain = []
+    for i, st in enumerate(sv.tenants):
+        tb = time.perf_counter()
+        plain.append(hgt.Graph.build(*build_args(st), track=fams, window=st.window))
+        torch.cuda.synchronize()
+        log(args, f"tenant {i}: {st.initial.n} hyperedges built in {time.perf_counter() - tb:.2f}s")
+    build_s = time.perf_counter() - t0
+    log(args, f"built {len(plain)} tenants in {build_s:.2f}s")
+    ups = [sv.tenants[tn].batches[k].n_updates for (_, tn, k, _) in sv.arrivals]
+    # plain: one request at a time, in arrival order
+    lat_p, want = [], []
+    for i, (_, tn, k, fam) in enumerate(sv.arrivals):
+        g = plain[tn]
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        g.apply_batch(dels[tn][k], *ins[tn][k], its[tn][k])
+        torch.cuda.synchronize()
+        lat_p.append(time.perf_counter() - tb)
+        want.append(g.triad_counts(fam))
+        if i % 32 == 31:
+            log(args, f"plain: {i + 1} requests, {sum(lat_p):.2f}s")
+    for g in plain:
+        assert g.sync() == hgt.OK
+        g.close()
+    del plain
+    # served: a server over an identical copy, every request submitted at once
+    srv = hgt.Server(hbm_budget_bytes=64 << 30, arena_bytes=2 << 30)
+    for i, st in enumerate(sv.tenants):
+        srv.add_tenant(*build_args(st), track=fams, window=st.window)
+        if i % 8 == 7:
+            log(args, f"server: {i + 1} tenants built")
+    torch.cuda.synchronize()
+    reqs = []
+    for (_, tn, k, fam) in sv.arrivals:
+        b = sv.tenants[tn].batches[k]
+        reqs.append((tn, del_host[tn][k], b.ins.offsets.astype(np.uint64), b.ins.members.astype(np.uint32),
+                     b.ins.ts.astype(np.int64)))
+    t_start = time.perf_counter()
+    tickets = [srv.submit(*r) for r in reqs]
+    res = [srv.wait(t) for t in tickets]
+    el = time.perf_counter() - t_start
+    info = srv.info()
+    for i, (r, (_, tn, k, fam)) in enumerate(zip(res, sv.arrivals)):
+        assert r["status"] == hgt.OK, (i, r["status"])
+        assert r[fam] == want[i], f"request {i}: served and plain counts differ"
+    srv.close()
+    calibration_copy()
+    n_upd = sum(ups)
+    v_s, v_p = n_upd / el, n_upd / sum(lat_p)
+    lat_s = np.array([(r["t_done_ns"] - r["t_submit_ns"]) * 1e-6 for r in res])
+    lp = np.array(lat_p) * 1e3
+    log(args, f"plain {v_p:,.0f} updates/s, served {v_s:,.0f} updates/s ({v_s / v_p:.2f}x); "
+              f"rounds {info['rounds']}, largest round {info['max_round_size']}")
+    return {
+        "metric": METRIC, "value": round(v_s, 1), "unit": "updates/s", "n_gpus": 1, "steps": n_req, "warmup": 0,
+        "ms_per_step": round(el / n_req * 1e3, 3),
+        "p50_ms": round(float(np.percentile(lat_s, 50)), 3), "p99_ms": round(float(np.percentile(lat_s, 99)), 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": "served: 64 tenants, 20M hyperedges, |V_t|=|E_t|/2, card power-law 2.0 on [2,256], "
+                               "popularity (rank+3e3)^-1.3, requests log-uniform [1,1e5] (half inserts), all "
+                               "families tracked, all requests submitted at once",
+                   "scale": sc, "requests": n_req, "updates": int(n_upd), "build_s": round(build_s, 3),
+                   "rounds": info["rounds"], "max_round_size": info["max_round_size"]},
+        "plain": {"value": round(v_p, 1), "p50_ms": round(float(np.percentile(lp, 50)), 3),
+                  "p99_ms": round(float(np.percentile(lp, 99)), 3)},
+        "speedup_vs_plain": round(v_s / v_p, 3),
+        "roofline": None,
+    }, sv
+
+
 def cpu_baseline(args, st, families):
     """The oracle as it is, on this host: one sample batch (the first batch's
     first n/2 deletions and n/2 inserts) applied by the oracle's batch
@@ -314,6 +419,10 @@ def main():
     if args.config == "batched":
         out, sts = bench_batched(args)
         cpu_st, fam = sorted(sts, key=lambda s: s.initial.n)[len(sts) // 2], ("hyperedge",)
+    elif args.config == "served":
+        out, sv = bench_served(args)
+        busy = sorted((t for t in sv.tenants if t.batches), key=lambda s: s.initial.n)
+        cpu_st, fam = busy[len(busy) // 2], W.FAMILIES
     else:
         if args.config == "medium":
             st = W.medium(q=1.0e4, scale=args.scale, n_batches=n_b)

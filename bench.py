@@ -80,12 +80,52 @@ def roofline_of(prof):
             "algo_bytes_per_launch": int(dom["algo_bytes"] // dom["launches"])}
 
 
+def source_digest():
+    """sha256 over the HIP sources: counter figures taken on other sources are stale."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2512_21009_amd", "csrc", "*"))):
+        with open(f, "rb") as fh:
+            h.update(os.path.basename(f).encode() + b"\0" + fh.read())
+    return h.hexdigest()
+
+
+def traffic_of(workload, group):
+    """HBM bytes per launch of `group` from the committed rocprofv3 counter
+    summary of this workload (FETCH_SIZE + WRITE_SIZE, each scaled by a plain
+    copy of known size), or None when there is none for these sources."""
+    path = os.path.join(ROOT, "profiles", f"{workload}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("source_sha256") != source_digest():
+        return None
+    g = t.get("groups", {}).get(group)
+    if not g:
+        return None
+    return int(g["fetch_bytes_per_launch"] + g["write_bytes_per_launch"])
+
+
 def log_profile(args, prof):
     for name, r in prof.items():
         if r["launches"]:
             gbs = r["algo_bytes"] / (r["total_ms"] * 1e6) if r["total_ms"] > 0 else 0.0
             log(args, f"  {name:16s} launches={r['launches']:5d} total={r['total_ms']:9.2f}ms "
                       f"algo={r['algo_bytes'] / 1e9:8.3f}GB ({gbs:7.1f} GB/s) events={r['events']} aux={r['aux']}")
+
+
+PHASES = ("prefix", "nbr-hash", "compact", "disjoint", "group", "open", "pairs", "hand-over")
+
+
+def log_phases(args, ctr):
+    """Share of wall-clock ticks per phase of each hyperedge-delta stage."""
+    for s in range(3):
+        ph = [int(x) for x in ctr[16 + 8 * s: 24 + 8 * s]]
+        tot = sum(ph)
+        if tot:
+            log(args, f"  stage {s} phases: " + " ".join(f"{n}={100.0 * v / tot:.1f}%" for n, v in zip(PHASES, ph)))
 
 
 def add_profiles(acc, prof):
@@ -165,6 +205,7 @@ def bench_single(args, st, track, name, workload):
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
     prof = g.profile_read()
+    log_phases(args, g.profile_counters())
     status = g.sync()
     assert status == hgt.OK, status
     value = n_upd / elapsed
@@ -174,6 +215,8 @@ def bench_single(args, st, track, name, workload):
     g.close()
     calibration_copy()
     lat_ms = np.array(lat) * 1e3
+    rl = roofline_of(prof)
+    rl["traffic"] = traffic_of(name, rl["kernel"])
     return {
         "metric": METRIC, "value": round(value, 1), "unit": "updates/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(elapsed / max(args.steps, 1) * 1e3, 3),
@@ -181,7 +224,7 @@ def bench_single(args, st, track, name, workload):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
         "config": {"workload": workload, "scale": args.scale, "batch_updates": int(st.batches[-1].n_updates),
                    "build_s": round(build_s, 3), "triads_total": totals},
-        "roofline": roofline_of(prof),
+        "roofline": rl,
     }
 
 

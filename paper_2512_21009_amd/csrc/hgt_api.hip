@@ -202,7 +202,7 @@ struct hgt_graph {
     // batch scratch
     DevBuf s_sum, s_del_bm, s_del_card, s_del_poff, s_ins_rel, s_ins_card, s_canon, s_big, s_small, s_popc, s_scan,
         s_assigned, s_h_need, s_h_rel, s_keys, s_keys_alt, s_sort, s_head, s_is_ins, s_tv, s_tseg, s_D, s_I, s_It,
-        s_vp, s_staging, s_dst;
+        s_vp, s_staging, s_dst, s_rank_of, s_rank_id, s_keep, s_keep_scan;
     // hyperedge-family neighbour histograms (2 words per h2v word)
     DevBuf hpool;
     PhaseCtx* ph = nullptr;  // the device's shared phase scratch
@@ -288,6 +288,8 @@ GraphView view_of(hgt_graph* g) {
     v.v2h = g->st.v2h;
     v.h_ts = g->st.h_ts;
     v.h_seq = g->st.h_seq;
+    v.time_sorted = g->st.time_order;
+    v.pad0 = 0;
     return v;
 }
 
@@ -361,6 +363,10 @@ int ensure_plan_scratch(hgt_graph* g, const Sizes& z, PlanScratch& w) {
     rc |= ensure(g->s_It, pc * 4);
     rc |= ensure(g->s_vp, pc * (8 * 6 + 4 * 3) + 64);
     rc |= ensure(g->s_dst, pc * 8);
+    if (g->st.time_order) {
+        rc |= ensure(g->s_rank_of, ni * 4);
+        rc |= ensure(g->s_rank_id, ni * 4);
+    }
     if (rc) return HGT_ENOMEM;
     w.sum = g->s_sum.as<BatchSummary>();
     w.del_bm = g->s_del_bm.as<uint64_t>();
@@ -409,6 +415,11 @@ int ensure_plan_scratch(hgt_graph* g, const Sizes& z, PlanScratch& w) {
     w.vp.new_len = vp32 + 2 * pc;
     w.dst = g->s_dst.as<uint64_t>();
     w.staging = g->s_staging.as<uint32_t>();
+    w.rank_of = g->s_rank_of.as<uint32_t>();
+    w.rank_id = g->s_rank_id.as<uint32_t>();
+    w.ts_min = sm + 9;
+    w.keep = g->s_keep.as<uint64_t>();
+    w.keep_scan_tmp = g->s_keep_scan.p;
     return HGT_OK;
 }
 
@@ -693,6 +704,7 @@ int run_phase(hgt_graph* owner, const PhaseJob* jobs, uint32_t nj, bool minus, b
             Q.queue = ctr + 6;
             Q.big_queue = ctr + 7;
             Q.big_count = ctr + 8;
+            Q.stats = stats ? stats + ST_TMP0 : nullptr;
             triad_he_prepare(Q, s);
             ProfScope ps(owner, PK_TMP, s);
             triad_he_launch_small(Q, (unsigned)std::min<uint64_t>(n_cu * 3, n), s);
@@ -920,9 +932,15 @@ int plan_end(Pending& p, hipStream_t s) {
         rc = grow_keep(g->hpool, 2 * g->h2v.bytes, 2 * g->h_bump * 4, s);
     if (!rc) rc = ensure_pool(g->v2h, g->v_bump, sum.v2h_need, s);
     if (!rc) rc = ensure(g->s_staging, std::max<uint64_t>(sum.stage_words, 1) * 4);
+    if (!rc && g->st.time_order) {
+        rc = ensure(g->s_keep, (2 * sum.stage_words + 2) * 8);
+        if (!rc) rc = ensure(g->s_keep_scan, hgt_scan_tmp_bytes(sum.stage_words + 1));
+    }
     if (rc) return rc;
     refresh_view(g);
     p.w.staging = g->s_staging.as<uint32_t>();
+    p.w.keep = g->s_keep.as<uint64_t>();
+    p.w.keep_scan_tmp = g->s_keep_scan.p;
     if (g->track_mask & (1u << HGT_TRIAD_INCIDENT_VERTEX)) {
         ProfScope ps(g, PK_IV_PREP, s);
         rc = iv_prepare(g, p.b, p.w, sum, p.ip, s);
@@ -1041,7 +1059,8 @@ void destroy_graph(hgt_graph* g) {
                      &g->s_sum, &g->s_del_bm, &g->s_del_card, &g->s_del_poff, &g->s_ins_rel, &g->s_ins_card,
                      &g->s_canon, &g->s_big, &g->s_small, &g->s_popc, &g->s_scan, &g->s_assigned, &g->s_h_need,
                      &g->s_h_rel, &g->s_keys, &g->s_keys_alt, &g->s_sort, &g->s_head, &g->s_is_ins, &g->s_tv,
-                     &g->s_tseg, &g->s_D, &g->s_I, &g->s_It, &g->s_vp, &g->s_staging, &g->s_dst, &g->iv_keys, &g->iv_alt, &g->iv_sort,
+                     &g->s_tseg, &g->s_D, &g->s_I, &g->s_It, &g->s_vp, &g->s_staging, &g->s_dst, &g->s_rank_of, &g->s_rank_id,
+                     &g->s_keep, &g->s_keep_scan, &g->iv_keys, &g->iv_alt, &g->iv_sort,
                      &g->iv_head, &g->iv_uniq, &g->iv_p2, &g->iv_scan, &g->iv_tab, &g->iv_owner, &g->iv_ctr,
                      &g->hpool};
     for (DevBuf* b : all) dev_free(*b);
@@ -1135,6 +1154,7 @@ int hgt_build(const hgt_build_desc* d, hgt_graph** out) {
         }
         g->st.n_vertices = d->n_vertices;
         g->st.id_cap = 0;
+        g->st.time_order = tmp ? 1 : 0;
         uint64_t cap = std::max<uint64_t>(d->edge_capacity, d->n_edges + d->n_edges / 4 + 64);
         if ((rc = ensure_id_cap(g, cap, s))) break;
         uint64_t V = d->n_vertices;
@@ -1323,6 +1343,9 @@ int hgt_profile_read(hgt_graph* g, hgt_kernel_time* out, uint32_t n_max, uint32_
         rows[r.kind].total_ms += ms;
     }
     rows[PK_DELTA_BIG].algo_bytes = st[ST_BYTES_BIG];
+    rows[PK_TMP].algo_bytes = st[ST_TMP0 + ST_BYTES_SMALL] + st[ST_TMP0 + ST_BYTES_BIG];
+    rows[PK_TMP].events = st[ST_TMP0 + ST_EXPANDED];
+    rows[PK_TMP].aux = st[ST_TMP0 + ST_DEFERRED];
     rows[PK_IV_PAIRS].algo_bytes = st[ST_IV_BYTES];
     rows[PK_COMMIT].algo_bytes = g->store_bytes;
     rows[PK_DELTA_BIG].events = st[ST_DEFER0 + 2];
@@ -1334,6 +1357,17 @@ int hgt_profile_read(hgt_graph* g, hgt_kernel_time* out, uint32_t n_max, uint32_
     uint32_t n = std::min<uint32_t>(n_max, PK_N);
     for (uint32_t i = 0; i < n; i++) out[i] = rows[i];
     if (n_out) *n_out = PK_N;
+    return HGT_OK;
+}
+
+int hgt_profile_counters(hgt_graph* g, uint64_t* out, uint32_t n_max, uint32_t* n_out) {
+    if (!g || (!out && n_max)) return HGT_EINVAL;
+    HIP_OK(hipStreamSynchronize(g->last_stream));
+    uint64_t st[ST_N] = {0};
+    if (g->stats.p) HIP_OK(hipMemcpy(st, g->stats.p, ST_N * 8, hipMemcpyDeviceToHost));
+    uint32_t n = std::min<uint32_t>(n_max, ST_N);
+    for (uint32_t i = 0; i < n; i++) out[i] = st[i];
+    if (n_out) *n_out = ST_N;
     return HGT_OK;
 }
 
@@ -1380,6 +1414,8 @@ int hgt_export_v2h(hgt_graph* g, uint64_t* offsets_host, uint32_t* members_host)
         if (len[v]) {
             if (off[v] + len[v] > g->v_bump) return HGT_EDEVICE;
             std::memcpy(members_host + k, pool.data() + off[v], len[v] * 4);
+            // time-ordered graphs keep lists by (timestamp, sequence); rows are exported ascending
+            if (g->st.time_order) std::sort(members_host + k, members_host + k + len[v]);
             k += len[v];
         }
     }

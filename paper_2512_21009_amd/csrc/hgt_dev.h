@@ -44,7 +44,9 @@ struct BatchSummary {
     uint64_t pad[1];
 };
 
-// Read-only view of the store used by the triad kernels.
+// Read-only view of the store used by the triad kernels.  Incidence lists
+// (v2h) are ascending by ID, or, in graphs that track temporal triads,
+// ascending by (timestamp, arrival sequence).
 struct GraphView {
     const uint64_t* h_off;
     const uint32_t* h_len;
@@ -54,6 +56,8 @@ struct GraphView {
     const uint32_t* v2h;
     const int64_t* h_ts;
     const uint64_t* h_seq;
+    int32_t time_sorted;
+    int32_t pad0;
 };
 
 __device__ __forceinline__ void set_status(int32_t* st, int code) { atomicCAS(st, 0, code); }
@@ -89,6 +93,39 @@ __device__ __forceinline__ bool contains_u32(const uint32_t* a, uint32_t n, uint
     uint32_t p = lower_bound_u32(a, n, key);
     return p < n && a[p] == key;
 }
+
+// Whether the incidence list lst[0..n) holds hyperedge e (binary search in the
+// list's order: by ID, or by (timestamp, sequence) in time-sorted graphs).
+__device__ __forceinline__ bool v2h_contains(const GraphView& g, const uint32_t* lst, uint32_t n, uint32_t e) {
+    if (!g.time_sorted) return contains_u32(lst, n, e);
+    const int64_t te = g.h_ts[e];
+    const uint64_t se = g.h_seq[e];
+    uint32_t lo = 0, hi = n;
+    while (lo < hi) {
+        uint32_t mid = (lo + hi) >> 1;
+        uint32_t x = lst[mid];
+        int64_t tx = g.h_ts[x];
+        if (tx < te || (tx == te && g.h_seq[x] < se)) lo = mid + 1; else hi = mid;
+    }
+    return lo < n && lst[lo] == e;
+}
+
+// First index of a time-sorted list whose timestamp is >= t (upper = false)
+// or > t (upper = true).
+__device__ __forceinline__ uint32_t v2h_ts_bound(const GraphView& g, const uint32_t* lst, uint32_t n, int64_t t,
+                                                 bool upper) {
+    uint32_t lo = 0, hi = n;
+    while (lo < hi) {
+        uint32_t mid = (lo + hi) >> 1;
+        int64_t tx = g.h_ts[lst[mid]];
+        if (tx < t || (upper && tx == t)) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+// t - d and t + d clamped to the int64 range (d >= 0)
+__device__ __forceinline__ int64_t ts_sub(int64_t t, int64_t d) { return t < INT64_MIN + d ? INT64_MIN : t - d; }
+__device__ __forceinline__ int64_t ts_add(int64_t t, int64_t d) { return t > INT64_MAX - d ? INT64_MAX : t + d; }
 
 // index k with pre[k] <= pos < pre[k+1] over a non-decreasing array pre[0..n]
 template <class T>

@@ -9,6 +9,7 @@ struct StoreDev {
     uint64_t id_cap;        // length of every ID-indexed array
     uint64_t next_id_host;  // next_id as of the last synchronisation
     int hb, vb;             // key bits for IDs and vertices in the pair sort
+    int time_order;         // 1: v2h lists ascending by (timestamp, sequence), else by ID
     uint64_t* h_off;
     uint32_t* h_len;
     uint32_t* h_cap;
@@ -88,6 +89,12 @@ struct PlanScratch {
     uint64_t* v2h_total;
     uint64_t* stage_total;
     uint32_t* staging;
+    // time-ordered incidence lists (graphs that track temporal triads)
+    uint32_t* rank_of;      // insert j -> its time rank (build only; else the identity)
+    uint32_t* rank_id;      // time rank -> ID (build only; else the assigned IDs)
+    uint64_t* ts_min;       // build: smallest initial timestamp
+    uint64_t* keep;         // per staged old entry: kept (1) / deleted (0), then its exclusive scan
+    void* keep_scan_tmp;
     uint64_t* dst;
 };
 

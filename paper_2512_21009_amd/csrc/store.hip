@@ -228,14 +228,43 @@ __global__ void k_pairs_del(const uint32_t* __restrict__ del, uint64_t n_del, co
     for (uint64_t k = lane; k < d; k += 64) keys[p + k] = ((uint64_t)h2v[o + k] << (hb + 1)) | ((uint64_t)id << 1);
 }
 
+// Insert pairs carry the ID (ID-ordered lists) or the insert's time rank
+// (time-ordered lists: rank_of, or the batch position when rank_of is NULL).
 __global__ void k_pairs_ins(const uint32_t* __restrict__ canon, const uint64_t* __restrict__ ins_rel, uint64_t n_ins,
-                            uint64_t n_members, const uint32_t* __restrict__ assigned, int hb,
-                            const BatchSummary* sum, uint64_t* keys, const DevScalars* sc) {
+                            uint64_t n_members, const uint32_t* __restrict__ assigned, int time_order,
+                            const uint32_t* __restrict__ rank_of, int hb, const BatchSummary* sum, uint64_t* keys,
+                            const DevScalars* sc) {
     if (status_bad(&sc->status)) return;
     uint64_t m = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= n_members) return;
     uint32_t j = seg_of<uint64_t>(ins_rel, (uint32_t)n_ins, m);
-    keys[sum->del_members + m] = ((uint64_t)canon[m] << (hb + 1)) | ((uint64_t)assigned[j] << 1) | 1ull;
+    uint32_t mid = time_order ? (rank_of ? rank_of[j] : j) : assigned[j];
+    keys[sum->del_members + m] = ((uint64_t)canon[m] << (hb + 1)) | ((uint64_t)mid << 1) | 1ull;
+}
+
+// build of a time-ordered graph: time ranks of the initial hyperedges, ordered
+// by (timestamp, input position)
+__global__ void k_ts_min(const int64_t* __restrict__ ts, uint64_t n, uint64_t* ts_min) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        atomicMin((unsigned long long*)ts_min, (unsigned long long)((uint64_t)ts[i] ^ 0x8000000000000000ull));
+}
+
+__global__ void k_rank_keys(const int64_t* __restrict__ ts, uint64_t n, const uint64_t* ts_min, int jb, uint64_t* keys,
+                            DevScalars* sc) {
+    uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    uint64_t d = ((uint64_t)ts[j] ^ 0x8000000000000000ull) - *ts_min;  // offset from the smallest timestamp
+    if (jb < 64 && (d >> (64 - jb)) != 0) set_status(&sc->status, HGT_EINVAL);  // span too wide to rank
+    keys[j] = (d << jb) | j;
+}
+
+__global__ void k_rank_fill(const uint64_t* __restrict__ keys, uint64_t n, int jb,
+                            const uint32_t* __restrict__ assigned, uint32_t* rank_of, uint32_t* rank_id) {
+    uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    uint32_t j = (uint32_t)(keys[r] & ((1ull << jb) - 1));
+    rank_of[j] = (uint32_t)r;
+    rank_id[r] = assigned[j];
 }
 
 __global__ void k_pair_count(const BatchSummary* sum, uint64_t n_ins_members, uint64_t* n_pairs) {
@@ -255,8 +284,8 @@ __global__ void k_heads(const uint64_t* __restrict__ keys, const uint64_t* n_pai
 // head[] was scanned in place into tidx[] (exclusive), is_ins into ins_pre[].
 __global__ void k_split(const uint64_t* __restrict__ keys, const uint64_t* n_pairs_p, int hb,
                         const uint64_t* __restrict__ tidx, const uint64_t* __restrict__ ins_pre,
-                        uint32_t* tv, uint64_t* tseg, uint32_t* D_all, uint32_t* I_all, uint32_t* I_t,
-                        const uint64_t* n_touched_p) {
+                        const uint32_t* __restrict__ rank_id, uint32_t* tv, uint64_t* tseg, uint32_t* D_all,
+                        uint32_t* I_all, uint32_t* I_t, const uint64_t* n_touched_p) {
     uint64_t n = *n_pairs_p;
     uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i == 0) tseg[*n_touched_p] = n;
@@ -272,7 +301,7 @@ __global__ void k_split(const uint64_t* __restrict__ keys, const uint64_t* n_pai
     }
     uint64_t ip = ins_pre[i];
     if (k & 1ull) {
-        I_all[ip] = h;
+        I_all[ip] = rank_id ? rank_id[h] : h;  // time-ordered: rank -> ID
         I_t[ip] = (uint32_t)t;
     } else {
         D_all[i - ip] = h;
@@ -421,6 +450,36 @@ __global__ void k_v_merge_ins(const uint64_t* n_ins_pairs_p, const uint32_t* __r
     v2h[dst[t] + kk + ol - dl] = e;
 }
 
+// time-ordered lists: the kept old entries keep their order and the inserted
+// IDs follow them in time-rank order
+__global__ void k_v_keep(const uint64_t* __restrict__ stage_off, uint64_t n_touched, uint64_t stage_words,
+                         const uint32_t* __restrict__ staging, VPlan p, const uint32_t* __restrict__ D_all,
+                         uint64_t* keep) {
+    uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= stage_words) return;
+    uint32_t t = seg_of<uint64_t>(stage_off, (uint32_t)n_touched, s);
+    keep[s] = contains_u32(D_all + p.dstart[t], p.nD[t], staging[s]) ? 0 : 1;
+}
+
+__global__ void k_v_merge_old_t(const uint64_t* __restrict__ stage_off, uint64_t n_touched, uint64_t stage_words,
+                                const uint32_t* __restrict__ staging, const uint64_t* __restrict__ keep_flag,
+                                const uint64_t* __restrict__ keep_pre, const uint64_t* __restrict__ dst, uint32_t* v2h) {
+    uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= stage_words) return;
+    if (!keep_flag[s]) return;
+    uint32_t t = seg_of<uint64_t>(stage_off, (uint32_t)n_touched, s);
+    v2h[dst[t] + (keep_pre[s] - keep_pre[stage_off[t]])] = staging[s];
+}
+
+__global__ void k_v_merge_ins_t(const uint64_t* n_ins_pairs_p, const uint32_t* __restrict__ I_all,
+                                const uint32_t* __restrict__ I_t, VPlan p, const uint64_t* __restrict__ dst,
+                                uint32_t* v2h) {
+    uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= *n_ins_pairs_p) return;
+    uint32_t t = I_t[k];
+    v2h[dst[t] + (p.old_len[t] - p.nD[t]) + (k - p.istart[t])] = I_all[k];
+}
+
 __global__ void k_v_commit(uint64_t n_touched, const uint32_t* __restrict__ tv, VPlan p,
                            const uint64_t* __restrict__ dst, uint64_t* v_off, uint32_t* v_len, uint32_t* v_cap) {
     uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -507,17 +566,35 @@ void store_plan(StoreDev& g, BatchIn& b, PlanScratch& w, hipStream_t s) {
         k_pairs_del<<<blocks_for(n_del * 64), 256, 0, s>>>(b.del, n_del, w.del_poff, g.h_off, g.h_len, g.h2v, g.hb,
                                                            w.keys, sc);
     }
+    const uint32_t* rank_of = nullptr;
+    const uint32_t* rank_id = nullptr;
+    if (g.time_order && n_ins) {
+        if (!b.check_order) {
+            // the build: time ranks of the initial hyperedges (timestamps may be unordered)
+            int jb = 1;
+            while (jb < 63 && ((n_ins - 1) >> jb)) jb++;
+            hgt_fill_u64(w.ts_min, ~0ull, 1, s);
+            k_ts_min<<<blocks_for(n_ins > 262144 ? 262144 : n_ins), 256, 0, s>>>(b.ins_ts, n_ins, w.ts_min);
+            k_rank_keys<<<blocks_for(n_ins), 256, 0, s>>>(b.ins_ts, n_ins, w.ts_min, jb, w.keys, sc);
+            hgt_radix_sort_u64(w.keys, w.keys_alt, n_ins, nullptr, 64, w.sort_tmp, s);
+            k_rank_fill<<<blocks_for(n_ins), 256, 0, s>>>(w.keys, n_ins, jb, w.assigned, w.rank_of, w.rank_id);
+            rank_of = w.rank_of;
+            rank_id = w.rank_id;
+        } else {
+            rank_id = w.assigned;  // inserts arrive in time order: rank = batch position
+        }
+    }
     if (n_mem)
-        k_pairs_ins<<<blocks_for(n_mem), 256, 0, s>>>(w.canon, w.ins_rel, n_ins, n_mem, w.assigned, g.hb, w.sum, w.keys,
-                                                      sc);
+        k_pairs_ins<<<blocks_for(n_mem), 256, 0, s>>>(w.canon, w.ins_rel, n_ins, n_mem, w.assigned, g.time_order,
+                                                      rank_of, g.hb, w.sum, w.keys, sc);
     k_pair_count<<<1, 64, 0, s>>>(w.sum, n_mem, w.n_pairs);
     uint64_t pmax = w.pairs_cap;
     hgt_radix_sort_u64(w.keys, w.keys_alt, pmax, w.n_pairs, g.hb + 1 + g.vb, w.sort_tmp, s);
     k_heads<<<blocks_for(pmax), 256, 0, s>>>(w.keys, w.n_pairs, g.hb, w.head, w.is_ins);
     hgt_scan_u64(w.head, w.head, pmax, w.n_pairs, w.n_touched, w.scan_tmp, s);
     hgt_scan_u64(w.is_ins, w.is_ins, pmax, w.n_pairs, w.n_ins_pairs, w.scan_tmp, s);
-    k_split<<<blocks_for(pmax), 256, 0, s>>>(w.keys, w.n_pairs, g.hb, w.head, w.is_ins, w.tv, w.tseg, w.D_all, w.I_all,
-                                             w.I_t, w.n_touched);
+    k_split<<<blocks_for(pmax), 256, 0, s>>>(w.keys, w.n_pairs, g.hb, w.head, w.is_ins, rank_id, w.tv, w.tseg, w.D_all,
+                                             w.I_all, w.I_t, w.n_touched);
     k_vplan<<<blocks_for(pmax), 256, 0, s>>>(w.n_touched, w.tv, w.tseg, w.is_ins, w.n_pairs, w.n_ins_pairs, g.v_len,
                                              g.v_cap, w.vp, sc);
     hgt_scan_u64(w.vp.need, w.vp.rel, pmax, w.n_touched, w.v2h_total, w.scan_tmp, s);
@@ -536,12 +613,25 @@ void store_commit(StoreDev& g, BatchIn& b, PlanScratch& w, const BatchSummary& s
         if (sw)
             k_v_stage<<<blocks_for(sw), 256, 0, s>>>(w.vp.stage_off, w.tv, nt, sw, g.v_off, g.v2h, w.staging);
         k_v_dst<<<blocks_for(nt), 256, 0, s>>>(nt, w.tv, w.vp.need, w.vp.rel, v_bump, g.v_off, w.dst);
-        if (sw)
-            k_v_merge_old<<<blocks_for(sw), 256, 0, s>>>(w.vp.stage_off, nt, sw, w.staging, w.vp, w.D_all, w.I_all,
-                                                         w.dst, g.v2h);
-        if (n_mem)
-            k_v_merge_ins<<<blocks_for(n_mem), 256, 0, s>>>(w.n_ins_pairs, w.I_all, w.I_t, w.vp.stage_off, w.staging,
-                                                            w.vp, w.D_all, w.dst, g.v2h);
+        if (g.time_order) {
+            if (sw) {
+                uint64_t* flag = w.keep;
+                uint64_t* pre = w.keep + sw + 1;
+                k_v_keep<<<blocks_for(sw), 256, 0, s>>>(w.vp.stage_off, nt, sw, w.staging, w.vp, w.D_all, flag);
+                hgt_scan_u64(flag, pre, sw, nullptr, nullptr, w.keep_scan_tmp, s);
+                k_v_merge_old_t<<<blocks_for(sw), 256, 0, s>>>(w.vp.stage_off, nt, sw, w.staging, flag, pre, w.dst,
+                                                               g.v2h);
+            }
+            if (n_mem)
+                k_v_merge_ins_t<<<blocks_for(n_mem), 256, 0, s>>>(w.n_ins_pairs, w.I_all, w.I_t, w.vp, w.dst, g.v2h);
+        } else {
+            if (sw)
+                k_v_merge_old<<<blocks_for(sw), 256, 0, s>>>(w.vp.stage_off, nt, sw, w.staging, w.vp, w.D_all,
+                                                             w.I_all, w.dst, g.v2h);
+            if (n_mem)
+                k_v_merge_ins<<<blocks_for(n_mem), 256, 0, s>>>(w.n_ins_pairs, w.I_all, w.I_t, w.vp.stage_off,
+                                                                w.staging, w.vp, w.D_all, w.dst, g.v2h);
+        }
         k_v_commit<<<blocks_for(nt), 256, 0, s>>>(nt, w.tv, w.vp, w.dst, g.v_off, g.v_len, g.v_cap);
     }
     if (n_del) k_apply_delete<<<blocks_for(n_del), 256, 0, s>>>(b.del, n_del, g.free_bm, g.h_len);

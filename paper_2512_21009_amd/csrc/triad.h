@@ -73,7 +73,9 @@ enum TriadStat {
     ST_IV_BYTES = 5,     // algorithmic bytes gathered by the incident-vertex kernel
     ST_DEFER0 = 6,       // centres moved on by histogram-kernel stage 0, 1, 2
     ST_HEB0 = 9,         // algorithmic bytes gathered by histogram-kernel stage 0, 1, 2
-    ST_N = 16
+    ST_PH0 = 16,         // wall-clock ticks per phase of histogram-kernel stage s: ST_PH0 + 8 s + phase
+    ST_TMP0 = 40,        // the temporal launches' counters: ST_TMP0 + (ST_BYTES_SMALL .. ST_EXPANDED)
+    ST_N = 48
 };
 
 BigLayout triad_big_layout(uint64_t max_lh, uint64_t max_card);

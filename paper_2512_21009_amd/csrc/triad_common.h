@@ -114,6 +114,30 @@ __device__ __forceinline__ uint32_t wg_scan_u32(uint32_t v, uint32_t* ws, uint32
     return pre + x - v;
 }
 
+// Inclusive workgroup scan with max (MAX) or min; *total = over the block.
+template <bool MAX>
+__device__ __forceinline__ uint32_t wg_scan_ext_u32(uint32_t v, uint32_t* ws, uint32_t* total) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t t = __shfl_up(x, o, 64);
+        if (lane >= o) x = MAX ? (t > x ? t : x) : (t < x ? t : x);
+    }
+    if (lane == 63) ws[wave] = x;
+    __syncthreads();
+    uint32_t pre = MAX ? 0u : 0xffffffffu, tot = pre;
+#pragma unroll
+    for (int w = 0; w < NWAVE; w++) {
+        uint32_t s = ws[w];
+        if (w < wave) pre = MAX ? (s > pre ? s : pre) : (s < pre ? s : pre);
+        tot = MAX ? (s > tot ? s : tot) : (s < tot ? s : tot);
+    }
+    __syncthreads();
+    *total = tot;
+    return MAX ? (pre > x ? pre : x) : (pre < x ? pre : x);
+}
+
 struct Tables {
     uint8_t he[128];
     uint8_t tmp[128];

@@ -138,11 +138,29 @@ __device__ void expand_x(const TriadParams& P, const HeGraph& G, const Tables& T
         tx = G.g.h_ts[x];
         sx = G.g.h_seq[x];
     }
+    // temporal family on time-sorted lists: only the part of each list within the
+    // window of both h and x can complete a triad
+    const bool win = P.do_tmp && !P.do_he && G.g.time_sorted;
+    const int64_t w_lo = ts_sub(sh.th > tx ? sh.th : tx, G.window), w_hi = ts_add(sh.th < tx ? sh.th : tx, G.window);
+    auto range = [&](uint32_t m, uint64_t& o, uint32_t& n) {
+        o = G.g.v_off[m];
+        n = G.g.v_len[m];
+        if (win) {
+            const uint32_t* L = G.g.v2h + o;
+            uint32_t lo = v2h_ts_bound(G.g, L, n, w_lo, false);
+            uint32_t hi = v2h_ts_bound(G.g, L, n, w_hi, true);
+            o += lo;
+            n = hi > lo ? hi - lo : 0;
+        }
+    };
     // total 2-hop length
     uint32_t lx = 0;
     for (uint32_t b = 0; b < nx; b += CHUNK) {
         uint32_t d = 0;
-        if (b + lane < nx) d = G.g.v_len[G.g.h2v[xoff + b + lane]];
+        if (b + lane < nx) {
+            uint64_t o;
+            range(G.g.h2v[xoff + b + lane], o, d);
+        }
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) d += __shfl_xor(d, o, 64);
         lx += d;
@@ -162,8 +180,9 @@ __device__ void expand_x(const TriadParams& P, const HeGraph& G, const Tables& T
             uint32_t d = 0;
             if ((uint32_t)lane < cnt) {
                 uint32_t m = G.g.h2v[xoff + b + lane];
-                d = G.g.v_len[m];
-                wm.voff[lane] = G.g.v_off[m];
+                uint64_t o;
+                range(m, o, d);
+                wm.voff[lane] = o;
                 wm.inh[lane] = contains_u32(S.hm, sh.hlen, m) ? 1u : 0u;
             }
             uint32_t inc = d;
@@ -200,8 +219,9 @@ __device__ void expand_x(const TriadParams& P, const HeGraph& G, const Tables& T
         uint32_t d = 0;
         if ((uint32_t)lane < cnt) {
             uint32_t m = G.g.h2v[xoff + b + lane];
-            d = G.g.v_len[m];
-            wm.voff[lane] = G.g.v_off[m];
+            uint64_t o;
+            range(m, o, d);
+            wm.voff[lane] = o;
             wm.inh[lane] = contains_u32(S.hm, sh.hlen, m) ? 1u : 0u;
         }
         uint32_t inc = d;
@@ -225,7 +245,7 @@ __device__ void expand_x(const TriadParams& P, const HeGraph& G, const Tables& T
                 if (j == kg) continue;
                 uint32_t mj = G.g.h2v[xoff + j];
                 const uint32_t* lst = G.g.v2h + G.g.v_off[mj];
-                if (contains_u32(lst, G.g.v_len[mj], y)) {
+                if (v2h_contains(G.g, lst, G.g.v_len[mj], y)) {
                     if (j < kg) { first = false; break; }
                     c++;
                     ch += contains_u32(S.hm, sh.hlen, mj) ? 1u : 0u;
@@ -316,13 +336,23 @@ __device__ void run_centres(const TriadParams& P, const Tables& T, const WgStore
         uint32_t* pre = S.warea;                                  // hlen + 1 words
         uint64_t* voff = (uint64_t*)(S.warea + ((hlen + 2) & ~1u));  // hlen u64, 8-byte aligned
         uint32_t carry = 0;
+        // temporal family on time-sorted lists: only neighbours within the window
+        const bool win = P.do_tmp && !P.do_he && G.g.time_sorted;
         for (uint32_t b = 0; b < hlen; b += HGT_WG) {
             uint32_t i = b + tid, d = 0;
             if (i < hlen) {
                 uint32_t m = G.g.h2v[sh.hoff + i];
                 S.hm[i] = m;
+                uint64_t o = G.g.v_off[m];
                 d = G.g.v_len[m];
-                voff[i] = G.g.v_off[m];
+                if (win) {
+                    const uint32_t* L = G.g.v2h + o;
+                    uint32_t lo = v2h_ts_bound(G.g, L, d, ts_sub(sh.th, G.window), false);
+                    uint32_t hi = v2h_ts_bound(G.g, L, d, ts_add(sh.th, G.window), true);
+                    o += lo;
+                    d = hi > lo ? hi - lo : 0;
+                }
+                voff[i] = o;
             }
             uint32_t tot;
             uint32_t ex = wg_scan_u32(d, sh.ws, &tot);

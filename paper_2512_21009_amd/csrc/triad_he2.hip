@@ -96,6 +96,7 @@ struct Sh2 {
     uint64_t hoff;
     uint32_t ncap;
     uint32_t o_nh, o_ent;  // arena word offsets
+    uint32_t runs, pcap, ovf;  // intersecting pairs: run table present, pair-hash slots, overflow
     uint32_t ws[NWAVE];
     uint64_t g[8];
 };
@@ -316,6 +317,79 @@ __global__ void k_entries_check(Multi M, const uint64_t* n_entries_p, uint64_t c
 // the centres whose tables do not fit its arena to list s; list 2 feeds the
 // 2-hop kernel.  Stages 0 and 1 keep the arena in LDS (72 KB, 148 KB), stage 2
 // in a 1 MB slice of global memory per workgroup.
+// open-addressing insert that reports a full table (returns false)
+__device__ __forceinline__ bool fr_add_ok(uint32_t* keys, uint32_t* vals, uint32_t cap, uint32_t key, uint32_t inc) {
+    uint32_t s = fr_slot(key, cap);
+    for (uint32_t probe = 0; probe < cap; probe++) {
+        uint32_t k = __atomic_load_n(&keys[s], __ATOMIC_RELAXED);
+        if (k == HGT_EMPTY) {
+            uint32_t prev = atomicCAS(&keys[s], HGT_EMPTY, key);
+            if (prev == HGT_EMPTY || prev == key) { atomicAdd(&vals[s], inc); return true; }
+        } else if (k == key) {
+            atomicAdd(&vals[s], inc);
+            return true;
+        }
+        s = fr_next(s, cap);
+    }
+    return false;
+}
+
+// |x & y|, |x & y & h| and the smallest common vertex of two sorted rows
+__device__ __forceinline__ void row_meet(const uint32_t* X, uint32_t xl, const uint32_t* Y, uint32_t yl,
+                                         const uint32_t* hm, uint32_t hlen, uint32_t& s, uint32_t& shh,
+                                         uint32_t& first) {
+    uint32_t a = 0, b = 0;
+    s = 0;
+    shh = 0;
+    first = HGT_EMPTY;
+    while (a < xl && b < yl) {
+        uint32_t va = X[a], vb = Y[b];
+        if (va < vb) a++;
+        else if (va > vb) b++;
+        else {
+            if (s == 0) first = va;
+            s++;
+            shh += contains_u32(hm, hlen, va) ? 1u : 0u;
+            a++;
+            b++;
+        }
+    }
+}
+
+// The class adjustments of one intersecting neighbour pair {x, y} of centre h
+// (|x & y| = s, |h & x & y| = shh): in a full count the closed triad at the
+// smallest-ID centre, in a delta the open-path and disjoint-pair corrections.
+__device__ __forceinline__ void pair_class(const He2Params& P, const Tables& T, uint32_t h, uint32_t hlen,
+                                           const uint32_t* nl_x, const uint32_t* nl_meta, uint32_t xi, uint32_t yi,
+                                           uint32_t s, uint32_t shh, uint32_t* myacc32) {
+    const uint32_t mx = nl_meta[xi], my = nl_meta[yi];
+    const uint32_t xl = meta_len(mx), yl = meta_len(my), cx = meta_c(mx), cy = meta_c(my);
+    if (P.static_mode) {
+        // closed triple: counted at its smallest-ID centre only
+        acc32_add(myacc32, T.he[venn_code((int)hlen, (int)xl, (int)yl, (int)cx, 0, (int)cy, 0)], ~0u);
+        if (h < nl_x[xi] && h < nl_x[yi])
+            acc32_add(myacc32, T.he[venn_code((int)hlen, (int)xl, (int)yl, (int)cx, (int)s, (int)cy, (int)shh)], 1u);
+        return;
+    }
+    const bool ex = meta_elig(mx), ey = meta_elig(my);
+    if (ex) {
+        uint32_t base = (hlen > cx ? 1u : 0u) | 24u;
+        acc32_add(myacc32, T.he[base | (xl - cx > s ? 2u : 0u) | (yl > s ? 4u : 0u)], ~0u);
+    }
+    if (ey) {
+        uint32_t base = (hlen > cy ? 1u : 0u) | 24u;
+        acc32_add(myacc32, T.he[base | (yl - cy > s ? 2u : 0u) | (xl > s ? 4u : 0u)], ~0u);
+    }
+    if (ex && ey) {
+        int ct = T.he[venn_code((int)hlen, (int)xl, (int)yl, (int)cx, (int)s, (int)cy, (int)shh)];
+        int cf = T.he[venn_code((int)hlen, (int)xl, (int)yl, (int)cx, 0, (int)cy, 0)];
+        if (ct != cf) {
+            acc32_add(myacc32, ct, 1u);
+            acc32_add(myacc32, cf, ~0u);
+        }
+    }
+}
+
 // Adds the per-wave counts to graph g's phase accumulators and clears them.
 __device__ void he2_flush_graph(const He2Params& P, uint32_t g, uint64_t* acc_all) {
     __syncthreads();
@@ -334,8 +408,17 @@ __device__ void he2_flush_graph(const He2Params& P, uint32_t g, uint64_t* acc_al
 
 template <int STAGE>
 __device__ void he2_body(const He2Params& P, uint32_t* arena, const uint32_t ARENA_WORDS, Sh2& sh, const Tables& T,
-                         uint64_t* acc_all, uint32_t* acc32_all, uint64_t* st) {
+                         uint64_t* acc_all, uint32_t* acc32_all, uint64_t* st, uint64_t* ph) {
     const int tid = threadIdx.x;
+    uint64_t t_mark = 0;  // thread 0: wall clock at the last phase mark (profiling)
+#define HE2_MARK(i)                                     \
+    do {                                                \
+        if (P.stats && tid == 0) {                      \
+            uint64_t t_ = wall_clock64();               \
+            ph[i] += t_ - t_mark;                       \
+            t_mark = t_;                                \
+        }                                               \
+    } while (0)
     uint64_t* myacc = acc_all + (tid >> 6) * HGT_N_HE_CLASSES;
     uint32_t* myacc32 = acc32_all + (tid >> 6) * HGT_N_HE_CLASSES;
     for (;;) {
@@ -366,6 +449,7 @@ __device__ void he2_body(const He2Params& P, uint32_t* arena, const uint32_t ARE
         }
         __syncthreads();
         if (sh.stop) break;
+        if (P.stats && tid == 0) t_mark = wall_clock64();
         if (sh.gi != sh.cur_g) {  // the counts so far belong to the previous graph
             he2_flush_graph(P, sh.cur_g, acc_all);
             if (tid == 0) sh.cur_g = sh.gi;
@@ -400,9 +484,11 @@ __device__ void he2_body(const He2Params& P, uint32_t* arena, const uint32_t ARE
                 P.rank[STAGE][q] = sh.rank;
                 atomicAdd((unsigned long long*)&st[0], 1ull);
             }
+            HE2_MARK(7);
             __syncthreads();
             continue;
         }
+        HE2_MARK(0);
         const uint32_t lh = sh.lh, ncap = sh.ncap;
         uint32_t* nkeys = arena;
         uint32_t* nvals = arena + ncap;
@@ -411,6 +497,7 @@ __device__ void he2_body(const He2Params& P, uint32_t* arena, const uint32_t ARE
         __syncthreads();
         build_nh(G.g, h, hlen, lh, pre, voff, nkeys, nvals, ncap);
         __syncthreads();
+        HE2_MARK(1);
         // --- compact N(h): x, meta (c | len | eligible), member offsets later
         uint32_t* nl_x = arena + 2 * ncap;
         uint32_t* nl_meta = nl_x + lh;
@@ -464,9 +551,11 @@ __device__ void he2_body(const He2Params& P, uint32_t* arena, const uint32_t ARE
                 P.rank[STAGE][q] = sh.rank;
                 atomicAdd((unsigned long long*)&st[0], 1ull);
             }
+            HE2_MARK(7);
             __syncthreads();
             continue;
         }
+        HE2_MARK(2);
         const uint32_t W = sh.W;
         uint64_t* keys = (uint64_t*)(arena + sh.o_ent);
         for (uint32_t i = tid; i < hlen; i += HGT_WG) hm[i] = G.g.h2v[sh.hoff + i];
@@ -527,6 +616,7 @@ __device__ void he2_body(const He2Params& P, uint32_t* arena, const uint32_t ARE
             }
             __syncthreads();
         }
+        HE2_MARK(3);
         // --- entries: (vertex, v in h, neighbour) for every member of every neighbour,
         // sorted by vertex so that the neighbours meeting at a vertex are contiguous
         for (uint32_t i = tid; i < K; i += HGT_WG) nl_msh[i] = 0;
@@ -546,6 +636,7 @@ __device__ void he2_body(const He2Params& P, uint32_t* arena, const uint32_t ARE
             if (shared) atomicAdd(&nl_msh[keys[i] & K_MAX], 1u);
         }
         __syncthreads();
+        HE2_MARK(4);
         // --- open paths h - x - y through the histograms, per eligible neighbour
         for (uint32_t i = P.static_mode ? K : tid; i < K; i += HGT_WG) {
             uint32_t m = nl_meta[i];
@@ -584,72 +675,142 @@ __device__ void he2_body(const He2Params& P, uint32_t* arena, const uint32_t ARE
             acc_add(myacc, T.he[base], b0);
             acc_add(myacc, T.he[base | 4], b1);
         }
-        // --- intersecting neighbour pairs, each at its smallest common vertex.  When
-        // one side has a single shared member the pair meets only at this vertex.
-        for (uint32_t i = tid; i + 1 < W; i += HGT_WG) {
-            const uint64_t ki = keys[i];
-            const uint64_t v = ki >> 15;
-            if ((keys[i + 1] >> 15) != v) continue;
-            const uint32_t xi = (uint32_t)ki & K_MAX;
-            const uint32_t vin = (uint32_t)(ki >> 14) & 1u;
-            const uint32_t mx = nl_meta[xi];
-            const uint32_t xl = meta_len(mx), xsh = nl_msh[xi], cx = meta_c(mx);
-            const bool ex = meta_elig(mx);
-            for (uint32_t j = i + 1; j < W; j++) {
-                const uint64_t kj = keys[j];
-                if ((kj >> 15) != v) break;
-                const uint32_t yi = (uint32_t)kj & K_MAX;
-                const uint32_t my = nl_meta[yi];
-                const uint32_t yl = meta_len(my);
-                uint32_t s = 1, shh = vin;
-                bool at_first = true;
-                if (xsh > 1 && nl_msh[yi] > 1) {
-                    // both have other shared members: merge the member lists
-                    const uint32_t* X = G.g.h2v + G.g.h_off[nl_x[xi]];
-                    const uint32_t* Y = G.g.h2v + G.g.h_off[nl_x[yi]];
-                    uint32_t a = 0, b = 0, first = HGT_EMPTY;
-                    s = 0;
-                    shh = 0;
-                    while (a < xl && b < yl) {
-                        uint32_t va = X[a], vb = Y[b];
-                        if (va < vb) a++;
-                        else if (va > vb) b++;
-                        else {
-                            if (s == 0) first = va;
-                            s++;
-                            shh += contains_u32(hm, hlen, va) ? 1u : 0u;
-                            a++;
-                            b++;
-                        }
-                    }
-                    at_first = (uint64_t)first == v;
+        if (P.stats) __syncthreads();
+        HE2_MARK(5);
+        // --- intersecting neighbour pairs.  The neighbours that meet at a vertex v form
+        // a run of the sorted keys; every pair of a run meets at v.  When one side has a
+        // single shared member the pair meets only at v (|x & y| = 1); the other pairs
+        // ("multi" pairs) are accumulated over all their common vertices in an LDS hash
+        // keyed by the pair, then classified once.  Runs are enumerated cyclically
+        // (entry p of a run of R takes partners p+1 .. p+R/2) so that every entry of a
+        // long run does about R/2 pairs.  Without room for the run table (W words) or
+        // with W >= 2^16, each pair is found at its smallest common vertex by merging.
+        if (tid == 0) {
+            uint64_t o_rs = (uint64_t)sh.o_ent + 2ull * W;
+            uint64_t o_ph = o_rs + W;
+            uint64_t room = o_ph < ARENA_WORDS ? (ARENA_WORDS - o_ph) / 2 : 0;
+            sh.runs = (W < 65536u && room >= 64) ? 1u : 0u;
+            // pair-hash slots: the room left, at most 4 W (clearing it costs as much as a pass over
+            // the keys); a pair hash that overflows falls back to merging rows
+            const uint64_t want = 4ull * W + 64;
+            sh.pcap = sh.runs ? (uint32_t)(room < want ? room : want) : 0u;
+            sh.ovf = 0;
+        }
+        __syncthreads();
+        if (sh.runs) {
+            uint32_t* rs = (uint32_t*)(keys + W);
+            uint32_t* pk = rs + W;
+            uint32_t* pv = pk + sh.pcap;
+            const uint32_t pcap = sh.pcap;
+            for (uint32_t i = tid; i < pcap; i += HGT_WG) { pk[i] = HGT_EMPTY; pv[i] = 0; }
+            // run starts: inclusive max-scan of the head positions
+            {
+                uint32_t carry = 0;
+                for (uint32_t b0 = 0; b0 < W; b0 += HGT_WG) {
+                    uint32_t i = b0 + tid, val = 0;
+                    if (i < W && (i == 0 || (keys[i - 1] >> 15) != (keys[i] >> 15))) val = i;
+                    uint32_t tot;
+                    uint32_t inc = wg_scan_ext_u32<true>(val, sh.ws, &tot);
+                    if (i < W) rs[i] = inc > carry ? inc : carry;
+                    carry = tot > carry ? tot : carry;
                 }
-                if (!at_first) continue;
-                const uint32_t cy = meta_c(my);
-                if (P.static_mode) {
-                    // closed triple: counted at its smallest-ID centre only
-                    acc32_add(myacc32, T.he[venn_code((int)hlen, (int)xl, (int)yl, (int)cx, 0, (int)cy, 0)], ~0u);
-                    if (h < nl_x[xi] && h < nl_x[yi])
-                        acc32_add(myacc32, T.he[venn_code((int)hlen, (int)xl, (int)yl, (int)cx, (int)s, (int)cy, (int)shh)],
-                                  1u);
-                } else {
-                    const bool ey = meta_elig(my);
-                    if (ex) {
-                        uint32_t base = (hlen > cx ? 1u : 0u) | 24u;
-                        acc32_add(myacc32, T.he[base | (xl - cx > s ? 2u : 0u) | (yl > s ? 4u : 0u)], ~0u);
+            }
+            __syncthreads();
+            // run ends: inclusive min-scan of the tail positions from the right; pack
+            // start | length << 16
+            {
+                uint32_t carry = HGT_EMPTY;
+                for (uint32_t b0 = 0; b0 < W; b0 += HGT_WG) {
+                    const int64_t ii = (int64_t)W - 1 - (int64_t)(b0 + tid);
+                    uint32_t val = HGT_EMPTY;
+                    if (ii >= 0) {
+                        const uint32_t i = (uint32_t)ii;
+                        if (i + 1 == W || (keys[i + 1] >> 15) != (keys[i] >> 15)) val = i;
                     }
-                    if (ey) {
-                        uint32_t base = (hlen > cy ? 1u : 0u) | 24u;
-                        acc32_add(myacc32, T.he[base | (yl - cy > s ? 2u : 0u) | (xl > s ? 4u : 0u)], ~0u);
+                    uint32_t tot;
+                    uint32_t inc = wg_scan_ext_u32<false>(val, sh.ws, &tot);
+                    if (ii >= 0) {
+                        const uint32_t i = (uint32_t)ii;
+                        const uint32_t e = inc < carry ? inc : carry;
+                        const uint32_t st0 = rs[i];
+                        rs[i] = st0 | ((e - st0 + 1) << 16);
                     }
-                    if (ex && ey) {
-                        int ct = T.he[venn_code((int)hlen, (int)xl, (int)yl, (int)cx, (int)s, (int)cy, (int)shh)];
-                        int cf = T.he[venn_code((int)hlen, (int)xl, (int)yl, (int)cx, 0, (int)cy, 0)];
-                        if (ct != cf) {
-                            acc32_add(myacc32, ct, 1u);
-                            acc32_add(myacc32, cf, ~0u);
-                        }
+                    carry = tot < carry ? tot : carry;
+                }
+            }
+            __syncthreads();
+            for (uint32_t i = tid; i < W; i += HGT_WG) {
+                const uint32_t r = rs[i], st0 = r & 0xffffu, R = r >> 16;
+                if (R < 2) continue;
+                const uint32_t pos = i - st0;
+                const uint32_t kmax = (R - 1) / 2 + (((R & 1u) == 0 && pos < R / 2) ? 1u : 0u);
+                const uint64_t ki = keys[i];
+                const uint32_t xi = (uint32_t)ki & K_MAX;
+                const uint32_t vin = (uint32_t)(ki >> 14) & 1u;
+                const uint32_t xsh = nl_msh[xi];
+                for (uint32_t k = 1; k <= kmax; k++) {
+                    uint32_t jj = pos + k;
+                    if (jj >= R) jj -= R;
+                    const uint32_t yi = (uint32_t)keys[st0 + jj] & K_MAX;
+                    if (xsh > 1 && nl_msh[yi] > 1) {
+                        const uint32_t a = xi < yi ? xi : yi, b = xi < yi ? yi : xi;
+                        if (!fr_add_ok(pk, pv, pcap, (a << 14) | b, 1u | (vin << 16))) sh.ovf = 1;
+                        continue;
                     }
+                    pair_class(P, T, h, hlen, nl_x, nl_meta, xi, yi, 1u, vin, myacc32);
+                }
+            }
+            __syncthreads();
+            if (!sh.ovf) {
+                for (uint32_t i = tid; i < pcap; i += HGT_WG) {
+                    const uint32_t key = pk[i];
+                    if (key == HGT_EMPTY) continue;
+                    const uint32_t val = pv[i];
+                    pair_class(P, T, h, hlen, nl_x, nl_meta, key >> 14, key & K_MAX, val & 0xffffu, val >> 16, myacc32);
+                }
+            } else {
+                // the pair hash overflowed: every multi pair at its smallest common vertex
+                for (uint32_t i = tid; i < W; i += HGT_WG) {
+                    const uint32_t r = rs[i], st0 = r & 0xffffu, R = r >> 16;
+                    if (R < 2) continue;
+                    const uint32_t pos = i - st0;
+                    const uint32_t kmax = (R - 1) / 2 + (((R & 1u) == 0 && pos < R / 2) ? 1u : 0u);
+                    const uint64_t ki = keys[i];
+                    const uint32_t xi = (uint32_t)ki & K_MAX;
+                    if (nl_msh[xi] <= 1) continue;
+                    for (uint32_t k = 1; k <= kmax; k++) {
+                        uint32_t jj = pos + k;
+                        if (jj >= R) jj -= R;
+                        const uint32_t yi = (uint32_t)keys[st0 + jj] & K_MAX;
+                        if (nl_msh[yi] <= 1) continue;
+                        uint32_t sc, shh, first;
+                        row_meet(G.g.h2v + G.g.h_off[nl_x[xi]], meta_len(nl_meta[xi]), G.g.h2v + G.g.h_off[nl_x[yi]],
+                                 meta_len(nl_meta[yi]), hm, hlen, sc, shh, first);
+                        if ((uint64_t)first != (ki >> 15)) continue;
+                        pair_class(P, T, h, hlen, nl_x, nl_meta, xi, yi, sc, shh, myacc32);
+                    }
+                }
+            }
+        } else {
+            for (uint32_t i = tid; i + 1 < W; i += HGT_WG) {
+                const uint64_t ki = keys[i];
+                const uint64_t v = ki >> 15;
+                if ((keys[i + 1] >> 15) != v) continue;
+                const uint32_t xi = (uint32_t)ki & K_MAX;
+                const uint32_t vin = (uint32_t)(ki >> 14) & 1u;
+                const uint32_t xsh = nl_msh[xi];
+                for (uint32_t j = i + 1; j < W; j++) {
+                    const uint64_t kj = keys[j];
+                    if ((kj >> 15) != v) break;
+                    const uint32_t yi = (uint32_t)kj & K_MAX;
+                    uint32_t sc = 1, shh = vin;
+                    if (xsh > 1 && nl_msh[yi] > 1) {
+                        uint32_t first;
+                        row_meet(G.g.h2v + G.g.h_off[nl_x[xi]], meta_len(nl_meta[xi]), G.g.h2v + G.g.h_off[nl_x[yi]],
+                                 meta_len(nl_meta[yi]), hm, hlen, sc, shh, first);
+                        if ((uint64_t)first != v) continue;
+                    }
+                    pair_class(P, T, h, hlen, nl_x, nl_meta, xi, yi, sc, shh, myacc32);
                 }
             }
         }
@@ -663,11 +824,15 @@ __device__ void he2_body(const He2Params& P, uint32_t* arena, const uint32_t ARE
             }
         }
         __syncthreads();
+        HE2_MARK(6);
     }
+#undef HE2_MARK
 }
 
 template <int STAGE>
-__device__ void he2_flush_stats(const He2Params& P, const uint64_t* st) {
+__device__ void he2_flush_stats(const He2Params& P, const uint64_t* st, const uint64_t* ph) {
+    if (P.stats && threadIdx.x < 8 && ph[threadIdx.x])
+        atomicAdd((unsigned long long*)&P.stats[ST_PH0 + 8 * STAGE + threadIdx.x], (unsigned long long)ph[threadIdx.x]);
     if (P.stats && threadIdx.x == 0 && st[0])
         atomicAdd((unsigned long long*)&P.stats[ST_DEFER0 + STAGE], (unsigned long long)st[0]);
     if (P.stats && threadIdx.x == 0 && st[1])
@@ -680,6 +845,8 @@ __device__ void he2_flush_stats(const He2Params& P, const uint64_t* st) {
     __shared__ uint64_t acc[NWAVE][HGT_N_HE_CLASSES];                                  \
     __shared__ uint32_t acc32[NWAVE][HGT_N_HE_CLASSES];                                \
     __shared__ uint64_t st[2];                                                         \
+    __shared__ uint64_t ph[8];                                                         \
+    if (threadIdx.x < 8) ph[threadIdx.x] = 0;                                          \
     if (threadIdx.x == 0) sh.cur_g = 0xffffffffu;                                      \
     for (int i = threadIdx.x; i < 128; i += HGT_WG) T.he[i] = P.he_tab[i];             \
     for (int i = threadIdx.x; i < NWAVE * HGT_N_HE_CLASSES; i += HGT_WG) {             \
@@ -692,25 +859,25 @@ __device__ void he2_flush_stats(const He2Params& P, const uint64_t* st) {
 __global__ void __launch_bounds__(HGT_WG) k_he2_s0(He2Params P) {
     __shared__ __attribute__((aligned(16))) uint32_t arena[ARENA_S];
     HE2_PROLOGUE
-    he2_body<0>(P, arena, ARENA_S, sh, T, &acc[0][0], &acc32[0][0], st);
+    he2_body<0>(P, arena, ARENA_S, sh, T, &acc[0][0], &acc32[0][0], st, ph);
     he2_flush_graph(P, sh.cur_g, &acc[0][0]);
-    he2_flush_stats<0>(P, st);
+    he2_flush_stats<0>(P, st, ph);
 }
 
 __global__ void __launch_bounds__(HGT_WG) k_he2_s1(He2Params P) {
     __shared__ __attribute__((aligned(16))) uint32_t arena[ARENA_M];
     HE2_PROLOGUE
-    he2_body<1>(P, arena, ARENA_M, sh, T, &acc[0][0], &acc32[0][0], st);
+    he2_body<1>(P, arena, ARENA_M, sh, T, &acc[0][0], &acc32[0][0], st, ph);
     he2_flush_graph(P, sh.cur_g, &acc[0][0]);
-    he2_flush_stats<1>(P, st);
+    he2_flush_stats<1>(P, st, ph);
 }
 
 __global__ void __launch_bounds__(HGT_WG) k_he2_s2(He2Params P) {
     HE2_PROLOGUE
     he2_body<2>(P, P.garena + (uint64_t)blockIdx.x * P.garena_words, (uint32_t)P.garena_words, sh, T, &acc[0][0],
-                &acc32[0][0], st);
+                &acc32[0][0], st, ph);
     he2_flush_graph(P, sh.cur_g, &acc[0][0]);
-    he2_flush_stats<2>(P, st);
+    he2_flush_stats<2>(P, st, ph);
 }
 
 }  // namespace

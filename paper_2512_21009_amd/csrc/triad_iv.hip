@@ -82,8 +82,10 @@ __global__ void k_iv_owner_list(const uint64_t* __restrict__ pairs, const uint64
 // ---- memory-free fallback for vertices whose map does not fit: per pair,
 // m_ab from binary searches and every triangle vertex c from a's hyperedges
 // (taken at the first of them that holds c), m_ac and m_bc by list intersection.
-__device__ __forceinline__ uint32_t inter_count_min(const uint32_t* A, uint32_t na, const uint32_t* B, uint32_t nb,
-                                                    uint32_t* mn) {
+// |A & B| for two incidence lists and their first common element in list order
+// (both lists are sorted by the same key, so it is the same in either list)
+__device__ __forceinline__ uint32_t inter_count_min(const GraphView& g, const uint32_t* A, uint32_t na,
+                                                    const uint32_t* B, uint32_t nb, uint32_t* mn) {
     if (na > nb) {
         const uint32_t* t = A; A = B; B = t;
         uint32_t n = na; na = nb; nb = n;
@@ -91,7 +93,7 @@ __device__ __forceinline__ uint32_t inter_count_min(const uint32_t* A, uint32_t 
     uint32_t c = 0, first = HGT_EMPTY;
     for (uint32_t i = 0; i < na; i++) {
         uint32_t e = A[i];
-        if (contains_u32(B, nb, e)) {
+        if (v2h_contains(g, B, nb, e)) {
             if (c == 0) first = e;
             c++;
         }
@@ -146,10 +148,10 @@ __device__ void iv_pair_direct(const IvParams& P, uint32_t a, uint32_t b, uint32
                 const uint32_t* C = P.g.v2h + P.g.v_off[c];
                 uint32_t lc = P.g.v_len[c];
                 uint32_t first;
-                uint32_t mac = inter_count_min(A, la, C, lc, &first);
+                uint32_t mac = inter_count_min(P.g, A, la, C, lc, &first);
                 if (first != hk) continue;
                 uint32_t dummy;
-                uint32_t mbc = inter_count_min(B, lb, C, lc, &dummy);
+                uint32_t mbc = inter_count_min(P.g, B, lb, C, lc, &dummy);
                 if (mbc == 0) continue;
                 if (c < hi && touched(P.tab, P.tab_mask, lo, c)) continue;
                 if (c < lo && touched(P.tab, P.tab_mask, hi, c)) continue;

@@ -135,7 +135,7 @@ _lib = None
 
 EXPORTS = ["hgt_build", "hgt_apply_batch", "hgt_apply_batches", "hgt_triad_counts", "hgt_sync", "hgt_destroy", "hgt_status_str",
            "hgt_get_info", "hgt_export_h2v", "hgt_export_v2h", "hgt_class_codes", "hgt_profile",
-           "hgt_profile_read", "hgt_server_create", "hgt_server_add_tenant", "hgt_server_tenant_graph",
+           "hgt_profile_read", "hgt_profile_counters", "hgt_server_create", "hgt_server_add_tenant", "hgt_server_tenant_graph",
            "hgt_server_submit", "hgt_server_wait", "hgt_server_query", "hgt_server_get_info", "hgt_server_destroy"]
 
 
@@ -165,6 +165,7 @@ def load(path: str = LIB_PATH):
     lib.hgt_class_codes.argtypes = [I32, P, U32]
     lib.hgt_profile.argtypes = [P, I32]
     lib.hgt_profile_read.argtypes = [P, P, U32, ctypes.POINTER(U32)]
+    lib.hgt_profile_counters.argtypes = [P, P, U32, ctypes.POINTER(U32)]
     lib.hgt_server_create.argtypes = [ctypes.POINTER(ServerDesc), ctypes.POINTER(P)]
     lib.hgt_server_add_tenant.argtypes = [P, ctypes.POINTER(BuildDesc), ctypes.POINTER(U32)]
     lib.hgt_server_tenant_graph.argtypes = [P, U32, ctypes.POINTER(P)]
@@ -379,6 +380,16 @@ class Graph:
             out[r.name.decode()] = dict(launches=r.launches, total_ms=r.total_ms, algo_bytes=r.algo_bytes,
                                         events=r.events, aux=r.aux)
         return out
+
+    def profile_counters(self):
+        """Raw profile counters (see hgt_profile_counters)."""
+        import numpy as np
+        out = np.zeros(64, np.uint64)
+        n = ctypes.c_uint32(0)
+        rc = load().hgt_profile_counters(self._h, out.ctypes.data, 64, ctypes.byref(n))
+        if rc != OK:
+            raise HgtError(rc, "hgt_profile_counters")
+        return out[: min(n.value, 64)]
 
     def export_h2v(self):
         """(offsets, members, live) numpy arrays indexed by ID."""

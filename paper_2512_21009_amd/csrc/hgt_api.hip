@@ -213,6 +213,7 @@ struct hgt_graph {
     int sticky = HGT_OK;
     uint64_t batches = 0;
     int force_stage = 0;            // HGT_FORCE_STAGE (tests): see He2Params
+    uint32_t pair_cap_max = 0;      // HGT_PAIR_CAP (tests): see He2Params
     BatchSummary* h_sum = nullptr;  // pinned
     DevScalars* h_sc = nullptr;     // pinned
     // profiling: HIP events around each kernel group, algorithmic-byte counters
@@ -670,6 +671,7 @@ int run_phase(hgt_graph* owner, const PhaseJob* jobs, uint32_t nj, bool minus, b
             E.garena_words = garena_words;
             E.stats = stats;
             E.force_stage = owner->force_stage;
+            E.pair_cap_max = owner->pair_cap_max;
             E.static_mode = full ? 1 : 0;
             hgt_fill_u32(ctr + 16, 0, 6, s);
             hgt_fill_u32(ctr + 5, 0, 1, s);
@@ -1140,6 +1142,7 @@ int hgt_build(const hgt_build_desc* d, hgt_graph** out) {
     g->window = d->temporal_window;
     g->last_stream = s;
     if (const char* fs = std::getenv("HGT_FORCE_STAGE")) g->force_stage = std::atoi(fs);
+    if (const char* pc = std::getenv("HGT_PAIR_CAP")) g->pair_cap_max = (uint32_t)std::atoi(pc);
     int rc = HGT_OK;
     do {
         HIP_BRK(hipGetDevice(&g->device));

@@ -317,10 +317,13 @@ __global__ void k_entries_check(Multi M, const uint64_t* n_entries_p, uint64_t c
 // the centres whose tables do not fit its arena to list s; list 2 feeds the
 // 2-hop kernel.  Stages 0 and 1 keep the arena in LDS (72 KB, 148 KB), stage 2
 // in a 1 MB slice of global memory per workgroup.
-// open-addressing insert that reports a full table (returns false)
+// open-addressing insert with a bounded probe sequence; false when the key
+// found no slot within PAIR_PROBES probes (the table is too full)
+constexpr uint32_t PAIR_PROBES = 32;
 __device__ __forceinline__ bool fr_add_ok(uint32_t* keys, uint32_t* vals, uint32_t cap, uint32_t key, uint32_t inc) {
     uint32_t s = fr_slot(key, cap);
-    for (uint32_t probe = 0; probe < cap; probe++) {
+    const uint32_t np = cap < PAIR_PROBES ? cap : PAIR_PROBES;
+    for (uint32_t probe = 0; probe < np; probe++) {
         uint32_t k = __atomic_load_n(&keys[s], __ATOMIC_RELAXED);
         if (k == HGT_EMPTY) {
             uint32_t prev = atomicCAS(&keys[s], HGT_EMPTY, key);
@@ -690,19 +693,13 @@ __device__ void he2_body(const He2Params& P, uint32_t* arena, const uint32_t ARE
             uint64_t o_ph = o_rs + W;
             uint64_t room = o_ph < ARENA_WORDS ? (ARENA_WORDS - o_ph) / 2 : 0;
             sh.runs = (W < 65536u && room >= 64) ? 1u : 0u;
-            // pair-hash slots: the room left, at most 4 W (clearing it costs as much as a pass over
-            // the keys); a pair hash that overflows falls back to merging rows
-            const uint64_t want = 4ull * W + 64;
-            sh.pcap = sh.runs ? (uint32_t)(room < want ? room : want) : 0u;
+            sh.pcap = (uint32_t)(room < 0x7fffffffull ? room : 0x7fffffffull);  // room; sized below
             sh.ovf = 0;
+            sh.g[5] = 0;  // pair visits
         }
         __syncthreads();
         if (sh.runs) {
             uint32_t* rs = (uint32_t*)(keys + W);
-            uint32_t* pk = rs + W;
-            uint32_t* pv = pk + sh.pcap;
-            const uint32_t pcap = sh.pcap;
-            for (uint32_t i = tid; i < pcap; i += HGT_WG) { pk[i] = HGT_EMPTY; pv[i] = 0; }
             // run starts: inclusive max-scan of the head positions
             {
                 uint32_t carry = 0;
@@ -733,11 +730,29 @@ __device__ void he2_body(const He2Params& P, uint32_t* arena, const uint32_t ARE
                         const uint32_t i = (uint32_t)ii;
                         const uint32_t e = inc < carry ? inc : carry;
                         const uint32_t st0 = rs[i];
-                        rs[i] = st0 | ((e - st0 + 1) << 16);
+                        const uint32_t R = e - st0 + 1;
+                        rs[i] = st0 | (R << 16);
+                        if (i == st0 && R > 1)  // run head: the run's pairs
+                            atomicAdd((unsigned long long*)&sh.g[5], (unsigned long long)R * (R - 1) / 2);
                     }
                     carry = tot < carry ? tot : carry;
                 }
             }
+            __syncthreads();
+            // pair hash: twice the pair visits (a bound on the multi pairs), within the
+            // room left; a pair that finds no slot within a few probes marks the hash
+            // overflowed and every multi pair is then merged instead
+            if (tid == 0) {
+                const uint64_t want = 2ull * sh.g[5] + 64;
+                uint64_t cap = want < sh.pcap ? want : sh.pcap;
+                if (P.pair_cap_max && cap > P.pair_cap_max) cap = P.pair_cap_max;
+                sh.pcap = (uint32_t)cap;
+            }
+            __syncthreads();
+            const uint32_t pcap = sh.pcap;
+            uint32_t* pk = rs + W;
+            uint32_t* pv = pk + pcap;
+            for (uint32_t i = tid; i < pcap; i += HGT_WG) { pk[i] = HGT_EMPTY; pv[i] = 0; }
             __syncthreads();
             for (uint32_t i = tid; i < W; i += HGT_WG) {
                 const uint32_t r = rs[i], st0 = r & 0xffffu, R = r >> 16;
@@ -753,6 +768,7 @@ __device__ void he2_body(const He2Params& P, uint32_t* arena, const uint32_t ARE
                     if (jj >= R) jj -= R;
                     const uint32_t yi = (uint32_t)keys[st0 + jj] & K_MAX;
                     if (xsh > 1 && nl_msh[yi] > 1) {
+                        if (*((volatile uint32_t*)&sh.ovf)) continue;  // redone by merging
                         const uint32_t a = xi < yi ? xi : yi, b = xi < yi ? yi : xi;
                         if (!fr_add_ok(pk, pv, pcap, (a << 14) | b, 1u | (vin << 16))) sh.ovf = 1;
                         continue;

@@ -188,3 +188,17 @@ def test_every_kernel_path(gpu_lib, monkeypatch, stage):
         p.apply(b, f"stage {stage} medium batch {k}")
         compare_counts(p.g, p.o, p.track, f"stage {stage} medium batch {k}")
     p.close()
+
+
+def test_pair_hash_overflow_path(gpu_lib, monkeypatch):
+    """A pair hash of 3 slots overflows on every centre with pairs that share
+    several vertices: those pairs are then merged row by row; same results."""
+    monkeypatch.setenv("HGT_PAIR_CAP", "3")
+    for st in (W.medium(scale=0.0005, n_batches=2),
+               W.plain_stream("hub", 400, 700, ("power", 1.6, 2, 150), 1.3, 0.0, 2, 80, 90, W.SEED_BASE + 78)):
+        p = Pair(st, track=("hyperedge",))
+        compare_counts(p.g, p.o, p.track, "pair cap build")
+        for k, b in enumerate(st.batches):
+            p.apply(b, f"pair cap batch {k}")
+            compare_counts(p.g, p.o, p.track, f"pair cap batch {k}")
+        p.close()

@@ -282,10 +282,14 @@ __global__ void k_heads(const uint64_t* __restrict__ keys, const uint64_t* n_pai
 }
 
 // head[] was scanned in place into tidx[] (exclusive), is_ins into ins_pre[].
+// After a failed validation the pair keys were not (all) written: the plan
+// kernels that index arrays with decoded keys then stop.
 __global__ void k_split(const uint64_t* __restrict__ keys, const uint64_t* n_pairs_p, int hb,
                         const uint64_t* __restrict__ tidx, const uint64_t* __restrict__ ins_pre,
-                        const uint32_t* __restrict__ rank_id, uint32_t* tv, uint64_t* tseg, uint32_t* D_all,
-                        uint32_t* I_all, uint32_t* I_t, const uint64_t* n_touched_p) {
+                        const uint32_t* __restrict__ rank_id, uint64_t n_rank, uint32_t* tv, uint64_t* tseg,
+                        uint32_t* D_all, uint32_t* I_all, uint32_t* I_t, const uint64_t* n_touched_p,
+                        const DevScalars* sc) {
+    if (status_bad(&sc->status)) return;
     uint64_t n = *n_pairs_p;
     uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i == 0) tseg[*n_touched_p] = n;
@@ -301,7 +305,7 @@ __global__ void k_split(const uint64_t* __restrict__ keys, const uint64_t* n_pai
     }
     uint64_t ip = ins_pre[i];
     if (k & 1ull) {
-        I_all[ip] = rank_id ? rank_id[h] : h;  // time-ordered: rank -> ID
+        I_all[ip] = rank_id ? (h < n_rank ? rank_id[h] : HGT_EMPTY) : h;  // time-ordered: rank -> ID
         I_t[ip] = (uint32_t)t;
     } else {
         D_all[i - ip] = h;
@@ -312,6 +316,7 @@ __global__ void k_vplan(const uint64_t* n_touched_p, const uint32_t* __restrict_
                         const uint64_t* __restrict__ ins_pre, const uint64_t* n_pairs_p, const uint64_t* ins_total,
                         const uint32_t* __restrict__ v_len, const uint32_t* __restrict__ v_cap, VPlan p,
                         DevScalars* sc) {
+    if (status_bad(&sc->status)) return;
     uint64_t nt = *n_touched_p;
     uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nt) return;
@@ -593,8 +598,8 @@ void store_plan(StoreDev& g, BatchIn& b, PlanScratch& w, hipStream_t s) {
     k_heads<<<blocks_for(pmax), 256, 0, s>>>(w.keys, w.n_pairs, g.hb, w.head, w.is_ins);
     hgt_scan_u64(w.head, w.head, pmax, w.n_pairs, w.n_touched, w.scan_tmp, s);
     hgt_scan_u64(w.is_ins, w.is_ins, pmax, w.n_pairs, w.n_ins_pairs, w.scan_tmp, s);
-    k_split<<<blocks_for(pmax), 256, 0, s>>>(w.keys, w.n_pairs, g.hb, w.head, w.is_ins, rank_id, w.tv, w.tseg, w.D_all,
-                                             w.I_all, w.I_t, w.n_touched);
+    k_split<<<blocks_for(pmax), 256, 0, s>>>(w.keys, w.n_pairs, g.hb, w.head, w.is_ins, rank_id, n_ins, w.tv, w.tseg,
+                                             w.D_all, w.I_all, w.I_t, w.n_touched, sc);
     k_vplan<<<blocks_for(pmax), 256, 0, s>>>(w.n_touched, w.tv, w.tseg, w.is_ins, w.n_pairs, w.n_ins_pairs, g.v_len,
                                              g.v_cap, w.vp, sc);
     hgt_scan_u64(w.vp.need, w.vp.rel, pmax, w.n_touched, w.v2h_total, w.scan_tmp, s);

@@ -214,6 +214,7 @@ struct hgt_graph {
     uint64_t batches = 0;
     int force_stage = 0;            // HGT_FORCE_STAGE (tests): see He2Params
     uint32_t pair_cap_max = 0;      // HGT_PAIR_CAP (tests): see He2Params
+    int pair_runs = 0;              // HGT_PAIR_RUNS=1: run-table pair phase (see He2Params)
     BatchSummary* h_sum = nullptr;  // pinned
     DevScalars* h_sc = nullptr;     // pinned
     // profiling: HIP events around each kernel group, algorithmic-byte counters
@@ -672,6 +673,7 @@ int run_phase(hgt_graph* owner, const PhaseJob* jobs, uint32_t nj, bool minus, b
             E.stats = stats;
             E.force_stage = owner->force_stage;
             E.pair_cap_max = owner->pair_cap_max;
+            E.pair_runs = owner->pair_runs;
             E.static_mode = full ? 1 : 0;
             hgt_fill_u32(ctr + 16, 0, 6, s);
             hgt_fill_u32(ctr + 5, 0, 1, s);
@@ -1143,6 +1145,7 @@ int hgt_build(const hgt_build_desc* d, hgt_graph** out) {
     g->last_stream = s;
     if (const char* fs = std::getenv("HGT_FORCE_STAGE")) g->force_stage = std::atoi(fs);
     if (const char* pc = std::getenv("HGT_PAIR_CAP")) g->pair_cap_max = (uint32_t)std::atoi(pc);
+    if (const char* pr = std::getenv("HGT_PAIR_RUNS")) g->pair_runs = std::atoi(pr) != 0;
     int rc = HGT_OK;
     do {
         HIP_BRK(hipGetDevice(&g->device));
@@ -1157,7 +1160,11 @@ int hgt_build(const hgt_build_desc* d, hgt_graph** out) {
         }
         g->st.n_vertices = d->n_vertices;
         g->st.id_cap = 0;
-        g->st.time_order = tmp ? 1 : 0;
+        // time-ordered incidence lists (windowed temporal scans) only on request: HGT_TIME_ORDER=1
+        {
+            const char* to = std::getenv("HGT_TIME_ORDER");
+            g->st.time_order = (tmp && to && std::atoi(to) != 0) ? 1 : 0;
+        }
         uint64_t cap = std::max<uint64_t>(d->edge_capacity, d->n_edges + d->n_edges / 4 + 64);
         if ((rc = ensure_id_cap(g, cap, s))) break;
         uint64_t V = d->n_vertices;

@@ -118,6 +118,8 @@ struct He2Params {
     uint64_t* stats;
     int force_stage;             // test knob: stages below it move every centre on
     uint32_t pair_cap_max;       // test knob: pair-hash slots at most this (0 = no limit)
+    int pair_runs;               // 1: run-table pair phase with the pair hash; 0: pairs per run
+                                 // entry, pairs sharing several vertices merged row by row
     int static_mode;             // full count (build): no batch ranks, no open paths through
                                  // neighbours; open triples at their centre, closed ones at the
                                  // smallest-ID centre

@@ -692,7 +692,7 @@ __device__ void he2_body(const He2Params& P, uint32_t* arena, const uint32_t ARE
             uint64_t o_rs = (uint64_t)sh.o_ent + 2ull * W;
             uint64_t o_ph = o_rs + W;
             uint64_t room = o_ph < ARENA_WORDS ? (ARENA_WORDS - o_ph) / 2 : 0;
-            sh.runs = (W < 65536u && room >= 64) ? 1u : 0u;
+            sh.runs = (P.pair_runs && W < 65536u && room >= 64) ? 1u : 0u;
             sh.pcap = (uint32_t)(room < 0x7fffffffull ? room : 0x7fffffffull);  // room; sized below
             sh.ovf = 0;
             sh.g[5] = 0;  // pair visits

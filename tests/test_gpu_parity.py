@@ -190,9 +190,12 @@ def test_every_kernel_path(gpu_lib, monkeypatch, stage):
     p.close()
 
 
+@pytest.mark.skip(reason="the run-table pair phase (HGT_PAIR_RUNS=1) is switched off: a GPU run with it "
+                         "enabled faulted and the cause is not found yet")
 def test_pair_hash_overflow_path(gpu_lib, monkeypatch):
     """A pair hash of 3 slots overflows on every centre with pairs that share
     several vertices: those pairs are then merged row by row; same results."""
+    monkeypatch.setenv("HGT_PAIR_RUNS", "1")
     monkeypatch.setenv("HGT_PAIR_CAP", "3")
     for st in (W.medium(scale=0.0005, n_batches=2),
                W.plain_stream("hub", 400, 700, ("power", 1.6, 2, 150), 1.3, 0.0, 2, 80, 90, W.SEED_BASE + 78)):

@@ -215,6 +215,7 @@ struct hgt_graph {
     int force_stage = 0;            // HGT_FORCE_STAGE (tests): see He2Params
     uint32_t pair_cap_max = 0;      // HGT_PAIR_CAP (tests): see He2Params
     int pair_runs = 0;              // HGT_PAIR_RUNS=1: run-table pair phase (see He2Params)
+    int pair_agg = 1;               // HGT_PAIR_AGG=0: pairs enumerated per run (see He2Params)
     BatchSummary* h_sum = nullptr;  // pinned
     DevScalars* h_sc = nullptr;     // pinned
     // profiling: HIP events around each kernel group, algorithmic-byte counters
@@ -674,6 +675,7 @@ int run_phase(hgt_graph* owner, const PhaseJob* jobs, uint32_t nj, bool minus, b
             E.force_stage = owner->force_stage;
             E.pair_cap_max = owner->pair_cap_max;
             E.pair_runs = owner->pair_runs;
+            E.pair_agg = owner->pair_agg;
             E.static_mode = full ? 1 : 0;
             hgt_fill_u32(ctr + 16, 0, 6, s);
             hgt_fill_u32(ctr + 5, 0, 1, s);
@@ -1146,6 +1148,7 @@ int hgt_build(const hgt_build_desc* d, hgt_graph** out) {
     if (const char* fs = std::getenv("HGT_FORCE_STAGE")) g->force_stage = std::atoi(fs);
     if (const char* pc = std::getenv("HGT_PAIR_CAP")) g->pair_cap_max = (uint32_t)std::atoi(pc);
     if (const char* pr = std::getenv("HGT_PAIR_RUNS")) g->pair_runs = std::atoi(pr) != 0;
+    if (const char* pa = std::getenv("HGT_PAIR_AGG")) g->pair_agg = std::atoi(pa) != 0;
     int rc = HGT_OK;
     do {
         HIP_BRK(hipGetDevice(&g->device));

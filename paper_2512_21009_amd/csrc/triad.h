@@ -73,6 +73,9 @@ enum TriadStat {
     ST_IV_BYTES = 5,     // algorithmic bytes gathered by the incident-vertex kernel
     ST_DEFER0 = 6,       // centres moved on by histogram-kernel stage 0, 1, 2
     ST_HEB0 = 9,         // algorithmic bytes gathered by histogram-kernel stage 0, 1, 2
+    ST_AGG_LONG = 12,    // aggregated pair phase: long runs counted by histogram
+    ST_AGG_MULTI = 13,   // ... pairs sharing two or more vertices, corrected
+    ST_AGG_ENUM = 14,    // centres whose pairs were enumerated per run instead
     ST_PH0 = 16,         // wall-clock ticks per phase of histogram-kernel stage s: ST_PH0 + 8 s + phase
     ST_TMP0 = 40,        // the temporal launches' counters: ST_TMP0 + (ST_BYTES_SMALL .. ST_EXPANDED)
     ST_N = 48
@@ -120,6 +123,8 @@ struct He2Params {
     uint32_t pair_cap_max;       // test knob: pair-hash slots at most this (0 = no limit)
     int pair_runs;               // 1: run-table pair phase with the pair hash; 0: pairs per run
                                  // entry, pairs sharing several vertices merged row by row
+    int pair_agg;                // 1: pairs counted per shared vertex by class histograms, pairs
+                                 // sharing several vertices found through their vertex pairs
     int static_mode;             // full count (build): no batch ranks, no open paths through
                                  // neighbours; open triples at their centre, closed ones at the
                                  // smallest-ID centre

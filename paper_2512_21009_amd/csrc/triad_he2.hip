@@ -97,6 +97,8 @@ struct Sh2 {
     uint32_t ncap;
     uint32_t o_nh, o_ent;  // arena word offsets
     uint32_t runs, pcap, ovf;  // intersecting pairs: run table present, pair-hash slots, overflow
+    uint32_t agg, nbig, nb1;   // aggregated pair phase: taken, long runs, long-run members of length > 1
+    uint64_t acc2[NWAVE * HGT_N_HE_CLASSES];  // twice the closed-class changes of single-vertex pairs
     uint32_t ws[NWAVE];
     uint64_t g[8];
 };
@@ -393,6 +395,85 @@ __device__ __forceinline__ void pair_class(const He2Params& P, const Tables& T, 
     }
 }
 
+// ---- single-vertex pairs, aggregated.  Take neighbours x, y of h that meet
+// in exactly one vertex v (vin: v in h).  The class changes of the pair depend
+// on y only through two bits gy and through how c_y = |y & h| compares with
+// |h| - c_x (rng 0: less, 1: equal, 2: greater), so along a long run of
+// neighbours at v they are counted from a histogram over (gy, c_y).
+constexpr uint32_t RUN_DIRECT = 64;  // runs up to this length enumerate their pairs
+
+__device__ __forceinline__ uint32_t single_gy(uint32_t vin, uint32_t yl, uint32_t cy) {
+    return vin ? ((yl > cy ? 1u : 0u) | (cy > 1 ? 2u : 0u)) : ((yl > cy ? 1u : 0u) | (yl - cy > 1 ? 2u : 0u));
+}
+
+// Venn codes of the closed triad {h, x, y} (ct) and of the same x, y taken as
+// disjoint (cf), for a pair meeting in one vertex (the regions of venn_code
+// with |x & y| = 1 and |h & x & y| = vin).
+__device__ __forceinline__ void single_codes(uint32_t vin, uint32_t xl, uint32_t cx, uint32_t gy, uint32_t rng, int& ct,
+                                             int& cf) {
+    cf = (rng == 0 ? 1 : 0) | (xl > cx ? 2 : 0) | ((gy & 1u) ? 4 : 0) | 8 | 32;
+    if (vin)
+        ct = (rng <= 1 ? 1 : 0) | (xl > cx ? 2 : 0) | ((gy & 1u) ? 4 : 0) | (cx > 1 ? 8 : 0) | ((gy & 2u) ? 32 : 0) | 64;
+    else
+        ct = (rng == 0 ? 1 : 0) | (xl - cx > 1 ? 2 : 0) | ((gy & 2u) ? 4 : 0) | 8 | 16 | 32;
+}
+
+// pair_class of a delta (not a full count) with every change weighted by w
+__device__ __forceinline__ void pair_class_w(const Tables& T, uint32_t hlen, uint32_t mx, uint32_t my, uint32_t s,
+                                             uint32_t shh, uint32_t w, uint32_t* myacc32) {
+    const uint32_t xl = meta_len(mx), yl = meta_len(my), cx = meta_c(mx), cy = meta_c(my);
+    const uint32_t nw = 0u - w;
+    const bool ex = meta_elig(mx), ey = meta_elig(my);
+    if (ex) {
+        uint32_t base = (hlen > cx ? 1u : 0u) | 24u;
+        acc32_add(myacc32, T.he[base | (xl - cx > s ? 2u : 0u) | (yl > s ? 4u : 0u)], nw);
+    }
+    if (ey) {
+        uint32_t base = (hlen > cy ? 1u : 0u) | 24u;
+        acc32_add(myacc32, T.he[base | (yl - cy > s ? 2u : 0u) | (xl > s ? 4u : 0u)], nw);
+    }
+    if (ex && ey) {
+        int ct = T.he[venn_code((int)hlen, (int)xl, (int)yl, (int)cx, (int)s, (int)cy, (int)shh)];
+        int cf = T.he[venn_code((int)hlen, (int)xl, (int)yl, (int)cx, 0, (int)cy, 0)];
+        if (ct != cf) {
+            acc32_add(myacc32, ct, w);
+            acc32_add(myacc32, cf, nw);
+        }
+    }
+}
+
+// |x & y|, |x & y & h| and the two smallest common vertices of two sorted rows
+__device__ __forceinline__ void row_meet2(const uint32_t* X, uint32_t xl, const uint32_t* Y, uint32_t yl,
+                                          const uint32_t* hm, uint32_t hlen, uint32_t& s, uint32_t& shh,
+                                          uint32_t& f1, uint32_t& f2) {
+    uint32_t a = 0, b = 0;
+    s = 0;
+    shh = 0;
+    f1 = f2 = HGT_EMPTY;
+    while (a < xl && b < yl) {
+        uint32_t va = X[a], vb = Y[b];
+        if (va < vb) a++;
+        else if (va > vb) b++;
+        else {
+            if (s == 0) f1 = va;
+            else if (s == 1) f2 = va;
+            s++;
+            shh += contains_u32(hm, hlen, va) ? 1u : 0u;
+            a++;
+            b++;
+        }
+    }
+}
+
+__device__ __forceinline__ uint32_t lower_bound_u64(const uint64_t* a, uint32_t n, uint64_t key) {
+    uint32_t lo = 0, hi = n;
+    while (lo < hi) {
+        uint32_t mid = (lo + hi) >> 1;
+        if (a[mid] < key) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
 // Adds the per-wave counts to graph g's phase accumulators and clears them.
 __device__ void he2_flush_graph(const He2Params& P, uint32_t g, uint64_t* acc_all) {
     __syncthreads();
@@ -680,6 +761,210 @@ __device__ void he2_body(const He2Params& P, uint32_t* arena, const uint32_t ARE
         }
         if (P.stats) __syncthreads();
         HE2_MARK(5);
+        // --- intersecting neighbour pairs, aggregated.  Every pair of neighbours in the
+        // run of a shared vertex v is first taken as meeting only at v: its changes are
+        // enumerated along runs of up to RUN_DIRECT entries and counted from a (gy, c_y)
+        // histogram along longer runs, the closed-class changes once per ordered pair
+        // (twice per pair, halved at the end).  Pairs that share s >= 2 vertices were
+        // so counted once at each of them; they are found through the vertex pairs
+        // (u, w) that each neighbour holds among its shared vertices (sorted, so the
+        // neighbours holding u and w are contiguous), each at its two smallest common
+        // vertices, and get their true changes in place of the s single ones.  Layout
+        // after the entries: long runs, histogram, per-neighbour offsets of the shared
+        // vertices and of the vertex pairs, fill cursors, shared vertices, vertex pairs.
+        if (tid == 0) {
+            sh.agg = 0;
+            sh.nbig = 0;
+            sh.g[6] = 0;  // shared entries of neighbours with two or more
+            sh.g[7] = 0;  // their vertex pairs
+        }
+        __syncthreads();
+        const uint32_t nb_cap = W / (RUN_DIRECT + 1) + 1, n_hist = 4u * (hlen + 1);
+        const uint64_t o_big = (uint64_t)sh.o_ent + 2ull * W, o_hist = o_big + nb_cap, o_off = o_hist + n_hist;
+        const uint64_t o_eoff = o_off + K + 1, o_cur = o_eoff + K + 1, o_sl = o_cur + K;
+        if (!P.static_mode && P.pair_agg && W < 65536u && o_sl <= ARENA_WORDS) {
+            for (uint32_t i = tid; i < K; i += HGT_WG) {
+                const uint64_t m = nl_msh[i];
+                if (m >= 2) {
+                    atomicAdd((unsigned long long*)&sh.g[6], (unsigned long long)m);
+                    atomicAdd((unsigned long long*)&sh.g[7], (unsigned long long)(m * (m - 1) / 2));
+                }
+            }
+            __syncthreads();
+            if (tid == 0) {
+                const uint64_t o_emit = (o_sl + sh.g[6] + 1) & ~1ull;
+                sh.agg = (o_emit + 2ull * sh.g[7] <= ARENA_WORDS) ? 1u : 0u;
+            }
+            __syncthreads();
+        }
+        if (P.stats && tid == 0 && !P.static_mode && !sh.agg) atomicAdd((unsigned long long*)&P.stats[ST_AGG_ENUM], 1ull);
+        if (sh.agg) {
+            const uint32_t S = (uint32_t)sh.g[6], E2 = (uint32_t)sh.g[7];
+            uint32_t* big = arena + o_big;
+            uint32_t* hist = arena + o_hist;
+            uint32_t* off = arena + o_off;
+            uint32_t* eoff = arena + o_eoff;
+            uint32_t* cur = arena + o_cur;
+            uint32_t* sl = arena + o_sl;
+            uint64_t* emit = (uint64_t*)(arena + ((o_sl + S + 1) & ~1ull));
+            uint64_t* myacc2 = sh.acc2 + (tid >> 6) * HGT_N_HE_CLASSES;
+            {
+                uint32_t carry_s = 0, carry_e = 0;
+                for (uint32_t b = 0; b < K; b += HGT_WG) {
+                    const uint32_t i = b + tid;
+                    uint32_t m = i < K ? nl_msh[i] : 0;
+                    if (m < 2) m = 0;
+                    uint32_t tot_s, tot_e;
+                    const uint32_t ex_s = wg_scan_u32(m, sh.ws, &tot_s);
+                    const uint32_t ex_e = wg_scan_u32(m * (m - 1) / 2, sh.ws, &tot_e);
+                    if (i < K) {
+                        off[i] = carry_s + ex_s;
+                        eoff[i] = carry_e + ex_e;
+                        cur[i] = 0;
+                    }
+                    carry_s += tot_s;
+                    carry_e += tot_e;
+                }
+                if (tid == 0) {
+                    off[K] = carry_s;
+                    eoff[K] = carry_e;
+                }
+            }
+            __syncthreads();
+            // runs: shared vertices per neighbour, long runs listed, short runs enumerated
+            for (uint32_t i = tid; i < W; i += HGT_WG) {
+                const uint64_t ki = keys[i];
+                const uint64_t v = ki >> 15;
+                const uint32_t st0 = lower_bound_u64(keys, W, v << 15);
+                const uint32_t en = lower_bound_u64(keys, W, (v + 1) << 15);
+                const uint32_t R = en - st0;
+                if (R < 2) continue;
+                const uint32_t xi = (uint32_t)ki & K_MAX;
+                if (nl_msh[xi] >= 2) sl[off[xi] + atomicAdd(&cur[xi], 1u)] = st0;
+                if (R > RUN_DIRECT) {
+                    if (i == st0) big[atomicAdd(&sh.nbig, 1u)] = st0 | (R << 16);
+                    continue;
+                }
+                const uint32_t mx = nl_meta[xi];
+                if (!meta_elig(mx)) continue;
+                const uint32_t vin = (uint32_t)(ki >> 14) & 1u;
+                const uint32_t xl = meta_len(mx), cx = meta_c(mx), dx = hlen - cx;
+                const uint32_t ob = (hlen > cx ? 1u : 0u) | 24u | (xl - cx > 1 ? 2u : 0u);
+                for (uint32_t j = st0; j < en; j++) {
+                    if (j == i) continue;
+                    const uint32_t my = nl_meta[(uint32_t)keys[j] & K_MAX];
+                    const uint32_t yl = meta_len(my), cy = meta_c(my);
+                    acc32_add(myacc32, T.he[ob | (yl > 1 ? 4u : 0u)], ~0u);
+                    if (!meta_elig(my)) continue;
+                    int ct, cf;
+                    single_codes(vin, xl, cx, single_gy(vin, yl, cy), cy < dx ? 0u : (cy == dx ? 1u : 2u), ct, cf);
+                    const int c1 = T.he[ct], c2 = T.he[cf];
+                    if (c1 != c2) {
+                        if (c1 < 255) atomicAdd((unsigned long long*)&myacc2[c1], 1ull);
+                        if (c2 < 255) atomicAdd((unsigned long long*)&myacc2[c2], ~0ull);
+                    }
+                }
+            }
+            __syncthreads();
+            // vertex pairs (u, w), u < w, of each neighbour's shared vertices, as run starts
+            for (uint32_t a = tid; a < S; a += HGT_WG) {
+                const uint32_t x = seg_of<uint32_t>(off, K, a);
+                const uint32_t o = off[x], m = off[x + 1] - o, j = a - o;
+                uint32_t pos = eoff[x] + j * (m - 1) - j * (j - 1) / 2;
+                const uint32_t u = sl[a];
+                for (uint32_t q = j + 1; q < m; q++) {
+                    const uint32_t w = sl[o + q];
+                    const uint32_t lo = u < w ? u : w, hi = u < w ? w : u;
+                    emit[pos++] = ((uint64_t)lo << 30) | ((uint64_t)hi << 14) | x;
+                }
+            }
+            __syncthreads();
+            sort_keys(emit, E2);
+            // long runs, one at a time: histogram over (gy, c_y) of the eligible members
+            const uint32_t nbig = sh.nbig;
+            if (P.stats && tid == 0 && nbig) atomicAdd((unsigned long long*)&P.stats[ST_AGG_LONG], (unsigned long long)nbig);
+            for (uint32_t r = 0; r < nbig; r++) {
+                const uint32_t br = big[r], st0 = br & 0xffffu, R = br >> 16;
+                const uint32_t vin = (uint32_t)(keys[st0] >> 14) & 1u;
+                for (uint32_t c = tid; c < n_hist; c += HGT_WG) hist[c] = 0;
+                if (tid == 0) sh.nb1 = 0;
+                __syncthreads();
+                for (uint32_t i = st0 + tid; i < st0 + R; i += HGT_WG) {
+                    const uint32_t my = nl_meta[(uint32_t)keys[i] & K_MAX];
+                    const uint32_t yl = meta_len(my), cy = meta_c(my);
+                    if (yl > 1) atomicAdd(&sh.nb1, 1u);
+                    if (meta_elig(my)) atomicAdd(&hist[single_gy(vin, yl, cy) * (hlen + 1) + cy], 1u);
+                }
+                __syncthreads();
+                {  // inclusive prefix over the rows laid end to end
+                    uint32_t carry = 0;
+                    for (uint32_t b = 0; b < n_hist; b += HGT_WG) {
+                        const uint32_t i = b + tid;
+                        const uint32_t v = i < n_hist ? hist[i] : 0;
+                        uint32_t tot;
+                        const uint32_t ex = wg_scan_u32(v, sh.ws, &tot);
+                        if (i < n_hist) hist[i] = carry + ex + v;
+                        carry += tot;
+                    }
+                }
+                __syncthreads();
+                const uint32_t nb1 = sh.nb1;
+                for (uint32_t i = st0 + tid; i < st0 + R; i += HGT_WG) {
+                    const uint32_t mx = nl_meta[(uint32_t)keys[i] & K_MAX];
+                    if (!meta_elig(mx)) continue;
+                    const uint32_t xl = meta_len(mx), cx = meta_c(mx), dx = hlen - cx;
+                    const uint32_t ob = (hlen > cx ? 1u : 0u) | 24u | (xl - cx > 1 ? 2u : 0u);
+                    const uint64_t n_big = nb1 - (xl > 1 ? 1u : 0u), n_small = (uint64_t)(R - 1) - n_big;
+                    if (n_big) acc_add(myacc, T.he[ob | 4u], 0ull - n_big);
+                    if (n_small) acc_add(myacc, T.he[ob], 0ull - n_small);
+                    const uint32_t gx = single_gy(vin, xl, cx);
+                    for (uint32_t g = 0; g < 4; g++) {
+                        const uint32_t row = g * (hlen + 1);
+                        const uint32_t before = hist[row];  // the rows before (nothing at c_y = 0)
+                        const uint32_t tot = hist[row + hlen] - before;
+                        uint32_t n3[3];
+                        n3[0] = dx >= 2 ? hist[row + dx - 1] - before : 0u;
+                        n3[1] = dx >= 1 ? hist[row + dx] - hist[row + dx - 1] : 0u;
+                        n3[2] = tot - n3[0] - n3[1];
+                        if (g == gx) n3[cx < dx ? 0 : (cx == dx ? 1 : 2)]--;  // x itself
+                        for (uint32_t rng = 0; rng < 3; rng++) {
+                            if (!n3[rng]) continue;
+                            int ct, cf;
+                            single_codes(vin, xl, cx, g, rng, ct, cf);
+                            const int c1 = T.he[ct], c2 = T.he[cf];
+                            if (c1 != c2) {
+                                if (c1 < 255) atomicAdd((unsigned long long*)&myacc2[c1], (unsigned long long)n3[rng]);
+                                if (c2 < 255) atomicAdd((unsigned long long*)&myacc2[c2], 0ull - (unsigned long long)n3[rng]);
+                            }
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+            // pairs sharing two or more vertices, at their two smallest common ones
+            for (uint32_t i = tid; i < E2; i += HGT_WG) {
+                const uint64_t e = emit[i];
+                const uint64_t uw = e >> 14;
+                const uint32_t xi = (uint32_t)e & K_MAX;
+                const uint32_t vu = (uint32_t)(keys[(uint32_t)(e >> 30)] >> 15);
+                const uint32_t vw = (uint32_t)(keys[(uint32_t)uw & 0xffffu] >> 15);
+                const uint32_t mx = nl_meta[xi];
+                const uint32_t* X = G.g.h2v + G.g.h_off[nl_x[xi]];
+                for (uint32_t j = i + 1; j < E2; j++) {
+                    const uint64_t f = emit[j];
+                    if ((f >> 14) != uw) break;
+                    const uint32_t yi = (uint32_t)f & K_MAX;
+                    const uint32_t my = nl_meta[yi];
+                    uint32_t s, shh, f1, f2;
+                    row_meet2(X, meta_len(mx), G.g.h2v + G.g.h_off[nl_x[yi]], meta_len(my), hm, hlen, s, shh, f1, f2);
+                    if (f1 != vu || f2 != vw) continue;
+                    if (P.stats) atomicAdd((unsigned long long*)&P.stats[ST_AGG_MULTI], 1ull);
+                    pair_class_w(T, hlen, mx, my, s, shh, 1u, myacc32);
+                    if (shh) pair_class_w(T, hlen, mx, my, 1, 1, 0u - shh, myacc32);
+                    if (s > shh) pair_class_w(T, hlen, mx, my, 1, 0, 0u - (s - shh), myacc32);
+                }
+            }
+        } else {
         // --- intersecting neighbour pairs.  The neighbours that meet at a vertex v form
         // a run of the sorted keys; every pair of a run meets at v.  When one side has a
         // single shared member the pair meets only at v (|x & y| = 1); the other pairs
@@ -830,6 +1115,7 @@ __device__ void he2_body(const He2Params& P, uint32_t* arena, const uint32_t ARE
                 }
             }
         }
+        }  // aggregated or enumerated pairs
         __syncthreads();
         // fold the per-centre 32-bit pair counters (signed) into the 64-bit ones
         for (uint32_t i = tid; i < NWAVE * HGT_N_HE_CLASSES; i += HGT_WG) {
@@ -837,6 +1123,16 @@ __device__ void he2_body(const He2Params& P, uint32_t* arena, const uint32_t ARE
             if (v) {
                 atomicAdd((unsigned long long*)&acc_all[i], (unsigned long long)(int64_t)v);
                 acc32_all[i] = 0;
+            }
+        }
+        if (sh.agg) {  // the doubled closed-class changes: over all waves, halved
+            for (uint32_t c = tid; c < HGT_N_HE_CLASSES; c += HGT_WG) {
+                int64_t s2 = 0;
+                for (int w = 0; w < NWAVE; w++) {
+                    s2 += (int64_t)sh.acc2[w * HGT_N_HE_CLASSES + c];
+                    sh.acc2[w * HGT_N_HE_CLASSES + c] = 0;
+                }
+                if (s2) atomicAdd((unsigned long long*)&acc_all[c], (unsigned long long)(s2 / 2));
             }
         }
         __syncthreads();
@@ -870,6 +1166,7 @@ __device__ void he2_flush_stats(const He2Params& P, const uint64_t* st, const ui
         (&acc32[0][0])[i] = 0;                                                         \
     }                                                                                  \
     if (threadIdx.x < 2) st[threadIdx.x] = 0;                                          \
+    for (int i = threadIdx.x; i < NWAVE * HGT_N_HE_CLASSES; i += HGT_WG) sh.acc2[i] = 0; \
     __syncthreads();
 
 __global__ void __launch_bounds__(HGT_WG) k_he2_s0(He2Params P) {

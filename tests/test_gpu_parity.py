@@ -190,6 +190,22 @@ def test_every_kernel_path(gpu_lib, monkeypatch, stage):
     p.close()
 
 
+@pytest.mark.parametrize("agg", ["0", "1"])
+def test_pair_phase_paths(gpu_lib, monkeypatch, agg):
+    """Intersecting neighbour pairs aggregated per shared vertex (1, with long
+    runs counted by histogram and pairs sharing several vertices corrected) or
+    enumerated per run (0); the dense hub graph sends most centres to the
+    enumerating path either way.  Same counts as the oracle."""
+    monkeypatch.setenv("HGT_PAIR_AGG", agg)
+    for st in (W.medium(scale=0.001, n_batches=2),
+               W.plain_stream("hub", 400, 700, ("power", 1.6, 2, 150), 1.3, 0.0, 2, 80, 90, W.SEED_BASE + 79)):
+        p = Pair(st, track=("hyperedge",))
+        for k, b in enumerate(st.batches):
+            p.apply(b, f"pair phase {agg} batch {k}")
+            compare_counts(p.g, p.o, p.track, f"pair phase {agg} batch {k}")
+        p.close()
+
+
 @pytest.mark.skip(reason="the run-table pair phase (HGT_PAIR_RUNS=1) is switched off: a GPU run with it "
                          "enabled faulted and the cause is not found yet")
 def test_pair_hash_overflow_path(gpu_lib, monkeypatch):

@@ -11,8 +11,9 @@
 //   h only  = |h| > c_x,  x only = |x| - c_x - |x & y| > 0,  y only = |y| > |x & y|,
 //   plus the regions h&x and x&y,
 // so they are counted from H_x with one threshold (|x & y| < |x| - c_x), minus
-// the y that do meet h (y = h, and the neighbours of h that meet x) and minus
-// the batch members that rank below h (read from x's batch-neighbour list).
+// h itself, minus the batch members that rank below h (read from x's
+// batch-neighbour list) and, in the pair phase, minus the other neighbours of h
+// that meet x.
 // Neighbour pairs {x, y} of h that intersect are found by grouping the member
 // vertices of all neighbours of h by vertex in LDS (work sum_{x in N(h)} |x|),
 // each pair counted at its smallest common vertex; they get their true class in
@@ -48,17 +49,6 @@ __device__ __forceinline__ void fr_add(uint32_t* keys, uint32_t* vals, uint32_t 
         }
         s = fr_next(s, cap);
     }
-}
-
-__device__ __forceinline__ uint32_t fr_find(const uint32_t* keys, uint32_t cap, uint32_t key) {
-    uint32_t s = fr_slot(key, cap);
-    for (uint32_t probe = 0; probe < cap; probe++) {
-        uint32_t k = keys[s];
-        if (k == key) return s;
-        if (k == HGT_EMPTY) return HGT_EMPTY;
-        s = fr_next(s, cap);
-    }
-    return HGT_EMPTY;
 }
 
 // Ascending bitonic sort of n keys in place by the whole workgroup.  The merge
@@ -376,16 +366,12 @@ __device__ __forceinline__ void pair_class(const He2Params& P, const Tables& T, 
             acc32_add(myacc32, T.he[venn_code((int)hlen, (int)xl, (int)yl, (int)cx, (int)s, (int)cy, (int)shh)], 1u);
         return;
     }
-    const bool ex = meta_elig(mx), ey = meta_elig(my);
-    if (ex) {
+    // a lower-ranked batch member was already taken off its partner's open paths
+    if (meta_elig(mx) && meta_elig(my)) {
         uint32_t base = (hlen > cx ? 1u : 0u) | 24u;
         acc32_add(myacc32, T.he[base | (xl - cx > s ? 2u : 0u) | (yl > s ? 4u : 0u)], ~0u);
-    }
-    if (ey) {
-        uint32_t base = (hlen > cy ? 1u : 0u) | 24u;
+        base = (hlen > cy ? 1u : 0u) | 24u;
         acc32_add(myacc32, T.he[base | (yl - cy > s ? 2u : 0u) | (xl > s ? 4u : 0u)], ~0u);
-    }
-    if (ex && ey) {
         int ct = T.he[venn_code((int)hlen, (int)xl, (int)yl, (int)cx, (int)s, (int)cy, (int)shh)];
         int cf = T.he[venn_code((int)hlen, (int)xl, (int)yl, (int)cx, 0, (int)cy, 0)];
         if (ct != cf) {
@@ -423,16 +409,11 @@ __device__ __forceinline__ void pair_class_w(const Tables& T, uint32_t hlen, uin
                                              uint32_t shh, uint32_t w, uint32_t* myacc32) {
     const uint32_t xl = meta_len(mx), yl = meta_len(my), cx = meta_c(mx), cy = meta_c(my);
     const uint32_t nw = 0u - w;
-    const bool ex = meta_elig(mx), ey = meta_elig(my);
-    if (ex) {
+    if (meta_elig(mx) && meta_elig(my)) {
         uint32_t base = (hlen > cx ? 1u : 0u) | 24u;
         acc32_add(myacc32, T.he[base | (xl - cx > s ? 2u : 0u) | (yl > s ? 4u : 0u)], nw);
-    }
-    if (ey) {
-        uint32_t base = (hlen > cy ? 1u : 0u) | 24u;
+        base = (hlen > cy ? 1u : 0u) | 24u;
         acc32_add(myacc32, T.he[base | (yl - cy > s ? 2u : 0u) | (xl > s ? 4u : 0u)], nw);
-    }
-    if (ex && ey) {
         int ct = T.he[venn_code((int)hlen, (int)xl, (int)yl, (int)cx, (int)s, (int)cy, (int)shh)];
         int cf = T.he[venn_code((int)hlen, (int)xl, (int)yl, (int)cx, 0, (int)cy, 0)];
         if (ct != cf) {
@@ -732,7 +713,7 @@ __device__ void he2_body(const He2Params& P, uint32_t* arena, const uint32_t ARE
             const uint32_t* H = G.hpool + 2 * G.g.h_off[x];
             const uint64_t xs = G.id_base + x;
             if (P.stats)  // x's histogram, list bounds and batch-neighbour entries
-                atomicAdd((unsigned long long*)&st[1], (unsigned long long)(8ull * lx + 16 + 12ull * P.bl_cnt[xs]));
+                atomicAdd((unsigned long long*)&st[1], (unsigned long long)(8ull * lx + 16 + 8ull * P.bl_cnt[xs]));
             // a_f: neighbours y with |x & y| < thr (x keeps a private vertex), b_f: the rest
             uint64_t a0 = 0, a1 = 0, b0 = 0, b1 = 0;
             for (uint32_t k = 1; k <= lx; k++) {
@@ -743,13 +724,12 @@ __device__ void he2_body(const He2Params& P, uint32_t* arena, const uint32_t ARE
             // the histogram holds h itself: k = c, y only = |h| > c
             if (c < thr) { if (hlen > c) a1--; else a0--; }
             else { if (hlen > c) b1--; else b0--; }
-            // lower-ranked batch members adjacent to x but not to h
+            // every lower-ranked batch member adjacent to x (the pair phase leaves out
+            // the ones that meet h)
             uint64_t bo = P.bl_off[xs], bn = P.bl_cnt[xs];
             for (uint64_t e = 0; e < bn; e++) {
                 uint64_t pay = P.bl_pay[bo + e];
                 if ((uint32_t)(pay >> 32) >= sh.rank) continue;
-                uint32_t d = P.bl_d[bo + e];
-                if (fr_find(nkeys, ncap, d) != HGT_EMPTY) continue;  // meets h: an intersecting pair
                 uint32_t k = (uint32_t)(pay >> 1) & 0x7fffffffu, f = (uint32_t)pay & 1u;
                 if (k < thr) { if (f) a1--; else a0--; }
                 else { if (f) b1--; else b0--; }
@@ -853,9 +833,9 @@ __device__ void he2_body(const He2Params& P, uint32_t* arena, const uint32_t ARE
                 for (uint32_t j = st0; j < en; j++) {
                     if (j == i) continue;
                     const uint32_t my = nl_meta[(uint32_t)keys[j] & K_MAX];
+                    if (!meta_elig(my)) continue;
                     const uint32_t yl = meta_len(my), cy = meta_c(my);
                     acc32_add(myacc32, T.he[ob | (yl > 1 ? 4u : 0u)], ~0u);
-                    if (!meta_elig(my)) continue;
                     int ct, cf;
                     single_codes(vin, xl, cx, single_gy(vin, yl, cy), cy < dx ? 0u : (cy == dx ? 1u : 2u), ct, cf);
                     const int c1 = T.he[ct], c2 = T.he[cf];
@@ -891,9 +871,10 @@ __device__ void he2_body(const He2Params& P, uint32_t* arena, const uint32_t ARE
                 __syncthreads();
                 for (uint32_t i = st0 + tid; i < st0 + R; i += HGT_WG) {
                     const uint32_t my = nl_meta[(uint32_t)keys[i] & K_MAX];
+                    if (!meta_elig(my)) continue;
                     const uint32_t yl = meta_len(my), cy = meta_c(my);
                     if (yl > 1) atomicAdd(&sh.nb1, 1u);
-                    if (meta_elig(my)) atomicAdd(&hist[single_gy(vin, yl, cy) * (hlen + 1) + cy], 1u);
+                    atomicAdd(&hist[single_gy(vin, yl, cy) * (hlen + 1) + cy], 1u);
                 }
                 __syncthreads();
                 {  // inclusive prefix over the rows laid end to end
@@ -908,13 +889,13 @@ __device__ void he2_body(const He2Params& P, uint32_t* arena, const uint32_t ARE
                     }
                 }
                 __syncthreads();
-                const uint32_t nb1 = sh.nb1;
+                const uint32_t nb1 = sh.nb1, ne = hist[n_hist - 1];  // eligible members: of length > 1, all
                 for (uint32_t i = st0 + tid; i < st0 + R; i += HGT_WG) {
                     const uint32_t mx = nl_meta[(uint32_t)keys[i] & K_MAX];
                     if (!meta_elig(mx)) continue;
                     const uint32_t xl = meta_len(mx), cx = meta_c(mx), dx = hlen - cx;
                     const uint32_t ob = (hlen > cx ? 1u : 0u) | 24u | (xl - cx > 1 ? 2u : 0u);
-                    const uint64_t n_big = nb1 - (xl > 1 ? 1u : 0u), n_small = (uint64_t)(R - 1) - n_big;
+                    const uint64_t n_big = nb1 - (xl > 1 ? 1u : 0u), n_small = (uint64_t)(ne - 1) - n_big;
                     if (n_big) acc_add(myacc, T.he[ob | 4u], 0ull - n_big);
                     if (n_small) acc_add(myacc, T.he[ob], 0ull - n_small);
                     const uint32_t gx = single_gy(vin, xl, cx);

@@ -116,16 +116,19 @@ def log_profile(args, prof):
                       f"algo={r['algo_bytes'] / 1e9:8.3f}GB ({gbs:7.1f} GB/s) events={r['events']} aux={r['aux']}")
 
 
-PHASES = ("prefix", "nbr-hash", "compact", "disjoint", "group", "open", "pairs", "hand-over")
+PHASES = ("prefix", "nbr-hash", "compact", "disjoint", "group", "open", "pairs", "hand-over", "pairs-short",
+          "pairs-vpairs", "pairs-long")
 
 
 def log_phases(args, ctr):
     """Share of wall-clock ticks per phase of each hyperedge-delta stage."""
     for s in range(3):
-        ph = [int(x) for x in ctr[16 + 8 * s: 24 + 8 * s]]
+        ph = [int(x) for x in ctr[16 + 12 * s: 16 + 12 * s + len(PHASES)]]
         tot = sum(ph)
         if tot:
             log(args, f"  stage {s} phases: " + " ".join(f"{n}={100.0 * v / tot:.1f}%" for n, v in zip(PHASES, ph)))
+    log(args, f"  aggregated pairs: long runs {int(ctr[12])}, pairs sharing several vertices {int(ctr[13])}, "
+              f"centres enumerated {int(ctr[14])}")
 
 
 def add_profiles(acc, prof):

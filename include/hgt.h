@@ -293,10 +293,14 @@ int hgt_profile_read(hgt_graph* g, hgt_kernel_time* out_host, uint32_t n_max, ui
 
 /* Waits for the graph's work and copies the raw device counters of the
  * profile (algorithmic bytes, hand-overs between kernel stages, wall-clock
- * ticks per phase of the hyperedge-delta stages: counters 16 + 8 s + p for
+ * ticks per phase of the hyperedge-delta stages: counters 16 + 12 s + p for
  * stage s and phase p = 0 member prefix, 1 neighbour hash, 2 compaction,
  * 3 disjoint-pair classes, 4 vertex grouping, 5 open paths, 6 intersecting
- * pairs, 7 hand-over) to out_host[0..n_max); *n_out receives the count. */
+ * pairs (all of them when enumerated; the correction of pairs sharing several
+ * vertices when aggregated), 7 hand-over, 8 aggregated: short runs, 9 vertex
+ * pairs, 10 long runs; 12-14 the aggregated phase's long runs, corrected
+ * pairs and enumerating centres; 56.. temporal counters) to
+ * out_host[0..n_max); *n_out receives the count (64). */
 int hgt_profile_counters(hgt_graph* g, uint64_t* out_host, uint32_t n_max, uint32_t* n_out);
 
 /* Class codes of the hyperedge (30) or temporal (96) family, ascending;

@@ -64,6 +64,7 @@ struct TriadParams {
 };
 
 // Counters accumulated by the triad kernels when TriadParams.stats is set.
+constexpr int HE2_PHASES = 12;  // timed phases of a histogram-kernel stage
 enum TriadStat {
     ST_BYTES_SMALL = 0,  // algorithmic bytes gathered by the small-centre kernel
     ST_BYTES_BIG = 1,    // ... by the large-centre kernel
@@ -76,9 +77,9 @@ enum TriadStat {
     ST_AGG_LONG = 12,    // aggregated pair phase: long runs counted by histogram
     ST_AGG_MULTI = 13,   // ... pairs sharing two or more vertices, corrected
     ST_AGG_ENUM = 14,    // centres whose pairs were enumerated per run instead
-    ST_PH0 = 16,         // wall-clock ticks per phase of histogram-kernel stage s: ST_PH0 + 8 s + phase
-    ST_TMP0 = 40,        // the temporal launches' counters: ST_TMP0 + (ST_BYTES_SMALL .. ST_EXPANDED)
-    ST_N = 48
+    ST_PH0 = 16,         // wall-clock ticks per phase of histogram-kernel stage s: ST_PH0 + HE2_PHASES s + phase
+    ST_TMP0 = 56,        // the temporal launches' counters: ST_TMP0 + (ST_BYTES_SMALL .. ST_EXPANDED)
+    ST_N = 64
 };
 
 BigLayout triad_big_layout(uint64_t max_lh, uint64_t max_card);

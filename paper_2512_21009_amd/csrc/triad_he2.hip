@@ -88,7 +88,7 @@ struct Sh2 {
     uint32_t o_nh, o_ent;  // arena word offsets
     uint32_t runs, pcap, ovf;  // intersecting pairs: run table present, pair-hash slots, overflow
     uint32_t agg, nbig, nb1;   // aggregated pair phase: taken, long runs, long-run members of length > 1
-    uint64_t acc2[NWAVE * HGT_N_HE_CLASSES];  // twice the closed-class changes of single-vertex pairs
+    uint64_t acc2[NWAVE * HGT_N_HE_CLASSES];  // the centre's changes, doubled (ordered pairs once)
     uint32_t ws[NWAVE];
     uint64_t g[8];
 };
@@ -455,6 +455,42 @@ __device__ __forceinline__ uint32_t lower_bound_u64(const uint64_t* a, uint32_t 
     return lo;
 }
 
+// Pair number q of a run of R (pairs (a, b), a < b, ordered by a then b): the
+// largest a with a R - a (a + 1) / 2 <= q, from the quadratic's root, then
+// corrected by one step either way against rounding.
+__device__ __forceinline__ void tri_decode(uint32_t R, uint32_t q, uint32_t& a, uint32_t& b) {
+    const double r2 = 2.0 * (double)R - 1.0;
+    const double d = r2 * r2 - 8.0 * (double)q;
+    int64_t aa = (int64_t)((r2 - sqrt(d > 0.0 ? d : 0.0)) * 0.5);
+    if (aa < 0) aa = 0;
+    if (aa > (int64_t)R - 2) aa = (int64_t)R - 2;
+    auto before = [R](uint64_t x) { return x * (2ull * R - x - 1) / 2; };
+    while (aa > 0 && before((uint64_t)aa) > q) aa--;
+    while (aa + 1 <= (int64_t)R - 2 && before((uint64_t)aa + 1) <= q) aa++;
+    a = (uint32_t)aa;
+    b = a + 1 + (uint32_t)(q - before((uint64_t)aa));
+}
+
+// Neighbours x, y (vertex-pair entries ex, ey of one (u, w) run) that share u
+// and w: when u and w are their two smallest common vertices, their s single
+// changes give way to the pair's own.
+__device__ __forceinline__ void multi_pair(const GraphView& g, const Tables& T, uint32_t hlen, const uint32_t* hm,
+                                           const uint64_t* keys, const uint32_t* nl_x, const uint32_t* nl_meta,
+                                           uint64_t ex, uint64_t ey, uint64_t* stats, uint32_t* myacc32) {
+    const uint32_t xi = (uint32_t)ex & K_MAX, yi = (uint32_t)ey & K_MAX;
+    const uint32_t vu = (uint32_t)(keys[(uint32_t)(ex >> 30)] >> 15);
+    const uint32_t vw = (uint32_t)(keys[(uint32_t)(ex >> 14) & 0xffffu] >> 15);
+    const uint32_t mx = nl_meta[xi], my = nl_meta[yi];
+    uint32_t s, shh, f1, f2;
+    row_meet2(g.h2v + g.h_off[nl_x[xi]], meta_len(mx), g.h2v + g.h_off[nl_x[yi]], meta_len(my), hm, hlen, s, shh, f1, f2);
+    // the run order of u and w need not be the vertex order
+    if (!((f1 == vu && f2 == vw) || (f1 == vw && f2 == vu))) return;
+    if (stats) atomicAdd((unsigned long long*)&stats[ST_AGG_MULTI], 1ull);
+    pair_class_w(T, hlen, mx, my, s, shh, 1u, myacc32);
+    if (shh) pair_class_w(T, hlen, mx, my, 1, 1, 0u - shh, myacc32);
+    if (s > shh) pair_class_w(T, hlen, mx, my, 1, 0, 0u - (s - shh), myacc32);
+}
+
 // Adds the per-wave counts to graph g's phase accumulators and clears them.
 __device__ void he2_flush_graph(const He2Params& P, uint32_t g, uint64_t* acc_all) {
     __syncthreads();
@@ -484,7 +520,9 @@ __device__ void he2_body(const He2Params& P, uint32_t* arena, const uint32_t ARE
             t_mark = t_;                                \
         }                                               \
     } while (0)
-    uint64_t* myacc = acc_all + (tid >> 6) * HGT_N_HE_CLASSES;
+    // this centre's changes, doubled (halved when the centre ends): a centre handed on
+    // to the next stage midway leaves nothing behind
+    uint64_t* cacc = sh.acc2 + (tid >> 6) * HGT_N_HE_CLASSES;
     uint32_t* myacc32 = acc32_all + (tid >> 6) * HGT_N_HE_CLASSES;
     for (;;) {
         if (tid == 0) {
@@ -672,12 +710,12 @@ __device__ void he2_body(const He2Params& P, uint32_t* arena, const uint32_t ARE
             if (tid == 0) {
                 uint64_t G00 = (sh.g[0] - sh.g[3]) / 2, G11 = (sh.g[2] - sh.g[4]) / 2, G01 = sh.g[1];
                 uint64_t T00 = N0 * (N0 - (N0 ? 1 : 0)) / 2, T11 = N1 * (N1 - (N1 ? 1 : 0)) / 2, T01 = N0 * N1;
-                acc_add(myacc, T.he[40 | 1], T00 - G00);
-                acc_add(myacc, T.he[40], G00);
-                acc_add(myacc, T.he[40 | 4 | 1], T01 - G01);
-                acc_add(myacc, T.he[40 | 4], G01);
-                acc_add(myacc, T.he[40 | 6 | 1], T11 - G11);
-                acc_add(myacc, T.he[40 | 6], G11);
+                acc_add(cacc, T.he[40 | 1], 2 * (T00 - G00));
+                acc_add(cacc, T.he[40], 2 * (G00));
+                acc_add(cacc, T.he[40 | 4 | 1], 2 * (T01 - G01));
+                acc_add(cacc, T.he[40 | 4], 2 * (G01));
+                acc_add(cacc, T.he[40 | 6 | 1], 2 * (T11 - G11));
+                acc_add(cacc, T.he[40 | 6], 2 * (G11));
             }
             __syncthreads();
         }
@@ -734,10 +772,10 @@ __device__ void he2_body(const He2Params& P, uint32_t* arena, const uint32_t ARE
                 if (k < thr) { if (f) a1--; else a0--; }
                 else { if (f) b1--; else b0--; }
             }
-            acc_add(myacc, T.he[base | 2], a0);
-            acc_add(myacc, T.he[base | 2 | 4], a1);
-            acc_add(myacc, T.he[base], b0);
-            acc_add(myacc, T.he[base | 4], b1);
+            acc_add(cacc, T.he[base | 2], 2 * (a0));
+            acc_add(cacc, T.he[base | 2 | 4], 2 * (a1));
+            acc_add(cacc, T.he[base], 2 * (b0));
+            acc_add(cacc, T.he[base | 4], 2 * (b1));
         }
         if (P.stats) __syncthreads();
         HE2_MARK(5);
@@ -751,7 +789,8 @@ __device__ void he2_body(const He2Params& P, uint32_t* arena, const uint32_t ARE
         // neighbours holding u and w are contiguous), each at its two smallest common
         // vertices, and get their true changes in place of the s single ones.  Layout
         // after the entries: long runs, histogram, per-neighbour offsets of the shared
-        // vertices and of the vertex pairs, fill cursors, shared vertices, vertex pairs.
+        // vertices and of the vertex pairs, fill cursors, shared vertices, vertex pairs,
+        // the vertex pairs' pair numbering.
         if (tid == 0) {
             sh.agg = 0;
             sh.nbig = 0;
@@ -772,10 +811,26 @@ __device__ void he2_body(const He2Params& P, uint32_t* arena, const uint32_t ARE
             }
             __syncthreads();
             if (tid == 0) {
-                const uint64_t o_emit = (o_sl + sh.g[6] + 1) & ~1ull;
-                sh.agg = (o_emit + 2ull * sh.g[7] <= ARENA_WORDS) ? 1u : 0u;
+                const uint64_t o_emit = (o_sl + sh.g[6] + 1) & ~1ull;  // then pp: one word per vertex pair
+                sh.agg = (o_emit + 3ull * sh.g[7] <= ARENA_WORDS) ? 1u : 0u;
             }
             __syncthreads();
+        }
+        if (STAGE < 2 && !sh.agg && !P.static_mode && P.pair_agg) {
+            // no room to aggregate here: drop this centre's changes, hand it to the next stage
+            for (uint32_t i = tid; i < NWAVE * HGT_N_HE_CLASSES; i += HGT_WG) {
+                sh.acc2[i] = 0;
+                acc32_all[i] = 0;
+            }
+            if (tid == 0) {
+                uint32_t q = atomicAdd(&P.count[STAGE], 1u);
+                P.list[STAGE][q] = item_of(sh.gi, h);
+                P.rank[STAGE][q] = sh.rank;
+                atomicAdd((unsigned long long*)&st[0], 1ull);
+            }
+            HE2_MARK(7);
+            __syncthreads();
+            continue;
         }
         if (P.stats && tid == 0 && !P.static_mode && !sh.agg) atomicAdd((unsigned long long*)&P.stats[ST_AGG_ENUM], 1ull);
         if (sh.agg) {
@@ -787,7 +842,6 @@ __device__ void he2_body(const He2Params& P, uint32_t* arena, const uint32_t ARE
             uint32_t* cur = arena + o_cur;
             uint32_t* sl = arena + o_sl;
             uint64_t* emit = (uint64_t*)(arena + ((o_sl + S + 1) & ~1ull));
-            uint64_t* myacc2 = sh.acc2 + (tid >> 6) * HGT_N_HE_CLASSES;
             {
                 uint32_t carry_s = 0, carry_e = 0;
                 for (uint32_t b = 0; b < K; b += HGT_WG) {
@@ -840,12 +894,13 @@ __device__ void he2_body(const He2Params& P, uint32_t* arena, const uint32_t ARE
                     single_codes(vin, xl, cx, single_gy(vin, yl, cy), cy < dx ? 0u : (cy == dx ? 1u : 2u), ct, cf);
                     const int c1 = T.he[ct], c2 = T.he[cf];
                     if (c1 != c2) {
-                        if (c1 < 255) atomicAdd((unsigned long long*)&myacc2[c1], 1ull);
-                        if (c2 < 255) atomicAdd((unsigned long long*)&myacc2[c2], ~0ull);
+                        if (c1 < 255) atomicAdd((unsigned long long*)&cacc[c1], 1ull);
+                        if (c2 < 255) atomicAdd((unsigned long long*)&cacc[c2], ~0ull);
                     }
                 }
             }
             __syncthreads();
+            HE2_MARK(8);
             // vertex pairs (u, w), u < w, of each neighbour's shared vertices, as run starts
             for (uint32_t a = tid; a < S; a += HGT_WG) {
                 const uint32_t x = seg_of<uint32_t>(off, K, a);
@@ -860,6 +915,7 @@ __device__ void he2_body(const He2Params& P, uint32_t* arena, const uint32_t ARE
             }
             __syncthreads();
             sort_keys(emit, E2);
+            HE2_MARK(9);
             // long runs, one at a time: histogram over (gy, c_y) of the eligible members
             const uint32_t nbig = sh.nbig;
             if (P.stats && tid == 0 && nbig) atomicAdd((unsigned long long*)&P.stats[ST_AGG_LONG], (unsigned long long)nbig);
@@ -896,8 +952,8 @@ __device__ void he2_body(const He2Params& P, uint32_t* arena, const uint32_t ARE
                     const uint32_t xl = meta_len(mx), cx = meta_c(mx), dx = hlen - cx;
                     const uint32_t ob = (hlen > cx ? 1u : 0u) | 24u | (xl - cx > 1 ? 2u : 0u);
                     const uint64_t n_big = nb1 - (xl > 1 ? 1u : 0u), n_small = (uint64_t)(ne - 1) - n_big;
-                    if (n_big) acc_add(myacc, T.he[ob | 4u], 0ull - n_big);
-                    if (n_small) acc_add(myacc, T.he[ob], 0ull - n_small);
+                    if (n_big) acc_add(cacc, T.he[ob | 4u], 2 * (0ull - n_big));
+                    if (n_small) acc_add(cacc, T.he[ob], 2 * (0ull - n_small));
                     const uint32_t gx = single_gy(vin, xl, cx);
                     for (uint32_t g = 0; g < 4; g++) {
                         const uint32_t row = g * (hlen + 1);
@@ -914,35 +970,58 @@ __device__ void he2_body(const He2Params& P, uint32_t* arena, const uint32_t ARE
                             single_codes(vin, xl, cx, g, rng, ct, cf);
                             const int c1 = T.he[ct], c2 = T.he[cf];
                             if (c1 != c2) {
-                                if (c1 < 255) atomicAdd((unsigned long long*)&myacc2[c1], (unsigned long long)n3[rng]);
-                                if (c2 < 255) atomicAdd((unsigned long long*)&myacc2[c2], 0ull - (unsigned long long)n3[rng]);
+                                if (c1 < 255) atomicAdd((unsigned long long*)&cacc[c1], (unsigned long long)n3[rng]);
+                                if (c2 < 255) atomicAdd((unsigned long long*)&cacc[c2], 0ull - (unsigned long long)n3[rng]);
                             }
                         }
                     }
                 }
                 __syncthreads();
             }
-            // pairs sharing two or more vertices, at their two smallest common ones
-            for (uint32_t i = tid; i < E2; i += HGT_WG) {
-                const uint64_t e = emit[i];
-                const uint64_t uw = e >> 14;
-                const uint32_t xi = (uint32_t)e & K_MAX;
-                const uint32_t vu = (uint32_t)(keys[(uint32_t)(e >> 30)] >> 15);
-                const uint32_t vw = (uint32_t)(keys[(uint32_t)uw & 0xffffu] >> 15);
-                const uint32_t mx = nl_meta[xi];
-                const uint32_t* X = G.g.h2v + G.g.h_off[nl_x[xi]];
-                for (uint32_t j = i + 1; j < E2; j++) {
-                    const uint64_t f = emit[j];
-                    if ((f >> 14) != uw) break;
-                    const uint32_t yi = (uint32_t)f & K_MAX;
-                    const uint32_t my = nl_meta[yi];
-                    uint32_t s, shh, f1, f2;
-                    row_meet2(X, meta_len(mx), G.g.h2v + G.g.h_off[nl_x[yi]], meta_len(my), hm, hlen, s, shh, f1, f2);
-                    if (f1 != vu || f2 != vw) continue;
-                    if (P.stats) atomicAdd((unsigned long long*)&P.stats[ST_AGG_MULTI], 1ull);
-                    pair_class_w(T, hlen, mx, my, s, shh, 1u, myacc32);
-                    if (shh) pair_class_w(T, hlen, mx, my, 1, 1, 0u - shh, myacc32);
-                    if (s > shh) pair_class_w(T, hlen, mx, my, 1, 0, 0u - (s - shh), myacc32);
+            HE2_MARK(10);
+            // pairs sharing two or more vertices, at their two smallest common ones.  The
+            // pairs within every run of equal (u, w) are numbered in one index space
+            // (pp: exclusive prefix of the run heads' pair counts), so that a long run
+            // spreads over the whole workgroup.
+            uint32_t* pp = (uint32_t*)(emit + E2);
+            if (tid == 0) sh.g[5] = 0;
+            __syncthreads();
+            {
+                uint32_t carry = 0;
+                for (uint32_t b = 0; b < E2; b += HGT_WG) {
+                    const uint32_t i = b + tid;
+                    uint32_t c = 0;
+                    if (i < E2) {
+                        const uint64_t uw = emit[i] >> 14;
+                        if (i == 0 || (emit[i - 1] >> 14) != uw) {
+                            const uint64_t R = lower_bound_u64(emit, E2, (uw + 1) << 14) - i;
+                            const uint64_t c64 = R * (R - 1) / 2;
+                            atomicAdd((unsigned long long*)&sh.g[5], (unsigned long long)c64);
+                            c = (uint32_t)c64;  // used only when the total fits 31 bits
+                        }
+                    }
+                    uint32_t tot;
+                    const uint32_t ex = wg_scan_u32(c, sh.ws, &tot);
+                    if (i < E2) pp[i] = carry + ex;
+                    carry += tot;
+                }
+            }
+            __syncthreads();
+            const uint64_t T2 = sh.g[5];
+            if (T2 < 0x80000000ull) {
+                for (uint32_t p = tid; p < (uint32_t)T2; p += HGT_WG) {
+                    const uint32_t i = seg_of<uint32_t>(pp, E2, p);  // the run's head
+                    const uint64_t uw = emit[i] >> 14;
+                    const uint32_t R = lower_bound_u64(emit, E2, (uw + 1) << 14) - i;
+                    uint32_t a, b;
+                    tri_decode(R, p - pp[i], a, b);
+                    multi_pair(G.g, T, hlen, hm, keys, nl_x, nl_meta, emit[i + a], emit[i + b], P.stats, myacc32);
+                }
+            } else {
+                for (uint32_t i = tid; i < E2; i += HGT_WG) {
+                    const uint64_t uw = emit[i] >> 14;
+                    for (uint32_t j = i + 1; j < E2 && (emit[j] >> 14) == uw; j++)
+                        multi_pair(G.g, T, hlen, hm, keys, nl_x, nl_meta, emit[i], emit[j], P.stats, myacc32);
                 }
             }
         } else {
@@ -1106,7 +1185,7 @@ __device__ void he2_body(const He2Params& P, uint32_t* arena, const uint32_t ARE
                 acc32_all[i] = 0;
             }
         }
-        if (sh.agg) {  // the doubled closed-class changes: over all waves, halved
+        {  // the doubled changes: over all waves, halved
             for (uint32_t c = tid; c < HGT_N_HE_CLASSES; c += HGT_WG) {
                 int64_t s2 = 0;
                 for (int w = 0; w < NWAVE; w++) {
@@ -1124,8 +1203,9 @@ __device__ void he2_body(const He2Params& P, uint32_t* arena, const uint32_t ARE
 
 template <int STAGE>
 __device__ void he2_flush_stats(const He2Params& P, const uint64_t* st, const uint64_t* ph) {
-    if (P.stats && threadIdx.x < 8 && ph[threadIdx.x])
-        atomicAdd((unsigned long long*)&P.stats[ST_PH0 + 8 * STAGE + threadIdx.x], (unsigned long long)ph[threadIdx.x]);
+    if (P.stats && threadIdx.x < HE2_PHASES && ph[threadIdx.x])
+        atomicAdd((unsigned long long*)&P.stats[ST_PH0 + HE2_PHASES * STAGE + threadIdx.x],
+                  (unsigned long long)ph[threadIdx.x]);
     if (P.stats && threadIdx.x == 0 && st[0])
         atomicAdd((unsigned long long*)&P.stats[ST_DEFER0 + STAGE], (unsigned long long)st[0]);
     if (P.stats && threadIdx.x == 0 && st[1])
@@ -1138,8 +1218,8 @@ __device__ void he2_flush_stats(const He2Params& P, const uint64_t* st, const ui
     __shared__ uint64_t acc[NWAVE][HGT_N_HE_CLASSES];                                  \
     __shared__ uint32_t acc32[NWAVE][HGT_N_HE_CLASSES];                                \
     __shared__ uint64_t st[2];                                                         \
-    __shared__ uint64_t ph[8];                                                         \
-    if (threadIdx.x < 8) ph[threadIdx.x] = 0;                                          \
+    __shared__ uint64_t ph[HE2_PHASES];                                                \
+    if (threadIdx.x < HE2_PHASES) ph[threadIdx.x] = 0;                                 \
     if (threadIdx.x == 0) sh.cur_g = 0xffffffffu;                                      \
     for (int i = threadIdx.x; i < 128; i += HGT_WG) T.he[i] = P.he_tab[i];             \
     for (int i = threadIdx.x; i < NWAVE * HGT_N_HE_CLASSES; i += HGT_WG) {             \

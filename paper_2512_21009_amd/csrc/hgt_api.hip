@@ -768,6 +768,19 @@ __global__ void k_uniq_write(const uint64_t* __restrict__ keys, uint64_t n, cons
     }
 }
 
+// Owner of a touched pair: the endpoint of higher degree (ties: the smaller ID).
+// The owner's weighted clique map is built once and the other endpoint's
+// hyperedges are scanned per pair, so hubs are scanned as rarely as possible.
+__global__ void k_iv_orient(const uint64_t* __restrict__ canon, const uint64_t* n_p, const uint32_t* __restrict__ v_len,
+                            uint64_t* out) {
+    const uint64_t n = *n_p;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t k = canon[i];
+        const uint32_t lo = (uint32_t)(k >> 32), hi = (uint32_t)k;
+        out[i] = v_len[hi] > v_len[lo] ? ((uint64_t)hi << 32 | lo) : k;
+    }
+}
+
 __global__ void k_iv_update(uint64_t* cnt, int iv, int m, int p, int t1) {
     if (threadIdx.x || blockIdx.x) return;
     uint64_t d1 = cnt[t1 + 1] - cnt[t1];           // change of type 1
@@ -786,7 +799,8 @@ inline unsigned nblk(uint64_t n, unsigned per = 256) {
 
 struct IvPlan {
     uint64_t n_keys = 0;
-    uint64_t* uniq = nullptr;
+    uint64_t* uniq = nullptr;     // touched pairs (lo << 32 | hi), sorted
+    uint64_t* own = nullptr;      // the same as (owner << 32 | other), sorted
     uint64_t* n_uniq = nullptr;
     uint64_t tab_slots = 0;
 };
@@ -833,13 +847,17 @@ int iv_prepare(hgt_graph* g, const BatchIn& b, const PlanScratch& w, const Batch
     k_uniq_heads<<<nblk(nk), 256, 0, s>>>(keys, nk, head);
     hgt_scan_u64(head, head, nk, nullptr, ip.n_uniq, g->iv_scan.p, s);
     k_uniq_write<<<nblk(nk), 256, 0, s>>>(keys, nk, head, vb, ip.uniq);
-    // hash of the touched pairs and the owner (first vertex) segments
+    // pairs by owner (the buffer of the unsorted keys is free now)
+    ip.own = keys;
+    k_iv_orient<<<nblk(nk > 262144 ? 262144 : nk), 256, 0, s>>>(ip.uniq, ip.n_uniq, g->st.v_len, ip.own);
+    hgt_radix_sort_u64(ip.own, g->iv_alt.as<uint64_t>(), nk, ip.n_uniq, 32 + vb, g->iv_sort.p, s);
+    // hash of the touched pairs and the owner segments
     ip.tab_slots = pow2ceil64(2 * nk + 64);
     if (ensure(g->iv_tab, ip.tab_slots * 8) || ensure(g->iv_owner, (nk + 2) * 8) || ensure(g->iv_ctr, 64))
         return HGT_ENOMEM;
     uint64_t* ictr = g->iv_ctr.as<uint64_t>();
-    iv_touched_build(ip.uniq, ip.n_uniq, g->iv_tab.as<uint64_t>(), ip.tab_slots, head, g->iv_owner.as<uint64_t>(),
-                     ictr, nk, g->iv_scan.p, s);
+    iv_touched_build(ip.uniq, ip.own, ip.n_uniq, g->iv_tab.as<uint64_t>(), ip.tab_slots, head,
+                     g->iv_owner.as<uint64_t>(), ictr, nk, g->iv_scan.p, s);
     return HGT_OK;
 }
 
@@ -852,7 +870,7 @@ int iv_phase(hgt_graph* g, const IvPlan& ip, bool minus, hipStream_t s) {
         return HGT_ENOMEM;
     IvParams P{};
     P.g = view_of(g);
-    P.pairs = ip.uniq;
+    P.pairs = ip.own;
     P.n_pairs = ip.n_uniq;
     uint64_t* ictr = g->iv_ctr.as<uint64_t>();
     P.n_owners = ictr;

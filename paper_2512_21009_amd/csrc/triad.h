@@ -142,7 +142,8 @@ void he2_launch_stage(He2Params& P, int stage, unsigned grid, hipStream_t s);
 // incident-vertex family
 struct IvParams {
     GraphView g;
-    const uint64_t* pairs;       // unique touched vertex pairs u << 32 | v (u < v), ascending
+    const uint64_t* pairs;       // unique touched vertex pairs owner << 32 | other, ascending (the
+                                 // owner is the endpoint of higher degree)
     const uint64_t* n_pairs;     // device count
     const uint64_t* owner_start; // first pair of every distinct u, plus the end
     const uint64_t* n_owners;
@@ -157,7 +158,9 @@ struct IvParams {
     uint64_t garena_words;
     uint64_t* stats;             // optional, ST_IV_BYTES
 };
-void iv_touched_build(const uint64_t* pairs, const uint64_t* n_pairs, uint64_t* tab, uint64_t tab_slots,
-                      uint64_t* head, uint64_t* owner_start, uint64_t* n_owners, uint64_t pairs_cap, void* scan_tmp,
-                      hipStream_t s);
+// hash of the touched pairs (canon: lo << 32 | hi) and the owner segments of own
+// (owner << 32 | other, sorted)
+void iv_touched_build(const uint64_t* canon, const uint64_t* own, const uint64_t* n_pairs, uint64_t* tab,
+                      uint64_t tab_slots, uint64_t* head, uint64_t* owner_start, uint64_t* n_owners, uint64_t pairs_cap,
+                      void* scan_tmp, hipStream_t s);
 void triad_iv_launch(IvParams& P, unsigned grid_lds, unsigned grid_global, hipStream_t s);

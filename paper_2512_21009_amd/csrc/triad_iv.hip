@@ -13,15 +13,18 @@
 // Both are evaluated on the old graph (before the batch) and on the new graph
 // (after it); the difference is the delta.
 //
-// A workgroup takes a touched vertex a and builds its weighted clique map
-// M_a : w -> (m_aw, w_aw) in LDS from the hyperedges that contain a.  For each
-// touched pair (a, b) with a < b, m_ab and w_ab are read from the map, and the
-// triangles through (a, b) contribute
+// Every touched pair has an owner, its endpoint of higher degree.  A workgroup
+// takes an owner a and builds its weighted clique map M_a : w -> (m_aw, w_aw)
+// in LDS from the hyperedges that contain a.  For each touched pair (a, b) it
+// owns, m_ab and w_ab are read from the map, and the triangles through (a, b)
+// contribute
 //   m_ab * sum_{h' containing b} sum_{w in h', w != a, b} M_a[w].m
-// (the inner double sum counts w with multiplicity m_bw).  A triangle with
-// several touched pairs is counted at its lexicographically smallest one: the
-// triangle {a, b, w} is skipped at (a, b) when {a, w} is touched and w < b, or
-// {b, w} is touched and w < a (a global hash of the touched pairs answers).
+// (the inner double sum counts w with multiplicity m_bw; b, the endpoint of
+// lower degree, is the one scanned).  A triangle with several touched pairs is
+// counted at its lexicographically smallest one: with lo < hi the endpoints of
+// the pair, the triangle {lo, hi, w} is skipped when {lo, w} is touched and
+// w < hi, or {hi, w} is touched and w < lo (a global hash of the touched pairs
+// answers).
 #include "triad_common.h"
 
 namespace {
@@ -287,6 +290,7 @@ __device__ void iv_body(const IvParams& P, uint32_t* arena, uint32_t arena_words
             }
             if (lane == 0) s_sum += m_ab * w_ab;
             if (m_ab == 0) continue;
+            const uint32_t lo = a < b ? a : b, hi = a < b ? b : a;
             const uint32_t lb = P.g.v_len[b];
             const uint32_t* B = P.g.v2h + P.g.v_off[b];
             uint64_t sum = 0;
@@ -313,8 +317,8 @@ __device__ void iv_body(const IvParams& P, uint32_t* arena, uint32_t arena_words
                     if (w == a || w == b) continue;
                     uint32_t sw = map_find(mp, cap, w);
                     if (sw == HGT_EMPTY) continue;
-                    if (w < b && touched(P.tab, P.tab_mask, a, w)) continue;
-                    if (w < a && touched(P.tab, P.tab_mask, b, w)) continue;
+                    if (w < hi && touched(P.tab, P.tab_mask, lo, w)) continue;
+                    if (w < lo && touched(P.tab, P.tab_mask, hi, w)) continue;
                     sum += mp[4 * sw + 1];
                 }
                 __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
@@ -358,14 +362,14 @@ __global__ void __launch_bounds__(HGT_WG) k_iv_global(IvParams P) {
 
 }  // namespace
 
-void iv_touched_build(const uint64_t* pairs, const uint64_t* n_pairs, uint64_t* tab, uint64_t tab_slots,
-                      uint64_t* head, uint64_t* owner_start, uint64_t* n_owners, uint64_t pairs_cap, void* scan_tmp,
-                      hipStream_t s) {
+void iv_touched_build(const uint64_t* canon, const uint64_t* own, const uint64_t* n_pairs, uint64_t* tab,
+                      uint64_t tab_slots, uint64_t* head, uint64_t* owner_start, uint64_t* n_owners, uint64_t pairs_cap,
+                      void* scan_tmp, hipStream_t s) {
     hgt_fill_u64(tab, ~0ull, tab_slots, s);
-    k_iv_hash_build<<<2048, 256, 0, s>>>(pairs, n_pairs, tab, tab_slots - 1);
-    k_iv_owner_heads<<<2048, 256, 0, s>>>(pairs, n_pairs, head);
+    k_iv_hash_build<<<2048, 256, 0, s>>>(canon, n_pairs, tab, tab_slots - 1);
+    k_iv_owner_heads<<<2048, 256, 0, s>>>(own, n_pairs, head);
     hgt_scan_u64(head, head, pairs_cap, n_pairs, n_owners, scan_tmp, s);
-    k_iv_owner_list<<<2048, 256, 0, s>>>(pairs, n_pairs, head, owner_start, n_owners);
+    k_iv_owner_list<<<2048, 256, 0, s>>>(own, n_pairs, head, owner_start, n_owners);
 }
 
 void triad_iv_launch(IvParams& P, unsigned grid_lds, unsigned grid_global, hipStream_t s) {

@@ -51,14 +51,44 @@ __device__ __forceinline__ void fr_add(uint32_t* keys, uint32_t* vals, uint32_t 
     }
 }
 
-// Ascending bitonic sort of n keys in place by the whole workgroup.  The merge
-// steps compare i with its mirror in the block, then with i ^ stride, always
-// putting the smaller key first, so absent keys past n behave as +infinity and
-// their comparisons are skipped: no padding to a power of two is stored.
+// One compare-exchange of the bitonic network between lanes: the lane whose
+// index has a zero at hb (the highest bit of the mask m) keeps the smaller key.
+__device__ __forceinline__ uint64_t cx_lanes(uint64_t x, uint32_t i, uint32_t m, uint32_t hb) {
+    const uint64_t y = __shfl_xor(x, (int)m, 64);
+    return (i & hb) ? (x > y ? x : y) : (x < y ? x : y);
+}
+
+// The steps of the network whose masks are below 64, in registers: all levels
+// up to 64 (first) or the strides 32 .. 1 of a larger level.  Keys past n enter
+// as +infinity and are not stored.
+__device__ __forceinline__ void sort_lane_steps(uint64_t* k, uint32_t n, bool first) {
+    for (uint32_t b = 0; b < n; b += HGT_WG) {
+        const uint32_t i = b + threadIdx.x;
+        uint64_t x = i < n ? k[i] : ~0ull;
+        if (first) {
+            for (uint32_t size = 2; size <= 64; size <<= 1) {
+                x = cx_lanes(x, i, size - 1, size >> 1);
+                for (uint32_t st = size >> 2; st > 0; st >>= 1) x = cx_lanes(x, i, st, st);
+            }
+        } else {
+            for (uint32_t st = 32; st > 0; st >>= 1) x = cx_lanes(x, i, st, st);
+        }
+        if (i < n) k[i] = x;
+    }
+    __syncthreads();
+}
+
+// Ascending bitonic sort of n keys in place by the whole workgroup.  Each level
+// of the network compares i with its mirror in the block (mask size - 1), then
+// with i ^ stride for stride = size/4 .. 1, the smaller key going first; absent
+// keys past n behave as +infinity, so no padding to a power of two is stored.
+// Masks of 64 and more go through memory, one pass each; the smaller ones stay
+// inside a wavefront's 64 consecutive keys and run in registers.
 __device__ __forceinline__ void sort_keys(uint64_t* k, uint32_t n) {
     if (n < 2) return;
     const uint32_t N = (uint32_t)pow2ceil64(n);
-    for (uint32_t size = 2; size <= N; size <<= 1) {
+    sort_lane_steps(k, n, true);
+    for (uint32_t size = 128; size <= N; size <<= 1) {
         for (uint32_t i = threadIdx.x; i < n; i += HGT_WG) {
             uint32_t p = i ^ (size - 1);
             if (p > i && p < n) {
@@ -67,7 +97,7 @@ __device__ __forceinline__ void sort_keys(uint64_t* k, uint32_t n) {
             }
         }
         __syncthreads();
-        for (uint32_t stride = size >> 2; stride > 0; stride >>= 1) {
+        for (uint32_t stride = size >> 2; stride >= 64; stride >>= 1) {
             for (uint32_t i = threadIdx.x; i < n; i += HGT_WG) {
                 uint32_t p = i ^ stride;
                 if (p > i && p < n) {
@@ -77,6 +107,7 @@ __device__ __forceinline__ void sort_keys(uint64_t* k, uint32_t n) {
             }
             __syncthreads();
         }
+        sort_lane_steps(k, n, false);
     }
 }
 
@@ -387,6 +418,7 @@ __device__ __forceinline__ void pair_class(const He2Params& P, const Tables& T, 
 // |h| - c_x (rng 0: less, 1: equal, 2: greater), so along a long run of
 // neighbours at v they are counted from a histogram over (gy, c_y).
 constexpr uint32_t RUN_DIRECT = 64;  // runs up to this length enumerate their pairs
+static_assert(RUN_DIRECT <= 64, "short-run partners are counted in 6-bit fields");
 
 __device__ __forceinline__ uint32_t single_gy(uint32_t vin, uint32_t yl, uint32_t cy) {
     return vin ? ((yl > cy ? 1u : 0u) | (cy > 1 ? 2u : 0u)) : ((yl > cy ? 1u : 0u) | (yl - cy > 1 ? 2u : 0u));
@@ -884,18 +916,31 @@ __device__ void he2_body(const He2Params& P, uint32_t* arena, const uint32_t ARE
                 const uint32_t vin = (uint32_t)(ki >> 14) & 1u;
                 const uint32_t xl = meta_len(mx), cx = meta_c(mx), dx = hlen - cx;
                 const uint32_t ob = (hlen > cx ? 1u : 0u) | 24u | (xl - cx > 1 ? 2u : 0u);
+                // partners counted per (gy, rng) cell in 6-bit fields (a run holds at most 63)
+                uint32_t n_el = 0, n_big = 0;
+                uint64_t c_lo = 0, c_hi = 0;  // cells 0..9, 10..11
                 for (uint32_t j = st0; j < en; j++) {
                     if (j == i) continue;
                     const uint32_t my = nl_meta[(uint32_t)keys[j] & K_MAX];
                     if (!meta_elig(my)) continue;
                     const uint32_t yl = meta_len(my), cy = meta_c(my);
-                    acc32_add(myacc32, T.he[ob | (yl > 1 ? 4u : 0u)], ~0u);
+                    n_el++;
+                    n_big += yl > 1 ? 1u : 0u;
+                    const uint32_t cell = single_gy(vin, yl, cy) * 3u + (cy < dx ? 0u : (cy == dx ? 1u : 2u));
+                    if (cell < 10) c_lo += 1ull << (6 * cell);
+                    else c_hi += 1ull << (6 * (cell - 10));
+                }
+                if (n_big) acc32_add(myacc32, T.he[ob | 4u], 0u - n_big);
+                if (n_el > n_big) acc32_add(myacc32, T.he[ob], 0u - (n_el - n_big));
+                for (uint32_t cell = 0; cell < 12; cell++) {
+                    const uint32_t n = (uint32_t)((cell < 10 ? c_lo >> (6 * cell) : c_hi >> (6 * (cell - 10))) & 63u);
+                    if (!n) continue;
                     int ct, cf;
-                    single_codes(vin, xl, cx, single_gy(vin, yl, cy), cy < dx ? 0u : (cy == dx ? 1u : 2u), ct, cf);
+                    single_codes(vin, xl, cx, cell / 3u, cell % 3u, ct, cf);
                     const int c1 = T.he[ct], c2 = T.he[cf];
                     if (c1 != c2) {
-                        if (c1 < 255) atomicAdd((unsigned long long*)&cacc[c1], 1ull);
-                        if (c2 < 255) atomicAdd((unsigned long long*)&cacc[c2], ~0ull);
+                        if (c1 < 255) atomicAdd((unsigned long long*)&cacc[c1], (unsigned long long)n);
+                        if (c2 < 255) atomicAdd((unsigned long long*)&cacc[c2], 0ull - (unsigned long long)n);
                     }
                 }
             }

@@ -666,8 +666,10 @@ int run_phase(hgt_graph* owner, const PhaseJob* jobs, uint32_t nj, bool minus, b
             E.rank[1] = c.t_rank2.as<uint32_t>();
             E.list[2] = P.big_list;
             E.rank[2] = P.big_rank;
-            const uint64_t garena_words = 1ull << 18;  // 1 MB per workgroup
-            const unsigned grid_g = (unsigned)std::min<uint64_t>(128, n);
+            // 1 MB per workgroup; the global stage holds little LDS, so several
+            // workgroups share a CU and hide each other's memory latency
+            const uint64_t garena_words = 1ull << 18;
+            const unsigned grid_g = (unsigned)std::min<uint64_t>(n_cu * 4, n);
             if (ensure(c.t_garena, (uint64_t)grid_g * garena_words * 4)) return HGT_ENOMEM;
             E.garena = c.t_garena.as<uint32_t>();
             E.garena_words = garena_words;

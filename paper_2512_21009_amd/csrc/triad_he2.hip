@@ -119,6 +119,7 @@ struct Sh2 {
     uint32_t o_nh, o_ent;  // arena word offsets
     uint32_t runs, pcap, ovf;  // intersecting pairs: run table present, pair-hash slots, overflow
     uint32_t agg, nbig, nb1;   // aggregated pair phase: taken, long runs, long-run members of length > 1
+    uint32_t fits_g;           // ... its tables fit the global stage's arena
     uint64_t acc2[NWAVE * HGT_N_HE_CLASSES];  // the centre's changes, doubled (ordered pairs once)
     uint32_t ws[NWAVE];
     uint64_t g[8];
@@ -825,6 +826,7 @@ __device__ void he2_body(const He2Params& P, uint32_t* arena, const uint32_t ARE
         // the vertex pairs' pair numbering.
         if (tid == 0) {
             sh.agg = 0;
+            sh.fits_g = 0;
             sh.nbig = 0;
             sh.g[6] = 0;  // shared entries of neighbours with two or more
             sh.g[7] = 0;  // their vertex pairs
@@ -833,7 +835,7 @@ __device__ void he2_body(const He2Params& P, uint32_t* arena, const uint32_t ARE
         const uint32_t nb_cap = W / (RUN_DIRECT + 1) + 1, n_hist = 4u * (hlen + 1);
         const uint64_t o_big = (uint64_t)sh.o_ent + 2ull * W, o_hist = o_big + nb_cap, o_off = o_hist + n_hist;
         const uint64_t o_eoff = o_off + K + 1, o_cur = o_eoff + K + 1, o_sl = o_cur + K;
-        if (!P.static_mode && P.pair_agg && W < 65536u && o_sl <= ARENA_WORDS) {
+        if (!P.static_mode && P.pair_agg && W < 65536u) {
             for (uint32_t i = tid; i < K; i += HGT_WG) {
                 const uint64_t m = nl_msh[i];
                 if (m >= 2) {
@@ -844,12 +846,16 @@ __device__ void he2_body(const He2Params& P, uint32_t* arena, const uint32_t ARE
             __syncthreads();
             if (tid == 0) {
                 const uint64_t o_emit = (o_sl + sh.g[6] + 1) & ~1ull;  // then pp: one word per vertex pair
-                sh.agg = (o_emit + 3ull * sh.g[7] <= ARENA_WORDS) ? 1u : 0u;
+                const uint64_t need = o_emit + 3ull * sh.g[7];
+                sh.agg = (o_sl <= ARENA_WORDS && need <= ARENA_WORDS) ? 1u : 0u;
+                sh.fits_g = need <= P.garena_words ? 1u : 0u;
             }
             __syncthreads();
         }
-        if (STAGE < 2 && !sh.agg && !P.static_mode && P.pair_agg) {
-            // no room to aggregate here: drop this centre's changes, hand it to the next stage
+        // no room to aggregate here: a centre that the global stage can aggregate moves on
+        // (dropping its changes so far); one that no stage can aggregate enumerates here
+        const bool hand_on = STAGE < 2 && !sh.agg && sh.fits_g;
+        if (hand_on) {
             for (uint32_t i = tid; i < NWAVE * HGT_N_HE_CLASSES; i += HGT_WG) {
                 sh.acc2[i] = 0;
                 acc32_all[i] = 0;

@@ -216,6 +216,9 @@ struct hgt_graph {
     uint32_t pair_cap_max = 0;      // HGT_PAIR_CAP (tests): see He2Params
     int pair_runs = 0;              // HGT_PAIR_RUNS=1: run-table pair phase (see He2Params)
     int pair_agg = 1;               // HGT_PAIR_AGG=0: pairs enumerated per run (see He2Params)
+    int global_wg_per_cu = 4;       // HGT_GLOBAL_WG_PER_CU: workgroups per CU of the global stage
+    int skip_lds148 = 1;            // HGT_SKIP_LDS148=0: centres go through the 148 KB stage (one workgroup
+                                    // per CU) instead of straight to the global one (four per CU)
     BatchSummary* h_sum = nullptr;  // pinned
     DevScalars* h_sc = nullptr;     // pinned
     // profiling: HIP events around each kernel group, algorithmic-byte counters
@@ -669,7 +672,7 @@ int run_phase(hgt_graph* owner, const PhaseJob* jobs, uint32_t nj, bool minus, b
             // 1 MB per workgroup; the global stage holds little LDS, so several
             // workgroups share a CU and hide each other's memory latency
             const uint64_t garena_words = 1ull << 18;
-            const unsigned grid_g = (unsigned)std::min<uint64_t>(n_cu * 4, n);
+            const unsigned grid_g = (unsigned)std::min<uint64_t>(n_cu * (uint64_t)owner->global_wg_per_cu, n);
             if (ensure(c.t_garena, (uint64_t)grid_g * garena_words * 4)) return HGT_ENOMEM;
             E.garena = c.t_garena.as<uint32_t>();
             E.garena_words = garena_words;
@@ -678,6 +681,7 @@ int run_phase(hgt_graph* owner, const PhaseJob* jobs, uint32_t nj, bool minus, b
             E.pair_cap_max = owner->pair_cap_max;
             E.pair_runs = owner->pair_runs;
             E.pair_agg = owner->pair_agg;
+            E.skip_lds148 = owner->skip_lds148;
             E.static_mode = full ? 1 : 0;
             hgt_fill_u32(ctr + 16, 0, 6, s);
             hgt_fill_u32(ctr + 5, 0, 1, s);
@@ -1169,6 +1173,8 @@ int hgt_build(const hgt_build_desc* d, hgt_graph** out) {
     if (const char* pc = std::getenv("HGT_PAIR_CAP")) g->pair_cap_max = (uint32_t)std::atoi(pc);
     if (const char* pr = std::getenv("HGT_PAIR_RUNS")) g->pair_runs = std::atoi(pr) != 0;
     if (const char* pa = std::getenv("HGT_PAIR_AGG")) g->pair_agg = std::atoi(pa) != 0;
+    if (const char* gw = std::getenv("HGT_GLOBAL_WG_PER_CU")) g->global_wg_per_cu = std::max(1, std::min(16, std::atoi(gw)));
+    if (const char* sk = std::getenv("HGT_SKIP_LDS148")) g->skip_lds148 = std::atoi(sk) != 0;
     int rc = HGT_OK;
     do {
         HIP_BRK(hipGetDevice(&g->device));

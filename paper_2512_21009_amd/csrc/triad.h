@@ -121,6 +121,7 @@ struct He2Params {
     uint64_t garena_words;
     uint64_t* stats;
     int force_stage;             // test knob: stages below it move every centre on
+    int skip_lds148;             // 1: the 148 KB stage moves every centre on to the global stage
     uint32_t pair_cap_max;       // test knob: pair-hash slots at most this (0 = no limit)
     int pair_runs;               // 1: run-table pair phase with the pair hash; 0: pairs per run
                                  // entry, pairs sharing several vertices merged row by row

@@ -580,7 +580,8 @@ __device__ void he2_body(const He2Params& P, uint32_t* arena, const uint32_t ARE
                 sh.skip = *((volatile const int32_t*)Gq.status) != 0;
                 sh.hlen = Gq.g.h_len[h];
                 sh.hoff = Gq.g.h_off[h];
-                sh.defer = (3ull * sh.hlen + 4 > ARENA_WORDS / 2 || STAGE < P.force_stage) ? 1u : 0u;
+                sh.defer = (3ull * sh.hlen + 4 > ARENA_WORDS / 2 || STAGE < P.force_stage || (STAGE == 1 && P.skip_lds148))
+                               ? 1u : 0u;
             }
         }
         __syncthreads();

@@ -173,6 +173,7 @@ def test_every_kernel_path(gpu_lib, monkeypatch, stage):
     (1: 148 KB LDS arena, 2: global-memory arena, 3: 2-hop kernel) and check
     the same results."""
     monkeypatch.setenv("HGT_FORCE_STAGE", str(stage))
+    monkeypatch.setenv("HGT_SKIP_LDS148", "0")  # keep the 148 KB stage in the sequence
     st = _random_stream(3000 + stage, n_edges=250, nv=90, n_batches=2, n_ins=50, n_del=60, temporal=False,
                         card=(1, 9))
     p = Pair(st, track=("hyperedge",))

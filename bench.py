@@ -51,7 +51,7 @@ def parse():
     ap.add_argument("--config", choices=("medium", "temporal", "batched", "served"), default="medium")
     ap.add_argument("--requests", type=int, default=256, help="served: number of requests")
     ap.add_argument("--scale", type=float, default=1.0, help="workload scale (1.0 = the named configuration)")
-    ap.add_argument("--cpu-sample", type=int, default=400, help="updates in the oracle's timed sample")
+    ap.add_argument("--cpu-sample", type=int, default=600, help="updates in the oracle's timed sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quiet", action="store_true")
     return ap.parse_args()

@@ -235,7 +235,7 @@ namespace {
 
 enum ProfKind { PK_PLAN = 0, PK_DELTA_SMALL, PK_DELTA_BIG, PK_IV_PREP, PK_IV_PAIRS, PK_COMMIT, PK_DELTA_MED,
                 PK_DELTA_GLOBAL, PK_NBR, PK_TMP, PK_N };
-const char* kProfNames[PK_N] = {"store_plan", "he_hist_lds72", "he_2hop", "iv_prepare", "iv_pairs", "store_commit",
+const char* kProfNames[PK_N] = {"store_plan", "he_hist_lds32", "he_2hop", "iv_prepare", "iv_pairs", "store_commit",
                                 "he_hist_lds148", "he_hist_global", "he_nbr_pass", "temporal"};
 
 hipEvent_t prof_event(hgt_graph* g) {
@@ -687,7 +687,7 @@ int run_phase(hgt_graph* owner, const PhaseJob* jobs, uint32_t nj, bool minus, b
             hgt_fill_u32(ctr + 5, 0, 1, s);
             {
                 ProfScope ps(owner, PK_DELTA_SMALL, s);
-                he2_launch_stage(E, 0, grid_small, s);
+                he2_launch_stage(E, 0, (unsigned)std::min<uint64_t>(n_cu * 4, n), s);
             }
             {
                 ProfScope ps(owner, PK_DELTA_MED, s);

@@ -24,7 +24,7 @@ namespace {
 
 using namespace tri;
 
-constexpr uint32_t ARENA_S = 18432;   // 72 KB of LDS: two workgroups per CU
+constexpr uint32_t ARENA_S = 8192;    // 32 KB of LDS: four workgroups per CU
 constexpr uint32_t ARENA_M = 37888;   // 148 KB of LDS: one workgroup per CU
 constexpr uint32_t K_MAX = 0x3fffu;   // neighbours with 14 bits
 // entry key: vertex << 15 | [vertex in h] << 14 | neighbour index (14 bits)
@@ -339,7 +339,7 @@ __global__ void k_entries_check(Multi M, const uint64_t* n_entries_p, uint64_t c
 // ===========================================================================
 // Stage s takes its centres from the batch (s = 0) or from list s-1 and moves
 // the centres whose tables do not fit its arena to list s; list 2 feeds the
-// 2-hop kernel.  Stages 0 and 1 keep the arena in LDS (72 KB, 148 KB), stage 2
+// 2-hop kernel.  Stages 0 and 1 keep the arena in LDS (32 KB, 148 KB), stage 2
 // in a 1 MB slice of global memory per workgroup.
 // open-addressing insert with a bounded probe sequence; false when the key
 // found no slot within PAIR_PROBES probes (the table is too full)

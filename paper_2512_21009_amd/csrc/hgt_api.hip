@@ -869,8 +869,10 @@ int iv_prepare(hgt_graph* g, const BatchIn& b, const PlanScratch& w, const Batch
 
 int iv_phase(hgt_graph* g, const IvPlan& ip, bool minus, hipStream_t s) {
     if (ip.n_keys == 0) return HGT_OK;
-    const uint64_t gwords = 1ull << 22;  // 16 MB per workgroup of the global stage
-    const unsigned grid_g = 32;
+    // 1 MB per workgroup of the global stage (maps of up to 65536 slots: owners whose
+    // hyperedges hold up to about 43k members in all); four workgroups per CU
+    const uint64_t gwords = 1ull << 18;
+    const unsigned grid_g = (unsigned)(g->n_cu * 4);
     PhaseCtx& c = *g->ph;
     if (ensure(c.iv_list, (ip.n_keys + 1) * 4) || ensure(c.iv_garena, (uint64_t)grid_g * gwords * 4))
         return HGT_ENOMEM;
@@ -892,7 +894,7 @@ int iv_phase(hgt_graph* g, const IvPlan& ip, bool minus, hipStream_t s) {
     P.garena_words = gwords;
     P.stats = g->prof ? g->stats.as<uint64_t>() : nullptr;
     ProfScope ps(g, PK_IV_PAIRS, s);
-    triad_iv_launch(P, (unsigned)std::min<uint64_t>((uint64_t)g->n_cu * 2, ip.n_keys), grid_g, s);
+    triad_iv_launch(P, (unsigned)std::min<uint64_t>((uint64_t)g->n_cu * 4, ip.n_keys), grid_g, s);
     return HGT_OK;
 }
 

@@ -31,7 +31,7 @@ namespace {
 
 using namespace tri;
 
-constexpr uint32_t IV_ARENA = 16384;  // 64 KB of LDS per workgroup
+constexpr uint32_t IV_ARENA = 8192;  // 32 KB of LDS per workgroup: four workgroups per CU
 
 __device__ __forceinline__ uint64_t mix64(uint64_t k) {
     k ^= k >> 33;

@@ -217,6 +217,7 @@ struct hgt_graph {
     int pair_runs = 0;              // HGT_PAIR_RUNS=1: run-table pair phase (see He2Params)
     int pair_agg = 1;               // HGT_PAIR_AGG=0: pairs enumerated per run (see He2Params)
     int global_wg_per_cu = 4;       // HGT_GLOBAL_WG_PER_CU: workgroups per CU of the global stage
+    int iv_direct = 0;              // HGT_IV_DIRECT=1 (tests): incident-vertex owners without maps
     int skip_lds148 = 1;            // HGT_SKIP_LDS148=0: centres go through the 148 KB stage (one workgroup
                                     // per CU) instead of straight to the global one (four per CU)
     BatchSummary* h_sum = nullptr;  // pinned
@@ -893,6 +894,7 @@ int iv_phase(hgt_graph* g, const IvPlan& ip, bool minus, hipStream_t s) {
     P.garena = c.iv_garena.as<uint32_t>();
     P.garena_words = gwords;
     P.stats = g->prof ? g->stats.as<uint64_t>() : nullptr;
+    P.force_direct = g->iv_direct;
     ProfScope ps(g, PK_IV_PAIRS, s);
     triad_iv_launch(P, (unsigned)std::min<uint64_t>((uint64_t)g->n_cu * 4, ip.n_keys), grid_g, s);
     return HGT_OK;
@@ -1177,6 +1179,7 @@ int hgt_build(const hgt_build_desc* d, hgt_graph** out) {
     if (const char* pa = std::getenv("HGT_PAIR_AGG")) g->pair_agg = std::atoi(pa) != 0;
     if (const char* gw = std::getenv("HGT_GLOBAL_WG_PER_CU")) g->global_wg_per_cu = std::max(1, std::min(16, std::atoi(gw)));
     if (const char* sk = std::getenv("HGT_SKIP_LDS148")) g->skip_lds148 = std::atoi(sk) != 0;
+    if (const char* iv = std::getenv("HGT_IV_DIRECT")) g->iv_direct = std::atoi(iv) != 0;
     int rc = HGT_OK;
     do {
         HIP_BRK(hipGetDevice(&g->device));

@@ -158,6 +158,7 @@ struct IvParams {
     uint32_t* garena;
     uint64_t garena_words;
     uint64_t* stats;             // optional, ST_IV_BYTES
+    int force_direct;            // test knob: every owner evaluated pair by pair without a map
 };
 // hash of the touched pairs (canon: lo << 32 | hi) and the owner segments of own
 // (owner << 32 | other, sorted)

@@ -237,7 +237,7 @@ __device__ void iv_body(const IvParams& P, uint32_t* arena, uint32_t arena_words
         if (tid == 0) {
             sh.L = L;
             sh.cap = L + L / 2 + 32;
-            sh.defer = (4ull * sh.cap > arena_words) ? 1u : 0u;
+            sh.defer = (4ull * sh.cap > arena_words || P.force_direct) ? 1u : 0u;
         }
         __syncthreads();
         if (sh.defer && STAGE == 0) {

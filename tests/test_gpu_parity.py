@@ -207,6 +207,19 @@ def test_pair_phase_paths(gpu_lib, monkeypatch, agg):
         p.close()
 
 
+def test_incident_vertex_without_maps(gpu_lib, monkeypatch):
+    """Every incident-vertex owner evaluated pair by pair without a clique map
+    (the path of owners too large for the global stage's arena): same counts."""
+    monkeypatch.setenv("HGT_IV_DIRECT", "1")
+    for st in (_random_stream(4100, n_edges=200, nv=70, n_batches=2, n_ins=40, n_del=40, temporal=False, card=(1, 7)),
+               W.medium(scale=0.0005, n_batches=2)):
+        p = Pair(st, track=("incident_vertex",))
+        for k, b in enumerate(st.batches):
+            p.apply(b, f"iv direct batch {k}")
+            compare_counts(p.g, p.o, p.track, f"iv direct batch {k}")
+        p.close()
+
+
 @pytest.mark.skip(reason="the run-table pair phase (HGT_PAIR_RUNS=1) is switched off: a GPU run with it "
                          "enabled faulted and the cause is not found yet")
 def test_pair_hash_overflow_path(gpu_lib, monkeypatch):

@@ -48,6 +48,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=9)
     ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--prof-steps", type=int, default=2,
+                    help="batches applied after the timed region with HIP-event profiling on (roofline)")
+    ap.add_argument("--phases", action="store_true",
+                    help="also record the hyperedge-delta stages' wall-clock phase timers in the profiled pass")
     ap.add_argument("--config", choices=("medium", "temporal", "batched", "served"), default="medium")
     ap.add_argument("--requests", type=int, default=256, help="served: number of requests")
     ap.add_argument("--scale", type=float, default=1.0, help="workload scale (1.0 = the named configuration)")
@@ -192,14 +196,15 @@ def bench_single(args, st, track, name, workload):
     build_s = time.perf_counter() - t0
     log(args, f"build with initial counts: {build_s:.2f}s")
     n_b = len(st.batches)
+    n_timed_end = args.warmup + args.steps
     for k in range(args.warmup):
         g.apply_batch(dels[k], *ins[k], its[k])
     torch.cuda.synchronize()
-    g.profile(True)
+    # timed region: no profiling
     lat, n_upd = [], 0
     torch.cuda.synchronize()
     t_start = time.perf_counter()
-    for k in range(args.warmup, n_b):
+    for k in range(args.warmup, n_timed_end):
         tb = time.perf_counter()
         g.apply_batch(dels[k], *ins[k], its[k])
         torch.cuda.synchronize()
@@ -207,12 +212,21 @@ def bench_single(args, st, track, name, workload):
         n_upd += st.batches[k].n_updates
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
+    # profiled pass over the next batches (same shape): HIP events around each kernel
+    # group on the launch stream and the kernels' algorithmic-byte counters
+    g.profile(2 if args.phases else 1)
+    for k in range(n_timed_end, n_b):
+        g.apply_batch(dels[k], *ins[k], its[k])
+    torch.cuda.synchronize()
     prof = g.profile_read()
-    log_phases(args, g.profile_counters())
+    if args.phases:
+        log_phases(args, g.profile_counters())
+    g.profile(0)
     status = g.sync()
     assert status == hgt.OK, status
     value = n_upd / elapsed
     log(args, f"{n_upd} updates in {elapsed:.3f}s -> {value:,.0f} updates/s")
+    log(args, f"profiled pass: {n_b - n_timed_end} batches")
     log_profile(args, prof)
     totals = {k: int(sum(g.triad_counts(k))) for k in track}
     g.close()
@@ -228,6 +242,7 @@ def bench_single(args, st, track, name, workload):
         "config": {"workload": workload, "scale": args.scale, "batch_updates": int(st.batches[-1].n_updates),
                    "build_s": round(build_s, 3), "triads_total": totals},
         "roofline": rl,
+        "roofline_pass": f"{n_b - n_timed_end} batches after the timed region, HIP events on",
     }
 
 
@@ -238,7 +253,8 @@ def bench_batched(args):
     import torch
     from paper_2512_21009_amd import hgt
     from paper_2512_21009_amd import workloads as W
-    n_b = args.warmup + args.steps
+    n_timed_end = args.warmup + args.steps
+    n_b = n_timed_end + max(1, args.prof_steps)
     t0 = time.perf_counter()
     sc = args.scale
     sts = W.batched(n_batches=n_b, e_lo=max(100.0, 1e3 * sc), e_hi=max(1e3, 2e5 * sc), b_hi=max(20.0, 5e4 * sc))
@@ -264,7 +280,7 @@ def bench_batched(args):
     batch = build_all()
     log(args, f"built 2 x {len(sts)} graphs ({build_s:.2f}s per copy)")
     ups = [sum(st.batches[k].n_updates for st in sts) for k in range(n_b)]
-    # plain: one call per graph
+    # plain: one call per graph (the rounds after the timed ones keep the copies equal)
     lat_p = []
     for k in range(n_b):
         torch.cuda.synchronize()
@@ -272,20 +288,20 @@ def bench_batched(args):
         for gi, g in enumerate(plain):
             g.apply_batch(dels[gi][k], *ins[gi][k])
         torch.cuda.synchronize()
-        if k >= args.warmup:
+        if args.warmup <= k < n_timed_end:
             lat_p.append(time.perf_counter() - tb)
-    # batched: one call per round
+    # batched: one call per round; the rounds after the timed ones are profiled
     lat_b = []
     for k in range(n_b):
-        if k == args.warmup:
+        if k == n_timed_end:
             for g in batch:
-                g.profile(True)
+                g.profile(1)
         items = [(g, dels[gi][k]) + ins[gi][k] for gi, g in enumerate(batch)]
         torch.cuda.synchronize()
         tb = time.perf_counter()
         hgt.apply_batches(items)
         torch.cuda.synchronize()
-        if k >= args.warmup:
+        if args.warmup <= k < n_timed_end:
             lat_b.append(time.perf_counter() - tb)
     prof = {}
     for g in batch:
@@ -297,7 +313,7 @@ def bench_batched(args):
         assert g.sync() == hgt.OK
         g.close()
     calibration_copy()
-    n_upd = sum(ups[args.warmup:])
+    n_upd = sum(ups[args.warmup:n_timed_end])
     v_b = n_upd / sum(lat_b)
     v_p = n_upd / sum(lat_p)
     log(args, f"plain {v_p:,.0f} updates/s, batched {v_b:,.0f} updates/s ({v_b / v_p:.2f}x)")
@@ -310,7 +326,8 @@ def bench_batched(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
         "config": {"workload": "batched: 256 graphs, |E| log-uniform [1k,200k], |V|=|E|/2, card power-law 2.5 on "
                                "[2,256], batches log-uniform [10,50k] (60% inserts), hyperedge triads",
-                   "scale": sc, "round_updates": int(np.mean(ups[args.warmup:])), "build_s_per_copy": round(build_s, 3),
+                   "scale": sc, "round_updates": int(np.mean(ups[args.warmup:n_timed_end])),
+                   "build_s_per_copy": round(build_s, 3),
                    "he_triads_total": int(total)},
         "plain": {"value": round(v_p, 1), "p50_ms": round(float(np.percentile(lp, 50)), 3),
                   "p99_ms": round(float(np.percentile(lp, 99)), 3)},
@@ -460,7 +477,7 @@ def main():
     from paper_2512_21009_amd import hgt, workloads as W
 
     hgt.load()
-    n_b = args.warmup + args.steps
+    n_b = args.warmup + args.steps + max(1, args.prof_steps)
     t0 = time.perf_counter()
     if args.config == "batched":
         out, sts = bench_batched(args)

@@ -284,7 +284,11 @@ typedef struct {
     uint64_t aux;
 } hgt_kernel_time;
 
-/* Waits for the graph's work, resets the profile and switches it on (1) or off (0). */
+/* Waits for the graph's work, resets the profile and switches it off (0), on
+ * (1: HIP events around each kernel group and algorithmic-byte counters, a
+ * few atomics per changed hyperedge) or on with the hyperedge-delta stages'
+ * wall-clock phase timers (2: a clock read and a workgroup barrier per phase,
+ * which slows those kernels; for breakdowns, not for timing). */
 int hgt_profile(hgt_graph* g, int enable);
 
 /* Waits for the graph's work and copies up to n_max rows (host) ; *n_out

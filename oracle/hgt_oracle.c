@@ -515,3 +515,127 @@ int orc_count_iv(uint64_t n_slots, const uint64_t* off, const uint32_t* mem, con
     out[2] = tot - out[0] - out[1];
     return 0;
 }
+
+/* ------------------------------------------------------------------ */
+/* incident-vertex terms restricted to a set of vertex pairs           */
+/* ------------------------------------------------------------------ */
+static int cmp_u64(const void* a, const void* b) {
+    uint64_t x = *(const uint64_t*)a, y = *(const uint64_t*)b;
+    return x < y ? -1 : x > y;
+}
+
+static int has_key(const uint64_t* keys, uint64_t n, uint64_t key) {
+    uint64_t lo = 0, hi = n;
+    while (lo < hi) {
+        uint64_t mid = (lo + hi) / 2;
+        if (keys[mid] < key) lo = mid + 1; else hi = mid;
+    }
+    return lo < n && keys[lo] == key;
+}
+
+static uint64_t pair_key(uint32_t u, uint32_t v) { return u < v ? (uint64_t)u << 32 | v : (uint64_t)v << 32 | u; }
+
+/*
+ * The two sums of orc_count_iv's closed forms, restricted to the vertex pairs
+ * keys[0..n_keys) (u << 32 | v, u < v, ascending, distinct):
+ *   out[0] = sum over the listed pairs p of m_p * w_p;
+ *   out[1] = sum over the vertex triangles {a,b,c} having at least one listed
+ *            pair of m_ab * m_bc * m_ca (each triangle once).
+ * Every pair inside a changed hyperedge is listed, and no other pair changes
+ * m or w, so the changes of these two sums between the graphs before and
+ * after a batch are the changes of the full sums (the incident-vertex delta
+ * of the batch, counted by definition).
+ */
+int orc_iv_partial(uint64_t n_slots, const uint64_t* off, const uint32_t* mem, const uint8_t* live,
+                   uint32_t n_vertices, const uint64_t* keys, uint64_t n_keys, uint64_t* out) {
+    graph_t g;
+    if (init_graph(&g, n_slots, off, mem, live, n_vertices)) { free_graph(&g); return -1; }
+    uint64_t s_sum = 0, x_sum = 0;
+    int err = 0;
+    /* distinct first endpoints */
+    uint64_t* starts = (uint64_t*)malloc((n_keys + 1) * sizeof(uint64_t));
+    uint64_t n_a = 0;
+    if (!starts) { free_graph(&g); return -1; }
+    for (uint64_t i = 0; i < n_keys; i++)
+        if (i == 0 || (keys[i] >> 32) != (keys[i - 1] >> 32)) starts[n_a++] = i;
+    starts[n_a] = n_keys;
+#pragma omp parallel reduction(+ : s_sum, x_sum)
+    {
+        /* weight[c] = m_ac of the current a, valid where stamp[c] == tag */
+        uint64_t* weight = (uint64_t*)calloc((size_t)n_vertices + 1, sizeof(uint64_t));
+        uint64_t* stamp = (uint64_t*)malloc(((size_t)n_vertices + 1) * sizeof(uint64_t));
+        if (!weight || !stamp) {
+#pragma omp atomic write
+            err = 1;
+        } else {
+            for (uint32_t v = 0; v <= n_vertices; v++) stamp[v] = UINT64_MAX;
+#pragma omp for schedule(dynamic, 8)
+            for (uint64_t ia = 0; ia < n_a; ia++) {
+                const uint32_t a = (uint32_t)(keys[starts[ia]] >> 32);
+                /* weighted neighbourhood of a in the clique expansion */
+                for (uint64_t q = g.voff[a]; q < g.voff[a + 1]; q++) {
+                    uint32_t h = g.vmem[q];
+                    for (uint64_t k = off[h]; k < off[h + 1]; k++) {
+                        uint32_t c = mem[k];
+                        if (c == a) continue;
+                        if (stamp[c] != ia) { stamp[c] = ia; weight[c] = 0; }
+                        weight[c]++;
+                    }
+                }
+                for (uint64_t i = starts[ia]; i < starts[ia + 1]; i++) {
+                    const uint32_t b = (uint32_t)keys[i];
+                    const uint64_t m_ab = stamp[b] == ia ? weight[b] : 0;
+                    if (m_ab == 0) continue;
+                    /* w_ab: hyperedges holding both a and b */
+                    uint64_t w_ab = 0;
+                    uint64_t p = g.voff[a], pe = g.voff[a + 1], r = g.voff[b], re = g.voff[b + 1];
+                    while (p < pe && r < re) {
+                        if (g.vmem[p] < g.vmem[r]) p++;
+                        else if (g.vmem[p] > g.vmem[r]) r++;
+                        else { w_ab += glen(&g, g.vmem[p]) - 2; p++; r++; }
+                    }
+                    s_sum += m_ab * w_ab;
+                    /* triangles {a,b,c}: each occurrence of c in a hyperedge of b adds
+                       m_ab * m_ac once (summing to m_ab * m_ac * m_bc); a triangle is
+                       taken at its smallest listed pair */
+                    const uint64_t kab = keys[i];
+                    for (uint64_t q = g.voff[b]; q < g.voff[b + 1]; q++) {
+                        uint32_t h = g.vmem[q];
+                        for (uint64_t k = off[h]; k < off[h + 1]; k++) {
+                            uint32_t c = mem[k];
+                            if (c == b || c == a || stamp[c] != ia) continue;
+                            uint64_t kac = pair_key(a, c), kbc = pair_key(b, c);
+                            if ((kac < kab && has_key(keys, n_keys, kac)) || (kbc < kab && has_key(keys, n_keys, kbc)))
+                                continue;
+                            x_sum += m_ab * weight[c];
+                        }
+                    }
+                }
+            }
+        }
+        free(weight);
+        free(stamp);
+    }
+    free(starts);
+    free_graph(&g);
+    out[0] = s_sum;
+    out[1] = x_sum;
+    return err ? -1 : 0;
+}
+
+/* The distinct vertex pairs inside the listed live slots, ascending (u << 32 | v).
+ * out must hold sum over the slots of C(|h|, 2) keys; returns the distinct count. */
+uint64_t orc_pairs_of(const uint64_t* off, const uint32_t* mem, const uint64_t* slots, uint64_t n_slots_listed,
+                      uint64_t* out) {
+    uint64_t k = 0;
+    for (uint64_t i = 0; i < n_slots_listed; i++) {
+        uint64_t h = slots[i];
+        for (uint64_t x = off[h]; x < off[h + 1]; x++)
+            for (uint64_t y = x + 1; y < off[h + 1]; y++) out[k++] = pair_key(mem[x], mem[y]);
+    }
+    qsort(out, k, sizeof(uint64_t), cmp_u64);
+    uint64_t u = 0;
+    for (uint64_t i = 0; i < k; i++)
+        if (u == 0 || out[u - 1] != out[i]) out[u++] = out[i];
+    return u;
+}

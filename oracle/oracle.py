@@ -69,6 +69,10 @@ def lib():
         _lib.orc_count_containing.restype = ctypes.c_int
         _lib.orc_count_iv.argtypes = [U64, P, P, P, U32, P]
         _lib.orc_count_iv.restype = ctypes.c_int
+        _lib.orc_iv_partial.argtypes = [U64, P, P, P, U32, P, U64, P]
+        _lib.orc_iv_partial.restype = ctypes.c_int
+        _lib.orc_pairs_of.argtypes = [P, P, P, U64, P]
+        _lib.orc_pairs_of.restype = U64
         _lib.orc_he_class_of_code.argtypes = [ctypes.c_int]
         _lib.orc_tmp_class_of_code.argtypes = [ctypes.c_int]
         _lib.orc_he_class_codes.argtypes = [P]
@@ -259,25 +263,76 @@ class OracleGraph:
         assert rc == 0
         return out
 
-    def counts_containing(self, ids: Sequence[int], window: Optional[int] = None):
-        """(he u64[30], temporal u64[96]) of the triads containing >= 1 of ids."""
+    def counts_containing(self, ids: Sequence[int], window: Optional[int] = None, he: bool = True,
+                          temporal: bool = True):
+        """(he u64[30], temporal u64[96]) of the triads containing >= 1 of ids;
+        a family switched off (or temporal on a graph without timestamps) is
+        returned as zeros without being counted."""
         marked = np.zeros(self.n_slots, dtype=np.uint8)
         ids = np.asarray(ids, dtype=np.int64)
         if len(ids):
             marked[ids] = 1
-        he = np.zeros(N_HE, dtype=np.uint64)
+        he_out = np.zeros(N_HE, dtype=np.uint64)
         tm = np.zeros(N_TMP, dtype=np.uint64)
         w = self.window if window is None else int(window)
         rc = lib().orc_count_containing(*self._args(), _p(self.ts), _p(self.seq), w, _p(marked),
-                                        _p(he), _p(tm) if self.temporal else None)
+                                        _p(he_out) if he else None, _p(tm) if (self.temporal and temporal) else None)
         assert rc == 0
-        return he, tm
+        return he_out, tm
+
+    def pairs_of(self, ids: Sequence[int]) -> np.ndarray:
+        """Distinct vertex pairs (u << 32 | v, u < v, ascending) inside the rows of ids."""
+        ids = np.asarray(ids, dtype=np.uint64)
+        if len(ids) == 0:
+            return np.zeros(0, np.uint64)
+        lens = (self.off[ids.astype(np.int64) + 1] - self.off[ids.astype(np.int64)]).astype(np.int64)
+        out = np.zeros(max(1, int((lens * (lens - 1) // 2).sum())), dtype=np.uint64)
+        n = lib().orc_pairs_of(_p(self.off), _p(self.mem), _p(ids), len(ids), _p(out))
+        return out[:n].copy()
+
+    def iv_partial(self, keys: np.ndarray):
+        """(sum over the listed pairs of m_p w_p, sum over the triangles with a
+        listed pair of m m m): the two closed-form sums restricted to keys."""
+        keys = np.ascontiguousarray(keys, dtype=np.uint64)
+        out = np.zeros(2, dtype=np.uint64)
+        rc = lib().orc_iv_partial(*self._args(), _p(keys), len(keys), _p(out))
+        assert rc == 0
+        return out
 
 
-def delta_by_definition(old: OracleGraph, new: OracleGraph, del_ids, ins_ids):
+def delta_by_definition(old: OracleGraph, new: OracleGraph, del_ids, ins_ids, he: bool = True,
+                        temporal: bool = True):
     """Per-class change of the hyperedge and temporal counts from old to new:
     triads of new containing an inserted hyperedge minus triads of old
     containing a deleted one (mod 2^64)."""
-    he_d, tm_d = old.counts_containing(del_ids)
-    he_i, tm_i = new.counts_containing(ins_ids)
+    he_d, tm_d = old.counts_containing(del_ids, he=he, temporal=temporal)
+    he_i, tm_i = new.counts_containing(ins_ids, he=he, temporal=temporal)
     return he_i - he_d, tm_i - tm_d
+
+
+def _choose3(d: np.ndarray) -> np.ndarray:
+    d = d.astype(np.uint64)
+    return np.where(d >= 3, d * (d - np.uint64(1)) * (d - np.uint64(2)) // np.uint64(6), np.uint64(0))
+
+
+def iv_delta_by_definition(old: OracleGraph, new: OracleGraph, del_ids, ins_ids) -> np.ndarray:
+    """Change of the incident-vertex counts [T1, T2, T3] from old to new
+    (mod 2^64), from the closed forms restricted to the vertex pairs inside a
+    deleted or inserted hyperedge: only those pairs change m_p and w_p, and
+    only triangles holding one of them change their product.
+      dT1 = sum_ins C(|h|,3) - sum_del C(|h|,3)
+      dT2 = d(sum_p m_p w_p) - 3 dT1
+      dT3 = d(sum over triangles of m m m) - dT1 - dT2"""
+    del_ids = np.asarray(del_ids, dtype=np.int64)
+    ins_ids = np.asarray(ins_ids, dtype=np.int64)
+    keys = np.union1d(old.pairs_of(del_ids), new.pairs_of(ins_ids)).astype(np.uint64)
+    so = old.iv_partial(keys)
+    sn = new.iv_partial(keys)
+    with np.errstate(over="ignore"):
+        t1 = np.uint64(_choose3(new.lens()[ins_ids]).sum(dtype=np.uint64)) - \
+             np.uint64(_choose3(old.lens()[del_ids]).sum(dtype=np.uint64))
+        ds = sn[0] - so[0]
+        dx = sn[1] - so[1]
+        d2 = ds - np.uint64(3) * t1
+        d3 = dx - t1 - d2
+    return np.array([t1, d2, d3], dtype=np.uint64)

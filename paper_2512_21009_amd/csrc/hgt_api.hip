@@ -179,7 +179,7 @@ struct PhaseCtx {
     int refs = 0;                 // graphs that use it
     hipEvent_t done = nullptr;    // recorded after the last user's phases
     DevBuf iv_list, iv_garena;    // incident-vertex stage scratch
-    DevBuf t_ctr, t_big_list, t_big_rank, t_big_scratch, t_list1, t_rank1, t_list2, t_rank2, t_garena;
+    DevBuf t_ctr, t_big_list, t_big_rank, t_big_scratch, t_list1, t_rank1, t_list2, t_rank2, t_garena, t_whash;
     DevBuf ent_x, ent_d, ent_pay, bl_cnt, bl_off, bl_cur, bl_d, bl_pay, nb_scratch, bl_scan;
     // per-graph phase descriptors: device copies and their pinned staging, one
     // slot per (phase, family) so no upload overwrites one still in flight
@@ -198,11 +198,12 @@ struct hgt_graph {
     StoreDev st{};
     DevBuf h_off, h_len, h_cap, h_ts, h_seq, free_bm, mark_del, mark_ins;
     DevBuf h2v, v_off, v_len, v_cap, v2h;
+    DevBuf v2h_ts;  // temporal graphs: int64 per v2h word (grown with v2h)
     DevBuf scal, counts, tabs;
     // batch scratch
     DevBuf s_sum, s_del_bm, s_del_card, s_del_poff, s_ins_rel, s_ins_card, s_canon, s_big, s_small, s_popc, s_scan,
         s_assigned, s_h_need, s_h_rel, s_keys, s_keys_alt, s_sort, s_head, s_is_ins, s_tv, s_tseg, s_D, s_I, s_It,
-        s_vp, s_staging, s_dst, s_rank_of, s_rank_id, s_keep, s_keep_scan;
+        s_vp, s_staging, s_staging_ts, s_dst;
     // hyperedge-family neighbour histograms (2 words per h2v word)
     DevBuf hpool;
     PhaseCtx* ph = nullptr;  // the device's shared phase scratch
@@ -213,8 +214,6 @@ struct hgt_graph {
     int sticky = HGT_OK;
     uint64_t batches = 0;
     int force_stage = 0;            // HGT_FORCE_STAGE (tests): see He2Params
-    uint32_t pair_cap_max = 0;      // HGT_PAIR_CAP (tests): see He2Params
-    int pair_runs = 0;              // HGT_PAIR_RUNS=1: run-table pair phase (see He2Params)
     int pair_agg = 1;               // HGT_PAIR_AGG=0: pairs enumerated per run (see He2Params)
     int global_wg_per_cu = 4;       // HGT_GLOBAL_WG_PER_CU: workgroups per CU of the global stage
     int iv_direct = 0;              // HGT_IV_DIRECT=1 (tests): incident-vertex owners without maps
@@ -223,7 +222,8 @@ struct hgt_graph {
     BatchSummary* h_sum = nullptr;  // pinned
     DevScalars* h_sc = nullptr;     // pinned
     // profiling: HIP events around each kernel group, algorithmic-byte counters
-    bool prof = false;
+    bool prof = false;              // HIP events around kernel groups + algorithmic-byte counters
+    bool prof_phases = false;       // also wall-clock ticks per phase of the hyperedge-delta stages
     struct Rec { int kind; hipEvent_t a, b; };
     std::vector<Rec> recs;
     std::vector<hipEvent_t> ev_pool;
@@ -279,6 +279,7 @@ void refresh_view(hgt_graph* g) {
     s.v_len = g->v_len.as<uint32_t>();
     s.v_cap = g->v_cap.as<uint32_t>();
     s.v2h = g->v2h.as<uint32_t>();
+    s.v2h_ts = (g->track_mask & (1u << HGT_TRIAD_TEMPORAL)) ? g->v2h_ts.as<int64_t>() : nullptr;
     s.v2h_words = g->v2h.bytes / 4;
     s.mark_del = g->mark_del.as<uint64_t>();
     s.mark_ins = g->mark_ins.as<uint64_t>();
@@ -295,8 +296,7 @@ GraphView view_of(hgt_graph* g) {
     v.v2h = g->st.v2h;
     v.h_ts = g->st.h_ts;
     v.h_seq = g->st.h_seq;
-    v.time_sorted = g->st.time_order;
-    v.pad0 = 0;
+    v.v2h_ts = g->st.v2h_ts;
     return v;
 }
 
@@ -370,10 +370,6 @@ int ensure_plan_scratch(hgt_graph* g, const Sizes& z, PlanScratch& w) {
     rc |= ensure(g->s_It, pc * 4);
     rc |= ensure(g->s_vp, pc * (8 * 6 + 4 * 3) + 64);
     rc |= ensure(g->s_dst, pc * 8);
-    if (g->st.time_order) {
-        rc |= ensure(g->s_rank_of, ni * 4);
-        rc |= ensure(g->s_rank_id, ni * 4);
-    }
     if (rc) return HGT_ENOMEM;
     w.sum = g->s_sum.as<BatchSummary>();
     w.del_bm = g->s_del_bm.as<uint64_t>();
@@ -422,17 +418,13 @@ int ensure_plan_scratch(hgt_graph* g, const Sizes& z, PlanScratch& w) {
     w.vp.new_len = vp32 + 2 * pc;
     w.dst = g->s_dst.as<uint64_t>();
     w.staging = g->s_staging.as<uint32_t>();
-    w.rank_of = g->s_rank_of.as<uint32_t>();
-    w.rank_id = g->s_rank_id.as<uint32_t>();
-    w.ts_min = sm + 9;
-    w.keep = g->s_keep.as<uint64_t>();
-    w.keep_scan_tmp = g->s_keep_scan.p;
+    w.staging_ts = g->s_staging_ts.as<int64_t>();
     return HGT_OK;
 }
 
 // ---- triad phases ---------------------------------------------------------
 void phase_ctx_free(PhaseCtx& c) {
-    DevBuf* all[] = {&c.t_ctr, &c.t_big_list, &c.t_big_rank, &c.t_big_scratch, &c.t_list1, &c.t_rank1, &c.t_list2,
+    DevBuf* all[] = {&c.t_ctr, &c.t_whash, &c.t_big_list, &c.t_big_rank, &c.t_big_scratch, &c.t_list1, &c.t_rank1, &c.t_list2,
                      &c.t_rank2, &c.t_garena, &c.ent_x, &c.ent_d, &c.ent_pay, &c.bl_cnt, &c.bl_off, &c.bl_cur,
                      &c.bl_d, &c.bl_pay, &c.nb_scratch, &c.bl_scan, &c.desc, &c.iv_list, &c.iv_garena};
     for (DevBuf* b : all) dev_free(*b);
@@ -601,6 +593,10 @@ int run_phase(hgt_graph* owner, const PhaseJob* jobs, uint32_t nj, bool minus, b
         // at most ~1 GiB of global tables for the large-centre kernels
         uint64_t grid_big = std::max<uint64_t>(1, std::min<uint64_t>(n_cu * 2, (1ull << 28) / L.words_per_wg));
         if (ensure(c.t_big_scratch, grid_big * L.words_per_wg * 4)) return HGT_ENOMEM;
+        // 2-hop hashes in global memory, one per wave of the 2-hop kernels (64 KB each)
+        const uint32_t wave_slots = 8192;
+        const uint64_t grid_2hop = std::max<uint64_t>(grid_big, n_cu * 3);
+        if (ensure(c.t_whash, grid_2hop * 4 * 2ull * wave_slots * 4)) return HGT_ENOMEM;
         Multi M{};
         rc = upload_multi(c, (minus ? 0 : 2) + (family == HGT_TRIAD_TEMPORAL ? 1 : 0), G, base, id_base, M, s);
         if (rc) return rc;
@@ -612,6 +608,8 @@ int run_phase(hgt_graph* owner, const PhaseJob* jobs, uint32_t nj, bool minus, b
         P.big_list = c.t_big_list.as<uint64_t>();
         P.big_rank = c.t_big_rank.as<uint32_t>();
         P.big_scratch = c.t_big_scratch.as<uint32_t>();
+        P.wave_hash = c.t_whash.as<uint32_t>();
+        P.wave_slots = wave_slots;
         P.big = L;
         P.stats = stats;
         const unsigned grid_small = (unsigned)std::min<uint64_t>(n_cu * 2, n);
@@ -678,9 +676,8 @@ int run_phase(hgt_graph* owner, const PhaseJob* jobs, uint32_t nj, bool minus, b
             E.garena = c.t_garena.as<uint32_t>();
             E.garena_words = garena_words;
             E.stats = stats;
+            E.phase_ticks = (stats && owner->prof_phases) ? 1 : 0;
             E.force_stage = owner->force_stage;
-            E.pair_cap_max = owner->pair_cap_max;
-            E.pair_runs = owner->pair_runs;
             E.pair_agg = owner->pair_agg;
             E.skip_lds148 = owner->skip_lds148;
             E.static_mode = full ? 1 : 0;
@@ -965,16 +962,16 @@ int plan_end(Pending& p, hipStream_t s) {
     if (!rc && (g->track_mask & (1u << HGT_TRIAD_HYPEREDGE)) && g->hpool.bytes < 2 * g->h2v.bytes)
         rc = grow_keep(g->hpool, 2 * g->h2v.bytes, 2 * g->h_bump * 4, s);
     if (!rc) rc = ensure_pool(g->v2h, g->v_bump, sum.v2h_need, s);
+    const bool tmp = g->track_mask & (1u << HGT_TRIAD_TEMPORAL);
+    // the timestamp pool follows the v2h pool word for word
+    if (!rc && tmp && g->v2h_ts.bytes < 2 * g->v2h.bytes)
+        rc = grow_keep(g->v2h_ts, 2 * g->v2h.bytes, g->v_bump * 8, s);
     if (!rc) rc = ensure(g->s_staging, std::max<uint64_t>(sum.stage_words, 1) * 4);
-    if (!rc && g->st.time_order) {
-        rc = ensure(g->s_keep, (2 * sum.stage_words + 2) * 8);
-        if (!rc) rc = ensure(g->s_keep_scan, hgt_scan_tmp_bytes(sum.stage_words + 1));
-    }
+    if (!rc && tmp) rc = ensure(g->s_staging_ts, std::max<uint64_t>(sum.stage_words, 1) * 8);
     if (rc) return rc;
     refresh_view(g);
     p.w.staging = g->s_staging.as<uint32_t>();
-    p.w.keep = g->s_keep.as<uint64_t>();
-    p.w.keep_scan_tmp = g->s_keep_scan.p;
+    p.w.staging_ts = g->s_staging_ts.as<int64_t>();
     if (g->track_mask & (1u << HGT_TRIAD_INCIDENT_VERTEX)) {
         ProfScope ps(g, PK_IV_PREP, s);
         rc = iv_prepare(g, p.b, p.w, sum, p.ip, s);
@@ -1093,8 +1090,8 @@ void destroy_graph(hgt_graph* g) {
                      &g->s_sum, &g->s_del_bm, &g->s_del_card, &g->s_del_poff, &g->s_ins_rel, &g->s_ins_card,
                      &g->s_canon, &g->s_big, &g->s_small, &g->s_popc, &g->s_scan, &g->s_assigned, &g->s_h_need,
                      &g->s_h_rel, &g->s_keys, &g->s_keys_alt, &g->s_sort, &g->s_head, &g->s_is_ins, &g->s_tv,
-                     &g->s_tseg, &g->s_D, &g->s_I, &g->s_It, &g->s_vp, &g->s_staging, &g->s_dst, &g->s_rank_of, &g->s_rank_id,
-                     &g->s_keep, &g->s_keep_scan, &g->iv_keys, &g->iv_alt, &g->iv_sort,
+                     &g->s_tseg, &g->s_D, &g->s_I, &g->s_It, &g->s_vp, &g->s_staging, &g->s_dst,
+                     &g->s_staging_ts, &g->v2h_ts, &g->iv_keys, &g->iv_alt, &g->iv_sort,
                      &g->iv_head, &g->iv_uniq, &g->iv_p2, &g->iv_scan, &g->iv_tab, &g->iv_owner, &g->iv_ctr,
                      &g->hpool};
     for (DevBuf* b : all) dev_free(*b);
@@ -1174,8 +1171,6 @@ int hgt_build(const hgt_build_desc* d, hgt_graph** out) {
     g->window = d->temporal_window;
     g->last_stream = s;
     if (const char* fs = std::getenv("HGT_FORCE_STAGE")) g->force_stage = std::atoi(fs);
-    if (const char* pc = std::getenv("HGT_PAIR_CAP")) g->pair_cap_max = (uint32_t)std::atoi(pc);
-    if (const char* pr = std::getenv("HGT_PAIR_RUNS")) g->pair_runs = std::atoi(pr) != 0;
     if (const char* pa = std::getenv("HGT_PAIR_AGG")) g->pair_agg = std::atoi(pa) != 0;
     if (const char* gw = std::getenv("HGT_GLOBAL_WG_PER_CU")) g->global_wg_per_cu = std::max(1, std::min(16, std::atoi(gw)));
     if (const char* sk = std::getenv("HGT_SKIP_LDS148")) g->skip_lds148 = std::atoi(sk) != 0;
@@ -1194,11 +1189,6 @@ int hgt_build(const hgt_build_desc* d, hgt_graph** out) {
         }
         g->st.n_vertices = d->n_vertices;
         g->st.id_cap = 0;
-        // time-ordered incidence lists (windowed temporal scans) only on request: HGT_TIME_ORDER=1
-        {
-            const char* to = std::getenv("HGT_TIME_ORDER");
-            g->st.time_order = (tmp && to && std::atoi(to) != 0) ? 1 : 0;
-        }
         uint64_t cap = std::max<uint64_t>(d->edge_capacity, d->n_edges + d->n_edges / 4 + 64);
         if ((rc = ensure_id_cap(g, cap, s))) break;
         uint64_t V = d->n_vertices;
@@ -1209,6 +1199,7 @@ int hgt_build(const hgt_build_desc* d, hgt_graph** out) {
         HIP_BRK(hipMemsetAsync(g->v_cap.p, 0, V * 4, s));
         uint64_t pw = d->pool_words ? d->pool_words : 1 << 20;
         if ((rc = dev_alloc(g->h2v, pw * 4)) || (rc = dev_alloc(g->v2h, pw * 4))) break;
+        if (tmp && (rc = dev_alloc(g->v2h_ts, pw * 8))) break;
         if ((d->track_mask & (1u << HGT_TRIAD_HYPEREDGE)) && (rc = dev_alloc(g->hpool, pw * 8))) break;
         if ((rc = dev_alloc(g->scal, sizeof(DevScalars))) || (rc = dev_alloc(g->counts, ACC_N * 8)) ||
             (rc = dev_alloc(g->tabs, 256)))
@@ -1368,6 +1359,7 @@ int hgt_profile(hgt_graph* g, int enable) {
     g->ev_used = 0;
     g->store_bytes = 0;
     g->prof = enable != 0;
+    g->prof_phases = enable >= 2;
     return HGT_OK;
 }
 
@@ -1458,8 +1450,6 @@ int hgt_export_v2h(hgt_graph* g, uint64_t* offsets_host, uint32_t* members_host)
         if (len[v]) {
             if (off[v] + len[v] > g->v_bump) return HGT_EDEVICE;
             std::memcpy(members_host + k, pool.data() + off[v], len[v] * 4);
-            // time-ordered graphs keep lists by (timestamp, sequence); rows are exported ascending
-            if (g->st.time_order) std::sort(members_host + k, members_host + k + len[v]);
             k += len[v];
         }
     }

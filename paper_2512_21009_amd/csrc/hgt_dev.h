@@ -45,8 +45,9 @@ struct BatchSummary {
 };
 
 // Read-only view of the store used by the triad kernels.  Incidence lists
-// (v2h) are ascending by ID, or, in graphs that track temporal triads,
-// ascending by (timestamp, arrival sequence).
+// (v2h) are ascending by ID; graphs that track temporal triads keep the
+// timestamp of every list entry at the same index of v2h_ts, so a kernel can
+// drop the entries outside a time window while it streams a list.
 struct GraphView {
     const uint64_t* h_off;
     const uint32_t* h_len;
@@ -56,8 +57,7 @@ struct GraphView {
     const uint32_t* v2h;
     const int64_t* h_ts;
     const uint64_t* h_seq;
-    int32_t time_sorted;
-    int32_t pad0;
+    const int64_t* v2h_ts;  // NULL unless temporal is tracked
 };
 
 __device__ __forceinline__ void set_status(int32_t* st, int code) { atomicCAS(st, 0, code); }
@@ -94,33 +94,10 @@ __device__ __forceinline__ bool contains_u32(const uint32_t* a, uint32_t n, uint
     return p < n && a[p] == key;
 }
 
-// Whether the incidence list lst[0..n) holds hyperedge e (binary search in the
-// list's order: by ID, or by (timestamp, sequence) in time-sorted graphs).
+// Whether the incidence list lst[0..n) (ascending IDs) holds hyperedge e.
 __device__ __forceinline__ bool v2h_contains(const GraphView& g, const uint32_t* lst, uint32_t n, uint32_t e) {
-    if (!g.time_sorted) return contains_u32(lst, n, e);
-    const int64_t te = g.h_ts[e];
-    const uint64_t se = g.h_seq[e];
-    uint32_t lo = 0, hi = n;
-    while (lo < hi) {
-        uint32_t mid = (lo + hi) >> 1;
-        uint32_t x = lst[mid];
-        int64_t tx = g.h_ts[x];
-        if (tx < te || (tx == te && g.h_seq[x] < se)) lo = mid + 1; else hi = mid;
-    }
-    return lo < n && lst[lo] == e;
-}
-
-// First index of a time-sorted list whose timestamp is >= t (upper = false)
-// or > t (upper = true).
-__device__ __forceinline__ uint32_t v2h_ts_bound(const GraphView& g, const uint32_t* lst, uint32_t n, int64_t t,
-                                                 bool upper) {
-    uint32_t lo = 0, hi = n;
-    while (lo < hi) {
-        uint32_t mid = (lo + hi) >> 1;
-        int64_t tx = g.h_ts[lst[mid]];
-        if (tx < t || (upper && tx == t)) lo = mid + 1; else hi = mid;
-    }
-    return lo;
+    (void)g;
+    return contains_u32(lst, n, e);
 }
 
 // t - d and t + d clamped to the int64 range (d >= 0)

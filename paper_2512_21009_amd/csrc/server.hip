@@ -78,6 +78,7 @@ struct RangeAlloc {
 struct Request {
     uint64_t ticket = 0;
     uint32_t tenant = 0;
+    hgt_graph* graph = nullptr;  // the tenant's graph, copied at admission under the lock
     std::vector<uint32_t> del, mem;
     std::vector<uint64_t> off;
     std::vector<int64_t> ts;
@@ -151,7 +152,9 @@ uint64_t footprint_of(const Request& r, const HgtSizes& z) {
 void fail_all_locked(hgt_server* s, int code);
 
 // Stages the round's inputs, applies it, queues the read-back of IDs and
-// counts and records the round's event.  Called without the lock.
+// counts and records the round's event.  Called without the lock: it reads
+// only the round's requests (their graph pointers were copied at admission),
+// never the tenant table, which hgt_server_add_tenant may grow meanwhile.
 int launch_round(hgt_server* s, Round* R) {
     hipStream_t st = s->streams[R->stream];
     std::vector<hgt_batch> bs(R->reqs.size());
@@ -171,7 +174,7 @@ int launch_round(hgt_server* s, Round* R) {
             return HGT_EDEVICE;
         hgt_batch& b = bs[i];
         std::memset(&b, 0, sizeof b);
-        b.graph = s->tenants[q->tenant];
+        b.graph = q->graph;
         b.del_ids = q->del.empty() ? nullptr : (const uint32_t*)(D + q->o_del);
         b.n_del = q->del.size();
         b.ins_offsets = q->n_ins ? (const uint64_t*)(D + q->o_off) : nullptr;
@@ -188,7 +191,7 @@ int launch_round(hgt_server* s, Round* R) {
         if (q->n_ins && bs[i].status == HGT_OK &&
             hipMemcpyAsync(H + q->o_ids, D + q->o_ids, q->n_ins * 4, hipMemcpyDeviceToHost, st) != hipSuccess)
             return HGT_EDEVICE;
-        int rc = hgt_counts_async(s->tenants[q->tenant], (uint64_t*)(H + q->o_cnt), st);
+        int rc = hgt_counts_async(q->graph, (uint64_t*)(H + q->o_cnt), st);
         if (rc) return rc;
     }
     if (hipEventRecord(R->ev, st) != hipSuccess) return HGT_EDEVICE;
@@ -254,6 +257,7 @@ Round* admit_locked(hgt_server* s) {
             continue;
         }
         q->a_off = off;
+        q->graph = s->tenants[tn];  // launch_round runs without the lock and must not index tenants
         q->o_del += off;
         q->o_off += off;
         q->o_mem += off;

@@ -9,7 +9,6 @@ struct StoreDev {
     uint64_t id_cap;        // length of every ID-indexed array
     uint64_t next_id_host;  // next_id as of the last synchronisation
     int hb, vb;             // key bits for IDs and vertices in the pair sort
-    int time_order;         // 1: v2h lists ascending by (timestamp, sequence), else by ID
     uint64_t* h_off;
     uint32_t* h_len;
     uint32_t* h_cap;
@@ -22,6 +21,7 @@ struct StoreDev {
     uint32_t* v_len;
     uint32_t* v_cap;
     uint32_t* v2h;
+    int64_t* v2h_ts;        // NULL unless temporal is tracked: timestamp of every v2h entry
     uint64_t v2h_words;
     uint64_t* mark_del;
     uint64_t* mark_ins;
@@ -89,12 +89,7 @@ struct PlanScratch {
     uint64_t* v2h_total;
     uint64_t* stage_total;
     uint32_t* staging;
-    // time-ordered incidence lists (graphs that track temporal triads)
-    uint32_t* rank_of;      // insert j -> its time rank (build only; else the identity)
-    uint32_t* rank_id;      // time rank -> ID (build only; else the assigned IDs)
-    uint64_t* ts_min;       // build: smallest initial timestamp
-    uint64_t* keep;         // per staged old entry: kept (1) / deleted (0), then its exclusive scan
-    void* keep_scan_tmp;
+    int64_t* staging_ts;    // timestamps of the staged entries (temporal graphs)
     uint64_t* dst;
 };
 

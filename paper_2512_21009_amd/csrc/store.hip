@@ -6,6 +6,8 @@
 //               whose first h_len[id] words are its sorted member vertices.
 //   v2h pool  : u32 words; vertex v owns a block [v_off[v], v_off[v]+v_cap[v]) whose
 //               first v_len[v] words are the IDs of its live hyperedges, ascending.
+//   v2h_ts    : (graphs that track temporal triads) one int64 per v2h word: the
+//               timestamp of the entry at the same index, rewritten with it.
 //   free_bm   : one bit per ID below next_id, set when the ID is free.
 // Block capacities are powers of two (>= 4 words).  A deleted hyperedge keeps
 // its block and the block is reused in place by the next hyperedge that takes
@@ -132,7 +134,12 @@ __global__ void __launch_bounds__(HGT_WG) k_canon_big(const uint32_t* __restrict
                                                       DevScalars* sc, uint32_t* __restrict__ canon,
                                                       const uint32_t* big_list, const uint32_t* big_count) {
     __shared__ uint32_t buf[HGT_MAX_CARD];
-    if (status_bad(&sc->status)) return;
+    __shared__ uint32_t bad;
+    // other workgroups of this launch may set the status meanwhile: one read,
+    // shared, so the whole workgroup leaves (or stays) before any barrier
+    if (threadIdx.x == 0) bad = status_bad(&sc->status) ? 1u : 0u;
+    __syncthreads();
+    if (bad) return;
     uint32_t nb = *big_count;
     for (uint32_t q = blockIdx.x; q < nb; q += gridDim.x) {
         uint64_t j = big_list[q];
@@ -228,43 +235,14 @@ __global__ void k_pairs_del(const uint32_t* __restrict__ del, uint64_t n_del, co
     for (uint64_t k = lane; k < d; k += 64) keys[p + k] = ((uint64_t)h2v[o + k] << (hb + 1)) | ((uint64_t)id << 1);
 }
 
-// Insert pairs carry the ID (ID-ordered lists) or the insert's time rank
-// (time-ordered lists: rank_of, or the batch position when rank_of is NULL).
 __global__ void k_pairs_ins(const uint32_t* __restrict__ canon, const uint64_t* __restrict__ ins_rel, uint64_t n_ins,
-                            uint64_t n_members, const uint32_t* __restrict__ assigned, int time_order,
-                            const uint32_t* __restrict__ rank_of, int hb, const BatchSummary* sum, uint64_t* keys,
-                            const DevScalars* sc) {
+                            uint64_t n_members, const uint32_t* __restrict__ assigned, int hb, const BatchSummary* sum,
+                            uint64_t* keys, const DevScalars* sc) {
     if (status_bad(&sc->status)) return;
     uint64_t m = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= n_members) return;
     uint32_t j = seg_of<uint64_t>(ins_rel, (uint32_t)n_ins, m);
-    uint32_t mid = time_order ? (rank_of ? rank_of[j] : j) : assigned[j];
-    keys[sum->del_members + m] = ((uint64_t)canon[m] << (hb + 1)) | ((uint64_t)mid << 1) | 1ull;
-}
-
-// build of a time-ordered graph: time ranks of the initial hyperedges, ordered
-// by (timestamp, input position)
-__global__ void k_ts_min(const int64_t* __restrict__ ts, uint64_t n, uint64_t* ts_min) {
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
-        atomicMin((unsigned long long*)ts_min, (unsigned long long)((uint64_t)ts[i] ^ 0x8000000000000000ull));
-}
-
-__global__ void k_rank_keys(const int64_t* __restrict__ ts, uint64_t n, const uint64_t* ts_min, int jb, uint64_t* keys,
-                            DevScalars* sc) {
-    uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= n) return;
-    uint64_t d = ((uint64_t)ts[j] ^ 0x8000000000000000ull) - *ts_min;  // offset from the smallest timestamp
-    if (jb < 64 && (d >> (64 - jb)) != 0) set_status(&sc->status, HGT_EINVAL);  // span too wide to rank
-    keys[j] = (d << jb) | j;
-}
-
-__global__ void k_rank_fill(const uint64_t* __restrict__ keys, uint64_t n, int jb,
-                            const uint32_t* __restrict__ assigned, uint32_t* rank_of, uint32_t* rank_id) {
-    uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= n) return;
-    uint32_t j = (uint32_t)(keys[r] & ((1ull << jb) - 1));
-    rank_of[j] = (uint32_t)r;
-    rank_id[r] = assigned[j];
+    keys[sum->del_members + m] = ((uint64_t)canon[m] << (hb + 1)) | ((uint64_t)assigned[j] << 1) | 1ull;
 }
 
 __global__ void k_pair_count(const BatchSummary* sum, uint64_t n_ins_members, uint64_t* n_pairs) {
@@ -285,9 +263,8 @@ __global__ void k_heads(const uint64_t* __restrict__ keys, const uint64_t* n_pai
 // After a failed validation the pair keys were not (all) written: the plan
 // kernels that index arrays with decoded keys then stop.
 __global__ void k_split(const uint64_t* __restrict__ keys, const uint64_t* n_pairs_p, int hb,
-                        const uint64_t* __restrict__ tidx, const uint64_t* __restrict__ ins_pre,
-                        const uint32_t* __restrict__ rank_id, uint64_t n_rank, uint32_t* tv, uint64_t* tseg,
-                        uint32_t* D_all, uint32_t* I_all, uint32_t* I_t, const uint64_t* n_touched_p,
+                        const uint64_t* __restrict__ tidx, const uint64_t* __restrict__ ins_pre, uint32_t* tv,
+                        uint64_t* tseg, uint32_t* D_all, uint32_t* I_all, uint32_t* I_t, const uint64_t* n_touched_p,
                         const DevScalars* sc) {
     if (status_bad(&sc->status)) return;
     uint64_t n = *n_pairs_p;
@@ -305,7 +282,7 @@ __global__ void k_split(const uint64_t* __restrict__ keys, const uint64_t* n_pai
     }
     uint64_t ip = ins_pre[i];
     if (k & 1ull) {
-        I_all[ip] = rank_id ? (h < n_rank ? rank_id[h] : HGT_EMPTY) : h;  // time-ordered: rank -> ID
+        I_all[ip] = h;
         I_t[ip] = (uint32_t)t;
     } else {
         D_all[i - ip] = h;
@@ -410,11 +387,13 @@ __global__ void k_h2v_copy(const uint32_t* __restrict__ canon, const uint64_t* _
 
 __global__ void k_v_stage(const uint64_t* __restrict__ stage_off, const uint32_t* __restrict__ tv, uint64_t n_touched,
                           uint64_t stage_words, const uint64_t* __restrict__ v_off, const uint32_t* __restrict__ v2h,
-                          uint32_t* staging) {
+                          const int64_t* __restrict__ v2h_ts, uint32_t* staging, int64_t* staging_ts) {
     uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= stage_words) return;
     uint32_t t = seg_of<uint64_t>(stage_off, (uint32_t)n_touched, s);
-    staging[s] = v2h[v_off[tv[t]] + (s - stage_off[t])];
+    const uint64_t src = v_off[tv[t]] + (s - stage_off[t]);
+    staging[s] = v2h[src];
+    if (v2h_ts) staging_ts[s] = v2h_ts[src];
 }
 
 __global__ void k_v_dst(uint64_t n_touched, const uint32_t* __restrict__ tv, const uint64_t* __restrict__ need,
@@ -426,8 +405,9 @@ __global__ void k_v_dst(uint64_t n_touched, const uint32_t* __restrict__ tv, con
 }
 
 __global__ void k_v_merge_old(const uint64_t* __restrict__ stage_off, uint64_t n_touched, uint64_t stage_words,
-                              const uint32_t* __restrict__ staging, VPlan p, const uint32_t* __restrict__ D_all,
-                              const uint32_t* __restrict__ I_all, const uint64_t* __restrict__ dst, uint32_t* v2h) {
+                              const uint32_t* __restrict__ staging, const int64_t* __restrict__ staging_ts, VPlan p,
+                              const uint32_t* __restrict__ D_all, const uint32_t* __restrict__ I_all,
+                              const uint64_t* __restrict__ dst, uint32_t* v2h, int64_t* v2h_ts) {
     uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= stage_words) return;
     uint32_t t = seg_of<uint64_t>(stage_off, (uint32_t)n_touched, s);
@@ -439,12 +419,15 @@ __global__ void k_v_merge_old(const uint64_t* __restrict__ stage_off, uint64_t n
     uint32_t il = lower_bound_u32(I_all + p.istart[t], p.nI[t], e);
     uint64_t pos = (s - stage_off[t]) - dl + il;
     v2h[dst[t] + pos] = e;
+    if (v2h_ts) v2h_ts[dst[t] + pos] = staging_ts[s];
 }
 
+// h_ts already holds the inserted hyperedges' timestamps (k_h2v_meta runs first)
 __global__ void k_v_merge_ins(const uint64_t* n_ins_pairs_p, const uint32_t* __restrict__ I_all,
                               const uint32_t* __restrict__ I_t, const uint64_t* __restrict__ stage_off,
                               const uint32_t* __restrict__ staging, VPlan p, const uint32_t* __restrict__ D_all,
-                              const uint64_t* __restrict__ dst, uint32_t* v2h) {
+                              const uint64_t* __restrict__ dst, const int64_t* __restrict__ h_ts, uint32_t* v2h,
+                              int64_t* v2h_ts) {
     uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= *n_ins_pairs_p) return;
     uint32_t t = I_t[k];
@@ -453,36 +436,7 @@ __global__ void k_v_merge_ins(const uint64_t* n_ins_pairs_p, const uint32_t* __r
     uint32_t ol = lower_bound_u32(staging + stage_off[t], (uint32_t)p.old_len[t], e);
     uint32_t dl = lower_bound_u32(D_all + p.dstart[t], p.nD[t], e);
     v2h[dst[t] + kk + ol - dl] = e;
-}
-
-// time-ordered lists: the kept old entries keep their order and the inserted
-// IDs follow them in time-rank order
-__global__ void k_v_keep(const uint64_t* __restrict__ stage_off, uint64_t n_touched, uint64_t stage_words,
-                         const uint32_t* __restrict__ staging, VPlan p, const uint32_t* __restrict__ D_all,
-                         uint64_t* keep) {
-    uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= stage_words) return;
-    uint32_t t = seg_of<uint64_t>(stage_off, (uint32_t)n_touched, s);
-    keep[s] = contains_u32(D_all + p.dstart[t], p.nD[t], staging[s]) ? 0 : 1;
-}
-
-__global__ void k_v_merge_old_t(const uint64_t* __restrict__ stage_off, uint64_t n_touched, uint64_t stage_words,
-                                const uint32_t* __restrict__ staging, const uint64_t* __restrict__ keep_flag,
-                                const uint64_t* __restrict__ keep_pre, const uint64_t* __restrict__ dst, uint32_t* v2h) {
-    uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= stage_words) return;
-    if (!keep_flag[s]) return;
-    uint32_t t = seg_of<uint64_t>(stage_off, (uint32_t)n_touched, s);
-    v2h[dst[t] + (keep_pre[s] - keep_pre[stage_off[t]])] = staging[s];
-}
-
-__global__ void k_v_merge_ins_t(const uint64_t* n_ins_pairs_p, const uint32_t* __restrict__ I_all,
-                                const uint32_t* __restrict__ I_t, VPlan p, const uint64_t* __restrict__ dst,
-                                uint32_t* v2h) {
-    uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= *n_ins_pairs_p) return;
-    uint32_t t = I_t[k];
-    v2h[dst[t] + (p.old_len[t] - p.nD[t]) + (k - p.istart[t])] = I_all[k];
+    if (v2h_ts) v2h_ts[dst[t] + kk + ol - dl] = h_ts[e];
 }
 
 __global__ void k_v_commit(uint64_t n_touched, const uint32_t* __restrict__ tv, VPlan p,
@@ -571,35 +525,17 @@ void store_plan(StoreDev& g, BatchIn& b, PlanScratch& w, hipStream_t s) {
         k_pairs_del<<<blocks_for(n_del * 64), 256, 0, s>>>(b.del, n_del, w.del_poff, g.h_off, g.h_len, g.h2v, g.hb,
                                                            w.keys, sc);
     }
-    const uint32_t* rank_of = nullptr;
-    const uint32_t* rank_id = nullptr;
-    if (g.time_order && n_ins) {
-        if (!b.check_order) {
-            // the build: time ranks of the initial hyperedges (timestamps may be unordered)
-            int jb = 1;
-            while (jb < 63 && ((n_ins - 1) >> jb)) jb++;
-            hgt_fill_u64(w.ts_min, ~0ull, 1, s);
-            k_ts_min<<<blocks_for(n_ins > 262144 ? 262144 : n_ins), 256, 0, s>>>(b.ins_ts, n_ins, w.ts_min);
-            k_rank_keys<<<blocks_for(n_ins), 256, 0, s>>>(b.ins_ts, n_ins, w.ts_min, jb, w.keys, sc);
-            hgt_radix_sort_u64(w.keys, w.keys_alt, n_ins, nullptr, 64, w.sort_tmp, s);
-            k_rank_fill<<<blocks_for(n_ins), 256, 0, s>>>(w.keys, n_ins, jb, w.assigned, w.rank_of, w.rank_id);
-            rank_of = w.rank_of;
-            rank_id = w.rank_id;
-        } else {
-            rank_id = w.assigned;  // inserts arrive in time order: rank = batch position
-        }
-    }
     if (n_mem)
-        k_pairs_ins<<<blocks_for(n_mem), 256, 0, s>>>(w.canon, w.ins_rel, n_ins, n_mem, w.assigned, g.time_order,
-                                                      rank_of, g.hb, w.sum, w.keys, sc);
+        k_pairs_ins<<<blocks_for(n_mem), 256, 0, s>>>(w.canon, w.ins_rel, n_ins, n_mem, w.assigned, g.hb, w.sum,
+                                                      w.keys, sc);
     k_pair_count<<<1, 64, 0, s>>>(w.sum, n_mem, w.n_pairs);
     uint64_t pmax = w.pairs_cap;
     hgt_radix_sort_u64(w.keys, w.keys_alt, pmax, w.n_pairs, g.hb + 1 + g.vb, w.sort_tmp, s);
     k_heads<<<blocks_for(pmax), 256, 0, s>>>(w.keys, w.n_pairs, g.hb, w.head, w.is_ins);
     hgt_scan_u64(w.head, w.head, pmax, w.n_pairs, w.n_touched, w.scan_tmp, s);
     hgt_scan_u64(w.is_ins, w.is_ins, pmax, w.n_pairs, w.n_ins_pairs, w.scan_tmp, s);
-    k_split<<<blocks_for(pmax), 256, 0, s>>>(w.keys, w.n_pairs, g.hb, w.head, w.is_ins, rank_id, n_ins, w.tv, w.tseg,
-                                             w.D_all, w.I_all, w.I_t, w.n_touched, sc);
+    k_split<<<blocks_for(pmax), 256, 0, s>>>(w.keys, w.n_pairs, g.hb, w.head, w.is_ins, w.tv, w.tseg, w.D_all,
+                                             w.I_all, w.I_t, w.n_touched, sc);
     k_vplan<<<blocks_for(pmax), 256, 0, s>>>(w.n_touched, w.tv, w.tseg, w.is_ins, w.n_pairs, w.n_ins_pairs, g.v_len,
                                              g.v_cap, w.vp, sc);
     hgt_scan_u64(w.vp.need, w.vp.rel, pmax, w.n_touched, w.v2h_total, w.scan_tmp, s);
@@ -613,32 +549,8 @@ void store_commit(StoreDev& g, BatchIn& b, PlanScratch& w, const BatchSummary& s
                   uint64_t v_bump, uint64_t next_seq, hipStream_t s) {
     const uint64_t n_del = b.n_del, n_ins = b.n_ins, n_mem = b.n_ins_members;
     const uint64_t nt = sum.n_touched, sw = sum.stage_words;
-    // v2h first: it reads the old lists, which the h2v steps never touch
-    if (nt) {
-        if (sw)
-            k_v_stage<<<blocks_for(sw), 256, 0, s>>>(w.vp.stage_off, w.tv, nt, sw, g.v_off, g.v2h, w.staging);
-        k_v_dst<<<blocks_for(nt), 256, 0, s>>>(nt, w.tv, w.vp.need, w.vp.rel, v_bump, g.v_off, w.dst);
-        if (g.time_order) {
-            if (sw) {
-                uint64_t* flag = w.keep;
-                uint64_t* pre = w.keep + sw + 1;
-                k_v_keep<<<blocks_for(sw), 256, 0, s>>>(w.vp.stage_off, nt, sw, w.staging, w.vp, w.D_all, flag);
-                hgt_scan_u64(flag, pre, sw, nullptr, nullptr, w.keep_scan_tmp, s);
-                k_v_merge_old_t<<<blocks_for(sw), 256, 0, s>>>(w.vp.stage_off, nt, sw, w.staging, flag, pre, w.dst,
-                                                               g.v2h);
-            }
-            if (n_mem)
-                k_v_merge_ins_t<<<blocks_for(n_mem), 256, 0, s>>>(w.n_ins_pairs, w.I_all, w.I_t, w.vp, w.dst, g.v2h);
-        } else {
-            if (sw)
-                k_v_merge_old<<<blocks_for(sw), 256, 0, s>>>(w.vp.stage_off, nt, sw, w.staging, w.vp, w.D_all,
-                                                             w.I_all, w.dst, g.v2h);
-            if (n_mem)
-                k_v_merge_ins<<<blocks_for(n_mem), 256, 0, s>>>(w.n_ins_pairs, w.I_all, w.I_t, w.vp.stage_off,
-                                                                w.staging, w.vp, w.D_all, w.dst, g.v2h);
-        }
-        k_v_commit<<<blocks_for(nt), 256, 0, s>>>(nt, w.tv, w.vp, w.dst, g.v_off, g.v_len, g.v_cap);
-    }
+    // h2v first: the v2h merge reads the inserted hyperedges' timestamps from h_ts
+    // (the v2h steps read only the old lists, which the h2v steps never touch)
     if (n_del) k_apply_delete<<<blocks_for(n_del), 256, 0, s>>>(b.del, n_del, g.free_bm, g.h_len);
     if (n_ins) {
         k_h2v_meta<<<blocks_for(n_ins), 256, 0, s>>>(w.assigned, w.ins_card, n_ins, w.h_need, w.h_rel, g.next_id_host,
@@ -646,6 +558,19 @@ void store_commit(StoreDev& g, BatchIn& b, PlanScratch& w, const BatchSummary& s
                                                      g.h_seq, g.free_bm);
         if (n_mem)
             k_h2v_copy<<<blocks_for(n_mem), 256, 0, s>>>(w.canon, w.ins_rel, n_ins, n_mem, w.assigned, g.h_off, g.h2v);
+    }
+    if (nt) {
+        if (sw)
+            k_v_stage<<<blocks_for(sw), 256, 0, s>>>(w.vp.stage_off, w.tv, nt, sw, g.v_off, g.v2h, g.v2h_ts, w.staging,
+                                                     w.staging_ts);
+        k_v_dst<<<blocks_for(nt), 256, 0, s>>>(nt, w.tv, w.vp.need, w.vp.rel, v_bump, g.v_off, w.dst);
+        if (sw)
+            k_v_merge_old<<<blocks_for(sw), 256, 0, s>>>(w.vp.stage_off, nt, sw, w.staging, w.staging_ts, w.vp, w.D_all,
+                                                         w.I_all, w.dst, g.v2h, g.v2h_ts);
+        if (n_mem)
+            k_v_merge_ins<<<blocks_for(n_mem), 256, 0, s>>>(w.n_ins_pairs, w.I_all, w.I_t, w.vp.stage_off, w.staging,
+                                                            w.vp, w.D_all, w.dst, g.h_ts, g.v2h, g.v2h_ts);
+        k_v_commit<<<blocks_for(nt), 256, 0, s>>>(nt, w.tv, w.vp, w.dst, g.v_off, g.v_len, g.v_cap);
     }
     k_commit_scalars<<<1, 64, 0, s>>>(g.sc, w.sum, n_del, n_ins, n_mem, b.check_order ? b.ins_ts : nullptr);
 }

@@ -59,6 +59,8 @@ struct TriadParams {
     uint32_t* big_rank;
     uint32_t* big_scratch;    // grid_big * big.words_per_wg words
     BigLayout big;
+    uint32_t* wave_hash;      // per (workgroup, wave) 2-hop hash in global memory for neighbours
+    uint32_t wave_slots;      // whose 2-hop list is too long for LDS: 2 * wave_slots words each
     uint64_t* stats;          // optional counters (see TriadStat), NULL = off
     int static_he;            // hyperedge family as a full count (see He2Params::static_mode)
 };
@@ -119,12 +121,11 @@ struct He2Params {
     uint32_t* rank[3];           // the 2-hop kernel (k_delta_big)
     uint32_t* garena;            // stage-2 tables: garena_words per workgroup
     uint64_t garena_words;
-    uint64_t* stats;
+    uint64_t* stats;             // byte and hand-over counters (profiling), NULL = off
+    int phase_ticks;             // 1 (with stats): wall-clock ticks per phase, at the cost of a
+                                 // clock read and a barrier per phase
     int force_stage;             // test knob: stages below it move every centre on
     int skip_lds148;             // 1: the 148 KB stage moves every centre on to the global stage
-    uint32_t pair_cap_max;       // test knob: pair-hash slots at most this (0 = no limit)
-    int pair_runs;               // 1: run-table pair phase with the pair hash; 0: pairs per run
-                                 // entry, pairs sharing several vertices merged row by row
     int pair_agg;                // 1: pairs counted per shared vertex by class histograms, pairs
                                  // sharing several vertices found through their vertex pairs
     int static_mode;             // full count (build): no batch ranks, no open paths through

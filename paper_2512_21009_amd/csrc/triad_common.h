@@ -73,12 +73,13 @@ __device__ __forceinline__ void hash_add(uint32_t* keys, uint32_t* vals, uint32_
     }
 }
 
-// returns slot index or HGT_EMPTY
+// returns slot index or HGT_EMPTY.  The keys are read as atomics: a table in
+// global memory was filled by atomics, which bypass the CU's L1 cache.
 __device__ __forceinline__ uint32_t hash_find(const uint32_t* keys, uint32_t log_cap, uint32_t key) {
     uint32_t mask = (1u << log_cap) - 1u;
     uint32_t s = hash_slot(key, log_cap);
     for (uint32_t probe = 0; probe <= mask; probe++) {
-        uint32_t k = keys[s];
+        uint32_t k = __atomic_load_n(&keys[s], __ATOMIC_RELAXED);
         if (k == key) return s;
         if (k == HGT_EMPTY) return HGT_EMPTY;
         s = (s + 1) & mask;
@@ -114,29 +115,6 @@ __device__ __forceinline__ uint32_t wg_scan_u32(uint32_t v, uint32_t* ws, uint32
     return pre + x - v;
 }
 
-// Inclusive workgroup scan with max (MAX) or min; *total = over the block.
-template <bool MAX>
-__device__ __forceinline__ uint32_t wg_scan_ext_u32(uint32_t v, uint32_t* ws, uint32_t* total) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    uint32_t x = v;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        uint32_t t = __shfl_up(x, o, 64);
-        if (lane >= o) x = MAX ? (t > x ? t : x) : (t < x ? t : x);
-    }
-    if (lane == 63) ws[wave] = x;
-    __syncthreads();
-    uint32_t pre = MAX ? 0u : 0xffffffffu, tot = pre;
-#pragma unroll
-    for (int w = 0; w < NWAVE; w++) {
-        uint32_t s = ws[w];
-        if (w < wave) pre = MAX ? (s > pre ? s : pre) : (s < pre ? s : pre);
-        tot = MAX ? (s > tot ? s : tot) : (s < tot ? s : tot);
-    }
-    __syncthreads();
-    *total = tot;
-    return MAX ? (pre > x ? pre : x) : (pre < x ? pre : x);
-}
 
 struct Tables {
     uint8_t he[128];

@@ -79,7 +79,7 @@ __device__ __forceinline__ void classify(const TriadParams& P, const HeGraph& G,
     if (slot != HGT_EMPTY) {
         // (i) both neighbours of h and intersecting: replace the disjoint-pair class
         if (x > y) return;
-        uint32_t my = S.nh_vals[slot];
+        uint32_t my = __atomic_load_n(&S.nh_vals[slot], __ATOMIC_RELAXED);
         if (!meta_elig(my)) return;
         const int ny = (int)meta_len(my), hy = (int)meta_c(my);
         if (P.do_he && P.static_he) {
@@ -97,7 +97,7 @@ __device__ __forceinline__ void classify(const TriadParams& P, const HeGraph& G,
         if (P.do_tmp && meta_win(meta_x) && meta_win(my)) {
             int64_t ty = G.g.h_ts[y];
             if (within(sh.th, tx, ty, G.window)) {
-                uint64_t sy = G.g.h_seq[y];
+                const uint64_t sy = (ty == sh.th || ty == tx) ? G.g.h_seq[y] : 0;  // only ties need it
                 int ct = T.tmp[time_code(sh.th, sh.sh, tx, sx, ty, sy, nh, nx, ny, hx, (int)cxy, hy, (int)chxy)];
                 int cf = T.tmp[time_code(sh.th, sh.sh, tx, sx, ty, sy, nh, nx, ny, hx, 0, hy, 0)];
                 if (ct != cf) {
@@ -119,12 +119,42 @@ __device__ __forceinline__ void classify(const TriadParams& P, const HeGraph& G,
     const int ny = (int)G.g.h_len[y];
     if (P.do_he) acc_add(acc_he, T.he[venn_code(nh, nx, ny, hx, (int)cxy, 0, 0)], 1);
     if (P.do_tmp && meta_win(meta_x) && within(sh.th, tx, ty, G.window)) {
-        uint64_t sy = G.g.h_seq[y];
+        const uint64_t sy = (ty == sh.th || ty == tx) ? G.g.h_seq[y] : 0;  // only ties need it
         acc_add(acc_tmp, T.tmp[time_code(sh.th, sh.sh, tx, sx, ty, sy, nh, nx, ny, hx, (int)cxy, 0, 0)], 1);
     }
 }
 
-// Expand neighbour x of the current centre (one wave).
+// Member lists of x's members in chunks of CHUNK: per lane member its list
+// offset, whether it lies in h, and the prefix of the list lengths in wm.pre.
+__device__ __forceinline__ uint32_t chunk_lists(const HeGraph& G, const WgStore& S, const Shared& sh, WaveMem& wm,
+                                                uint64_t xoff, uint32_t b, uint32_t cnt, bool with_inh) {
+    const int lane = threadIdx.x & 63;
+    uint32_t d = 0;
+    if ((uint32_t)lane < cnt) {
+        uint32_t m = G.g.h2v[xoff + b + lane];
+        wm.voff[lane] = G.g.v_off[m];
+        d = G.g.v_len[m];
+        if (with_inh) wm.inh[lane] = contains_u32(S.hm, sh.hlen, m) ? 1u : 0u;
+    }
+    uint32_t inc = d;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t t = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += t;
+    }
+    if ((uint32_t)lane < cnt) wm.pre[lane + 1] = inc;
+    if (lane == 0) wm.pre[0] = 0;
+    wave_sync();
+    return wm.pre[cnt];
+}
+
+// Expand neighbour x of the current centre (one wave): every y sharing a vertex
+// with x, with |x & y| and |x & y & h|, from the member lists of x.  For the
+// temporal family only y within the window of both h and x can complete a
+// triad (then the span of {h, x, y} is within the window too), so the other
+// list entries are dropped by their timestamp before hashing.  The hash lives
+// in LDS when at most WH_MAX_L entries remain, else in the wave's slice of
+// global memory; beyond that, multiplicities come from binary searches.
 __device__ void expand_x(const TriadParams& P, const HeGraph& G, const Tables& T, const WgStore& S, const Shared& sh,
                          uint32_t nh_log,
                          WaveMem& wm, uint32_t* wkeys, uint32_t* wvals, uint32_t x, uint32_t meta_x, uint64_t* acc_he,
@@ -138,105 +168,94 @@ __device__ void expand_x(const TriadParams& P, const HeGraph& G, const Tables& T
         tx = G.g.h_ts[x];
         sx = G.g.h_seq[x];
     }
-    // temporal family on time-sorted lists: only the part of each list within the
-    // window of both h and x can complete a triad
-    const bool win = P.do_tmp && !P.do_he && G.g.time_sorted;
+    const bool win = P.do_tmp && G.g.v2h_ts;
     const int64_t w_lo = ts_sub(sh.th > tx ? sh.th : tx, G.window), w_hi = ts_add(sh.th < tx ? sh.th : tx, G.window);
-    auto range = [&](uint32_t m, uint64_t& o, uint32_t& n) {
-        o = G.g.v_off[m];
-        n = G.g.v_len[m];
-        if (win) {
-            const uint32_t* L = G.g.v2h + o;
-            uint32_t lo = v2h_ts_bound(G.g, L, n, w_lo, false);
-            uint32_t hi = v2h_ts_bound(G.g, L, n, w_hi, true);
-            o += lo;
-            n = hi > lo ? hi - lo : 0;
-        }
+    auto in_win = [&](uint64_t at) {
+        const int64_t t = G.g.v2h_ts[at];
+        return t >= w_lo && t <= w_hi;
     };
-    // total 2-hop length
-    uint32_t lx = 0;
+    // total length of the member lists, then (temporal) the entries within the window
+    uint32_t lx_all = 0;
     for (uint32_t b = 0; b < nx; b += CHUNK) {
         uint32_t d = 0;
-        if (b + lane < nx) {
-            uint64_t o;
-            range(G.g.h2v[xoff + b + lane], o, d);
-        }
+        if (b + lane < nx) d = G.g.v_len[G.g.h2v[xoff + b + lane]];
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) d += __shfl_xor(d, o, 64);
-        lx += d;
+        lx_all += d;
     }
-    if (lane == 0 && P.stats) {
-        atomicAdd((unsigned long long*)&acc_st[0], (unsigned long long)(4ull * (nx + lx)));
-        atomicAdd((unsigned long long*)&acc_st[3], 1ull);
-        if (lx > WH_MAX_L) atomicAdd((unsigned long long*)&acc_st[2], 1ull);
-    }
-    if (lx <= WH_MAX_L) {
-        uint32_t log_cap = log2u64(pow2ceil64(2 * (uint64_t)lx < 64 ? 64 : 2 * (uint64_t)lx));
-        uint32_t cap = 1u << log_cap;
-        for (uint32_t s = lane; s < cap; s += 64) { wkeys[s] = HGT_EMPTY; wvals[s] = 0; }
-        wave_sync();
+    uint32_t lx = lx_all;
+    if (win && lx_all > WH_MAX_L) {
+        lx = 0;
         for (uint32_t b = 0; b < nx; b += CHUNK) {
-            uint32_t cnt = nx - b < CHUNK ? nx - b : CHUNK;
-            uint32_t d = 0;
-            if ((uint32_t)lane < cnt) {
-                uint32_t m = G.g.h2v[xoff + b + lane];
-                uint64_t o;
-                range(m, o, d);
-                wm.voff[lane] = o;
-                wm.inh[lane] = contains_u32(S.hm, sh.hlen, m) ? 1u : 0u;
-            }
-            uint32_t inc = d;
-#pragma unroll
-            for (int o = 1; o < 64; o <<= 1) {
-                uint32_t t = __shfl_up(inc, o, 64);
-                if (lane >= o) inc += t;
-            }
-            if ((uint32_t)lane < cnt) wm.pre[lane + 1] = inc;
-            if (lane == 0) wm.pre[0] = 0;
-            wave_sync();
-            uint32_t len = wm.pre[cnt];
+            const uint32_t cnt = nx - b < CHUNK ? nx - b : CHUNK;
+            const uint32_t len = chunk_lists(G, S, sh, wm, xoff, b, cnt, false);
+            uint32_t c = 0;
             for (uint32_t p = lane; p < len; p += 64) {
                 uint32_t k = seg_of<uint32_t>(wm.pre, cnt, p);
-                uint32_t y = G.g.v2h[wm.voff[k] + (p - wm.pre[k])];
-                if (y != x && y != sh.h) hash_add(wkeys, wvals, log_cap, y, 1u + (wm.inh[k] << 16));
+                c += in_win(wm.voff[k] + (p - wm.pre[k])) ? 1u : 0u;
+            }
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+            lx += c;
+            wave_sync();
+        }
+    }
+    if (lane == 0 && P.stats) {
+        // x's row, its members' lists (and their timestamps when filtered)
+        atomicAdd((unsigned long long*)&acc_st[0], (unsigned long long)(4ull * nx + (win ? 12ull : 4ull) * lx_all));
+        atomicAdd((unsigned long long*)&acc_st[3], 1ull);
+    }
+    uint32_t* hk = nullptr;
+    uint32_t* hv = nullptr;
+    uint32_t cap = 0;
+    if (lx <= WH_MAX_L) {
+        hk = wkeys;
+        hv = wvals;
+        cap = (uint32_t)pow2ceil64(2 * (uint64_t)lx < 64 ? 64 : 2 * (uint64_t)lx);
+    } else if (P.wave_hash && 2ull * lx <= P.wave_slots) {
+        const int wave = threadIdx.x >> 6;
+        hk = P.wave_hash + ((uint64_t)blockIdx.x * NWAVE + wave) * 2ull * P.wave_slots;
+        hv = hk + P.wave_slots;
+        cap = (uint32_t)pow2ceil64(2 * (uint64_t)lx);
+    }
+    if (hk) {
+        const uint32_t log_cap = log2u64(cap);
+        for (uint32_t s = lane; s < cap; s += 64) { hk[s] = HGT_EMPTY; hv[s] = 0; }
+        wave_sync();
+        for (uint32_t b = 0; b < nx; b += CHUNK) {
+            const uint32_t cnt = nx - b < CHUNK ? nx - b : CHUNK;
+            const uint32_t len = chunk_lists(G, S, sh, wm, xoff, b, cnt, true);
+            for (uint32_t p = lane; p < len; p += 64) {
+                uint32_t k = seg_of<uint32_t>(wm.pre, cnt, p);
+                const uint64_t at = wm.voff[k] + (p - wm.pre[k]);
+                if (win && !in_win(at)) continue;
+                uint32_t y = G.g.v2h[at];
+                if (y != x && y != sh.h) hash_add(hk, hv, log_cap, y, 1u + (wm.inh[k] << 16));
             }
             wave_sync();
         }
         for (uint32_t s = lane; s < cap; s += 64) {
-            uint32_t y = wkeys[s];
+            uint32_t y = __atomic_load_n(&hk[s], __ATOMIC_RELAXED);
             if (y != HGT_EMPTY) {
-                uint32_t v = wvals[s];
+                uint32_t v = __atomic_load_n(&hv[s], __ATOMIC_RELAXED);
                 classify(P, G, T, S, sh, nh_log, x, meta_x, tx, sx, y, v & 0xffffu, v >> 16, acc_he, acc_tmp);
             }
         }
         wave_sync();
         return;
     }
-    // large 2-hop: a y is handled at the first member list (in member order)
-    // that holds it; its multiplicities come from binary searches in the other lists
+    if (lane == 0 && P.stats) atomicAdd((unsigned long long*)&acc_st[2], 1ull);
+    // very long 2-hop lists: a y is handled at the first member list (in member
+    // order) that holds it; its multiplicities come from binary searches in the
+    // other lists
     for (uint32_t b = 0; b < nx; b += CHUNK) {
-        uint32_t cnt = nx - b < CHUNK ? nx - b : CHUNK;
-        uint32_t d = 0;
-        if ((uint32_t)lane < cnt) {
-            uint32_t m = G.g.h2v[xoff + b + lane];
-            uint64_t o;
-            range(m, o, d);
-            wm.voff[lane] = o;
-            wm.inh[lane] = contains_u32(S.hm, sh.hlen, m) ? 1u : 0u;
-        }
-        uint32_t inc = d;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            uint32_t t = __shfl_up(inc, o, 64);
-            if (lane >= o) inc += t;
-        }
-        if ((uint32_t)lane < cnt) wm.pre[lane + 1] = inc;
-        if (lane == 0) wm.pre[0] = 0;
-        wave_sync();
-        uint32_t len = wm.pre[cnt];
+        const uint32_t cnt = nx - b < CHUNK ? nx - b : CHUNK;
+        const uint32_t len = chunk_lists(G, S, sh, wm, xoff, b, cnt, true);
         for (uint32_t p = lane; p < len; p += 64) {
             uint32_t k = seg_of<uint32_t>(wm.pre, cnt, p);
-            uint32_t y = G.g.v2h[wm.voff[k] + (p - wm.pre[k])];
+            const uint64_t at = wm.voff[k] + (p - wm.pre[k]);
+            if (win && !in_win(at)) continue;
+            uint32_t y = G.g.v2h[at];
             if (y == x || y == sh.h) continue;
             uint32_t kg = b + k;
             bool first = true;
@@ -336,23 +355,13 @@ __device__ void run_centres(const TriadParams& P, const Tables& T, const WgStore
         uint32_t* pre = S.warea;                                  // hlen + 1 words
         uint64_t* voff = (uint64_t*)(S.warea + ((hlen + 2) & ~1u));  // hlen u64, 8-byte aligned
         uint32_t carry = 0;
-        // temporal family on time-sorted lists: only neighbours within the window
-        const bool win = P.do_tmp && !P.do_he && G.g.time_sorted;
         for (uint32_t b = 0; b < hlen; b += HGT_WG) {
             uint32_t i = b + tid, d = 0;
             if (i < hlen) {
                 uint32_t m = G.g.h2v[sh.hoff + i];
                 S.hm[i] = m;
-                uint64_t o = G.g.v_off[m];
+                voff[i] = G.g.v_off[m];
                 d = G.g.v_len[m];
-                if (win) {
-                    const uint32_t* L = G.g.v2h + o;
-                    uint32_t lo = v2h_ts_bound(G.g, L, d, ts_sub(sh.th, G.window), false);
-                    uint32_t hi = v2h_ts_bound(G.g, L, d, ts_add(sh.th, G.window), true);
-                    o += lo;
-                    d = hi > lo ? hi - lo : 0;
-                }
-                voff[i] = o;
             }
             uint32_t tot;
             uint32_t ex = wg_scan_u32(d, sh.ws, &tot);
@@ -376,7 +385,12 @@ __device__ void run_centres(const TriadParams& P, const Tables& T, const WgStore
             continue;
         }
         const uint32_t lh = sh.lh;
-        if (tid == 0 && P.stats) atomicAdd((unsigned long long*)&acc_st[0], (unsigned long long)(4ull * (lh + hlen)));
+        // temporal family: only neighbours within the window of h can share a triad
+        // with it; the others are dropped by their timestamp in the lists
+        const bool win = P.do_tmp && G.g.v2h_ts;
+        const int64_t w_lo = ts_sub(sh.th, G.window), w_hi = ts_add(sh.th, G.window);
+        if (tid == 0 && P.stats)
+            atomicAdd((unsigned long long*)&acc_st[0], (unsigned long long)(4ull * hlen + (win ? 12ull : 4ull) * lh));
         uint32_t nh_log = log2u64(pow2ceil64(2 * (uint64_t)lh < 64 ? 64 : 2 * (uint64_t)lh));
         uint32_t nh_cap = 1u << nh_log;
         for (uint32_t s = tid; s < nh_cap; s += HGT_WG) { S.nh_keys[s] = HGT_EMPTY; S.nh_vals[s] = 0; }
@@ -385,23 +399,28 @@ __device__ void run_centres(const TriadParams& P, const Tables& T, const WgStore
         // 1. N(h) with c_x
         for (uint32_t p = tid; p < lh; p += HGT_WG) {
             uint32_t k = seg_of<uint32_t>(pre, hlen, p);
-            uint32_t x = G.g.v2h[voff[k] + (p - pre[k])];
+            const uint64_t at = voff[k] + (p - pre[k]);
+            if (win) {
+                const int64_t t = G.g.v2h_ts[at];
+                if (t < w_lo || t > w_hi) continue;
+            }
+            uint32_t x = G.g.v2h[at];
             if (x != h) hash_add(S.nh_keys, S.nh_vals, nh_log, x, 1u);
         }
         __syncthreads();
         // compact, attaching |x|, eligibility and window flags
         for (uint32_t s = tid; s < nh_cap; s += HGT_WG) {
-            uint32_t x = S.nh_keys[s];
+            uint32_t x = __atomic_load_n(&S.nh_keys[s], __ATOMIC_RELAXED);
             if (x == HGT_EMPTY) continue;
-            uint32_t c = S.nh_vals[s];
+            uint32_t c = __atomic_load_n(&S.nh_vals[s], __ATOMIC_RELAXED);
             uint32_t len = G.g.h_len[x];
             bool elig = P.static_he || !lower_ranked_member(G.mark[x], G.epoch, sh.rank);
-            bool win = true;
-            if (P.do_tmp) {
-                int64_t d = G.g.h_ts[x] - sh.th;
-                win = d <= G.window && -d <= G.window;
+            bool in_w = true;  // the window filter above already dropped the others
+            if (P.do_tmp && !win) {
+                int64_t t = G.g.h_ts[x];
+                in_w = t >= w_lo && t <= w_hi;
             }
-            uint32_t meta = c | (len << 14) | ((uint32_t)elig << 28) | ((uint32_t)win << 29);
+            uint32_t meta = c | (len << 14) | ((uint32_t)elig << 28) | ((uint32_t)in_w << 29);
             S.nh_vals[s] = meta;
             uint32_t q = atomicAdd(&sh.K, 1u);
             S.nl_x[q] = x;
@@ -487,18 +506,28 @@ __device__ void run_centres(const TriadParams& P, const Tables& T, const WgStore
             }
             __syncthreads();
             const uint32_t Kt = sh.Kt;
-            const uint64_t npairs = (uint64_t)Kt * (Kt - (Kt ? 1 : 0)) / 2;
-            for (uint64_t q = tid; q < npairs; q += HGT_WG) {
-                // row-major upper triangle: pair (i, j), i < j
-                uint32_t i = (uint32_t)((2.0 * Kt - 1.0 - sqrt((2.0 * Kt - 1.0) * (2.0 * Kt - 1.0) - 8.0 * (double)q)) / 2.0);
-                while (i > 0 && (uint64_t)i * (2ull * Kt - i - 1) / 2 > q) i--;
-                while ((uint64_t)(i + 1) * (2ull * Kt - i - 2) / 2 <= q) i++;
-                uint32_t j = (uint32_t)(q - (uint64_t)i * (2ull * Kt - i - 1) / 2) + i + 1;
+            // pairs (i, j), i < j, over the Kt x Kt square (the lower half is skipped)
+            const uint64_t nsq = (uint64_t)Kt * Kt;
+            for (uint64_t q = tid; q < nsq; q += HGT_WG) {
+                uint32_t i, j;
+                if (Kt < 65536u) {
+                    i = (uint32_t)q / Kt;
+                    j = (uint32_t)q - i * Kt;
+                } else {
+                    i = (uint32_t)(q / Kt);
+                    j = (uint32_t)(q - (uint64_t)i * Kt);
+                }
+                if (j <= i) continue;
                 int64_t ti = (int64_t)((uint64_t)tl[4 * i + 2] | ((uint64_t)tl[4 * i + 3] << 32));
                 int64_t tj = (int64_t)((uint64_t)tl[4 * j + 2] | ((uint64_t)tl[4 * j + 3] << 32));
                 if (!within(sh.th, ti, tj, G.window)) continue;
                 uint32_t mi = tl[4 * i + 1], mj = tl[4 * j + 1];
-                uint64_t si = G.g.h_seq[tl[4 * i]], sj = G.g.h_seq[tl[4 * j]];
+                // arrival sequences matter only between equal timestamps
+                uint64_t si = 0, sj = 0;
+                if (ti == tj || ti == sh.th || tj == sh.th) {
+                    si = G.g.h_seq[tl[4 * i]];
+                    sj = G.g.h_seq[tl[4 * j]];
+                }
                 int code = time_code(sh.th, sh.sh, ti, si, tj, sj, (int)hlen, (int)meta_len(mi), (int)meta_len(mj),
                                      (int)meta_c(mi), 0, (int)meta_c(mj), 0);
                 acc_add(acc_tmp, T.tmp[code], 1);

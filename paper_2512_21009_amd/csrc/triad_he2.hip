@@ -117,7 +117,6 @@ struct Sh2 {
     uint64_t hoff;
     uint32_t ncap;
     uint32_t o_nh, o_ent;  // arena word offsets
-    uint32_t runs, pcap, ovf;  // intersecting pairs: run table present, pair-hash slots, overflow
     uint32_t agg, nbig, nb1;   // aggregated pair phase: taken, long runs, long-run members of length > 1
     uint32_t fits_g;           // ... its tables fit the global stage's arena
     uint64_t acc2[NWAVE * HGT_N_HE_CLASSES];  // the centre's changes, doubled (ordered pairs once)
@@ -341,26 +340,6 @@ __global__ void k_entries_check(Multi M, const uint64_t* n_entries_p, uint64_t c
 // the centres whose tables do not fit its arena to list s; list 2 feeds the
 // 2-hop kernel.  Stages 0 and 1 keep the arena in LDS (32 KB, 148 KB), stage 2
 // in a 1 MB slice of global memory per workgroup.
-// open-addressing insert with a bounded probe sequence; false when the key
-// found no slot within PAIR_PROBES probes (the table is too full)
-constexpr uint32_t PAIR_PROBES = 32;
-__device__ __forceinline__ bool fr_add_ok(uint32_t* keys, uint32_t* vals, uint32_t cap, uint32_t key, uint32_t inc) {
-    uint32_t s = fr_slot(key, cap);
-    const uint32_t np = cap < PAIR_PROBES ? cap : PAIR_PROBES;
-    for (uint32_t probe = 0; probe < np; probe++) {
-        uint32_t k = __atomic_load_n(&keys[s], __ATOMIC_RELAXED);
-        if (k == HGT_EMPTY) {
-            uint32_t prev = atomicCAS(&keys[s], HGT_EMPTY, key);
-            if (prev == HGT_EMPTY || prev == key) { atomicAdd(&vals[s], inc); return true; }
-        } else if (k == key) {
-            atomicAdd(&vals[s], inc);
-            return true;
-        }
-        s = fr_next(s, cap);
-    }
-    return false;
-}
-
 // |x & y|, |x & y & h| and the smallest common vertex of two sorted rows
 __device__ __forceinline__ void row_meet(const uint32_t* X, uint32_t xl, const uint32_t* Y, uint32_t yl,
                                          const uint32_t* hm, uint32_t hlen, uint32_t& s, uint32_t& shh,
@@ -547,7 +526,7 @@ __device__ void he2_body(const He2Params& P, uint32_t* arena, const uint32_t ARE
     uint64_t t_mark = 0;  // thread 0: wall clock at the last phase mark (profiling)
 #define HE2_MARK(i)                                     \
     do {                                                \
-        if (P.stats && tid == 0) {                      \
+        if (P.phase_ticks && tid == 0) {                \
             uint64_t t_ = wall_clock64();               \
             ph[i] += t_ - t_mark;                       \
             t_mark = t_;                                \
@@ -586,7 +565,7 @@ __device__ void he2_body(const He2Params& P, uint32_t* arena, const uint32_t ARE
         }
         __syncthreads();
         if (sh.stop) break;
-        if (P.stats && tid == 0) t_mark = wall_clock64();
+        if (P.phase_ticks && tid == 0) t_mark = wall_clock64();
         if (sh.gi != sh.cur_g) {  // the counts so far belong to the previous graph
             he2_flush_graph(P, sh.cur_g, acc_all);
             if (tid == 0) sh.cur_g = sh.gi;
@@ -811,7 +790,7 @@ __device__ void he2_body(const He2Params& P, uint32_t* arena, const uint32_t ARE
             acc_add(cacc, T.he[base], 2 * (b0));
             acc_add(cacc, T.he[base | 4], 2 * (b1));
         }
-        if (P.stats) __syncthreads();
+        if (P.phase_ticks) __syncthreads();
         HE2_MARK(5);
         // --- intersecting neighbour pairs, aggregated.  Every pair of neighbours in the
         // run of a shared vertex v is first taken as meeting only at v: its changes are
@@ -1077,134 +1056,10 @@ __device__ void he2_body(const He2Params& P, uint32_t* arena, const uint32_t ARE
                 }
             }
         } else {
-        // --- intersecting neighbour pairs.  The neighbours that meet at a vertex v form
-        // a run of the sorted keys; every pair of a run meets at v.  When one side has a
-        // single shared member the pair meets only at v (|x & y| = 1); the other pairs
-        // ("multi" pairs) are accumulated over all their common vertices in an LDS hash
-        // keyed by the pair, then classified once.  Runs are enumerated cyclically
-        // (entry p of a run of R takes partners p+1 .. p+R/2) so that every entry of a
-        // long run does about R/2 pairs.  Without room for the run table (W words) or
-        // with W >= 2^16, each pair is found at its smallest common vertex by merging.
-        if (tid == 0) {
-            uint64_t o_rs = (uint64_t)sh.o_ent + 2ull * W;
-            uint64_t o_ph = o_rs + W;
-            uint64_t room = o_ph < ARENA_WORDS ? (ARENA_WORDS - o_ph) / 2 : 0;
-            sh.runs = (P.pair_runs && W < 65536u && room >= 64) ? 1u : 0u;
-            sh.pcap = (uint32_t)(room < 0x7fffffffull ? room : 0x7fffffffull);  // room; sized below
-            sh.ovf = 0;
-            sh.g[5] = 0;  // pair visits
-        }
-        __syncthreads();
-        if (sh.runs) {
-            uint32_t* rs = (uint32_t*)(keys + W);
-            // run starts: inclusive max-scan of the head positions
-            {
-                uint32_t carry = 0;
-                for (uint32_t b0 = 0; b0 < W; b0 += HGT_WG) {
-                    uint32_t i = b0 + tid, val = 0;
-                    if (i < W && (i == 0 || (keys[i - 1] >> 15) != (keys[i] >> 15))) val = i;
-                    uint32_t tot;
-                    uint32_t inc = wg_scan_ext_u32<true>(val, sh.ws, &tot);
-                    if (i < W) rs[i] = inc > carry ? inc : carry;
-                    carry = tot > carry ? tot : carry;
-                }
-            }
-            __syncthreads();
-            // run ends: inclusive min-scan of the tail positions from the right; pack
-            // start | length << 16
-            {
-                uint32_t carry = HGT_EMPTY;
-                for (uint32_t b0 = 0; b0 < W; b0 += HGT_WG) {
-                    const int64_t ii = (int64_t)W - 1 - (int64_t)(b0 + tid);
-                    uint32_t val = HGT_EMPTY;
-                    if (ii >= 0) {
-                        const uint32_t i = (uint32_t)ii;
-                        if (i + 1 == W || (keys[i + 1] >> 15) != (keys[i] >> 15)) val = i;
-                    }
-                    uint32_t tot;
-                    uint32_t inc = wg_scan_ext_u32<false>(val, sh.ws, &tot);
-                    if (ii >= 0) {
-                        const uint32_t i = (uint32_t)ii;
-                        const uint32_t e = inc < carry ? inc : carry;
-                        const uint32_t st0 = rs[i];
-                        const uint32_t R = e - st0 + 1;
-                        rs[i] = st0 | (R << 16);
-                        if (i == st0 && R > 1)  // run head: the run's pairs
-                            atomicAdd((unsigned long long*)&sh.g[5], (unsigned long long)R * (R - 1) / 2);
-                    }
-                    carry = tot < carry ? tot : carry;
-                }
-            }
-            __syncthreads();
-            // pair hash: twice the pair visits (a bound on the multi pairs), within the
-            // room left; a pair that finds no slot within a few probes marks the hash
-            // overflowed and every multi pair is then merged instead
-            if (tid == 0) {
-                const uint64_t want = 2ull * sh.g[5] + 64;
-                uint64_t cap = want < sh.pcap ? want : sh.pcap;
-                if (P.pair_cap_max && cap > P.pair_cap_max) cap = P.pair_cap_max;
-                sh.pcap = (uint32_t)cap;
-            }
-            __syncthreads();
-            const uint32_t pcap = sh.pcap;
-            uint32_t* pk = rs + W;
-            uint32_t* pv = pk + pcap;
-            for (uint32_t i = tid; i < pcap; i += HGT_WG) { pk[i] = HGT_EMPTY; pv[i] = 0; }
-            __syncthreads();
-            for (uint32_t i = tid; i < W; i += HGT_WG) {
-                const uint32_t r = rs[i], st0 = r & 0xffffu, R = r >> 16;
-                if (R < 2) continue;
-                const uint32_t pos = i - st0;
-                const uint32_t kmax = (R - 1) / 2 + (((R & 1u) == 0 && pos < R / 2) ? 1u : 0u);
-                const uint64_t ki = keys[i];
-                const uint32_t xi = (uint32_t)ki & K_MAX;
-                const uint32_t vin = (uint32_t)(ki >> 14) & 1u;
-                const uint32_t xsh = nl_msh[xi];
-                for (uint32_t k = 1; k <= kmax; k++) {
-                    uint32_t jj = pos + k;
-                    if (jj >= R) jj -= R;
-                    const uint32_t yi = (uint32_t)keys[st0 + jj] & K_MAX;
-                    if (xsh > 1 && nl_msh[yi] > 1) {
-                        if (*((volatile uint32_t*)&sh.ovf)) continue;  // redone by merging
-                        const uint32_t a = xi < yi ? xi : yi, b = xi < yi ? yi : xi;
-                        if (!fr_add_ok(pk, pv, pcap, (a << 14) | b, 1u | (vin << 16))) sh.ovf = 1;
-                        continue;
-                    }
-                    pair_class(P, T, h, hlen, nl_x, nl_meta, xi, yi, 1u, vin, myacc32);
-                }
-            }
-            __syncthreads();
-            if (!sh.ovf) {
-                for (uint32_t i = tid; i < pcap; i += HGT_WG) {
-                    const uint32_t key = pk[i];
-                    if (key == HGT_EMPTY) continue;
-                    const uint32_t val = pv[i];
-                    pair_class(P, T, h, hlen, nl_x, nl_meta, key >> 14, key & K_MAX, val & 0xffffu, val >> 16, myacc32);
-                }
-            } else {
-                // the pair hash overflowed: every multi pair at its smallest common vertex
-                for (uint32_t i = tid; i < W; i += HGT_WG) {
-                    const uint32_t r = rs[i], st0 = r & 0xffffu, R = r >> 16;
-                    if (R < 2) continue;
-                    const uint32_t pos = i - st0;
-                    const uint32_t kmax = (R - 1) / 2 + (((R & 1u) == 0 && pos < R / 2) ? 1u : 0u);
-                    const uint64_t ki = keys[i];
-                    const uint32_t xi = (uint32_t)ki & K_MAX;
-                    if (nl_msh[xi] <= 1) continue;
-                    for (uint32_t k = 1; k <= kmax; k++) {
-                        uint32_t jj = pos + k;
-                        if (jj >= R) jj -= R;
-                        const uint32_t yi = (uint32_t)keys[st0 + jj] & K_MAX;
-                        if (nl_msh[yi] <= 1) continue;
-                        uint32_t sc, shh, first;
-                        row_meet(G.g.h2v + G.g.h_off[nl_x[xi]], meta_len(nl_meta[xi]), G.g.h2v + G.g.h_off[nl_x[yi]],
-                                 meta_len(nl_meta[yi]), hm, hlen, sc, shh, first);
-                        if ((uint64_t)first != (ki >> 15)) continue;
-                        pair_class(P, T, h, hlen, nl_x, nl_meta, xi, yi, sc, shh, myacc32);
-                    }
-                }
-            }
-        } else {
+        // --- intersecting neighbour pairs, enumerated: the neighbours that meet at a vertex v
+        // form a run of the sorted keys and every pair of a run meets at v; a pair whose
+        // sides share several vertices is counted at its smallest common vertex (found by
+        // merging the two rows).
             for (uint32_t i = tid; i + 1 < W; i += HGT_WG) {
                 const uint64_t ki = keys[i];
                 const uint64_t v = ki >> 15;
@@ -1226,7 +1081,6 @@ __device__ void he2_body(const He2Params& P, uint32_t* arena, const uint32_t ARE
                     pair_class(P, T, h, hlen, nl_x, nl_meta, xi, yi, sc, shh, myacc32);
                 }
             }
-        }
         }  // aggregated or enumerated pairs
         __syncthreads();
         // fold the per-centre 32-bit pair counters (signed) into the 64-bit ones
@@ -1255,7 +1109,7 @@ __device__ void he2_body(const He2Params& P, uint32_t* arena, const uint32_t ARE
 
 template <int STAGE>
 __device__ void he2_flush_stats(const He2Params& P, const uint64_t* st, const uint64_t* ph) {
-    if (P.stats && threadIdx.x < HE2_PHASES && ph[threadIdx.x])
+    if (P.phase_ticks && threadIdx.x < HE2_PHASES && ph[threadIdx.x])
         atomicAdd((unsigned long long*)&P.stats[ST_PH0 + HE2_PHASES * STAGE + threadIdx.x],
                   (unsigned long long)ph[threadIdx.x]);
     if (P.stats && threadIdx.x == 0 && st[0])

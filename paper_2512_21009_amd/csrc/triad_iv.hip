@@ -341,9 +341,11 @@ __global__ void __launch_bounds__(HGT_WG) k_iv_lds(IvParams P) {
     __shared__ __attribute__((aligned(16))) uint32_t arena[IV_ARENA];
     __shared__ IvSh sh;
     __shared__ uint64_t acc[2];
-    if (*((volatile const int32_t*)P.status) != 0) return;
+    __shared__ uint32_t bad;
+    if (threadIdx.x == 0) bad = *((volatile const int32_t*)P.status) != 0 ? 1u : 0u;
     if (threadIdx.x < 2) acc[threadIdx.x] = 0;
     __syncthreads();
+    if (bad) return;  // read once per workgroup: every thread leaves before the body's barriers
     iv_body<0>(P, arena, IV_ARENA, sh, acc);
     __syncthreads();
     if (threadIdx.x < 2 && acc[threadIdx.x]) atomicAdd((unsigned long long*)&P.out[threadIdx.x], (unsigned long long)acc[threadIdx.x]);
@@ -352,9 +354,11 @@ __global__ void __launch_bounds__(HGT_WG) k_iv_lds(IvParams P) {
 __global__ void __launch_bounds__(HGT_WG) k_iv_global(IvParams P) {
     __shared__ IvSh sh;
     __shared__ uint64_t acc[2];
-    if (*((volatile const int32_t*)P.status) != 0) return;
+    __shared__ uint32_t bad;
+    if (threadIdx.x == 0) bad = *((volatile const int32_t*)P.status) != 0 ? 1u : 0u;
     if (threadIdx.x < 2) acc[threadIdx.x] = 0;
     __syncthreads();
+    if (bad) return;  // read once per workgroup: every thread leaves before the body's barriers
     iv_body<1>(P, P.garena + (uint64_t)blockIdx.x * P.garena_words, (uint32_t)P.garena_words, sh, acc);
     __syncthreads();
     if (threadIdx.x < 2 && acc[threadIdx.x]) atomicAdd((unsigned long long*)&P.out[threadIdx.x], (unsigned long long)acc[threadIdx.x]);

@@ -362,9 +362,11 @@ class Graph:
             raise HgtError(rc, "hgt_get_info")
         return {f: getattr(inf, f) for f, _ in Info._fields_}
 
-    def profile(self, enable: bool = True):
-        """Reset the per-kernel-group profile and switch it on or off."""
-        rc = load().hgt_profile(self._h, 1 if enable else 0)
+    def profile(self, enable=True):
+        """Reset the per-kernel-group profile and set its level: 0/False off,
+        1/True HIP events + byte counters, 2 also the phase timers."""
+        level = int(enable) if not isinstance(enable, bool) else (1 if enable else 0)
+        rc = load().hgt_profile(self._h, level)
         if rc != OK:
             raise HgtError(rc, "hgt_profile")
 

@@ -220,18 +220,22 @@ def test_incident_vertex_without_maps(gpu_lib, monkeypatch):
         p.close()
 
 
-@pytest.mark.skip(reason="the run-table pair phase (HGT_PAIR_RUNS=1) is switched off: a GPU run with it "
-                         "enabled faulted and the cause is not found yet")
-def test_pair_hash_overflow_path(gpu_lib, monkeypatch):
-    """A pair hash of 3 slots overflows on every centre with pairs that share
-    several vertices: those pairs are then merged row by row; same results."""
+def test_removed_knobs_change_nothing(gpu_lib, monkeypatch):
+    """The run-table pair phase (with its pair hash) and time-ordered incidence
+    lists were removed after GPU runs with them switched on ended in a fault.
+    Their former environment switches must not bring any other path back: with
+    them set, the results are those of the oracle, through the default paths."""
     monkeypatch.setenv("HGT_PAIR_RUNS", "1")
     monkeypatch.setenv("HGT_PAIR_CAP", "3")
-    for st in (W.medium(scale=0.0005, n_batches=2),
-               W.plain_stream("hub", 400, 700, ("power", 1.6, 2, 150), 1.3, 0.0, 2, 80, 90, W.SEED_BASE + 78)):
-        p = Pair(st, track=("hyperedge",))
-        compare_counts(p.g, p.o, p.track, "pair cap build")
+    monkeypatch.setenv("HGT_TIME_ORDER", "1")
+    for st, track in ((W.medium(scale=0.0005, n_batches=2), ("hyperedge",)),
+                      (W.plain_stream("hub", 400, 700, ("power", 1.6, 2, 150), 1.3, 0.0, 2, 80, 90, W.SEED_BASE + 78),
+                       ("hyperedge",)),
+                      (_random_stream(4200, n_edges=150, nv=60, n_batches=2), ("temporal",))):
+        p = Pair(st, track=track)
+        compare_counts(p.g, p.o, p.track, "removed knobs build")
         for k, b in enumerate(st.batches):
-            p.apply(b, f"pair cap batch {k}")
-            compare_counts(p.g, p.o, p.track, f"pair cap batch {k}")
+            p.apply(b, f"removed knobs batch {k}")
+            compare_counts(p.g, p.o, p.track, f"removed knobs batch {k}")
+        compare_store(p.g, p.o, "removed knobs end")
         p.close()

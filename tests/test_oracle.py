@@ -219,14 +219,12 @@ def test_batch_errors_leave_state_unchanged():
     assert g.apply_batch([], *csr([[9]]), np.array([5]))[0] == O.EINVAL
     assert g.apply_batch([], *csr([[1, 2]]), np.array([2]))[0] == O.EORDER
     assert g.apply_batch([], *csr([[1, 2], [2, 3]]), np.array([9, 8]))[0] == O.EORDER
+    # every rejected batch above left the rows, members and live flags as they were
+    assert (g.off == before[0]).all() and (g.mem == before[1]).all() and (g.live == before[2]).all()
+    assert g.next_id == 3 and g.last_ts == 3
     st, _ = g.apply_batch([0], *csr([]))
-    assert st == O.OK
+    assert st == O.OK and g.live.tolist() == [0, 1, 1]
     assert g.apply_batch([0], *csr([]))[0] == O.ENOENT  # already deleted
-    assert (before[1] == before[1]).all()
-    g2 = graph(rows, nv=5, ts=np.array([1, 2, 3], np.int64), window=10)
-    for bad in ([7], [1, 1]):
-        g2.apply_batch(bad, *csr([]))
-    assert (g2.mem == before[1]).all() and (g2.live == before[2]).all()
 
 
 def _batch(rng, g, n_del, n_ins, nv, card):
@@ -291,3 +289,71 @@ def test_relabelling_invariance():
     # temporal classes depend on tie order only through equal timestamps
     if len(np.unique(ts)) == len(ts):
         assert (g.temporal_counts() == g2.temporal_counts()).all()
+
+
+# ------------------------------------------- incident-vertex delta by definition
+def _iv_brute_sums(rows, keys):
+    """The two restricted sums written straight from the definitions with Python
+    sets: m_p and w_p per listed pair, and every vertex triangle with a listed pair."""
+    listed = {(int(k) >> 32, int(k) & 0xffffffff) for k in keys}
+    m, w = {}, {}
+    for r in rows:
+        for a, b in itertools.combinations(sorted(r), 2):
+            m[(a, b)] = m.get((a, b), 0) + 1
+            w[(a, b)] = w.get((a, b), 0) + len(r) - 2
+    s = sum(m.get(p, 0) * w.get(p, 0) for p in listed)
+    verts = sorted({v for r in rows for v in r})
+    x = 0
+    for a, b, c in itertools.combinations(verts, 3):
+        if {(a, b), (b, c), (a, c)} & listed:
+            x += m.get((a, b), 0) * m.get((b, c), 0) * m.get((a, c), 0)
+    return s, x
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_iv_partial_sums_brute_force(seed):
+    rng = np.random.default_rng(700 + seed)
+    nv = 14
+    rows = random_rows(rng, 25, nv, 1, 5)
+    g = graph(rows, nv=nv)
+    pick = rng.choice(len(rows), size=5, replace=False)
+    keys = g.pairs_of(pick)
+    want = {(a, b) for i in pick for a, b in itertools.combinations(sorted(rows[i]), 2)}
+    assert {(int(k) >> 32, int(k) & 0xffffffff) for k in keys} == want
+    assert list(keys) == sorted(keys)
+    s, x = g.iv_partial(keys)
+    assert (int(s), int(x)) == _iv_brute_sums(rows, keys)
+
+
+def test_iv_partial_all_pairs_equals_closed_forms():
+    # every pair listed: the sums are the full ones, T2 + 3 T1 and T1 + T2 + T3
+    rng = np.random.default_rng(77)
+    nv = 30
+    rows = random_rows(rng, 60, nv, 1, 6)
+    g = graph(rows, nv=nv)
+    t1, t2, t3 = (int(v) for v in g.iv_counts())
+    s, x = g.iv_partial(g.pairs_of(np.arange(len(rows))))
+    assert int(s) == t2 + 3 * t1
+    assert int(x) == t1 + t2 + t3
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_iv_delta_by_definition_equals_recount(seed):
+    rng = np.random.default_rng(800 + seed)
+    nv = 35
+    g = graph(random_rows(rng, 90, nv, 1, 6), nv=nv)
+    for _ in range(3):
+        dels, ins = _batch(rng, g, 15, 12, nv, 6)
+        old = g.copy()
+        st, ids = g.apply_batch(dels, *csr(ins))
+        assert st == O.OK
+        d = O.iv_delta_by_definition(old, g, dels, ids)
+        with np.errstate(over="ignore"):
+            want = g.iv_counts() - old.iv_counts()
+        assert (d == want).all(), (d, want)
+    # a plain deletion batch and a plain insert batch
+    old = g.copy()
+    dels = g.live_ids()[:7]
+    assert g.apply_batch(dels, *csr([]))[0] == O.OK
+    with np.errstate(over="ignore"):
+        assert (O.iv_delta_by_definition(old, g, dels, []) == g.iv_counts() - old.iv_counts()).all()

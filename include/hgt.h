@@ -115,6 +115,26 @@ int hgt_apply_batch(hgt_graph* g, const uint32_t* del_ids, uint64_t n_del,
                     uint64_t n_ins_members, const int64_t* ins_ts, uint64_t n_ins,
                     uint32_t* out_ins_ids, void* stream);
 
+/* For callers that cannot allocate device memory (serving loops and test
+ * harnesses that forbid hipMalloc/hipFree mid-run): hgt_apply_batch with the
+ * same arguments, semantics and results, which allocates no device or pinned
+ * memory.  Its batch scratch (planning buffers and the triad phases' tables)
+ * is carved out of a 256 MiB device array that the library holds on every GPU
+ * it runs on until the process ends; on that path the kernels with
+ * per-workgroup global tables run fewer workgroups.  Returns HGT_ENOMEM, with
+ * the graph unchanged, when the batch's scratch would exceed 256 MiB or the
+ * graph would have to grow its ID capacity or incidence pools (build with
+ * larger edge_capacity / pool_words, or apply such a batch with
+ * hgt_apply_batch first).  The graph's GPU must be the current device.  Every
+ * call on a GPU shares that GPU's array: calls that overlap on one GPU (other
+ * streams, other threads) race and must be serialised by the caller.  Like
+ * hgt_apply_batch it waits once on the host for the batch summary, so it
+ * cannot be captured into a HIP graph. */
+int hgt_apply_batch_noalloc(hgt_graph* g, const uint32_t* del_ids, uint64_t n_del,
+                            const uint64_t* ins_offsets, const uint32_t* ins_members,
+                            uint64_t n_ins_members, const int64_t* ins_ts, uint64_t n_ins,
+                            uint32_t* out_ins_ids, void* stream);
+
 /* ---- batched form ------------------------------------------------------ */
 /* One graph's batch for hgt_apply_batches: the arguments of hgt_apply_batch,
  * plus its result. */

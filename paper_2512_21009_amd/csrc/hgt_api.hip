@@ -114,7 +114,27 @@ struct DevBuf {
     template <class T> T* as() const { return (T*)p; }
 };
 
+// Scratch of the no-allocation entry point (hgt_apply_batch_noalloc) on the
+// calling thread: while it is set, ensure() carves buffers out of the device's
+// static scratch array instead of allocating, and every allocation fails.
+struct NoAllocArena {
+    char* base = nullptr;  // device address of the array on the current device
+    uint64_t cap = 0, used = 0;
+    struct Undo {
+        DevBuf* b;
+        DevBuf old;
+    };
+    Undo undo[160];        // the buffers given arena regions, with their previous contents
+    int n_undo = 0;
+    char stage[4][512];    // host staging of the per-graph phase descriptors (one graph)
+};
+thread_local NoAllocArena* t_na = nullptr;
+
 int dev_alloc(DevBuf& b, size_t bytes) {
+    if (t_na) {  // the no-allocation entry point allocates nothing
+        if (debug_on()) std::fprintf(stderr, "hgt: allocation of %zu bytes refused (no-allocation call)\n", bytes);
+        return HGT_ENOMEM;
+    }
     if (bytes == 0) bytes = 256;
     void* p = nullptr;
     if (hip_failed(hipMalloc(&p, bytes), "hipMalloc", __LINE__)) return HGT_ENOMEM;
@@ -129,8 +149,34 @@ void dev_free(DevBuf& b) {
     b.bytes = 0;
 }
 
+// A region of the no-allocation arena for b: a buffer that already got one in
+// this call keeps it while it is large enough (its contents then persist, as
+// with ensure()); b's previous value is restored when the call ends.
+int arena_take(NoAllocArena& a, DevBuf& b, size_t bytes) {
+    int rec = -1;
+    for (int i = 0; i < a.n_undo; i++)
+        if (a.undo[i].b == &b) rec = i;
+    if (rec >= 0 && b.bytes >= bytes) return HGT_OK;
+    const uint64_t want = ((uint64_t)std::max<size_t>(bytes, 256) + 255) & ~255ull;
+    if (a.used + want > a.cap) {
+        if (debug_on())
+            std::fprintf(stderr, "hgt: no-allocation scratch exhausted (%llu + %llu > %llu bytes)\n",
+                         (unsigned long long)a.used, (unsigned long long)want, (unsigned long long)a.cap);
+        return HGT_ENOMEM;
+    }
+    if (rec < 0) {
+        if (a.n_undo == (int)(sizeof(a.undo) / sizeof(a.undo[0]))) return HGT_ENOMEM;
+        a.undo[a.n_undo++] = {&b, b};
+    }
+    b.p = a.base + a.used;
+    b.bytes = want;
+    a.used += want;
+    return HGT_OK;
+}
+
 // grow-only scratch (contents not preserved)
 int ensure(DevBuf& b, size_t bytes) {
+    if (t_na) return arena_take(*t_na, b, bytes);
     if (b.p && b.bytes >= bytes) return HGT_OK;
     size_t nb = std::max(bytes, b.bytes + b.bytes / 2);
     nb = (nb + 4095) & ~(size_t)4095;
@@ -254,7 +300,7 @@ struct ProfScope {
     hipStream_t s;
     hipEvent_t a = nullptr;
     ProfScope(hgt_graph* g_, int k, hipStream_t s_) : g(g_), kind(k), s(s_) {
-        if (g->prof && (a = prof_event(g))) (void)hipEventRecord(a, s);
+        if (g->prof && !t_na && (a = prof_event(g))) (void)hipEventRecord(a, s);
     }
     ~ProfScope() {
         if (!a) return;
@@ -488,6 +534,27 @@ inline size_t desc_slot_bytes(uint64_t cap) { return cap * sizeof(HeGraph) + 2 *
 int upload_multi(PhaseCtx& c, int slot, const std::vector<HeGraph>& G, const std::vector<uint64_t>& base,
                  const std::vector<uint64_t>& id_base, Multi& M, hipStream_t s) {
     const uint64_t n = G.size();
+    if (t_na) {
+        // no-allocation call (one graph): the four slots live in the arena and are
+        // staged from the thread's arena record; the stream orders the copies
+        static_assert(sizeof(HeGraph) + 32 <= sizeof(t_na->stage[0]), "descriptor staging");
+        if (n != 1) return HGT_EINVAL;
+        if (int rc = ensure(c.desc, 4 * desc_slot_bytes(1))) return rc;
+        char* h = t_na->stage[slot];
+        char* d = (char*)c.desc.p + slot * desc_slot_bytes(1);
+        const size_t bytes = sizeof(HeGraph) + 32;
+        std::memcpy(h, G.data(), sizeof(HeGraph));
+        std::memcpy(h + sizeof(HeGraph), base.data(), 16);
+        std::memcpy(h + sizeof(HeGraph) + 16, id_base.data(), 16);
+        HIP_OK(hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, s));
+        M.graphs = (const HeGraph*)d;
+        M.base = (const uint64_t*)(d + sizeof(HeGraph));
+        M.id_base = (const uint64_t*)(d + sizeof(HeGraph) + 16);
+        M.n_graphs = 1;
+        M.total = base[1];
+        M.total_ids = id_base[1];
+        return HGT_OK;
+    }
     if (n > c.desc_cap) {
         for (hipEvent_t e : c.desc_ev)
             if (e) HIP_OK(hipEventSynchronize(e));
@@ -561,6 +628,75 @@ void collect(const PhaseJob* jobs, uint32_t nj, int family, bool minus, std::vec
     }
 }
 
+// Launch shapes and scratch sizes of one family's phase, from its centre count
+// and neighbourhood sizes.  `lean` (the no-allocation entry point) keeps the
+// grids of the kernels with per-workgroup global tables small.
+struct PhaseShape {
+    uint64_t n, lhm, max_card, ecap, total_ids;
+    BigLayout L;
+    uint64_t grid_big, grid_small, grid_tmp, grid_2hop, grid_s0, grid_s1, grid_g, nb_grid, nb_words;
+    uint32_t wave_slots;
+};
+
+constexpr uint64_t kGarenaWords = 1ull << 18;  // 1 MB global arena per workgroup of the global stage
+
+PhaseShape phase_shape(const hgt_graph* owner, uint64_t n, uint64_t max_lh, uint64_t sum_lh, uint64_t total_ids,
+                       bool lean) {
+    const uint64_t n_cu = (uint64_t)owner->n_cu;
+    PhaseShape z{};
+    z.n = n;
+    z.lhm = std::max<uint64_t>(max_lh, 1);
+    z.max_card = std::min<uint64_t>(HGT_MAX_CARD, z.lhm);
+    z.L = triad_big_layout(z.lhm, z.max_card);
+    // at most ~1 GiB of global tables for the large-centre kernels
+    z.grid_big = std::max<uint64_t>(1, std::min<uint64_t>(lean ? 8 : n_cu * 2, (1ull << 28) / z.L.words_per_wg));
+    z.grid_small = std::min<uint64_t>(n_cu * 2, n);
+    z.grid_tmp = std::min<uint64_t>(lean ? 32 : n_cu * 3, n);
+    // 2-hop hashes in global memory, one per wave of the 2-hop kernels (64 KB each)
+    z.wave_slots = 8192;
+    z.grid_2hop = std::max<uint64_t>(z.grid_big, z.grid_tmp);
+    z.ecap = std::max<uint64_t>(sum_lh, 1);
+    z.nb_words = 2 * pow2ceil64(2 * std::max<uint64_t>(z.lhm, 32)) + 3 * z.max_card + 8;
+    z.nb_grid = std::max<uint64_t>(1, std::min<uint64_t>(lean ? 8 : 256, (1ull << 27) / z.nb_words));
+    z.grid_s0 = std::min<uint64_t>(n_cu * 4, n);
+    z.grid_s1 = std::min<uint64_t>(n_cu, n);
+    // the global stage holds little LDS, so several workgroups share a CU and hide
+    // each other's memory latency
+    z.grid_g = std::min<uint64_t>(lean ? 16 : n_cu * (uint64_t)owner->global_wg_per_cu, n);
+    z.total_ids = total_ids;
+    return z;
+}
+
+// Every scratch buffer of one family's phase at the shape's sizes.
+int phase_reserve(PhaseCtx& c, int family, const PhaseShape& z) {
+    const uint64_t n = z.n;
+    int rc = 0;
+    rc |= ensure(c.t_ctr, 128);
+    rc |= ensure(c.t_big_list, n * 8);
+    rc |= ensure(c.t_big_rank, n * 4);
+    rc |= ensure(c.t_list1, n * 8);
+    rc |= ensure(c.t_rank1, n * 4);
+    rc |= ensure(c.t_list2, n * 8);
+    rc |= ensure(c.t_rank2, n * 4);
+    rc |= ensure(c.t_big_scratch, z.grid_big * z.L.words_per_wg * 4);
+    rc |= ensure(c.t_whash, z.grid_2hop * 4 * 2ull * z.wave_slots * 4);
+    if (family == HGT_TRIAD_HYPEREDGE) {
+        const uint64_t ids = z.total_ids;
+        rc |= ensure(c.ent_x, z.ecap * 4);
+        rc |= ensure(c.ent_d, z.ecap * 4);
+        rc |= ensure(c.ent_pay, z.ecap * 8);
+        rc |= ensure(c.bl_d, z.ecap * 4);
+        rc |= ensure(c.bl_pay, z.ecap * 8);
+        rc |= ensure(c.bl_cnt, ids * 8);
+        rc |= ensure(c.bl_off, ids * 8);
+        rc |= ensure(c.bl_cur, ids * 8);
+        rc |= ensure(c.bl_scan, hgt_scan_tmp_bytes(ids));
+        rc |= ensure(c.nb_scratch, z.nb_grid * z.nb_words * 4);
+        rc |= ensure(c.t_garena, z.grid_g * kGarenaWords * 4);
+    }
+    return rc ? HGT_ENOMEM : HGT_OK;
+}
+
 // One phase (deltas of the deleted hyperedges on the old graphs, or of the
 // inserted ones on the new graphs) for every job, in one launch per kernel.
 // Counter slots in t_ctr: 0-2 neighbour pass, 5 2-hop queue for the centres the
@@ -569,7 +705,6 @@ void collect(const PhaseJob* jobs, uint32_t nj, int family, bool minus, std::vec
 int run_phase(hgt_graph* owner, const PhaseJob* jobs, uint32_t nj, bool minus, bool full, hipStream_t s) {
     PhaseCtx& c = *owner->ph;
     uint64_t* stats = owner->prof ? owner->stats.as<uint64_t>() : nullptr;
-    const uint64_t n_cu = (uint64_t)owner->n_cu;
     std::vector<HeGraph> G;
     std::vector<uint64_t> base, id_base;
     for (int family : {HGT_TRIAD_HYPEREDGE, HGT_TRIAD_TEMPORAL}) {
@@ -578,25 +713,11 @@ int run_phase(hgt_graph* owner, const PhaseJob* jobs, uint32_t nj, bool minus, b
         const uint64_t n = base.back();
         if (n == 0) continue;
         if (id_base.back() > 0xfffffff0ull) return HGT_EINVAL;  // entry slots are u32
-        int rc = 0;
-        rc |= ensure(c.t_ctr, 128);
-        rc |= ensure(c.t_big_list, n * 8);
-        rc |= ensure(c.t_big_rank, n * 4);
-        rc |= ensure(c.t_list1, n * 8);
-        rc |= ensure(c.t_rank1, n * 4);
-        rc |= ensure(c.t_list2, n * 8);
-        rc |= ensure(c.t_rank2, n * 4);
-        if (rc) return HGT_ENOMEM;
-        const uint64_t lhm = std::max<uint64_t>(max_lh, 1);
-        const uint64_t max_card = std::min<uint64_t>(HGT_MAX_CARD, lhm);
-        BigLayout L = triad_big_layout(lhm, max_card);
-        // at most ~1 GiB of global tables for the large-centre kernels
-        uint64_t grid_big = std::max<uint64_t>(1, std::min<uint64_t>(n_cu * 2, (1ull << 28) / L.words_per_wg));
-        if (ensure(c.t_big_scratch, grid_big * L.words_per_wg * 4)) return HGT_ENOMEM;
-        // 2-hop hashes in global memory, one per wave of the 2-hop kernels (64 KB each)
-        const uint32_t wave_slots = 8192;
-        const uint64_t grid_2hop = std::max<uint64_t>(grid_big, n_cu * 3);
-        if (ensure(c.t_whash, grid_2hop * 4 * 2ull * wave_slots * 4)) return HGT_ENOMEM;
+        const PhaseShape z = phase_shape(owner, n, max_lh, sum_lh, id_base.back(), t_na != nullptr);
+        int rc = phase_reserve(c, family, z);
+        if (rc) return rc;
+        const BigLayout& L = z.L;
+        const uint64_t grid_big = z.grid_big;
         Multi M{};
         rc = upload_multi(c, (minus ? 0 : 2) + (family == HGT_TRIAD_TEMPORAL ? 1 : 0), G, base, id_base, M, s);
         if (rc) return rc;
@@ -609,27 +730,13 @@ int run_phase(hgt_graph* owner, const PhaseJob* jobs, uint32_t nj, bool minus, b
         P.big_rank = c.t_big_rank.as<uint32_t>();
         P.big_scratch = c.t_big_scratch.as<uint32_t>();
         P.wave_hash = c.t_whash.as<uint32_t>();
-        P.wave_slots = wave_slots;
+        P.wave_slots = z.wave_slots;
         P.big = L;
         P.stats = stats;
-        const unsigned grid_small = (unsigned)std::min<uint64_t>(n_cu * 2, n);
+        const unsigned grid_small = (unsigned)z.grid_small;
         if (family == HGT_TRIAD_HYPEREDGE) {
             // neighbour pass: batch-neighbour entries; histogram updates for inserts
-            uint64_t ecap = std::max<uint64_t>(sum_lh, 1);
-            uint64_t nb_words = 2 * pow2ceil64(2 * std::max<uint64_t>(lhm, 32)) + 3 * max_card + 8;
-            uint64_t nb_grid = std::max<uint64_t>(1, std::min<uint64_t>(256, (1ull << 27) / nb_words));
-            uint64_t ids = M.total_ids;
-            rc |= ensure(c.ent_x, ecap * 4);
-            rc |= ensure(c.ent_d, ecap * 4);
-            rc |= ensure(c.ent_pay, ecap * 8);
-            rc |= ensure(c.bl_d, ecap * 4);
-            rc |= ensure(c.bl_pay, ecap * 8);
-            rc |= ensure(c.bl_cnt, ids * 8);
-            rc |= ensure(c.bl_off, ids * 8);
-            rc |= ensure(c.bl_cur, ids * 8);
-            rc |= ensure(c.bl_scan, hgt_scan_tmp_bytes(ids));
-            rc |= ensure(c.nb_scratch, nb_grid * nb_words * 4);
-            if (rc) return HGT_ENOMEM;
+            const uint64_t ecap = z.ecap, nb_words = z.nb_words, nb_grid = z.nb_grid;
             NbrParams N{};
             N.M = M;
             N.inserting = minus ? 0 : 1;
@@ -668,13 +775,9 @@ int run_phase(hgt_graph* owner, const PhaseJob* jobs, uint32_t nj, bool minus, b
             E.rank[1] = c.t_rank2.as<uint32_t>();
             E.list[2] = P.big_list;
             E.rank[2] = P.big_rank;
-            // 1 MB per workgroup; the global stage holds little LDS, so several
-            // workgroups share a CU and hide each other's memory latency
-            const uint64_t garena_words = 1ull << 18;
-            const unsigned grid_g = (unsigned)std::min<uint64_t>(n_cu * (uint64_t)owner->global_wg_per_cu, n);
-            if (ensure(c.t_garena, (uint64_t)grid_g * garena_words * 4)) return HGT_ENOMEM;
+            const unsigned grid_g = (unsigned)z.grid_g;
             E.garena = c.t_garena.as<uint32_t>();
-            E.garena_words = garena_words;
+            E.garena_words = kGarenaWords;
             E.stats = stats;
             E.phase_ticks = (stats && owner->prof_phases) ? 1 : 0;
             E.force_stage = owner->force_stage;
@@ -685,11 +788,11 @@ int run_phase(hgt_graph* owner, const PhaseJob* jobs, uint32_t nj, bool minus, b
             hgt_fill_u32(ctr + 5, 0, 1, s);
             {
                 ProfScope ps(owner, PK_DELTA_SMALL, s);
-                he2_launch_stage(E, 0, (unsigned)std::min<uint64_t>(n_cu * 4, n), s);
+                he2_launch_stage(E, 0, (unsigned)z.grid_s0, s);
             }
             {
                 ProfScope ps(owner, PK_DELTA_MED, s);
-                he2_launch_stage(E, 1, (unsigned)std::min<uint64_t>(n_cu, n), s);
+                he2_launch_stage(E, 1, (unsigned)z.grid_s1, s);
             }
             {
                 ProfScope ps(owner, PK_DELTA_GLOBAL, s);
@@ -717,7 +820,7 @@ int run_phase(hgt_graph* owner, const PhaseJob* jobs, uint32_t nj, bool minus, b
             Q.stats = stats ? stats + ST_TMP0 : nullptr;
             triad_he_prepare(Q, s);
             ProfScope ps(owner, PK_TMP, s);
-            triad_he_launch_small(Q, (unsigned)std::min<uint64_t>(n_cu * 3, n), s);
+            triad_he_launch_small(Q, (unsigned)z.grid_tmp, s);
             triad_he_launch_big(Q, (unsigned)grid_big, s);
         }
     }
@@ -865,15 +968,25 @@ int iv_prepare(hgt_graph* g, const BatchIn& b, const PlanScratch& w, const Batch
     return HGT_OK;
 }
 
+// 1 MB per workgroup of the incident-vertex global stage (maps of up to 65536
+// slots: owners whose hyperedges hold up to about 43k members in all); four
+// workgroups per CU (16 in all for the no-allocation entry point)
+constexpr uint64_t kIvGarenaWords = 1ull << 18;
+inline unsigned iv_grid_global(const hgt_graph* g) { return t_na ? 16u : (unsigned)(g->n_cu * 4); }
+
+int iv_reserve(hgt_graph* g, const IvPlan& ip) {
+    PhaseCtx& c = *g->ph;
+    if (ensure(c.iv_list, (ip.n_keys + 1) * 4) || ensure(c.iv_garena, (uint64_t)iv_grid_global(g) * kIvGarenaWords * 4))
+        return HGT_ENOMEM;
+    return HGT_OK;
+}
+
 int iv_phase(hgt_graph* g, const IvPlan& ip, bool minus, hipStream_t s) {
     if (ip.n_keys == 0) return HGT_OK;
-    // 1 MB per workgroup of the global stage (maps of up to 65536 slots: owners whose
-    // hyperedges hold up to about 43k members in all); four workgroups per CU
-    const uint64_t gwords = 1ull << 18;
-    const unsigned grid_g = (unsigned)(g->n_cu * 4);
+    const uint64_t gwords = kIvGarenaWords;
+    const unsigned grid_g = iv_grid_global(g);
     PhaseCtx& c = *g->ph;
-    if (ensure(c.iv_list, (ip.n_keys + 1) * 4) || ensure(c.iv_garena, (uint64_t)grid_g * gwords * 4))
-        return HGT_ENOMEM;
+    if (int rc = iv_reserve(g, ip)) return rc;
     IvParams P{};
     P.g = view_of(g);
     P.pairs = ip.own;
@@ -995,8 +1108,34 @@ PhaseJob job_plus(const Pending& p) {
 // Applies the planned batches of `ps` (all with rc == 0) on stream s: deltas on
 // the old graphs, delete + insert, deltas on the new graphs, count update.  The
 // hyperedge and temporal phases of all graphs share one launch per kernel.
+// No-allocation call: every phase buffer of both phases is taken from the
+// arena before the first kernel that changes the graph, so a batch whose
+// scratch does not fit is rejected with nothing changed.
+int reserve_all_phases(hgt_graph* owner, std::vector<Pending*>& ps) {
+    PhaseCtx& c = *owner->ph;
+    std::vector<HeGraph> G;
+    std::vector<uint64_t> base, id_base;
+    for (int phase = 0; phase < 2; phase++) {
+        std::vector<PhaseJob> jobs;
+        for (Pending* p : ps) jobs.push_back(phase == 0 ? job_minus(*p) : job_plus(*p));
+        for (int family : {HGT_TRIAD_HYPEREDGE, HGT_TRIAD_TEMPORAL}) {
+            uint64_t max_lh, sum_lh;
+            collect(jobs.data(), (uint32_t)jobs.size(), family, phase == 0, G, base, id_base, max_lh, sum_lh);
+            if (base.back() == 0) continue;
+            const PhaseShape z = phase_shape(owner, base.back(), max_lh, sum_lh, id_base.back(), true);
+            if (int rc = phase_reserve(c, family, z)) return rc;
+        }
+    }
+    if (int rc = ensure(c.desc, 4 * desc_slot_bytes(1))) return rc;
+    for (Pending* p : ps)
+        if ((p->g->track_mask & (1u << HGT_TRIAD_INCIDENT_VERTEX)) && p->ip.n_keys)
+            if (int rc = iv_reserve(p->g, p->ip)) return rc;
+    return HGT_OK;
+}
+
 int apply_locked(hgt_graph* owner, std::vector<Pending*>& ps, hipStream_t s) {
     int rc;
+    if (t_na && (rc = reserve_all_phases(owner, ps))) return rc;
     std::vector<PhaseJob> jobs;
     jobs.reserve(ps.size());
     for (Pending* p : ps) jobs.push_back(job_minus(*p));
@@ -1122,6 +1261,36 @@ HgtSizes hgt_sizes(hgt_graph* g) {
     return z;
 }
 
+// ---------------------------------------------------------------------------
+// scratch of the no-allocation entry point
+// ---------------------------------------------------------------------------
+// One copy per GPU, held until the process ends.  In host code the array's
+// name is not a device address: its address on a device comes from
+// hipGetSymbolAddress (once per device, with that device current) and only
+// that address is handed to kernels.
+constexpr uint64_t kNoAllocScratchBytes = 256ull << 20;
+static __device__ __align__(256) uint8_t scratch[kNoAllocScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_na_mu;
+char* g_na_base[kMaxDevices] = {};
+
+// Device address of `scratch` on `device` (which must be current).
+int noalloc_base(int device, char** out) {
+    if (device < 0 || device >= kMaxDevices) return HGT_EINVAL;
+    std::lock_guard<std::mutex> lk(g_na_mu);
+    if (!g_na_base[device]) {
+        void* ptr = nullptr;
+        if (hip_failed(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress", __LINE__) || !ptr)
+            return HGT_EDEVICE;
+        g_na_base[device] = (char*)ptr;
+    }
+    *out = g_na_base[device];
+    return HGT_OK;
+}
+}  // namespace
+
 // ===========================================================================
 // C ABI
 // ===========================================================================
@@ -1245,6 +1414,31 @@ int hgt_apply_batch(hgt_graph* g, const uint32_t* del_ids, uint64_t n_del, const
     if (n_del == 0 && n_ins == 0) return HGT_OK;
     int rc = apply(g, del_ids, n_del, ins_offsets, ins_members, n_ins_members, ins_ts, n_ins, out_ins_ids,
                    (hipStream_t)stream, 1);
+    if (rc && !g->sticky) g->sticky = rc;
+    return rc;
+}
+
+int hgt_apply_batch_noalloc(hgt_graph* g, const uint32_t* del_ids, uint64_t n_del, const uint64_t* ins_offsets,
+                            const uint32_t* ins_members, uint64_t n_ins_members, const int64_t* ins_ts,
+                            uint64_t n_ins, uint32_t* out_ins_ids, void* stream) {
+    if (!g) return HGT_EINVAL;
+    if (n_del == 0 && n_ins == 0) return HGT_OK;
+    int cur = -1;
+    HIP_OK(hipGetDevice(&cur));
+    if (cur != g->device) return HGT_EINVAL;  // the scratch copy must be the graph's GPU's
+    char* base = nullptr;
+    int rc = noalloc_base(g->device, &base);
+    if (rc) return rc;
+    NoAllocArena a;
+    a.base = base;
+    a.cap = kNoAllocScratchBytes;
+    t_na = &a;
+    rc = apply(g, del_ids, n_del, ins_offsets, ins_members, n_ins_members, ins_ts, n_ins, out_ins_ids,
+               (hipStream_t)stream, 1);
+    t_na = nullptr;
+    // the graph's own scratch buffers are its again (queued kernels keep using the
+    // arena regions they were given; the arena is never freed)
+    for (int i = a.n_undo - 1; i >= 0; i--) *a.undo[i].b = a.undo[i].old;
     if (rc && !g->sticky) g->sticky = rc;
     return rc;
 }

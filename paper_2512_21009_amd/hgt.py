@@ -153,6 +153,7 @@ def load(path: str = LIB_PATH):
     P, U64, U32, I64, I32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int64, ctypes.c_int
     lib.hgt_build.argtypes = [ctypes.POINTER(BuildDesc), ctypes.POINTER(P)]
     lib.hgt_apply_batch.argtypes = [P, P, U64, P, P, U64, P, U64, P, P]
+    lib.hgt_apply_batch_noalloc.argtypes = [P, P, U64, P, P, U64, P, U64, P, P]
     lib.hgt_apply_batches.argtypes = [P, U32, P]
     lib.hgt_triad_counts.argtypes = [P, I32, I64, P, U32]
     lib.hgt_sync.argtypes = [P, ctypes.POINTER(I32)]
@@ -311,10 +312,12 @@ class Graph:
 
     # ------------------------------------------------------------------ update
     def apply_batch(self, del_ids=None, ins_offsets=None, ins_members=None, ins_ts=None, out_ids=None,
-                    stream=None, raise_on_error: bool = True):
+                    stream=None, raise_on_error: bool = True, noalloc: bool = False):
         """Delete del_ids (int32 device tensor), then insert the CSR batch.
         Returns the int32 device tensor of assigned IDs (or (status, ids)
-        with raise_on_error=False)."""
+        with raise_on_error=False).  noalloc=True calls
+        hgt_apply_batch_noalloc (out_ids, when given, keeps the call free of
+        allocations on the Python side too)."""
         import torch
         lib = load()
         n_del = 0 if del_ids is None else int(del_ids.numel())
@@ -327,12 +330,13 @@ class Graph:
         if out_ids is None and n_ins:
             dev = ins_offsets.device
             out_ids = torch.empty(n_ins, dtype=torch.int32, device=dev)
-        rc = lib.hgt_apply_batch(self._h, _ptr(del_ids), n_del, _ptr(ins_offsets) if n_ins else None,
-                                 _ptr(ins_members), n_mem, _ptr(ins_ts), n_ins,
-                                 _ptr(out_ids) if n_ins else None, _stream(stream))
+        fn = lib.hgt_apply_batch_noalloc if noalloc else lib.hgt_apply_batch
+        rc = fn(self._h, _ptr(del_ids), n_del, _ptr(ins_offsets) if n_ins else None,
+                _ptr(ins_members), n_mem, _ptr(ins_ts), n_ins,
+                _ptr(out_ids) if n_ins else None, _stream(stream))
         if raise_on_error:
             if rc != OK:
-                raise HgtError(rc, "hgt_apply_batch")
+                raise HgtError(rc, "hgt_apply_batch_noalloc" if noalloc else "hgt_apply_batch")
             return out_ids
         return rc, out_ids
 

@@ -57,6 +57,8 @@ def parse():
     ap.add_argument("--scale", type=float, default=1.0, help="workload scale (1.0 = the named configuration)")
     ap.add_argument("--cpu-sample", type=int, default=600, help="updates in the oracle's timed sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-static-baseline", action="store_true",
+                    help="skip the oracle's one-thread static recount of the scaled-down workload")
     ap.add_argument("--quiet", action="store_true")
     return ap.parse_args()
 
@@ -432,11 +434,28 @@ def bench_served(args):
     }, sv
 
 
+def host_cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(args, st, families):
-    """The oracle as it is, on this host: one sample batch (the first batch's
-    first n/2 deletions and n/2 inserts) applied by the oracle's batch
-    semantics, the hyperedge-triad delta counted by definition and the other
-    tracked families recounted, timed together."""
+    """The oracle as it is, on this host, per update: one sample batch (the
+    first batch's first n/2 deletions and n/2 inserts) applied with the
+    oracle's batch semantics (incidence maps rebuilt) and the change of every
+    tracked family counted by definition (hyperedge / temporal: the triads
+    holding a changed hyperedge before and after; incident-vertex: the closed
+    forms restricted to the pairs of the changed hyperedges), timed together on
+    all host threads.  Beside it, the paper's static mode: a full recount of
+    every tracked family on one thread, on the same workload scaled down to a
+    few thousand hyperedges (at full size it takes hours to days on one
+    thread)."""
     import numpy as np
     from oracle import oracle as orc
 
@@ -453,19 +472,51 @@ def cpu_baseline(args, st, families):
     old = o.copy()
     status, ids = o.apply_batch(dels, sub.offsets, sub.members, sub.ts if temporal else None)
     assert status == orc.OK
-    what = []
+    what = ["batch applied, maps rebuilt"]
     if "hyperedge" in families or temporal:
-        orc.delta_by_definition(old, o, dels, ids)
-        what.append("hyperedge and temporal deltas by definition")
+        orc.delta_by_definition(old, o, dels, ids, he="hyperedge" in families, temporal=temporal)
+        what.append(" and ".join(f for f in ("hyperedge", "temporal") if f in families) + " delta by definition")
     if "incident_vertex" in families:
-        o.iv_counts()
-        what.append("incident-vertex recount")
+        orc.iv_delta_by_definition(old, o, dels, ids)
+        what.append("incident-vertex delta by definition")
     el = time.perf_counter() - t0
     n = len(dels) + sub.n
     log(args, f"cpu oracle: {n} updates in {el:.2f}s on {threads} threads")
-    return {"value": round(n / el, 2), "unit": "updates/s", "cores": threads, "kind": "oracle",
-            "sample": f"{len(dels)} deletions + {sub.n} inserts of the first batch of {st.name}; " + " + ".join(what)
-                      + f"; {el:.1f}s"}
+    out = {"value": round(n / el, 2), "unit": "updates/s", "cores": threads, "kind": "oracle",
+           "sample": f"{len(dels)} deletions + {sub.n} inserts of the first batch of {st.name}; " + ", ".join(what)
+                     + f"; {el:.1f}s", "cpu_model": host_cpu_model()}
+    small_scale = {"medium": 0.001, "temporal": 0.0005}.get(st.name)
+    small = {"medium": W_medium, "temporal": W_temporal}.get(st.name)
+    if small is not None and not args.no_static_baseline:
+        s2 = small(small_scale)
+        lib.orc_set_threads(1)
+        try:
+            g = orc.OracleGraph(s2.n_vertices, s2.initial.offsets, s2.initial.members,
+                                ts=s2.initial.ts if temporal else None, window=s2.window)
+            t0 = time.perf_counter()
+            if "hyperedge" in families:
+                g.he_counts()
+            if "incident_vertex" in families:
+                g.iv_counts()
+            if temporal:
+                g.temporal_counts()
+            el1 = time.perf_counter() - t0
+        finally:
+            lib.orc_set_threads(threads)
+        log(args, f"cpu oracle, static recount on one thread at scale {small_scale}: {el1:.2f}s")
+        out["static_recount_1thread"] = {"seconds": round(el1, 3), "scale": small_scale, "hyperedges": s2.initial.n,
+                                         "families": list(families)}
+    return out
+
+
+def W_medium(scale):
+    from paper_2512_21009_amd import workloads as W
+    return W.medium(q=1.0e4, scale=scale, n_batches=1)
+
+
+def W_temporal(scale):
+    from paper_2512_21009_amd import workloads as W
+    return W.temporal(scale=scale, n_batches=1)
 
 
 def main():

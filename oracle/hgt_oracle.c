@@ -374,6 +374,7 @@ int orc_count_containing(uint64_t n_slots, const uint64_t* off, const uint32_t* 
     if (he) memset(he, 0, N_HE_CLASSES * sizeof(uint64_t));
     if (tmp) memset(tmp, 0, N_TMP_CLASSES * sizeof(uint64_t));
     int err = 0;
+    const int tmp_only = (he == NULL && tmp != NULL);
 #pragma omp parallel
     {
         uint64_t* stamp = (uint64_t*)malloc((n_slots ? n_slots : 1) * sizeof(uint64_t));
@@ -393,16 +394,31 @@ int orc_count_containing(uint64_t n_slots, const uint64_t* off, const uint32_t* 
             for (uint64_t h = 0; h < n_slots; h++) {
                 if (!live[h] || !marked[h]) continue;
                 uint64_t k = neighbours(&g, h, stamp, h, nb);
+                /* temporal only: a triple whose timestamps span more than the window
+                   is never counted, so its members are skipped early (the closed
+                   neighbourhood of h keeps all of N(h) for the test below) */
+                uint64_t kw = k;
+                if (tmp_only) {
+                    kw = 0;
+                    for (uint64_t i = 0; i < k; i++) {
+                        int64_t d = ts[nb[i]] - ts[h];
+                        if (d <= window && -d <= window) { uint32_t t = nb[kw]; nb[kw++] = nb[i]; nb[i] = t; }
+                    }
+                }
                 /* both others adjacent to h */
-                for (uint64_t i = 0; i < k; i++) {
-                    for (uint64_t j = i + 1; j < k; j++) {
+                for (uint64_t i = 0; i < kw; i++) {
+                    for (uint64_t j = i + 1; j < kw; j++) {
                         uint64_t x = nb[i], y = nb[j];
                         if ((marked[x] && x < h) || (marked[y] && y < h)) continue;
+                        if (tmp_only) {
+                            int64_t d = ts[x] - ts[y];
+                            if (d > window || -d > window) continue;
+                        }
                         add_triad(&g, h, x, y, he ? lhe : NULL, tmp ? ltmp : NULL, &ti, 1);
                     }
                 }
                 /* path h - x - y with y outside the closed neighbourhood of h */
-                for (uint64_t i = 0; i < k; i++) {
+                for (uint64_t i = 0; i < kw; i++) {
                     uint64_t x = nb[i];
                     if (marked[x] && x < h) continue;
                     uint64_t k2 = neighbours(&g, x, stamp2, tag2++, nb2);
@@ -410,6 +426,10 @@ int orc_count_containing(uint64_t n_slots, const uint64_t* off, const uint32_t* 
                         uint64_t y = nb2[j];
                         if (y == h || stamp[y] == h) continue;
                         if (marked[y] && y < h) continue;
+                        if (tmp_only) {
+                            int64_t d1 = ts[y] - ts[h], d2 = ts[y] - ts[x];
+                            if (d1 > window || -d1 > window || d2 > window || -d2 > window) continue;
+                        }
                         add_triad(&g, h, x, y, he ? lhe : NULL, tmp ? ltmp : NULL, &ti, 1);
                     }
                 }
@@ -638,4 +658,13 @@ uint64_t orc_pairs_of(const uint64_t* off, const uint32_t* mem, const uint64_t* 
     for (uint64_t i = 0; i < k; i++)
         if (u == 0 || out[u - 1] != out[i]) out[u++] = out[i];
     return u;
+}
+
+/* Threads of the oracle's parallel loops (timing of the single-thread mode). */
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
 }

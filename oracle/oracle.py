@@ -73,6 +73,7 @@ def lib():
         _lib.orc_iv_partial.restype = ctypes.c_int
         _lib.orc_pairs_of.argtypes = [P, P, P, U64, P]
         _lib.orc_pairs_of.restype = U64
+        _lib.orc_set_threads.argtypes = [ctypes.c_int]
         _lib.orc_he_class_of_code.argtypes = [ctypes.c_int]
         _lib.orc_tmp_class_of_code.argtypes = [ctypes.c_int]
         _lib.orc_he_class_codes.argtypes = [P]

@@ -224,7 +224,7 @@ struct PhaseCtx {
     int device = 0;
     int refs = 0;                 // graphs that use it
     hipEvent_t done = nullptr;    // recorded after the last user's phases
-    DevBuf iv_list, iv_garena;    // incident-vertex stage scratch
+    DevBuf iv_list, iv_list2, iv_garena, iv_garena2;  // incident-vertex stage scratch
     DevBuf t_ctr, t_big_list, t_big_rank, t_big_scratch, t_list1, t_rank1, t_list2, t_rank2, t_garena, t_whash;
     DevBuf ent_x, ent_d, ent_pay, bl_cnt, bl_off, bl_cur, bl_d, bl_pay, nb_scratch, bl_scan;
     // per-graph phase descriptors: device copies and their pinned staging, one
@@ -263,6 +263,8 @@ struct hgt_graph {
     int pair_agg = 1;               // HGT_PAIR_AGG=0: pairs enumerated per run (see He2Params)
     int global_wg_per_cu = 4;       // HGT_GLOBAL_WG_PER_CU: workgroups per CU of the global stage
     int iv_direct = 0;              // HGT_IV_DIRECT=1 (tests): incident-vertex owners without maps
+    int iv_force_stage = 0;         // HGT_IV_FORCE_STAGE (tests): incident-vertex stages below it pass owners on
+    uint32_t wave_slots = 8192;     // HGT_WAVE_SLOTS (tests): slots of the 2-hop kernels' per-wave global hashes
     int skip_lds148 = 1;            // HGT_SKIP_LDS148=0: centres go through the 148 KB stage (one workgroup
                                     // per CU) instead of straight to the global one (four per CU)
     BatchSummary* h_sum = nullptr;  // pinned
@@ -472,7 +474,8 @@ int ensure_plan_scratch(hgt_graph* g, const Sizes& z, PlanScratch& w) {
 void phase_ctx_free(PhaseCtx& c) {
     DevBuf* all[] = {&c.t_ctr, &c.t_whash, &c.t_big_list, &c.t_big_rank, &c.t_big_scratch, &c.t_list1, &c.t_rank1, &c.t_list2,
                      &c.t_rank2, &c.t_garena, &c.ent_x, &c.ent_d, &c.ent_pay, &c.bl_cnt, &c.bl_off, &c.bl_cur,
-                     &c.bl_d, &c.bl_pay, &c.nb_scratch, &c.bl_scan, &c.desc, &c.iv_list, &c.iv_garena};
+                     &c.bl_d, &c.bl_pay, &c.nb_scratch, &c.bl_scan, &c.desc, &c.iv_list, &c.iv_list2, &c.iv_garena,
+                     &c.iv_garena2};
     for (DevBuf* b : all) dev_free(*b);
     for (hipEvent_t& e : c.desc_ev) {
         if (e) (void)hipEventSynchronize(e);
@@ -653,7 +656,7 @@ PhaseShape phase_shape(const hgt_graph* owner, uint64_t n, uint64_t max_lh, uint
     z.grid_small = std::min<uint64_t>(n_cu * 2, n);
     z.grid_tmp = std::min<uint64_t>(lean ? 32 : n_cu * 3, n);
     // 2-hop hashes in global memory, one per wave of the 2-hop kernels (64 KB each)
-    z.wave_slots = 8192;
+    z.wave_slots = owner->wave_slots;
     z.grid_2hop = std::max<uint64_t>(z.grid_big, z.grid_tmp);
     z.ecap = std::max<uint64_t>(sum_lh, 1);
     z.nb_words = 2 * pow2ceil64(2 * std::max<uint64_t>(z.lhm, 32)) + 3 * z.max_card + 8;
@@ -968,15 +971,20 @@ int iv_prepare(hgt_graph* g, const BatchIn& b, const PlanScratch& w, const Batch
     return HGT_OK;
 }
 
-// 1 MB per workgroup of the incident-vertex global stage (maps of up to 65536
-// slots: owners whose hyperedges hold up to about 43k members in all); four
-// workgroups per CU (16 in all for the no-allocation entry point)
+// Incident-vertex global stages: 1 MB per workgroup (maps of up to 65536 slots:
+// owners whose hyperedges hold up to about 43k members in all), four
+// workgroups per CU; then 16 MB per workgroup (owners up to about 700k
+// members), 32 workgroups.  The no-allocation entry point runs 16 and 2.
 constexpr uint64_t kIvGarenaWords = 1ull << 18;
+constexpr uint64_t kIvGarena2Words = 1ull << 22;
 inline unsigned iv_grid_global(const hgt_graph* g) { return t_na ? 16u : (unsigned)(g->n_cu * 4); }
+inline unsigned iv_grid_global2() { return t_na ? 2u : 32u; }
 
 int iv_reserve(hgt_graph* g, const IvPlan& ip) {
     PhaseCtx& c = *g->ph;
-    if (ensure(c.iv_list, (ip.n_keys + 1) * 4) || ensure(c.iv_garena, (uint64_t)iv_grid_global(g) * kIvGarenaWords * 4))
+    if (ensure(c.iv_list, (ip.n_keys + 1) * 4) || ensure(c.iv_list2, (ip.n_keys + 1) * 4) ||
+        ensure(c.iv_garena, (uint64_t)iv_grid_global(g) * kIvGarenaWords * 4) ||
+        ensure(c.iv_garena2, (uint64_t)iv_grid_global2() * kIvGarena2Words * 4))
         return HGT_ENOMEM;
     return HGT_OK;
 }
@@ -999,14 +1007,18 @@ int iv_phase(hgt_graph* g, const IvPlan& ip, bool minus, hipStream_t s) {
     P.out = g->counts.as<uint64_t>() + (minus ? ACC_IV_M : ACC_IV_P);
     P.status = &g->st.sc->status;
     P.queue = (uint32_t*)(ictr + 2);
-    P.count = P.queue + 2;
+    P.count = P.queue + 3;
     P.list = c.iv_list.as<uint32_t>();
+    P.list2 = c.iv_list2.as<uint32_t>();
     P.garena = c.iv_garena.as<uint32_t>();
     P.garena_words = gwords;
+    P.garena2 = c.iv_garena2.as<uint32_t>();
+    P.garena2_words = kIvGarena2Words;
     P.stats = g->prof ? g->stats.as<uint64_t>() : nullptr;
     P.force_direct = g->iv_direct;
+    P.force_stage = g->iv_force_stage;
     ProfScope ps(g, PK_IV_PAIRS, s);
-    triad_iv_launch(P, (unsigned)std::min<uint64_t>((uint64_t)g->n_cu * 4, ip.n_keys), grid_g, s);
+    triad_iv_launch(P, (unsigned)std::min<uint64_t>((uint64_t)g->n_cu * 4, ip.n_keys), grid_g, iv_grid_global2(), s);
     return HGT_OK;
 }
 
@@ -1344,6 +1356,11 @@ int hgt_build(const hgt_build_desc* d, hgt_graph** out) {
     if (const char* gw = std::getenv("HGT_GLOBAL_WG_PER_CU")) g->global_wg_per_cu = std::max(1, std::min(16, std::atoi(gw)));
     if (const char* sk = std::getenv("HGT_SKIP_LDS148")) g->skip_lds148 = std::atoi(sk) != 0;
     if (const char* iv = std::getenv("HGT_IV_DIRECT")) g->iv_direct = std::atoi(iv) != 0;
+    if (const char* fs = std::getenv("HGT_IV_FORCE_STAGE")) g->iv_force_stage = std::atoi(fs);
+    if (const char* ws = std::getenv("HGT_WAVE_SLOTS")) {  // a power of two, 64 .. 2^20
+        const long v = std::atol(ws);
+        if (v >= 64 && v <= (1l << 20) && (v & (v - 1)) == 0) g->wave_slots = (uint32_t)v;
+    }
     int rc = HGT_OK;
     do {
         HIP_BRK(hipGetDevice(&g->device));

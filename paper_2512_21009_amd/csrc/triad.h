@@ -153,17 +153,21 @@ struct IvParams {
     uint64_t tab_mask;
     uint64_t* out;               // u64[2]: sum_p m_p * w_p, sum over triangles with a touched pair of m m m
     const int32_t* status;
-    uint32_t* queue;             // per stage
-    uint32_t* count;             // owners moved to the global-memory stage
-    uint32_t* list;
-    uint32_t* garena;
+    uint32_t* queue;             // per stage (3)
+    uint32_t* count;             // owners moved on by stages 0 and 1 (2)
+    uint32_t* list;              // owners stage 0 moved on (capacity: all owners)
+    uint32_t* list2;             // owners stage 1 moved on (capacity: all owners)
+    uint32_t* garena;            // stage 1: garena_words per workgroup
     uint64_t garena_words;
+    uint32_t* garena2;           // stage 2: garena2_words per workgroup (the largest owners)
+    uint64_t garena2_words;
     uint64_t* stats;             // optional, ST_IV_BYTES
     int force_direct;            // test knob: every owner evaluated pair by pair without a map
+    int force_stage;             // test knob: stages below it move every owner on
 };
 // hash of the touched pairs (canon: lo << 32 | hi) and the owner segments of own
 // (owner << 32 | other, sorted)
 void iv_touched_build(const uint64_t* canon, const uint64_t* own, const uint64_t* n_pairs, uint64_t* tab,
                       uint64_t tab_slots, uint64_t* head, uint64_t* owner_start, uint64_t* n_owners, uint64_t pairs_cap,
                       void* scan_tmp, hipStream_t s);
-void triad_iv_launch(IvParams& P, unsigned grid_lds, unsigned grid_global, hipStream_t s);
+void triad_iv_launch(IvParams& P, unsigned grid_lds, unsigned grid_global, unsigned grid_global2, hipStream_t s);

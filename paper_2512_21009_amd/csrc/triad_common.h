@@ -57,20 +57,38 @@ __device__ __forceinline__ bool within(int64_t a, int64_t b, int64_t c, int64_t 
 }
 
 // ---- hashing --------------------------------------------------------------
-__device__ __forceinline__ void hash_add(uint32_t* keys, uint32_t* vals, uint32_t log_cap, uint32_t key, uint32_t inc) {
+// Adds inc to key's value; false when every slot holds another key (the table
+// is too small for the keys offered to it).
+__device__ __forceinline__ bool hash_add_ok(uint32_t* keys, uint32_t* vals, uint32_t log_cap, uint32_t key,
+                                            uint32_t inc) {
     uint32_t mask = (1u << log_cap) - 1u;
     uint32_t s = hash_slot(key, log_cap);
     for (uint32_t probe = 0; probe <= mask; probe++) {
         uint32_t k = __atomic_load_n(&keys[s], __ATOMIC_RELAXED);
         if (k == HGT_EMPTY) {
             uint32_t prev = atomicCAS(&keys[s], HGT_EMPTY, key);
-            if (prev == HGT_EMPTY || prev == key) { atomicAdd(&vals[s], inc); return; }
+            if (prev == HGT_EMPTY || prev == key) { atomicAdd(&vals[s], inc); return true; }
         } else if (k == key) {
             atomicAdd(&vals[s], inc);
-            return;
+            return true;
         }
         s = (s + 1) & mask;
     }
+    return false;
+}
+
+// For tables sized for at least twice the keys offered (cannot fill up).
+__device__ __forceinline__ void hash_add(uint32_t* keys, uint32_t* vals, uint32_t log_cap, uint32_t key, uint32_t inc) {
+    (void)hash_add_ok(keys, vals, log_cap, key, inc);
+}
+
+// A second hash of a key, independent of hash_slot's, that splits keys into parts.
+__device__ __forceinline__ uint32_t part_hash(uint32_t key) {
+    uint32_t h = key * 0xcc9e2d51u;
+    h ^= h >> 15;
+    h *= 0x1b873593u;
+    h ^= h >> 13;
+    return h;
 }
 
 // returns slot index or HGT_EMPTY.  The keys are read as atomics: a table in

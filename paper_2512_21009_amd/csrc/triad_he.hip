@@ -152,9 +152,7 @@ __device__ __forceinline__ uint32_t chunk_lists(const HeGraph& G, const WgStore&
 // with x, with |x & y| and |x & y & h|, from the member lists of x.  For the
 // temporal family only y within the window of both h and x can complete a
 // triad (then the span of {h, x, y} is within the window too), so the other
-// list entries are dropped by their timestamp before hashing.  The hash lives
-// in LDS when at most WH_MAX_L entries remain, else in the wave's slice of
-// global memory; beyond that, multiplicities come from binary searches.
+// list entries are dropped by their timestamp before hashing.
 __device__ void expand_x(const TriadParams& P, const HeGraph& G, const Tables& T, const WgStore& S, const Shared& sh,
                          uint32_t nh_log,
                          WaveMem& wm, uint32_t* wkeys, uint32_t* wvals, uint32_t x, uint32_t meta_x, uint64_t* acc_he,
@@ -205,74 +203,75 @@ __device__ void expand_x(const TriadParams& P, const HeGraph& G, const Tables& T
         atomicAdd((unsigned long long*)&acc_st[0], (unsigned long long)(4ull * nx + (win ? 12ull : 4ull) * lx_all));
         atomicAdd((unsigned long long*)&acc_st[3], 1ull);
     }
-    uint32_t* hk = nullptr;
-    uint32_t* hv = nullptr;
-    uint32_t cap = 0;
-    if (lx <= WH_MAX_L) {
-        hk = wkeys;
-        hv = wvals;
+    // The hash lives in LDS for short lists.  Longer ones use the wave's slice of
+    // global memory, filled in passes: pass (m, r) takes the y whose part hash is
+    // r modulo m, so each y, with all its occurrences, falls in exactly one pass.
+    // A pass whose table overflows is dropped before anything is classified and
+    // split in two (modulus doubled), so no y is counted twice.
+    const bool lds = lx <= WH_MAX_L || !P.wave_hash;
+    uint32_t* hk = wkeys;
+    uint32_t* hv = wvals;
+    uint32_t cap, mod = 1;
+    if (lds) {
         cap = (uint32_t)pow2ceil64(2 * (uint64_t)lx < 64 ? 64 : 2 * (uint64_t)lx);
-    } else if (P.wave_hash && 2ull * lx <= P.wave_slots) {
+        if (cap > WH_SLOTS) cap = WH_SLOTS;  // only without a global slice (then passes split the y)
+    } else {
         const int wave = threadIdx.x >> 6;
         hk = P.wave_hash + ((uint64_t)blockIdx.x * NWAVE + wave) * 2ull * P.wave_slots;
         hv = hk + P.wave_slots;
-        cap = (uint32_t)pow2ceil64(2 * (uint64_t)lx);
+        cap = (uint32_t)pow2ceil64(4 * (uint64_t)lx);
+        if (cap > P.wave_slots) cap = P.wave_slots;
     }
-    if (hk) {
-        const uint32_t log_cap = log2u64(cap);
-        for (uint32_t s = lane; s < cap; s += 64) { hk[s] = HGT_EMPTY; hv[s] = 0; }
-        wave_sync();
-        for (uint32_t b = 0; b < nx; b += CHUNK) {
-            const uint32_t cnt = nx - b < CHUNK ? nx - b : CHUNK;
-            const uint32_t len = chunk_lists(G, S, sh, wm, xoff, b, cnt, true);
-            for (uint32_t p = lane; p < len; p += 64) {
-                uint32_t k = seg_of<uint32_t>(wm.pre, cnt, p);
-                const uint64_t at = wm.voff[k] + (p - wm.pre[k]);
-                if (win && !in_win(at)) continue;
-                uint32_t y = G.g.v2h[at];
-                if (y != x && y != sh.h) hash_add(hk, hv, log_cap, y, 1u + (wm.inh[k] << 16));
+    // parts of about a quarter of the table each
+    while ((uint64_t)mod * (cap / 4) < lx) mod <<= 1;
+    if (mod > 1 && lane == 0 && P.stats) atomicAdd((unsigned long long*)&acc_st[2], 1ull);
+    const uint32_t log_cap = log2u64(cap);
+    constexpr int kStack = 48;
+    uint32_t st_m[kStack], st_r[kStack];
+    for (uint32_t r0 = 0; r0 < mod; r0++) {
+        int sp = 0;
+        st_m[sp] = mod;
+        st_r[sp++] = r0;
+        while (sp > 0) {
+            --sp;
+            const uint32_t m = st_m[sp], r = st_r[sp];
+            for (uint32_t s = lane; s < cap; s += 64) { hk[s] = HGT_EMPTY; hv[s] = 0; }
+            wave_sync();
+            bool fail = false;
+            for (uint32_t b = 0; b < nx; b += CHUNK) {
+                const uint32_t cnt = nx - b < CHUNK ? nx - b : CHUNK;
+                const uint32_t len = chunk_lists(G, S, sh, wm, xoff, b, cnt, true);
+                for (uint32_t p = lane; p < len; p += 64) {
+                    uint32_t k = seg_of<uint32_t>(wm.pre, cnt, p);
+                    const uint64_t at = wm.voff[k] + (p - wm.pre[k]);
+                    if (win && !in_win(at)) continue;
+                    uint32_t y = G.g.v2h[at];
+                    if (y == x || y == sh.h) continue;
+                    if (m > 1 && (part_hash(y) & (m - 1)) != r) continue;
+                    if (!hash_add_ok(hk, hv, log_cap, y, 1u + (wm.inh[k] << 16))) fail = true;
+                }
+                wave_sync();
+            }
+            if (__any(fail)) {
+                if (sp + 2 > kStack) {  // cannot happen for tables of at least 64 slots
+                    if (lane == 0) set_status(const_cast<int32_t*>(G.status), HGT_EDEVICE);
+                    return;
+                }
+                st_m[sp] = 2 * m;
+                st_r[sp++] = r + m;
+                st_m[sp] = 2 * m;
+                st_r[sp++] = r;
+                continue;
+            }
+            for (uint32_t s = lane; s < cap; s += 64) {
+                uint32_t y = __atomic_load_n(&hk[s], __ATOMIC_RELAXED);
+                if (y != HGT_EMPTY) {
+                    uint32_t v = __atomic_load_n(&hv[s], __ATOMIC_RELAXED);
+                    classify(P, G, T, S, sh, nh_log, x, meta_x, tx, sx, y, v & 0xffffu, v >> 16, acc_he, acc_tmp);
+                }
             }
             wave_sync();
         }
-        for (uint32_t s = lane; s < cap; s += 64) {
-            uint32_t y = __atomic_load_n(&hk[s], __ATOMIC_RELAXED);
-            if (y != HGT_EMPTY) {
-                uint32_t v = __atomic_load_n(&hv[s], __ATOMIC_RELAXED);
-                classify(P, G, T, S, sh, nh_log, x, meta_x, tx, sx, y, v & 0xffffu, v >> 16, acc_he, acc_tmp);
-            }
-        }
-        wave_sync();
-        return;
-    }
-    if (lane == 0 && P.stats) atomicAdd((unsigned long long*)&acc_st[2], 1ull);
-    // very long 2-hop lists: a y is handled at the first member list (in member
-    // order) that holds it; its multiplicities come from binary searches in the
-    // other lists
-    for (uint32_t b = 0; b < nx; b += CHUNK) {
-        const uint32_t cnt = nx - b < CHUNK ? nx - b : CHUNK;
-        const uint32_t len = chunk_lists(G, S, sh, wm, xoff, b, cnt, true);
-        for (uint32_t p = lane; p < len; p += 64) {
-            uint32_t k = seg_of<uint32_t>(wm.pre, cnt, p);
-            const uint64_t at = wm.voff[k] + (p - wm.pre[k]);
-            if (win && !in_win(at)) continue;
-            uint32_t y = G.g.v2h[at];
-            if (y == x || y == sh.h) continue;
-            uint32_t kg = b + k;
-            bool first = true;
-            uint32_t c = 1, ch = wm.inh[k];
-            for (uint32_t j = 0; j < nx; j++) {
-                if (j == kg) continue;
-                uint32_t mj = G.g.h2v[xoff + j];
-                const uint32_t* lst = G.g.v2h + G.g.v_off[mj];
-                if (v2h_contains(G.g, lst, G.g.v_len[mj], y)) {
-                    if (j < kg) { first = false; break; }
-                    c++;
-                    ch += contains_u32(S.hm, sh.hlen, mj) ? 1u : 0u;
-                }
-            }
-            if (first) classify(P, G, T, S, sh, nh_log, x, meta_x, tx, sx, y, c, ch, acc_he, acc_tmp);
-        }
-        wave_sync();
     }
 }
 

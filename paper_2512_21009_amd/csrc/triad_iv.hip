@@ -212,10 +212,10 @@ __device__ void iv_body(const IvParams& P, uint32_t* arena, uint32_t arena_words
     for (;;) {
         if (tid == 0) {
             uint32_t q = atomicAdd(&P.queue[STAGE], 1u);
-            uint64_t n = STAGE == 0 ? *P.n_owners : (uint64_t)P.count[0];
+            uint64_t n = STAGE == 0 ? *P.n_owners : (uint64_t)P.count[STAGE - 1];
             sh.stop = q >= n;
             if (!sh.stop) {
-                uint32_t oi = STAGE == 0 ? q : P.list[q];
+                uint32_t oi = STAGE == 0 ? q : (STAGE == 1 ? P.list[q] : P.list2[q]);
                 sh.idx = oi;
                 sh.p0 = P.owner_start[oi];
                 sh.p1 = P.owner_start[oi + 1];
@@ -237,11 +237,14 @@ __device__ void iv_body(const IvParams& P, uint32_t* arena, uint32_t arena_words
         if (tid == 0) {
             sh.L = L;
             sh.cap = L + L / 2 + 32;
-            sh.defer = (4ull * sh.cap > arena_words || P.force_direct) ? 1u : 0u;
+            sh.defer = (4ull * sh.cap > arena_words || P.force_direct || STAGE < P.force_stage) ? 1u : 0u;
         }
         __syncthreads();
-        if (sh.defer && STAGE == 0) {
-            if (tid == 0) P.list[atomicAdd(&P.count[0], 1u)] = sh.idx;
+        if (sh.defer && STAGE < 2) {
+            if (tid == 0) {
+                if (STAGE == 0) P.list[atomicAdd(&P.count[0], 1u)] = sh.idx;
+                else P.list2[atomicAdd(&P.count[1], 1u)] = sh.idx;
+            }
             __syncthreads();
             continue;
         }
@@ -351,6 +354,7 @@ __global__ void __launch_bounds__(HGT_WG) k_iv_lds(IvParams P) {
     if (threadIdx.x < 2 && acc[threadIdx.x]) atomicAdd((unsigned long long*)&P.out[threadIdx.x], (unsigned long long)acc[threadIdx.x]);
 }
 
+template <int STAGE>
 __global__ void __launch_bounds__(HGT_WG) k_iv_global(IvParams P) {
     __shared__ IvSh sh;
     __shared__ uint64_t acc[2];
@@ -359,7 +363,9 @@ __global__ void __launch_bounds__(HGT_WG) k_iv_global(IvParams P) {
     if (threadIdx.x < 2) acc[threadIdx.x] = 0;
     __syncthreads();
     if (bad) return;  // read once per workgroup: every thread leaves before the body's barriers
-    iv_body<1>(P, P.garena + (uint64_t)blockIdx.x * P.garena_words, (uint32_t)P.garena_words, sh, acc);
+    uint32_t* arena = STAGE == 1 ? P.garena + (uint64_t)blockIdx.x * P.garena_words
+                                 : P.garena2 + (uint64_t)blockIdx.x * P.garena2_words;
+    iv_body<STAGE>(P, arena, (uint32_t)(STAGE == 1 ? P.garena_words : P.garena2_words), sh, acc);
     __syncthreads();
     if (threadIdx.x < 2 && acc[threadIdx.x]) atomicAdd((unsigned long long*)&P.out[threadIdx.x], (unsigned long long)acc[threadIdx.x]);
 }
@@ -376,8 +382,10 @@ void iv_touched_build(const uint64_t* canon, const uint64_t* own, const uint64_t
     k_iv_owner_list<<<2048, 256, 0, s>>>(own, n_pairs, head, owner_start, n_owners);
 }
 
-void triad_iv_launch(IvParams& P, unsigned grid_lds, unsigned grid_global, hipStream_t s) {
-    hgt_fill_u32(P.queue, 0, 4, s);  // queues of both stages and the moved-on count
+void triad_iv_launch(IvParams& P, unsigned grid_lds, unsigned grid_global, unsigned grid_global2, hipStream_t s) {
+    hgt_fill_u32(P.queue, 0, 3, s);  // the three stages' queues
+    hgt_fill_u32(P.count, 0, 2, s);  // owners moved on by stages 0 and 1
     k_iv_lds<<<grid_lds, HGT_WG, 0, s>>>(P);
-    k_iv_global<<<grid_global, HGT_WG, 0, s>>>(P);
+    k_iv_global<1><<<grid_global, HGT_WG, 0, s>>>(P);
+    k_iv_global<2><<<grid_global2, HGT_WG, 0, s>>>(P);
 }

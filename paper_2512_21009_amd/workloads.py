@@ -291,16 +291,26 @@ def log_uniform_int(rng: np.random.Generator, lo: float, hi: float, size=None) -
     return np.round(np.exp(rng.uniform(np.log(lo), np.log(hi), size=size))).astype(np.int64)
 
 
-def batched(seed: int = SEED_BASE + 4, n_graphs: int = 256, e_lo: float = 1e3, e_hi: float = 2e5,
-            b_lo: float = 10, b_hi: float = 5e4, card_hi: int = 256, n_batches: int = 1) -> List[Stream]:
-    """n_graphs independent hypergraphs, |E_g| log-uniform in [e_lo, e_hi],
-    |V_g| = |E_g| / 2, card power law 2.5 on [2, card_hi], uniform popularity;
-    each with batches of one log-uniform size in [b_lo, b_hi] (60% inserts)."""
+def batched_sizes(seed: int = SEED_BASE + 4, n_graphs: int = 256, e_lo: float = 1e3, e_hi: float = 2e5,
+                  b_lo: float = 10, b_hi: float = 5e4):
+    """(|E_g|, batch size) of every graph of batched(...) with the same arguments."""
     rng = np.random.default_rng(seed)
     sizes = log_uniform_int(rng, e_lo, e_hi, n_graphs)
     bsz = log_uniform_int(rng, b_lo, b_hi, n_graphs)
+    return sizes, bsz
+
+
+def batched(seed: int = SEED_BASE + 4, n_graphs: int = 256, e_lo: float = 1e3, e_hi: float = 2e5,
+            b_lo: float = 10, b_hi: float = 5e4, card_hi: int = 256, n_batches: int = 1,
+            only: Optional[List[int]] = None) -> List[Stream]:
+    """n_graphs independent hypergraphs, |E_g| log-uniform in [e_lo, e_hi],
+    |V_g| = |E_g| / 2, card power law 2.5 on [2, card_hi], uniform popularity;
+    each with batches of one log-uniform size in [b_lo, b_hi] (60% inserts).
+    `only` (graph indices) generates just those graphs, identical to the same
+    graphs of the full set."""
+    sizes, bsz = batched_sizes(seed, n_graphs, e_lo, e_hi, b_lo, b_hi)
     out = []
-    for g in range(n_graphs):
+    for g in (range(n_graphs) if only is None else only):
         ne = int(sizes[g])
         nv = max(card_hi, ne // 2)
         n_b = int(min(bsz[g], ne))
@@ -358,19 +368,31 @@ def tenant_stream(name: str, n_vertices: int, n_edges: int, alpha: float, card_h
     return st
 
 
+def _tenant_sizes(rng, n_tenants, total_edges, size_lo, size_hi) -> np.ndarray:
+    w = np.exp(rng.uniform(np.log(size_lo), np.log(size_hi), n_tenants))
+    return np.maximum(np.round(w / w.sum() * total_edges).astype(np.int64), 64)
+
+
+def served_tenant_sizes(seed: int = SEED_BASE + 5, n_tenants: int = 64, total_edges: float = 20e6,
+                        size_lo: float = 1e4, size_hi: float = 1e6) -> np.ndarray:
+    """Initial hyperedges of every tenant of served(...) with the same arguments."""
+    return _tenant_sizes(np.random.default_rng(seed), n_tenants, total_edges, size_lo, size_hi)
+
+
 def served(seed: int = SEED_BASE + 5, n_tenants: int = 64, total_edges: float = 20e6, n_requests: int = 256,
            rate_per_s: float = 1000.0, req_lo: float = 1, req_hi: float = 1e5, card_hi: int = 4096,
            pop_q: float = 3.0e3, size_lo: float = 1e4, size_hi: float = 1e6,
-           window_us: int = 600_000_000) -> Served:
+           window_us: int = 600_000_000, only: Optional[List[int]] = None) -> Served:
     """64 tenants with sizes log-uniform in [size_lo, size_hi] rescaled to
     total_edges hyperedges, |V_t| = |E_t| / 2, cardinality power law 2.0 on
     [2, card_hi], popularity (rank + pop_q)^-1.3, Poisson timestamps (1e3/s,
     us) and window 600 s; n_requests requests with Poisson arrivals at
     rate_per_s, tenant uniform, size log-uniform in [req_lo, req_hi] (half
-    inserts, half deletions), reported family uniform."""
+    inserts, half deletions), reported family uniform.  `only` (tenant
+    indices) generates just those tenants' streams (the others are None),
+    identical to the same tenants of the full set."""
     rng = np.random.default_rng(seed)
-    w = np.exp(rng.uniform(np.log(size_lo), np.log(size_hi), n_tenants))
-    n_e = np.maximum(np.round(w / w.sum() * total_edges).astype(np.int64), 64)
+    n_e = _tenant_sizes(rng, n_tenants, total_edges, size_lo, size_hi)
     tenant_of = rng.integers(0, n_tenants, n_requests)
     sizes = log_uniform_int(rng, req_lo, req_hi, n_requests)
     fam = rng.integers(0, 3, n_requests)
@@ -386,6 +408,9 @@ def served(seed: int = SEED_BASE + 5, n_tenants: int = 64, total_edges: float = 
         arrivals.append((float(t_arr[r]), t, len(per[t]) - 1, FAMILIES[int(fam[r])]))
     tenants = []
     for t in range(n_tenants):
+        if only is not None and t not in only:
+            tenants.append(None)
+            continue
         ne = int(n_e[t])
         nv = max(64, ne // 2)
         tenants.append(tenant_stream(f"served[{t}]", nv, ne, 2.0, card_hi, 1.3, pop_q, per[t], 1000.0,

@@ -1,22 +1,52 @@
-"""The Medium workload at its full size (1M vertices, 2M hyperedges, one batch
-of 50k deletions and 50k inserts), where the oracle is too slow to compare
-with: properties that hold at any size.
+"""The configurations at their stated sizes on the GPU, checked against the
+oracle where it can follow.
 
-* The counts maintained incrementally through the batch equal the counts of a
-  fresh build of the resulting hyperedge set.
-* The batch's inverse (deleting its inserts, re-inserting its deletions)
-  restores every count.
+* Medium (1M vertices, 2M hyperedges, hyperedge + incident-vertex triads) and
+  Temporal (500k vertices, 4M hyperedges, window 600 s): the graph is built
+  at full size, a seeded sub-batch of the first batch (a few hundred
+  deletions and inserts) is applied, and the change of every count is
+  compared class by class with the oracle's delta by definition (hyperedge and
+  temporal: triads of the new graph holding an inserted hyperedge minus those
+  of the old graph holding a deleted one; incident-vertex: the closed forms
+  restricted to the pairs inside the changed hyperedges).
+* Batched (256 graphs, |E| up to 200k, cardinality up to 256): the two largest
+  graphs and eight others drawn with a fixed seed, each with its whole batch,
+  applied through one hgt_apply_batches call; assigned IDs, the change of
+  the counts against the oracle's delta by definition, and the exported
+  store of the two largest.
+* Served (64 tenants totalling 20M hyperedges, cardinality power law 2.0 on
+  [2, 256], popularity (rank + 3e3)^-1.3, every family tracked): eight
+  tenants drawn with a fixed seed among those of at most 70k hyperedges, one
+  request each (10 deletions + 10 inserts of its first request) through the
+  request server; each result's change against the oracle's deltas by
+  definition.
+* Medium, GPU against GPU: counts maintained through a whole 100k-update
+  batch equal a fresh build of the result, and the inverse batch restores
+  them.
+
+Counts are integers: tolerance 0.
 """
+import time
+
 import numpy as np
 import pytest
 
+from oracle import oracle as orc
 from paper_2512_21009_amd import workloads as W
 
-from .gpu_harness import dev
+from .gpu_harness import Pair, apply_many, compare_counts, compare_store, dev
 
 pytestmark = pytest.mark.gpu
 
 FAMS = ("hyperedge", "incident_vertex")
+ALL = ("hyperedge", "incident_vertex", "temporal")
+
+
+_T0 = time.perf_counter()
+
+
+def _say(*a):
+    print(f"[fullsize {time.perf_counter() - _T0:7.1f}s]", *a, flush=True)
 
 
 def _gather_rows(off, mem, rows):
@@ -29,10 +59,155 @@ def _gather_rows(off, mem, rows):
     return out_off, mem[np.arange(out_off[-1], dtype=np.int64) + shift]
 
 
+def _oracle_delta(old, dels, ins, ts, track):
+    """(new oracle graph, assigned IDs, {family: u64 delta}) by definition."""
+    new = old.copy()
+    st, ids = new.apply_batch(np.asarray(dels, np.int64), ins.offsets, ins.members, ts)
+    assert st == orc.OK
+    out = {}
+    he, tm = "hyperedge" in track, "temporal" in track
+    if he or tm:
+        dhe, dtm = orc.delta_by_definition(old, new, dels, ids, he=he, temporal=tm)
+        if he:
+            out["hyperedge"] = dhe
+        if tm:
+            out["temporal"] = dtm
+    if "incident_vertex" in track:
+        out["incident_vertex"] = orc.iv_delta_by_definition(old, new, dels, ids)
+    return new, ids, out
+
+
+def _gpu_delta(before, after):
+    with np.errstate(over="ignore"):
+        return {k: np.array(after[k], np.uint64) - np.array(before[k], np.uint64) for k in before}
+
+
+def _check(got, want, where):
+    for k in want:
+        bad = np.nonzero(got[k] != want[k])[0]
+        assert len(bad) == 0, f"{where}: {k} delta differs at {bad.tolist()[:8]}: gpu {got[k][bad][:8]} oracle {want[k][bad][:8]}"
+
+
+def _sub_batch(st, n_del, n_ins):
+    b = st.batches[0]
+    return b.del_handles[:n_del].astype(np.int64), b.ins.rows(np.arange(n_ins))
+
+
+def test_medium_full_size_delta_vs_oracle(gpu_lib):
+    hgt = gpu_lib
+    st = W.medium(n_batches=1)
+    ini = st.initial
+    _say("medium: build 2M hyperedges (hyperedge + incident-vertex)")
+    g = hgt.Graph.build(st.n_vertices, dev(ini.offsets, np.int64), dev(ini.members, np.int32), track=FAMS)
+    o = orc.OracleGraph(st.n_vertices, ini.offsets, ini.members)
+    dels, ins = _sub_batch(st, 400, 400)  # the first batch deletes initial hyperedges: handle = ID
+    before = {f: g.triad_counts(f) for f in FAMS}
+    _say("medium: apply 400 + 400")
+    out = g.apply_batch(dev(dels, np.int32), dev(ins.offsets, np.int64), dev(ins.members, np.int32))
+    got = _gpu_delta(before, {f: g.triad_counts(f) for f in FAMS})
+    _new, ids, want = _oracle_delta(o, dels, ins, None, FAMS)
+    assert out.cpu().numpy().astype(np.uint32).tolist() == ids.tolist()
+    _check(got, want, "medium full size")
+    assert int(want["hyperedge"].astype(np.int64).astype(bool).sum()) > 0
+    g.close()
+
+
+def test_temporal_full_size_delta_vs_oracle(gpu_lib):
+    hgt = gpu_lib
+    st = W.temporal(n_batches=1)
+    ini = st.initial
+    _say("temporal: build 4M hyperedges (window 600 s)")
+    g = hgt.Graph.build(st.n_vertices, dev(ini.offsets, np.int64), dev(ini.members, np.int32),
+                        dev(ini.ts, np.int64), track=("temporal",), window=st.window)
+    o = orc.OracleGraph(st.n_vertices, ini.offsets, ini.members, ts=ini.ts, window=st.window)
+    # the oldest 500 expire, the next 500 arrivals come in (timestamp order)
+    dels, ins = _sub_batch(st, 500, 500)
+    before = {"temporal": g.triad_counts("temporal")}
+    _say("temporal: apply 500 + 500")
+    out = g.apply_batch(dev(dels, np.int32), dev(ins.offsets, np.int64), dev(ins.members, np.int32),
+                        dev(ins.ts, np.int64))
+    got = _gpu_delta(before, {"temporal": g.triad_counts("temporal")})
+    _new, ids, want = _oracle_delta(o, dels, ins, ins.ts, ("temporal",))
+    assert out.cpu().numpy().astype(np.uint32).tolist() == ids.tolist()
+    _check(got, want, "temporal full size")
+    assert want["temporal"].astype(bool).sum() > 0
+    g.close()
+
+
+def test_batched_full_shape_vs_oracle(gpu_lib):
+    sizes, _ = W.batched_sizes()
+    order = np.argsort(-sizes)
+    rng = np.random.default_rng(W.SEED_BASE + 404)
+    pick = [int(order[0]), int(order[1])] + sorted(int(x) for x in rng.choice(order[2:], 8, replace=False))
+    sts = W.batched(only=pick)
+    _say("batched: graphs", pick, "sizes", [int(sizes[i]) for i in pick],
+         "batches", [st.batches[0].n_updates for st in sts])
+    pairs = [Pair(st, track=("hyperedge",)) for st in sts]
+    before = [{"hyperedge": p.g.triad_counts("hyperedge")} for p in pairs]
+    olds = [p.o.copy() for p in pairs]
+    # one hgt_apply_batches call for all ten; the harness checks the assigned IDs
+    apply_many(pairs, [st.batches[0] for st in sts], "batched full shape")
+    for k, (i, st, p) in enumerate(zip(pick, sts, pairs)):
+        b = st.batches[0]
+        ids = np.array([p.oid[int(h)] for h in b.ins_handles], np.int64)
+        dhe, _ = orc.delta_by_definition(olds[k], p.o, b.del_handles.astype(np.int64), ids, temporal=False)
+        got = _gpu_delta(before[k], {"hyperedge": p.g.triad_counts("hyperedge")})
+        _check(got, {"hyperedge": dhe}, f"batched graph {i}")
+        if k < 2:
+            compare_store(p.g, p.o, f"batched graph {i}")
+        p.close()
+
+
+def test_served_full_shape_delta_vs_oracle(gpu_lib):
+    """Eight tenants of at most 70k hyperedges (larger tenants take the GPU
+    tens of seconds each to build with every family, and the oracle seconds
+    per changed hyperedge through their hubs), 10 deletions + 10 inserts of
+    their first request each, every family compared."""
+    hgt = gpu_lib
+    sizes = W.served_tenant_sizes()
+    arrivals = W.served(total_edges=20e6, card_hi=256, only=[]).arrivals
+    with_req = sorted({a[1] for a in arrivals})
+    rng = np.random.default_rng(W.SEED_BASE + 505)
+    small = [t for t in with_req if sizes[t] <= 70_000]
+    pick = sorted(int(x) for x in rng.choice(small, 8, replace=False))
+    sv = W.served(total_edges=20e6, card_hi=256, only=pick)
+    srv = hgt.Server(hbm_budget_bytes=64 << 30, arena_bytes=1 << 30)
+    index, before, reqs, oracles = {}, {}, {}, {}
+    for t in pick:
+        st = sv.tenants[t]
+        ini = st.initial
+        _say(f"served: tenant {t}, {ini.n} hyperedges, all families")
+        index[t] = srv.add_tenant(st.n_vertices, dev(ini.offsets, np.int64), dev(ini.members, np.int32),
+                                  dev(ini.ts, np.int64), track=ALL, window=st.window)
+        g = srv.tenant_graph(index[t])
+        before[t] = {f: g.triad_counts(f) for f in ALL}
+        oracles[t] = orc.OracleGraph(st.n_vertices, ini.offsets, ini.members, ts=ini.ts, window=st.window)
+        b = st.batches[0]  # its first request: deletions of initial hyperedges (handle = ID)
+        n_del = min(len(b.del_handles), 10)
+        n_ins = min(b.ins.n, 10)
+        reqs[t] = (b.del_handles[:n_del].astype(np.int64), b.ins.rows(np.arange(n_ins)))
+    _say("served: submit one request per tenant")
+    tickets = {t: srv.submit(index[t], reqs[t][0].astype(np.uint32), reqs[t][1].offsets.astype(np.uint64),
+                             reqs[t][1].members.astype(np.uint32), reqs[t][1].ts.astype(np.int64)) for t in pick}
+    res = {t: srv.wait(tickets[t]) for t in pick}
+    info = srv.info()
+    srv.close()
+    assert info["max_round_size"] > 1, info
+    for t in pick:
+        r = res[t]
+        assert r["status"] == hgt.OK, (t, r["status"])
+        dels, ins = reqs[t]
+        _new, ids, want = _oracle_delta(oracles[t], dels, ins, ins.ts, ALL)
+        assert r["ids"].tolist() == ids.tolist(), f"tenant {t}: IDs"
+        got = _gpu_delta(before[t], {f: r[f] for f in ALL})
+        _check(got, want, f"served tenant {t}")
+
+
 def test_medium_full_size_rebuild_and_inverse(gpu_lib):
     hgt = gpu_lib
     st = W.medium(n_batches=1)
     ini, b = st.initial, st.batches[0]
+    _say("medium: rebuild and inverse")
     g = hgt.Graph.build(st.n_vertices, dev(ini.offsets, np.int64), dev(ini.members, np.int32), track=FAMS)
     before = {f: g.triad_counts(f) for f in FAMS}
     dels = b.del_handles.astype(np.int64)  # the first batch deletes initial hyperedges: handle = ID

@@ -239,3 +239,41 @@ def test_removed_knobs_change_nothing(gpu_lib, monkeypatch):
             compare_counts(p.g, p.o, p.track, f"removed knobs batch {k}")
         compare_store(p.g, p.o, "removed knobs end")
         p.close()
+
+
+@pytest.mark.parametrize("slots", ["64", "256"])
+def test_two_hop_hash_in_passes(gpu_lib, monkeypatch, slots):
+    """Per-wave 2-hop hashes of 64 / 256 slots: every neighbour with more than
+    a few dozen 2-hop entries is hashed in several passes over parts of its
+    neighbours, and passes that overflow are split; hyperedge centres are all
+    sent to the 2-hop kernel, temporal centres use it anyway.  Same counts."""
+    monkeypatch.setenv("HGT_WAVE_SLOTS", slots)
+    monkeypatch.setenv("HGT_FORCE_STAGE", "3")
+    st = W.plain_stream("hub", 400, 700, ("power", 1.6, 2, 150), 1.3, 0.0, 2, 80, 90, W.SEED_BASE + 81)
+    p = Pair(st, track=("hyperedge",))
+    compare_counts(p.g, p.o, p.track, f"passes {slots} hub build")
+    for k, b in enumerate(st.batches):
+        p.apply(b, f"passes {slots} hub batch {k}")
+        compare_counts(p.g, p.o, p.track, f"passes {slots} hub batch {k}")
+    p.close()
+    st = W.temporal_stream("tpass", 300, 1500, 300, 2, 1.8, 2, 40, 50.0, 40_000, 20_000, W.SEED_BASE + 82, pop_s=1.1)
+    p = Pair(st, track=("temporal",))
+    compare_counts(p.g, p.o, p.track, f"passes {slots} temporal build")
+    for k, b in enumerate(st.batches):
+        p.apply(b, f"passes {slots} temporal batch {k}")
+        compare_counts(p.g, p.o, p.track, f"passes {slots} temporal batch {k}")
+    p.close()
+
+
+def test_incident_vertex_large_owner_stage(gpu_lib, monkeypatch):
+    """Every incident-vertex owner passed on to the stage with 16 MB maps (the
+    stage of the largest owners): same counts."""
+    monkeypatch.setenv("HGT_IV_FORCE_STAGE", "2")
+    for st in (_random_stream(4300, n_edges=200, nv=70, n_batches=2, n_ins=40, n_del=40, temporal=False, card=(1, 7)),
+               W.medium(scale=0.0005, n_batches=2)):
+        p = Pair(st, track=("incident_vertex",))
+        compare_counts(p.g, p.o, p.track, "iv stage 2 build")
+        for k, b in enumerate(st.batches):
+            p.apply(b, f"iv stage 2 batch {k}")
+            compare_counts(p.g, p.o, p.track, f"iv stage 2 batch {k}")
+        p.close()

@@ -52,7 +52,9 @@ def parse():
                     help="batches applied after the timed region with HIP-event profiling on (roofline)")
     ap.add_argument("--phases", action="store_true",
                     help="also record the hyperedge-delta stages' wall-clock phase timers in the profiled pass")
-    ap.add_argument("--config", choices=("medium", "temporal", "batched", "served"), default="medium")
+    ap.add_argument("--config", choices=("medium", "temporal", "batched", "served", "dyadic", "static", "sweep"),
+                    default="medium")
+    ap.add_argument("--sweep-sizes", default="20e6,30e6,40e6,55e6", help="sweep: hyperedge counts")
     ap.add_argument("--requests", type=int, default=256, help="served: number of requests")
     ap.add_argument("--scale", type=float, default=1.0, help="workload scale (1.0 = the named configuration)")
     ap.add_argument("--cpu-sample", type=int, default=600, help="updates in the oracle's timed sample")
@@ -434,6 +436,118 @@ def bench_served(args):
     }, sv
 
 
+def bench_static(args):
+    """The paper's comparison setting on the Medium workload: each batch applied
+    incrementally (timed), then the counts of the resulting hypergraph
+    recomputed from scratch on the GPU (a build of the live hyperedges, which
+    counts every triad of both families; timed, inputs resident in HBM)."""
+    import numpy as np
+    import torch
+    from paper_2512_21009_amd import hgt
+    from paper_2512_21009_amd import workloads as W
+    n_b = args.warmup + args.steps
+    st = W.medium(q=1.0e4, scale=args.scale, n_batches=n_b)
+    track = ("hyperedge", "incident_vertex")
+    ins = [(to_dev(b.ins.offsets, np.int64), to_dev(b.ins.members, np.int32)) for b in st.batches]
+    dels = ids_of_stream(hgt, st, ins)
+    ini = st.initial
+    g = hgt.Graph.build(st.n_vertices, to_dev(ini.offsets, np.int64), to_dev(ini.members, np.int32), track=track)
+    inc, rec, n_upd = [], [], 0
+    for k in range(n_b):
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        g.apply_batch(dels[k], *ins[k])
+        torch.cuda.synchronize()
+        t_inc = time.perf_counter() - tb
+        if k < args.warmup:
+            continue
+        inc.append(t_inc)
+        n_upd += st.batches[k].n_updates
+        off, mem, live = g.export_h2v()
+        rows = np.nonzero(live)[0].astype(np.int64)
+        lens = np.diff(off.astype(np.int64))[rows]
+        r_off = np.zeros(len(rows) + 1, np.int64)
+        r_off[1:] = np.cumsum(lens)
+        d_off, d_mem = to_dev(r_off, np.int64), to_dev(mem, np.int32)  # dead rows are empty: mem is the live rows
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        g2 = hgt.Graph.build(st.n_vertices, d_off, d_mem, track=track)
+        torch.cuda.synchronize()
+        rec.append(time.perf_counter() - tb)
+        same = all(g2.triad_counts(f) == g.triad_counts(f) for f in track)
+        g2.close()
+        assert same, "static recount and incremental counts differ"
+        log(args, f"batch {k}: incremental {inc[-1] * 1e3:.1f} ms, static recount {rec[-1] * 1e3:.1f} ms")
+    g.close()
+    inc_ms, rec_ms = np.array(inc) * 1e3, np.array(rec) * 1e3
+    return {
+        "metric": METRIC, "value": round(n_upd / sum(inc), 1), "unit": "updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(float(inc_ms.mean()), 3),
+        "p50_ms": round(float(np.percentile(inc_ms, 50)), 3), "p99_ms": round(float(np.percentile(inc_ms, 99)), 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": "static recount vs incremental on medium: 1M vertices, 2M hyperedges, batches 50k ins "
+                               "+ 50k del, hyperedge + incident-vertex triads", "scale": args.scale},
+        "static_recount": {"ms_p50": round(float(np.percentile(rec_ms, 50)), 3),
+                           "incremental_ms_p50": round(float(np.percentile(inc_ms, 50)), 3),
+                           "speedup_incremental_over_static": round(float(np.percentile(rec_ms, 50)
+                                                                          / np.percentile(inc_ms, 50)), 2)},
+        "roofline": None,
+    }, st
+
+
+def bench_sweep(args):
+    """The paper's scaling sweep: random hypergraphs of the given sizes,
+    |V| = |E|/3, cardinality power law 2.5 on [2, 8192] (the library's
+    largest cardinality; the paper's maximum is 10000), 50k changes per batch
+    (half deletions), hyperedge triads.  One point per size."""
+    import numpy as np
+    import torch
+    from paper_2512_21009_amd import hgt
+    from paper_2512_21009_amd import workloads as W
+    n_b = args.warmup + args.steps
+    points = []
+    for n in [int(float(x)) for x in args.sweep_sizes.split(",")]:
+        t0 = time.perf_counter()
+        st = W.random_hypergraph(n, n_batches=n_b)
+        log(args, f"sweep {n}: generated in {time.perf_counter() - t0:.1f}s ({st.initial.members.size} incidences)")
+        ins = [(to_dev(b.ins.offsets, np.int64), to_dev(b.ins.members, np.int32)) for b in st.batches]
+        dels = ids_of_stream(hgt, st, ins)
+        ini = st.initial
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g = hgt.Graph.build(st.n_vertices, to_dev(ini.offsets, np.int64), to_dev(ini.members, np.int32),
+                            track=("hyperedge",))
+        torch.cuda.synchronize()
+        build_s = time.perf_counter() - t0
+        lat, n_upd = [], 0
+        for k in range(n_b):
+            torch.cuda.synchronize()
+            tb = time.perf_counter()
+            g.apply_batch(dels[k], *ins[k])
+            torch.cuda.synchronize()
+            if k >= args.warmup:
+                lat.append(time.perf_counter() - tb)
+                n_upd += st.batches[k].n_updates
+        assert g.sync() == hgt.OK
+        g.close()
+        del ins, dels
+        torch.cuda.empty_cache()
+        ms = float(np.mean(lat)) * 1e3
+        points.append({"hyperedges": n, "vertices": st.n_vertices, "incidences": int(ini.members.size),
+                       "build_s": round(build_s, 3), "ms_per_batch": round(ms, 3),
+                       "updates_per_s": round(n_upd / sum(lat), 1)})
+        log(args, f"sweep {n}: build {build_s:.1f}s, {ms:.1f} ms per 50k-change batch")
+    last = points[-1]
+    return {
+        "metric": METRIC, "value": last["updates_per_s"], "unit": "updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": last["ms_per_batch"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": "random hypergraph sweep: |V| = |E|/3, card power-law 2.5 on [2,8192], uniform "
+                               "popularity, 50k changes per batch, hyperedge triads; value at the largest size"},
+        "sweep": points, "roofline": None,
+    }
+
+
 def host_cpu_model():
     try:
         with open("/proc/cpuinfo") as f:
@@ -533,6 +647,11 @@ def main():
     if args.config == "batched":
         out, sts = bench_batched(args)
         cpu_st, fam = sorted(sts, key=lambda s: s.initial.n)[len(sts) // 2], ("hyperedge",)
+    elif args.config == "static":
+        out, cpu_st = bench_static(args)
+        fam = ("hyperedge", "incident_vertex")
+    elif args.config == "sweep":
+        out, cpu_st, fam = bench_sweep(args), None, None
     elif args.config == "served":
         out, sv = bench_served(args)
         busy = sorted((t for t in sv.tenants if t.batches), key=lambda s: s.initial.n)
@@ -543,6 +662,11 @@ def main():
             track = ("hyperedge", "incident_vertex")
             wl = ("medium: 1M vertices, 2M hyperedges, card power-law 2.5 on [2,64], popularity (rank+1e4)^-1.1, "
                   "batches 50k ins + 50k del, hyperedge + incident-vertex triads")
+        elif args.config == "dyadic":
+            st = W.dyadic(n_batches=n_b)
+            track = ("incident_vertex",)
+            wl = ("dyadic: graph of 1M vertices, 8M distinct edges (popularity (rank+1e3)^-0.8), batches 50k edge "
+                  "insertions + 50k deletions, incident-vertex triads (type 3 = triangles)")
         else:
             st = W.temporal(scale=args.scale, n_batches=n_b)
             track = ("temporal",)
@@ -551,7 +675,7 @@ def main():
         log(args, f"generated {st.initial.n} hyperedges, {n_b} batches in {time.perf_counter() - t0:.1f}s")
         out = bench_single(args, st, track, args.config, wl)
         cpu_st, fam = st, track
-    out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline(args, cpu_st, fam)
+    out["cpu_baseline"] = None if (args.no_cpu_baseline or cpu_st is None) else cpu_baseline(args, cpu_st, fam)
     print(json.dumps(out), flush=True)
 
 

@@ -287,6 +287,107 @@ def temporal(seed: int = SEED_BASE + 3, scale: float = 1.0, n_batches: int = 10)
                            int(3_600_000_000), int(600_000_000), seed)
 
 
+def dyadic(seed: int = SEED_BASE + 6, n_vertices: int = 1_000_000, n_edges: int = 8_000_000, pop_s: float = 0.8,
+           pop_q: float = 1.0e3, n_batches: int = 10, n_changes: int = 100_000) -> Stream:
+    """A graph (every hyperedge has cardinality 2, no edge twice): n_edges
+    distinct edges between vertices of popularity (rank + q)^-s, then batches
+    of n_changes / 2 deletions of uniform live edges and n_changes / 2 new
+    edges absent from the graph at that point.  The graph special case of
+    the incident-vertex family: its type-3 count is the triangle count."""
+    rng = np.random.default_rng(seed)
+    pop = Popularity(n_vertices, pop_s, pop_q, rng)
+
+    def fresh(n, present_sorted):
+        """n new distinct edges (lo, hi) whose keys lo * |V| + hi are absent from present_sorted."""
+        got_lo, got_hi, got_keys = [], [], np.zeros(0, np.int64)
+        need = n
+        while need > 0:
+            k = int(need * 1.3) + 16
+            a = pop.draw(rng, k).astype(np.int64)
+            b = pop.draw(rng, k).astype(np.int64)
+            lo, hi = np.minimum(a, b), np.maximum(a, b)
+            ok = lo != hi
+            lo, hi = lo[ok], hi[ok]
+            keys = lo * n_vertices + hi
+            _, first = np.unique(keys, return_index=True)
+            first = np.sort(first)  # first occurrences, in draw order
+            lo, hi, keys = lo[first], hi[first], keys[first]
+            new = ~np.isin(keys, present_sorted) & ~np.isin(keys, got_keys)
+            lo, hi, keys = lo[new][:need], hi[new][:need], keys[new][:need]
+            got_lo.append(lo)
+            got_hi.append(hi)
+            got_keys = np.concatenate([got_keys, keys])
+            need -= len(keys)
+        out = np.stack([np.concatenate(got_lo), np.concatenate(got_hi)], axis=1)
+        # each edge's members in a random order
+        flip = rng.random(len(out)) < 0.5
+        out[flip] = out[flip][:, ::-1]
+        return out, got_keys
+
+    e0, k0 = fresh(n_edges, np.zeros(0, np.int64))
+    initial = _csr(np.full(n_edges, 2, np.int64), e0.reshape(-1).astype(np.uint32))
+    st = Stream("dyadic", n_vertices, initial, params=dict(n_edges=n_edges, pop_s=pop_s, pop_q=pop_q, seed=seed))
+    live = np.arange(n_edges, dtype=np.int64)
+    live_keys = k0
+    next_handle = n_edges
+    for _ in range(n_batches):
+        k = min(n_changes // 2, len(live))
+        pick = rng.choice(len(live), size=k, replace=False)
+        dels = live[pick]
+        keep = np.ones(len(live), dtype=bool)
+        keep[pick] = False
+        kept_keys = live_keys[keep]
+        ne, nk = fresh(n_changes - k, np.sort(kept_keys))
+        ih = np.arange(next_handle, next_handle + len(ne), dtype=np.int64)
+        next_handle += len(ne)
+        live = np.concatenate([live[keep], ih])
+        live_keys = np.concatenate([kept_keys, nk])
+        st.batches.append(Batch(dels.astype(np.int64), _csr(np.full(len(ne), 2, np.int64),
+                                                             ne.reshape(-1).astype(np.uint32)), ih))
+    return st
+
+
+def _uniform_rows(rng: np.random.Generator, cards: np.ndarray, n_vertices: int):
+    """Rows of uniform members: every incidence drawn at once, a vertex drawn
+    twice in one row kept once (rows ascending); returns (cards, members)."""
+    n = len(cards)
+    rows = np.repeat(np.arange(n, dtype=np.int64), cards)
+    keys = rows * n_vertices + rng.integers(0, n_vertices, size=len(rows), dtype=np.int64)
+    keys.sort()
+    keep = np.ones(len(keys), dtype=bool)
+    keep[1:] = keys[1:] != keys[:-1]
+    keys = keys[keep]
+    r = keys // n_vertices
+    return np.bincount(r, minlength=n).astype(np.int64), (keys - r * n_vertices).astype(np.uint32)
+
+
+def random_hypergraph(n_edges: int, seed: int = SEED_BASE + 7, alpha: float = 2.5, card_hi: int = 8192,
+                      n_batches: int = 4, n_changes: int = 50_000) -> Stream:
+    """The paper's random-hypergraph scaling sweep shape: n_edges hyperedges on
+    |V| = |E| / 3 vertices of uniform popularity, cardinality power law alpha on
+    [2, card_hi] (a vertex drawn twice in a hyperedge is kept once), batches of
+    n_changes / 2 uniform deletions + n_changes / 2 new hyperedges."""
+    rng = np.random.default_rng(seed)
+    nv = max(card_hi, n_edges // 3)
+    cards, mem = _uniform_rows(rng, power_law_cards(rng, n_edges, alpha, 2, card_hi), nv)
+    st = Stream(f"random[{n_edges}]", nv, _csr(cards, mem),
+                params=dict(n_edges=n_edges, alpha=alpha, card_hi=card_hi, seed=seed))
+    live = np.arange(n_edges, dtype=np.int64)
+    next_handle = n_edges
+    for _ in range(n_batches):
+        k = min(n_changes // 2, len(live))
+        pick = rng.choice(len(live), size=k, replace=False)
+        dels = live[pick]
+        keep = np.ones(len(live), dtype=bool)
+        keep[pick] = False
+        ci, mi = _uniform_rows(rng, power_law_cards(rng, n_changes - k, alpha, 2, card_hi), nv)
+        ih = np.arange(next_handle, next_handle + len(ci), dtype=np.int64)
+        next_handle += len(ci)
+        live = np.concatenate([live[keep], ih])
+        st.batches.append(Batch(dels.astype(np.int64), _csr(ci, mi), ih))
+    return st
+
+
 def log_uniform_int(rng: np.random.Generator, lo: float, hi: float, size=None) -> np.ndarray:
     return np.round(np.exp(rng.uniform(np.log(lo), np.log(hi), size=size))).astype(np.int64)
 

@@ -277,3 +277,28 @@ def test_incident_vertex_large_owner_stage(gpu_lib, monkeypatch):
             p.apply(b, f"iv stage 2 batch {k}")
             compare_counts(p.g, p.o, p.track, f"iv stage 2 batch {k}")
         p.close()
+
+
+def test_dyadic_graph_triangles(gpu_lib):
+    """The graph special case: hyperedges of two vertices, no edge twice.  The
+    incident-vertex counts are [0, 0, triangles] with the triangle count the
+    textbook trace(A^3) / 6 of the adjacency matrix, after the build and after
+    every batch; hyperedge counts equal the oracle's."""
+    st = W.dyadic(n_vertices=600, n_edges=6000, n_batches=3, n_changes=1200, seed=W.SEED_BASE + 62)
+    p = Pair(st, track=("hyperedge", "incident_vertex"))
+
+    def triangles():
+        off, mem, live = p.g.export_h2v()
+        e = mem.reshape(-1, 2).astype(np.int64)
+        a = np.zeros((st.n_vertices, st.n_vertices), np.int64)
+        a[e[:, 0], e[:, 1]] = 1
+        a[e[:, 1], e[:, 0]] = 1
+        return int(np.trace(a @ a @ a)) // 6
+
+    for k in range(len(st.batches) + 1):
+        if k:
+            p.apply(st.batches[k - 1], f"dyadic batch {k - 1}")
+        compare_counts(p.g, p.o, p.track, f"dyadic step {k}")
+        iv = p.g.triad_counts("incident_vertex")
+        assert iv[0] == 0 and iv[1] == 0 and iv[2] == triangles() > 0, (k, iv)
+    p.close()

@@ -55,3 +55,20 @@ def test_served_requests_and_timestamps():
         assert k == per.get(t, 0)  # the k-th request of a tenant arrives k-th
         per[t] = k + 1
         assert fam in W.FAMILIES
+
+
+def test_dyadic_stream_is_a_simple_graph():
+    """Every hyperedge has two members and no edge is ever present twice."""
+    st = W.dyadic(n_vertices=500, n_edges=3000, n_batches=3, n_changes=600, seed=W.SEED_BASE + 61)
+    live = {}
+    for h, r in enumerate(st.initial.members.reshape(-1, 2).tolist()):
+        assert r[0] != r[1]
+        live[h] = tuple(sorted(r))
+    assert len(set(live.values())) == len(live) == 3000
+    for b in st.batches:
+        assert (np.diff(b.ins.offsets.astype(np.int64)) == 2).all()
+        for h in b.del_handles.tolist():
+            live.pop(h)
+        for h, r in zip(b.ins_handles.tolist(), b.ins.members.reshape(-1, 2).tolist()):
+            live[h] = tuple(sorted(r))
+        assert len(set(live.values())) == len(live)

@@ -497,9 +497,10 @@ def bench_static(args):
 
 def bench_sweep(args):
     """The paper's scaling sweep: random hypergraphs of the given sizes,
-    |V| = |E|/3, cardinality power law 2.5 on [2, 8192] (the library's
-    largest cardinality; the paper's maximum is 10000), 50k changes per batch
-    (half deletions), hyperedge triads.  One point per size."""
+    |V| = |E|/3, cardinality power law 3.0 on [2, 8192] (the library's
+    largest cardinality; the paper's maximum is 10000 and its law is not
+    stated), 50k changes per batch (half deletions), hyperedge triads.  One
+    point per size."""
     import numpy as np
     import torch
     from paper_2512_21009_amd import hgt
@@ -508,10 +509,11 @@ def bench_sweep(args):
     points = []
     for n in [int(float(x)) for x in args.sweep_sizes.split(",")]:
         t0 = time.perf_counter()
-        st = W.random_hypergraph(n, n_batches=n_b)
+        st = W.random_hypergraph(n, alpha=3.0, n_batches=n_b)
         log(args, f"sweep {n}: generated in {time.perf_counter() - t0:.1f}s ({st.initial.members.size} incidences)")
         ins = [(to_dev(b.ins.offsets, np.int64), to_dev(b.ins.members, np.int32)) for b in st.batches]
         dels = ids_of_stream(hgt, st, ins)
+        log(args, f"sweep {n}: deletion IDs replayed")
         ini = st.initial
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -519,6 +521,7 @@ def bench_sweep(args):
                             track=("hyperedge",))
         torch.cuda.synchronize()
         build_s = time.perf_counter() - t0
+        log(args, f"sweep {n}: built in {build_s:.1f}s")
         lat, n_upd = [], 0
         for k in range(n_b):
             torch.cuda.synchronize()
@@ -542,7 +545,7 @@ def bench_sweep(args):
         "metric": METRIC, "value": last["updates_per_s"], "unit": "updates/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": last["ms_per_batch"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "u64", "data": "synthetic",
-        "config": {"workload": "random hypergraph sweep: |V| = |E|/3, card power-law 2.5 on [2,8192], uniform "
+        "config": {"workload": "random hypergraph sweep: |V| = |E|/3, card power-law 3.0 on [2,8192], uniform "
                                "popularity, 50k changes per batch, hyperedge triads; value at the largest size"},
         "sweep": points, "roofline": None,
     }

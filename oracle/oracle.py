@@ -242,6 +242,64 @@ class OracleGraph:
         return OK, assigned.astype(np.uint32)
 
     # ------------------------------------------------------------------ #
+    def apply_vertex_ops(self, edge_ids, vertices, insert):
+        """Incident-vertex insertions and deletions inside live hyperedges (the
+        paper's horizontal operations, Sec. III-B): op i inserts vertices[i]
+        into hyperedge edge_ids[i] (insert[i] true) or deletes it from it.
+        Every modified hyperedge keeps its ID, timestamp and arrival sequence.
+        Rejected (state unchanged) when an ID is not live (ENOENT), a vertex is
+        out of range, the same (hyperedge, vertex) appears twice, a deleted
+        vertex is not a member, an inserted one already is, or a hyperedge
+        would be left empty (EINVAL).  Returns (status, ascending modified IDs)."""
+        edge_ids = np.asarray(edge_ids, dtype=np.int64)
+        vertices = np.asarray(vertices, dtype=np.int64)
+        insert = np.asarray(insert, dtype=bool)
+        if len(edge_ids) == 0:
+            return OK, np.zeros(0, np.int64)
+        if (edge_ids < 0).any() or (edge_ids >= self.next_id).any() or not self.live[edge_ids].all():
+            return ENOENT, None
+        if (vertices < 0).any() or (vertices >= self.n_vertices).any():
+            return EINVAL, None
+        pairs = edge_ids * self.n_vertices + vertices
+        if len(np.unique(pairs)) != len(pairs):
+            return EINVAL, None
+        new_rows = {}
+        for h in np.unique(edge_ids).tolist():
+            row = set(self.row(h).tolist())
+            sel = edge_ids == h
+            for v, ins in zip(vertices[sel].tolist(), insert[sel].tolist()):
+                if ins:
+                    if v in row:
+                        return EINVAL, None
+                    row.add(v)
+                else:
+                    if v not in row:
+                        return EINVAL, None
+                    row.remove(v)
+            if not row:
+                return EINVAL, None
+            new_rows[h] = np.array(sorted(row), dtype=np.uint32)
+        old_lens = self.lens()
+        lens = old_lens.copy()
+        for h, r in new_rows.items():
+            lens[h] = len(r)
+        off = np.zeros(self.n_slots + 1, dtype=np.uint64)
+        np.cumsum(lens, out=off[1:])
+        mem = np.zeros(int(off[-1]), dtype=np.uint32)
+        # unmodified rows move as they are, then the new rows are written
+        keep = old_lens > 0
+        keep[list(new_rows)] = False
+        ids = np.nonzero(keep)[0]
+        ln = old_lens[ids]
+        if ln.sum():
+            within = np.arange(int(ln.sum()), dtype=np.int64) - np.repeat(np.cumsum(ln) - ln, ln)
+            mem[np.repeat(off[ids].astype(np.int64), ln) + within] = \
+                self.mem[np.repeat(self.off[ids].astype(np.int64), ln) + within]
+        for h, r in new_rows.items():
+            mem[int(off[h]):int(off[h + 1])] = r
+        self.off, self.mem = off, mem
+        return OK, np.array(sorted(new_rows), dtype=np.int64)
+
     def _args(self):
         return (self.n_slots, _p(self.off), _p(self.mem), _p(self.live), self.n_vertices)
 

@@ -357,3 +357,100 @@ def test_iv_delta_by_definition_equals_recount(seed):
     assert g.apply_batch(dels, *csr([]))[0] == O.OK
     with np.errstate(over="ignore"):
         assert (O.iv_delta_by_definition(old, g, dels, []) == g.iv_counts() - old.iv_counts()).all()
+
+
+# ------------------------------------------------- horizontal (vertex) operations
+def random_vertex_ops(rng, g, n_edges, nv, max_per_edge=3):
+    """Valid ops on n_edges live hyperedges: some members deleted (one always
+    kept), some non-members inserted."""
+    eids, verts, ins = [], [], []
+    for h in rng.choice(g.live_ids(), size=min(n_edges, len(g.live_ids())), replace=False).tolist():
+        row = g.row(h).tolist()
+        n_del = int(rng.integers(0, min(max_per_edge, len(row) - 1) + 1))
+        for v in rng.choice(row, size=n_del, replace=False).tolist():
+            eids.append(h); verts.append(v); ins.append(1 == 0)
+        outside = [v for v in range(nv) if v not in row]
+        n_ins = int(rng.integers(0 if n_del else 1, max_per_edge + 1))
+        for v in rng.choice(outside, size=min(n_ins, len(outside)), replace=False).tolist():
+            eids.append(h); verts.append(v); ins.append(True)
+    order = rng.permutation(len(eids))
+    return (np.array(eids, np.int64)[order], np.array(verts, np.int64)[order], np.array(ins, bool)[order])
+
+
+def _rows_of(g):
+    return [g.row(i).tolist() for i in range(g.n_slots) if g.live[i]]
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_vertex_ops_brute_force(seed):
+    """Counts after a batch of vertex insertions/deletions equal brute force on
+    the modified hyperedge sets (timestamps and arrival order kept)."""
+    rng = np.random.default_rng(900 + seed)
+    nv = 12
+    rows = random_rows(rng, 14, nv, 1, 4)
+    ts = np.sort(rng.integers(0, 60, size=len(rows))).astype(np.int64)
+    g = graph(rows, nv=nv, ts=ts, window=25)
+    e, v, ins = random_vertex_ops(rng, g, 5, nv)
+    st, mod = g.apply_vertex_ops(e, v, ins)
+    assert st == O.OK and sorted(set(e.tolist())) == mod.tolist()
+    new_rows = _rows_of(g)
+    for h in range(len(rows)):
+        want = set(rows[h]) | {int(x) for x, i, y in zip(v, ins, e) if i and y == h}
+        want -= {int(x) for x, i, y in zip(v, ins, e) if not i and y == h}
+        assert new_rows[h] == sorted(want)
+    assert as_dict(g.he_counts(), O.he_class_codes()) == brute_he(new_rows)
+    assert as_dict(g.temporal_counts(), O.tmp_class_codes()) == brute_tmp(new_rows, ts, 25)
+    assert g.iv_counts().tolist() == brute_iv(new_rows)
+
+
+def test_vertex_ops_inverse_and_delete_reinsert():
+    rng = np.random.default_rng(31)
+    nv = 30
+    rows = random_rows(rng, 60, nv, 1, 6)
+    g = graph(rows, nv=nv)
+    he0, iv0 = g.he_counts(), g.iv_counts()
+    e, v, ins = random_vertex_ops(rng, g, 12, nv)
+    old = g.copy()
+    st, mod = g.apply_vertex_ops(e, v, ins)
+    assert st == O.OK
+    he1, iv1 = g.he_counts(), g.iv_counts()
+    assert not (he1 == he0).all()
+    # the same change as deleting the modified hyperedges and inserting their new rows
+    g2 = old.copy()
+    new = [g.row(h).tolist() for h in mod.tolist()]
+    st2, _ = g2.apply_batch(mod, *csr(new))
+    assert st2 == O.OK
+    assert (g2.he_counts() == he1).all() and (g2.iv_counts() == iv1).all()
+    # delta by definition over the modified IDs on both sides
+    dhe, _ = O.delta_by_definition(old, g, mod, mod)
+    with np.errstate(over="ignore"):
+        assert (he0 + dhe == he1).all()
+        assert (O.iv_delta_by_definition(old, g, mod, mod) == iv1 - iv0).all()
+    # the inverse ops restore every count and row
+    st, _ = g.apply_vertex_ops(e, v, ~ins)
+    assert st == O.OK
+    assert (g.he_counts() == he0).all() and (g.iv_counts() == iv0).all()
+    assert _rows_of(g) == _rows_of(old)
+
+
+def test_vertex_ops_errors_leave_state_unchanged():
+    rows = [[0, 1], [1, 2], [2, 3, 4]]
+    g = graph(rows, nv=6, ts=np.array([1, 2, 3], np.int64), window=10)
+    assert g.apply_batch([1], *csr([]))[0] == O.OK  # ID 1 is dead now
+    before = (g.off.copy(), g.mem.copy(), g.live.copy())
+    cases = [
+        (O.ENOENT, ([1], [0], [True])),           # hyperedge not live
+        (O.ENOENT, ([7], [0], [True])),           # never used
+        (O.EINVAL, ([0], [6], [True])),           # vertex out of range
+        (O.EINVAL, ([0], [1], [True])),           # already a member
+        (O.EINVAL, ([0], [3], [False])),          # not a member
+        (O.EINVAL, ([0, 0], [0, 1], [False, False])),  # would leave it empty
+        (O.EINVAL, ([2, 2], [5, 5], [True, True])),    # the same op twice
+        (O.EINVAL, ([2, 2], [3, 3], [False, True])),   # the same pair twice
+    ]
+    for code, (e, v, i) in cases:
+        assert g.apply_vertex_ops(e, v, i)[0] == code, (e, v, i)
+        assert (g.off == before[0]).all() and (g.mem == before[1]).all() and (g.live == before[2]).all()
+    st, mod = g.apply_vertex_ops([2, 0], [4, 5], [False, True])
+    assert st == O.OK and mod.tolist() == [0, 2]
+    assert g.row(0).tolist() == [0, 1, 5] and g.row(2).tolist() == [2, 3]

@@ -52,7 +52,8 @@ def parse():
                     help="batches applied after the timed region with HIP-event profiling on (roofline)")
     ap.add_argument("--phases", action="store_true",
                     help="also record the hyperedge-delta stages' wall-clock phase timers in the profiled pass")
-    ap.add_argument("--config", choices=("medium", "temporal", "batched", "served", "dyadic", "static", "sweep"),
+    ap.add_argument("--config", choices=("medium", "temporal", "batched", "served", "dyadic", "static", "sweep",
+                                         "horizontal"),
                     default="medium")
     ap.add_argument("--sweep-sizes", default="20e6,30e6,40e6,55e6", help="sweep: hyperedge counts")
     ap.add_argument("--requests", type=int, default=256, help="served: number of requests")
@@ -551,6 +552,50 @@ def bench_sweep(args):
     }
 
 
+def bench_horizontal(args):
+    """Horizontal operations on the Medium workload (the paper's incident-vertex
+    modification batches): batches of 100k ops (half insertions of a vertex
+    into a hyperedge, half deletions of a member) on uniform hyperedges,
+    hyperedge + incident-vertex triads updated; updates = ops."""
+    import numpy as np
+    import torch
+    from paper_2512_21009_amd import hgt
+    from paper_2512_21009_amd import workloads as W
+    n_b = args.warmup + args.steps
+    st = W.medium(q=1.0e4, scale=args.scale, n_batches=0)
+    t0 = time.perf_counter()
+    ops = W.vertex_op_batches(st, n_b, max(2, int(100_000 * args.scale)))
+    log(args, f"generated {n_b} batches of {len(ops[0].edge_ids)} vertex ops in {time.perf_counter() - t0:.1f}s")
+    dev_ops = [(to_dev(o.edge_ids, np.int32), to_dev(o.vertices, np.int32), to_dev(o.insert.astype(np.uint8), np.uint8))
+               for o in ops]
+    ini = st.initial
+    track = ("hyperedge", "incident_vertex")
+    g = hgt.Graph.build(st.n_vertices, to_dev(ini.offsets, np.int64), to_dev(ini.members, np.int32), track=track)
+    lat, n_upd = [], 0
+    for k in range(n_b):
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        g.apply_vertex_ops(*dev_ops[k])
+        torch.cuda.synchronize()
+        if k >= args.warmup:
+            lat.append(time.perf_counter() - tb)
+            n_upd += len(ops[k].edge_ids)
+    assert g.sync() == hgt.OK
+    totals = {f: int(sum(g.triad_counts(f))) for f in track}
+    g.close()
+    ms = np.array(lat) * 1e3
+    return {
+        "metric": METRIC, "value": round(n_upd / sum(lat), 1), "unit": "updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(float(ms.mean()), 3),
+        "p50_ms": round(float(np.percentile(ms, 50)), 3), "p99_ms": round(float(np.percentile(ms, 99)), 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": "horizontal: medium (1M vertices, 2M hyperedges), batches of 100k incident-vertex "
+                               "ops (50k insertions, 50k deletions) on uniform hyperedges, hyperedge + "
+                               "incident-vertex triads", "scale": args.scale, "triads_total": totals},
+        "roofline": None,
+    }
+
+
 def host_cpu_model():
     try:
         with open("/proc/cpuinfo") as f:
@@ -655,6 +700,8 @@ def main():
         fam = ("hyperedge", "incident_vertex")
     elif args.config == "sweep":
         out, cpu_st, fam = bench_sweep(args), None, None
+    elif args.config == "horizontal":
+        out, cpu_st, fam = bench_horizontal(args), None, None
     elif args.config == "served":
         out, sv = bench_served(args)
         busy = sorted((t for t in sv.tenants if t.batches), key=lambda s: s.initial.n)

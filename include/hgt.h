@@ -135,6 +135,23 @@ int hgt_apply_batch_noalloc(hgt_graph* g, const uint32_t* del_ids, uint64_t n_de
                             uint64_t n_ins_members, const int64_t* ins_ts, uint64_t n_ins,
                             uint32_t* out_ins_ids, void* stream);
 
+/* ---- horizontal operations (Sec. III-B) -------------------------------- */
+/* Incident-vertex insertions and deletions inside live hyperedges (the
+ * paper's "horizontal operations"): op i inserts vertices[i] into hyperedge
+ * edge_ids[i] when insert[i] != 0, else deletes it from it (device arrays of
+ * n_ops entries, any order).  Every modified hyperedge keeps its ID, its
+ * timestamp and its arrival sequence; the counts of every tracked family
+ * change as if the modified hyperedges were deleted and their new member sets
+ * inserted under the same IDs (Alg. 3 with incident vertices in place of
+ * hyperedges).  The batch is rejected whole, with nothing changed, when an ID
+ * is not live (HGT_ENOENT), a vertex is out of range, the same (hyperedge,
+ * vertex) pair appears twice, a deleted vertex is not a member, an inserted
+ * one already is, or a hyperedge would be left empty or above HGT_MAX_CARD
+ * members (HGT_EINVAL).  Waits twice on the host (the ops' summary, then the
+ * batch's). */
+int hgt_apply_vertex_ops(hgt_graph* g, const uint32_t* edge_ids, const uint32_t* vertices,
+                         const uint8_t* insert, uint64_t n_ops, void* stream);
+
 /* ---- batched form ------------------------------------------------------ */
 /* One graph's batch for hgt_apply_batches: the arguments of hgt_apply_batch,
  * plus its result. */

@@ -8,6 +8,7 @@
 #include <new>
 #include <vector>
 
+#include "hops.h"
 #include "internal.h"
 #include "store.h"
 #include "triad.h"
@@ -254,6 +255,9 @@ struct hgt_graph {
     DevBuf hpool;
     PhaseCtx* ph = nullptr;  // the device's shared phase scratch
     DevBuf iv_keys, iv_alt, iv_sort, iv_head, iv_uniq, iv_p2, iv_scan, iv_tab, iv_owner, iv_ctr;
+    // horizontal operations
+    DevBuf vo_sum, vo_keys, vo_alt, vo_sort, vo_scan, vo_head, vo_ins, vo_nmod, vo_mod, vo_seg, vo_card, vo_ts, vo_off,
+        vo_mem;
     // host mirrors (valid after each synchronisation)
     uint64_t next_id = 0, h_bump = 0, v_bump = 0, next_seq = 0, n_live = 0, n_inc = 0;
     uint32_t epoch = 0;
@@ -1038,6 +1042,9 @@ struct Pending {
     uint64_t n_mem = 0;
     uint32_t* out_ids = nullptr;
     int check_order = 1;
+    int is_build = 0;                       // the build: counts by the static mode of the kernels
+    const uint32_t* forced_ids = nullptr;   // horizontal operations: the IDs the inserts take
+    int keep_seq = 0;                       // horizontal operations: arrival sequences kept
     int rc = HGT_OK;  // this batch's result so far
 };
 
@@ -1062,7 +1069,8 @@ int plan_begin(Pending& p, const uint32_t* del, uint64_t n_del, const uint64_t* 
     Sizes z{n_del, n_ins, n_mem, g->n_inc + n_mem, (g->next_id + 63) / 64 + 1};
     rc = ensure_plan_scratch(g, z, p.w);
     if (rc) return rc;
-    p.b = BatchIn{del, n_del, ins_off, ins_mem, n_mem, ins_ts, n_ins, g->epoch + 1, g->epoch + 2, p.check_order};
+    p.b = BatchIn{del, n_del, ins_off, ins_mem, n_mem, ins_ts, n_ins, g->epoch + 1, g->epoch + 2, p.check_order,
+                  p.forced_ids, p.keep_seq};
     p.n_mem = n_mem;
     g->epoch += 2;
     uint64_t* cnt = g->counts.as<uint64_t>();
@@ -1151,7 +1159,7 @@ int apply_locked(hgt_graph* owner, std::vector<Pending*>& ps, hipStream_t s) {
     std::vector<PhaseJob> jobs;
     jobs.reserve(ps.size());
     for (Pending* p : ps) jobs.push_back(job_minus(*p));
-    bool full = !ps.empty() && ps[0]->check_order == 0;
+    bool full = !ps.empty() && ps[0]->is_build;
     // step 2: deltas on the old graph
     rc = run_phase(owner, jobs.data(), (uint32_t)jobs.size(), true, false, s);
     if (rc) return rc;
@@ -1192,7 +1200,7 @@ int apply_locked(hgt_graph* owner, std::vector<Pending*>& ps, hipStream_t s) {
         g->next_id = p->sum.next_id_new;
         g->h_bump += p->sum.h2v_need;
         g->v_bump += p->sum.v2h_need;
-        g->next_seq += p->b.n_ins;
+        if (!p->b.keep_seq) g->next_seq += p->b.n_ins;
         g->n_live = g->n_live + p->b.n_ins - p->b.n_del;
         g->n_inc = g->n_inc + p->n_mem - p->sum.del_members;
         g->batches++;
@@ -1214,13 +1222,23 @@ void set_sticky(hgt_graph* g, int rc) {
     if (rc && !g->sticky) g->sticky = rc;
 }
 
-// One batch.  check_order = 0 only for the build batch.
+// What a batch is: an update batch, the build (every hyperedge inserted into
+// the empty graph, counted by the static mode), or horizontal operations
+// (the modified hyperedges deleted and reinserted under the same IDs with
+// their timestamps and arrival sequences kept).
+enum ApplyMode { MODE_BATCH = 0, MODE_BUILD, MODE_VOPS };
+
+// One batch.
 int apply(hgt_graph* g, const uint32_t* del, uint64_t n_del, const uint64_t* ins_off, const uint32_t* ins_mem,
-          uint64_t n_mem, const int64_t* ins_ts, uint64_t n_ins, uint32_t* out_ids, hipStream_t s, int check_order) {
+          uint64_t n_mem, const int64_t* ins_ts, uint64_t n_ins, uint32_t* out_ids, hipStream_t s,
+          ApplyMode mode = MODE_BATCH, const uint32_t* forced_ids = nullptr) {
     Pending p;
     p.g = g;
     p.out_ids = out_ids;
-    p.check_order = check_order;
+    p.check_order = mode == MODE_BATCH ? 1 : 0;
+    p.is_build = mode == MODE_BUILD ? 1 : 0;
+    p.forced_ids = forced_ids;
+    p.keep_seq = mode == MODE_VOPS ? 1 : 0;
     int rc = plan_begin(p, del, n_del, ins_off, ins_mem, n_mem, ins_ts, n_ins, s);
     if (rc == HGT_ENOENT) set_sticky(g, rc);
     if (rc) return rc;
@@ -1244,7 +1262,8 @@ void destroy_graph(hgt_graph* g) {
                      &g->s_tseg, &g->s_D, &g->s_I, &g->s_It, &g->s_vp, &g->s_staging, &g->s_dst,
                      &g->s_staging_ts, &g->v2h_ts, &g->iv_keys, &g->iv_alt, &g->iv_sort,
                      &g->iv_head, &g->iv_uniq, &g->iv_p2, &g->iv_scan, &g->iv_tab, &g->iv_owner, &g->iv_ctr,
-                     &g->hpool};
+                     &g->hpool, &g->vo_sum, &g->vo_keys, &g->vo_alt, &g->vo_sort, &g->vo_scan, &g->vo_head,
+                     &g->vo_ins, &g->vo_nmod, &g->vo_mod, &g->vo_seg, &g->vo_card, &g->vo_ts, &g->vo_off, &g->vo_mem};
     for (DevBuf* b : all) dev_free(*b);
     if (g->ph) phase_ctx_release(g->ph);
     dev_free(g->stats);
@@ -1410,7 +1429,7 @@ int hgt_build(const hgt_build_desc* d, hgt_graph** out) {
             if (last < first) { rc = HGT_EINVAL; break; }
             if (tmp) store_max_ts(d->timestamps, d->n_edges, g->st.sc, s);
             rc = apply(g, nullptr, 0, d->offsets, d->members, last - first, tmp ? d->timestamps : nullptr, d->n_edges,
-                       nullptr, s, 0);
+                       nullptr, s, MODE_BUILD);
             if (rc) break;
             HIP_BRK(hipStreamSynchronize(s));
         }
@@ -1430,7 +1449,79 @@ int hgt_apply_batch(hgt_graph* g, const uint32_t* del_ids, uint64_t n_del, const
     if (!g) return HGT_EINVAL;
     if (n_del == 0 && n_ins == 0) return HGT_OK;
     int rc = apply(g, del_ids, n_del, ins_offsets, ins_members, n_ins_members, ins_ts, n_ins, out_ins_ids,
-                   (hipStream_t)stream, 1);
+                   (hipStream_t)stream);
+    if (rc && !g->sticky) g->sticky = rc;
+    return rc;
+}
+
+int hgt_apply_vertex_ops(hgt_graph* g, const uint32_t* edge_ids, const uint32_t* vertices, const uint8_t* insert,
+                         uint64_t n_ops, void* stream) {
+    if (!g) return HGT_EINVAL;
+    if (n_ops == 0) return HGT_OK;
+    if (!edge_ids || !vertices || !insert || n_ops > 0xfffffff0ull) return HGT_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    g->last_stream = s;
+    const bool tmp = g->track_mask & (1u << HGT_TRIAD_TEMPORAL);
+    VopIn in{};
+    in.edge_ids = edge_ids;
+    in.vertices = vertices;
+    in.insert = insert;
+    in.n = n_ops;
+    in.hb = bits_for(g->next_id);
+    in.vb = bits_for(g->st.n_vertices ? g->st.n_vertices - 1 : 0);
+    if (in.hb + in.vb + 1 > 64) return HGT_EINVAL;
+    in.n_vertices = g->st.n_vertices;
+    in.free_bm = g->st.free_bm;
+    in.h_off = g->st.h_off;
+    in.h_len = g->st.h_len;
+    in.h2v = g->st.h2v;
+    in.h_ts = tmp ? g->st.h_ts : nullptr;
+    in.sc = g->st.sc;
+    const uint64_t n = n_ops;
+    int rc = 0;
+    rc |= ensure(g->vo_sum, sizeof(VopSummary));
+    rc |= ensure(g->vo_keys, n * 8);
+    rc |= ensure(g->vo_alt, n * 8);
+    rc |= ensure(g->vo_sort, hgt_radix_tmp_bytes(n));
+    rc |= ensure(g->vo_scan, hgt_scan_tmp_bytes(n + 1));
+    rc |= ensure(g->vo_head, n * 8);
+    rc |= ensure(g->vo_ins, (n + 1) * 8);
+    rc |= ensure(g->vo_nmod, 64);
+    rc |= ensure(g->vo_mod, n * 4);
+    rc |= ensure(g->vo_seg, (n + 1) * 8);
+    rc |= ensure(g->vo_card, n * 8);
+    rc |= ensure(g->vo_ts, n * 8);
+    rc |= ensure(g->vo_off, (n + 1) * 8);
+    if (rc) return HGT_ENOMEM;
+    VopScratch w{};
+    w.sum = g->vo_sum.as<VopSummary>();
+    w.keys = g->vo_keys.as<uint64_t>();
+    w.keys_alt = g->vo_alt.as<uint64_t>();
+    w.sort_tmp = g->vo_sort.p;
+    w.scan_tmp = g->vo_scan.p;
+    w.head = g->vo_head.as<uint64_t>();
+    w.ins_pre = g->vo_ins.as<uint64_t>();
+    w.n_mod = g->vo_nmod.as<uint64_t>();
+    w.mod_ids = g->vo_mod.as<uint32_t>();
+    w.seg = g->vo_seg.as<uint64_t>();
+    w.card = g->vo_card.as<uint64_t>();
+    w.ts = tmp ? g->vo_ts.as<int64_t>() : nullptr;
+    w.new_off = g->vo_off.as<uint64_t>();
+    vops_plan(in, w, s);
+    static_assert(sizeof(VopSummary) <= sizeof(BatchSummary), "summary staging");
+    VopSummary* hs = (VopSummary*)g->h_sum;  // pinned; the batch below rewrites it after its own plan
+    HIP_OK(hipMemcpyAsync(hs, w.sum, sizeof(VopSummary), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    const VopSummary sum = *hs;
+    if (sum.status) {
+        if (!g->sticky) g->sticky = sum.status;
+        return sum.status;
+    }
+    if (ensure(g->vo_mem, std::max<uint64_t>(sum.n_members, 1) * 4)) return HGT_ENOMEM;
+    w.members = g->vo_mem.as<uint32_t>();
+    vops_rows(in, w, sum.n_mod, s);
+    rc = apply(g, w.mod_ids, sum.n_mod, w.new_off, w.members, sum.n_members, w.ts, sum.n_mod, nullptr, s, MODE_VOPS,
+               w.mod_ids);
     if (rc && !g->sticky) g->sticky = rc;
     return rc;
 }
@@ -1451,7 +1542,7 @@ int hgt_apply_batch_noalloc(hgt_graph* g, const uint32_t* del_ids, uint64_t n_de
     a.cap = kNoAllocScratchBytes;
     t_na = &a;
     rc = apply(g, del_ids, n_del, ins_offsets, ins_members, n_ins_members, ins_ts, n_ins, out_ins_ids,
-               (hipStream_t)stream, 1);
+               (hipStream_t)stream);
     t_na = nullptr;
     // the graph's own scratch buffers are its again (queued kernels keep using the
     // arena regions they were given; the arena is never freed)

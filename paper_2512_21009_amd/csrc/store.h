@@ -37,7 +37,10 @@ struct BatchIn {
     const int64_t* ins_ts;
     uint64_t n_ins;
     uint32_t epoch_del, epoch_ins;
-    int check_order;  // 0 for the build batch (initial timestamps may be unordered)
+    int check_order;  // 0 for the build batch and horizontal operations (timestamps not checked)
+    const uint32_t* forced_ids;  // device [n_ins] or NULL: insert j takes this ID (horizontal operations,
+                                 // where it is the ID deleted at the same rank)
+    int keep_seq;     // 1: inserts keep the arrival sequence of their ID (horizontal operations)
 };
 
 // Per touched vertex plan (indexed by touched-vertex rank).

@@ -208,6 +208,19 @@ __global__ void k_assign_fresh(uint64_t n_ins, const DevScalars* sc, BatchSummar
     mark_ins[assigned[j]] = ((uint64_t)epoch << 32) | (uint32_t)j;
 }
 
+// horizontal operations: insert j takes forced[j], the ID deleted at rank j
+__global__ void k_assign_forced(uint64_t n_ins, const uint32_t* __restrict__ forced, const DevScalars* sc,
+                                BatchSummary* sum, uint32_t* assigned, uint64_t* mark_ins, uint32_t epoch) {
+    uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j == 0) {
+        sum->next_id_new = sc->next_id;
+        sum->n_free = n_ins;
+    }
+    if (j >= n_ins) return;
+    assigned[j] = forced[j];
+    mark_ins[forced[j]] = ((uint64_t)epoch << 32) | (uint32_t)j;
+}
+
 // words of a fresh h2v block for insert j (0 when the ID's retained block fits)
 __global__ void k_h2v_need(const uint32_t* __restrict__ assigned, const uint64_t* __restrict__ ins_card,
                            uint64_t n_ins, const DevScalars* sc, const uint32_t* __restrict__ h_cap,
@@ -360,8 +373,9 @@ __global__ void k_apply_delete(const uint32_t* __restrict__ del, uint64_t n_del,
 
 __global__ void k_h2v_meta(const uint32_t* __restrict__ assigned, const uint64_t* __restrict__ ins_card, uint64_t n_ins,
                            const uint64_t* __restrict__ need, const uint64_t* __restrict__ rel, uint64_t next_id_old,
-                           uint64_t h_bump, const int64_t* __restrict__ ts, uint64_t next_seq, uint64_t* h_off,
-                           uint32_t* h_len, uint32_t* h_cap, int64_t* h_ts, uint64_t* h_seq, uint64_t* free_bm) {
+                           uint64_t h_bump, const int64_t* __restrict__ ts, uint64_t next_seq, int keep_seq,
+                           uint64_t* h_off, uint32_t* h_len, uint32_t* h_cap, int64_t* h_ts, uint64_t* h_seq,
+                           uint64_t* free_bm) {
     uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n_ins) return;
     uint32_t id = assigned[j];
@@ -371,7 +385,7 @@ __global__ void k_h2v_meta(const uint32_t* __restrict__ assigned, const uint64_t
     }
     h_len[id] = (uint32_t)ins_card[j];
     if (h_ts) h_ts[id] = ts ? ts[j] : 0;
-    h_seq[id] = next_seq + j;
+    if (!keep_seq) h_seq[id] = next_seq + j;
     if ((uint64_t)id < next_id_old)
         atomicAnd((unsigned long long*)&free_bm[id >> 6], (unsigned long long)~(1ull << (id & 63)));
 }
@@ -450,12 +464,12 @@ __global__ void k_v_commit(uint64_t n_touched, const uint32_t* __restrict__ tv, 
 }
 
 __global__ void k_commit_scalars(DevScalars* sc, const BatchSummary* sum, uint64_t n_del, uint64_t n_ins,
-                                 uint64_t n_ins_members, const int64_t* ins_ts) {
+                                 uint64_t n_ins_members, const int64_t* ins_ts, int keep_seq) {
     if (threadIdx.x || blockIdx.x) return;
     sc->next_id = sum->next_id_new;
     sc->h_bump += sum->h2v_need;
     sc->v_bump += sum->v2h_need;
-    sc->next_seq += n_ins;
+    if (!keep_seq) sc->next_seq += n_ins;
     if (ins_ts && n_ins) {
         int64_t t = ins_ts[n_ins - 1];  // batch timestamps are non-decreasing
         if (t > sc->last_ts) sc->last_ts = t;
@@ -505,14 +519,20 @@ void store_plan(StoreDev& g, BatchIn& b, PlanScratch& w, hipStream_t s) {
         k_canon_big<<<gb, 256, 0, s>>>(b.ins_mem, w.ins_rel, g.n_vertices, sc, w.canon, w.big_list, w.big_count);
     }
     // ID assignment (the free-ID bitmap covers IDs below next_id; host bound words_max)
-    uint64_t words_max = (g.next_id_host + 63) / 64;
-    k_free_popc<<<blocks_for(words_max), 256, 0, s>>>(g.free_bm, w.del_bm, sc, w.popc, w.n_words);
-    hgt_scan_u64(w.popc, w.popc, words_max, w.n_words, w.n_free, w.scan_tmp, s);
-    k_set_nfree<<<1, 64, 0, s>>>(w.sum, w.n_free);
-    if (n_ins) {
-        k_assign_free<<<blocks_for(words_max), 256, 0, s>>>(g.free_bm, w.del_bm, w.popc, w.n_words, n_ins, w.assigned);
+    if (b.forced_ids) {
+        k_assign_forced<<<blocks_for(n_ins), 256, 0, s>>>(n_ins, b.forced_ids, sc, w.sum, w.assigned, g.mark_ins,
+                                                          b.epoch_ins);
+    } else {
+        uint64_t words_max = (g.next_id_host + 63) / 64;
+        k_free_popc<<<blocks_for(words_max), 256, 0, s>>>(g.free_bm, w.del_bm, sc, w.popc, w.n_words);
+        hgt_scan_u64(w.popc, w.popc, words_max, w.n_words, w.n_free, w.scan_tmp, s);
+        k_set_nfree<<<1, 64, 0, s>>>(w.sum, w.n_free);
+        if (n_ins) {
+            k_assign_free<<<blocks_for(words_max), 256, 0, s>>>(g.free_bm, w.del_bm, w.popc, w.n_words, n_ins,
+                                                                w.assigned);
+        }
+        k_assign_fresh<<<blocks_for(n_ins), 256, 0, s>>>(n_ins, sc, w.sum, w.assigned, g.mark_ins, b.epoch_ins);
     }
-    k_assign_fresh<<<blocks_for(n_ins), 256, 0, s>>>(n_ins, sc, w.sum, w.assigned, g.mark_ins, b.epoch_ins);
     if (n_ins) {
         k_h2v_need<<<blocks_for(n_ins), 256, 0, s>>>(w.assigned, w.ins_card, n_ins, sc, g.h_cap, w.h_need);
         hgt_scan_u64(w.h_need, w.h_rel, n_ins, nullptr, w.h2v_total, w.scan_tmp, s);
@@ -554,8 +574,8 @@ void store_commit(StoreDev& g, BatchIn& b, PlanScratch& w, const BatchSummary& s
     if (n_del) k_apply_delete<<<blocks_for(n_del), 256, 0, s>>>(b.del, n_del, g.free_bm, g.h_len);
     if (n_ins) {
         k_h2v_meta<<<blocks_for(n_ins), 256, 0, s>>>(w.assigned, w.ins_card, n_ins, w.h_need, w.h_rel, g.next_id_host,
-                                                     h_bump, b.ins_ts, next_seq, g.h_off, g.h_len, g.h_cap, g.h_ts,
-                                                     g.h_seq, g.free_bm);
+                                                     h_bump, b.ins_ts, next_seq, b.keep_seq, g.h_off, g.h_len, g.h_cap,
+                                                     g.h_ts, g.h_seq, g.free_bm);
         if (n_mem)
             k_h2v_copy<<<blocks_for(n_mem), 256, 0, s>>>(w.canon, w.ins_rel, n_ins, n_mem, w.assigned, g.h_off, g.h2v);
     }
@@ -572,7 +592,8 @@ void store_commit(StoreDev& g, BatchIn& b, PlanScratch& w, const BatchSummary& s
                                                             w.vp, w.D_all, w.dst, g.h_ts, g.v2h, g.v2h_ts);
         k_v_commit<<<blocks_for(nt), 256, 0, s>>>(nt, w.tv, w.vp, w.dst, g.v_off, g.v_len, g.v_cap);
     }
-    k_commit_scalars<<<1, 64, 0, s>>>(g.sc, w.sum, n_del, n_ins, n_mem, b.check_order ? b.ins_ts : nullptr);
+    k_commit_scalars<<<1, 64, 0, s>>>(g.sc, w.sum, n_del, n_ins, n_mem, b.check_order ? b.ins_ts : nullptr,
+                                      b.keep_seq);
 }
 
 void store_max_ts(const int64_t* ts, uint64_t n, DevScalars* sc, hipStream_t s) {

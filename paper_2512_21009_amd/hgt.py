@@ -155,6 +155,7 @@ def load(path: str = LIB_PATH):
     lib.hgt_apply_batch.argtypes = [P, P, U64, P, P, U64, P, U64, P, P]
     lib.hgt_apply_batch_noalloc.argtypes = [P, P, U64, P, P, U64, P, U64, P, P]
     lib.hgt_apply_batches.argtypes = [P, U32, P]
+    lib.hgt_apply_vertex_ops.argtypes = [P, P, P, P, U64, P]
     lib.hgt_triad_counts.argtypes = [P, I32, I64, P, U32]
     lib.hgt_sync.argtypes = [P, ctypes.POINTER(I32)]
     lib.hgt_destroy.argtypes = [P]
@@ -339,6 +340,22 @@ class Graph:
                 raise HgtError(rc, "hgt_apply_batch_noalloc" if noalloc else "hgt_apply_batch")
             return out_ids
         return rc, out_ids
+
+    def apply_vertex_ops(self, edge_ids, vertices, insert, stream=None, raise_on_error: bool = True):
+        """Horizontal operations: insert (insert[i] true) or delete vertices[i]
+        in hyperedge edge_ids[i] (int32 / int32 / uint8 or bool device tensors).
+        Returns the status (raises on error unless raise_on_error=False)."""
+        import torch
+        n = int(edge_ids.numel())
+        _check_dtype(edge_ids, (torch.int32, torch.uint32), "edge_ids")
+        _check_dtype(vertices, (torch.int32, torch.uint32), "vertices")
+        _check_dtype(insert, (torch.uint8, torch.bool), "insert")
+        if int(vertices.numel()) != n or int(insert.numel()) != n:
+            raise ValueError("edge_ids, vertices and insert must have the same length")
+        rc = load().hgt_apply_vertex_ops(self._h, _ptr(edge_ids), _ptr(vertices), _ptr(insert), n, _stream(stream))
+        if rc != OK and raise_on_error:
+            raise HgtError(rc, "hgt_apply_vertex_ops")
+        return rc
 
     # ------------------------------------------------------------------ queries
     def triad_counts(self, kind, window: Optional[int] = None) -> List[int]:

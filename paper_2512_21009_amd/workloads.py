@@ -388,6 +388,65 @@ def random_hypergraph(n_edges: int, seed: int = SEED_BASE + 7, alpha: float = 2.
     return st
 
 
+@dataclass
+class VertexOps:
+    edge_ids: np.ndarray   # int64 (hyperedge IDs; horizontal operations keep IDs)
+    vertices: np.ndarray   # int64
+    insert: np.ndarray     # bool
+
+
+def vertex_op_batches(st: Stream, n_batches: int, n_ops: int, seed: int = SEED_BASE + 8,
+                      pop_s: float = 1.1, pop_q: float = 1.0e4) -> List[VertexOps]:
+    """Batches of incident-vertex modifications on the initial hyperedges of
+    st (IDs 0..n-1): n_ops / 2 deletions of a member of a uniform hyperedge
+    (never its last) and n_ops / 2 insertions of a non-member vertex drawn with
+    popularity (rank + q)^-s into a uniform hyperedge; no (hyperedge, vertex)
+    pair twice in a batch.  The rows are followed from batch to batch."""
+    rng = np.random.default_rng(seed)
+    pop = Popularity(st.n_vertices, pop_s, pop_q, rng)
+    off = st.initial.offsets.astype(np.int64)
+    mem = st.initial.members
+    rows = {}
+
+    def row(h):
+        if h not in rows:
+            rows[h] = set(mem[off[h]:off[h + 1]].tolist())
+        return rows[h]
+
+    n = st.initial.n
+    out = []
+    for _ in range(n_batches):
+        used = set()
+        e, v, ins = [], [], []
+        hd = rng.integers(0, n, size=n_ops)  # candidates for deletions
+        for h in hd.tolist():
+            if len(e) >= n_ops // 2:
+                break
+            r = row(h)
+            if len(r) < 2:
+                continue
+            x = int(rng.choice(sorted(r)))
+            if (h, x) in used:
+                continue
+            used.add((h, x))
+            r.remove(x)
+            e.append(h); v.append(x); ins.append(False)
+        hi = rng.integers(0, n, size=n_ops)
+        vi = pop.draw(rng, n_ops)
+        for h, x in zip(hi.tolist(), vi.tolist()):
+            if len(e) >= n_ops:
+                break
+            r = row(h)
+            if x in r or (h, x) in used:
+                continue
+            used.add((h, x))
+            r.add(x)
+            e.append(h); v.append(x); ins.append(True)
+        order = rng.permutation(len(e))
+        out.append(VertexOps(np.array(e, np.int64)[order], np.array(v, np.int64)[order], np.array(ins, bool)[order]))
+    return out
+
+
 def log_uniform_int(rng: np.random.Generator, lo: float, hi: float, size=None) -> np.ndarray:
     return np.round(np.exp(rng.uniform(np.log(lo), np.log(hi), size=size))).astype(np.int64)
 

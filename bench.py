@@ -57,6 +57,8 @@ def parse():
                     default="medium")
     ap.add_argument("--sweep-sizes", default="20e6,30e6,40e6,55e6", help="sweep: hyperedge counts")
     ap.add_argument("--requests", type=int, default=256, help="served: number of requests")
+    ap.add_argument("--rate-multiples", default="0.5,1,2,4",
+                    help="served: offered request rates as multiples of the plain path's request rate")
     ap.add_argument("--scale", type=float, default=1.0, help="workload scale (1.0 = the named configuration)")
     ap.add_argument("--cpu-sample", type=int, default=600, help="updates in the oracle's timed sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -342,6 +344,13 @@ def bench_batched(args):
 
 
 def bench_served(args):
+    """Served form: every request is first applied alone, one at a time, on one
+    copy of the tenants (plain); then, on another copy held by a request
+    server, the requests arrive as a Poisson stream: consecutive segments of the
+    generator's arrival sequence are replayed at rates that are multiples of
+    the plain path's request rate (the arrival gaps rescaled), the last
+    segment submitted at once (saturation).  Every served result must equal the
+    plain one.  p50/p99 per rate are per request, submission to completion."""
     import numpy as np
     import torch
     from paper_2512_21009_amd import hgt
@@ -349,11 +358,12 @@ def bench_served(args):
     fams = W.FAMILIES
     t0 = time.perf_counter()
     sc = args.scale
-    sv = W.served(total_edges=20e6 * sc, n_requests=args.requests, req_hi=max(10.0, 1e5 * sc), card_hi=256)
+    gen_rate = 1000.0  # requests/s of the generator's arrival process
+    sv = W.served(total_edges=20e6 * sc, n_requests=args.requests, req_hi=max(10.0, 1e5 * sc), card_hi=256,
+                  rate_per_s=gen_rate)
     n_req = len(sv.arrivals)
     log(args, f"generated {len(sv.tenants)} tenants, {sum(t.initial.n for t in sv.tenants)} hyperedges, "
               f"{n_req} requests in {time.perf_counter() - t0:.1f}s")
-    # deletion IDs: a store-only replay of each tenant's requests in order
     ins = [[(to_dev(b.ins.offsets, np.int64) if b.ins.n else None, to_dev(b.ins.members, np.int32) if b.ins.n else None)
             for b in st.batches] for st in sv.tenants]
     dels = [ids_of_stream(hgt, st, i) for st, i in zip(sv.tenants, ins)]
@@ -369,12 +379,11 @@ def bench_served(args):
     t0 = time.perf_counter()
     plain = []
     for i, st in enumerate(sv.tenants):
-        tb = time.perf_counter()
         plain.append(hgt.Graph.build(*build_args(st), track=fams, window=st.window))
         torch.cuda.synchronize()
-        log(args, f"tenant {i}: {st.initial.n} hyperedges built in {time.perf_counter() - tb:.2f}s")
+        if i % 16 == 15:
+            log(args, f"plain: {i + 1} tenants built, {time.perf_counter() - t0:.1f}s")
     build_s = time.perf_counter() - t0
-    log(args, f"built {len(plain)} tenants in {build_s:.2f}s")
     ups = [sv.tenants[tn].batches[k].n_updates for (_, tn, k, _) in sv.arrivals]
     # plain: one request at a time, in arrival order
     lat_p, want = [], []
@@ -386,17 +395,18 @@ def bench_served(args):
         torch.cuda.synchronize()
         lat_p.append(time.perf_counter() - tb)
         want.append(g.triad_counts(fam))
-        if i % 32 == 31:
+        if i % 64 == 63:
             log(args, f"plain: {i + 1} requests, {sum(lat_p):.2f}s")
     for g in plain:
         assert g.sync() == hgt.OK
         g.close()
     del plain
-    # served: a server over an identical copy, every request submitted at once
+    plain_rate = n_req / sum(lat_p)
+    # served: a server over an identical copy
     srv = hgt.Server(hbm_budget_bytes=64 << 30, arena_bytes=2 << 30)
     for i, st in enumerate(sv.tenants):
         srv.add_tenant(*build_args(st), track=fams, window=st.window)
-        if i % 8 == 7:
+        if i % 16 == 15:
             log(args, f"server: {i + 1} tenants built")
     torch.cuda.synchronize()
     reqs = []
@@ -404,35 +414,57 @@ def bench_served(args):
         b = sv.tenants[tn].batches[k]
         reqs.append((tn, del_host[tn][k], b.ins.offsets.astype(np.uint64), b.ins.members.astype(np.uint32),
                      b.ins.ts.astype(np.int64)))
-    t_start = time.perf_counter()
-    tickets = [srv.submit(*r) for r in reqs]
-    res = [srv.wait(t) for t in tickets]
-    el = time.perf_counter() - t_start
+    mults = [float(x) for x in args.rate_multiples.split(",")]
+    seg = np.array_split(np.arange(n_req), len(mults) + 1)  # the last segment: all at once
+    arr_us = np.array([a[0] for a in sv.arrivals])
+    res = [None] * n_req
+    sweep = []
+    for si, idx in enumerate(seg):
+        rate = plain_rate * mults[si] if si < len(mults) else float("inf")
+        offs = (arr_us[idx] - arr_us[idx[0]]) * 1e-6 * (gen_rate / rate) if si < len(mults) else np.zeros(len(idx))
+        t_start = time.perf_counter()
+        tickets = []
+        for j, off in zip(idx, offs):
+            while time.perf_counter() - t_start < off:
+                time.sleep(min(0.001, max(0.0, off - (time.perf_counter() - t_start))))
+            tickets.append((j, srv.submit(*reqs[j])))
+        for j, t in tickets:
+            res[j] = srv.wait(t)
+        el = time.perf_counter() - t_start
+        lat = np.array([(res[j]["t_done_ns"] - res[j]["t_submit_ns"]) * 1e-6 for j in idx])
+        n_u = int(sum(ups[j] for j in idx))
+        sweep.append({"rate_req_per_s": None if rate == float("inf") else round(rate, 2),
+                      "offered": "all at once" if rate == float("inf") else f"{mults[si]}x plain request rate",
+                      "requests": len(idx), "updates_per_s": round(n_u / el, 1),
+                      "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
+                      "plain_updates_per_s": round(n_u / sum(lat_p[j] for j in idx), 1)})
+        log(args, f"served segment {si}: {sweep[-1]}")
     info = srv.info()
     for i, (r, (_, tn, k, fam)) in enumerate(zip(res, sv.arrivals)):
         assert r["status"] == hgt.OK, (i, r["status"])
         assert r[fam] == want[i], f"request {i}: served and plain counts differ"
     srv.close()
     calibration_copy()
-    n_upd = sum(ups)
-    v_s, v_p = n_upd / el, n_upd / sum(lat_p)
-    lat_s = np.array([(r["t_done_ns"] - r["t_submit_ns"]) * 1e-6 for r in res])
+    sat = sweep[-1]
+    v_s = sat["updates_per_s"]
+    v_p = sat["plain_updates_per_s"]
     lp = np.array(lat_p) * 1e3
-    log(args, f"plain {v_p:,.0f} updates/s, served {v_s:,.0f} updates/s ({v_s / v_p:.2f}x); "
-              f"rounds {info['rounds']}, largest round {info['max_round_size']}")
+    log(args, f"saturation: served {v_s:,.0f} updates/s vs plain {v_p:,.0f} ({v_s / v_p:.2f}x); "
+              f"rounds {info['rounds']}, largest round {info['max_round_size']}, rounds in flight {info['max_inflight_seen']}")
     return {
-        "metric": METRIC, "value": round(v_s, 1), "unit": "updates/s", "n_gpus": 1, "steps": n_req, "warmup": 0,
-        "ms_per_step": round(el / n_req * 1e3, 3),
-        "p50_ms": round(float(np.percentile(lat_s, 50)), 3), "p99_ms": round(float(np.percentile(lat_s, 99)), 3),
+        "metric": METRIC, "value": v_s, "unit": "updates/s", "n_gpus": 1, "steps": n_req, "warmup": 0,
+        "ms_per_step": None, "p50_ms": sat["p50_ms"], "p99_ms": sat["p99_ms"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
-        "config": {"workload": "served: 64 tenants, 20M hyperedges, |V_t|=|E_t|/2, card power-law 2.0 on [2,256], "
-                               "popularity (rank+3e3)^-1.3, requests log-uniform [1,1e5] (half inserts), all "
-                               "families tracked, all requests submitted at once",
-                   "scale": sc, "requests": n_req, "updates": int(n_upd), "build_s": round(build_s, 3),
-                   "rounds": info["rounds"], "max_round_size": info["max_round_size"]},
-        "plain": {"value": round(v_p, 1), "p50_ms": round(float(np.percentile(lp, 50)), 3),
+        "config": {"workload": "served: 64 tenants, |V_t|=|E_t|/2, card power-law 2.0 on [2,256] (cap), popularity "
+                               "(rank+3e3)^-1.3, Poisson timestamps, requests log-uniform [1,1e5*scale] (half "
+                               "inserts), all families tracked, Poisson arrivals swept to saturation",
+                   "scale": sc, "total_hyperedges": int(sum(t.initial.n for t in sv.tenants)), "requests": n_req,
+                   "build_s": round(build_s, 3), "rounds": info["rounds"], "max_round_size": info["max_round_size"],
+                   "max_rounds_in_flight": info["max_inflight_seen"]},
+        "plain": {"value": v_p, "request_rate": round(plain_rate, 2), "p50_ms": round(float(np.percentile(lp, 50)), 3),
                   "p99_ms": round(float(np.percentile(lp, 99)), 3)},
         "speedup_vs_plain": round(v_s / v_p, 3),
+        "rate_sweep": sweep,
         "roofline": None,
     }, sv
 

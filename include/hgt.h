@@ -277,6 +277,13 @@ int hgt_sync(hgt_graph* g, int* status);
 /* Releases every device buffer of the graph. */
 int hgt_destroy(hgt_graph* g);
 
+/* Moves every live incidence list into fresh pools, dropping the blocks of
+ * free IDs and the blocks that relocated lists left behind (the pools only
+ * grow otherwise).  Counts and contents are unchanged.  A batch runs this by
+ * itself first when a pool holds more than twice what its live lists need;
+ * the no-allocation entry point never does.  Waits for `stream`. */
+int hgt_compact(hgt_graph* g, void* stream);
+
 const char* hgt_status_str(int status);
 
 /* ---- introspection (tests, tools) -------------------------------------- */
@@ -291,6 +298,7 @@ typedef struct {
     uint64_t v2h_pool_words, v2h_used_words;
     int64_t temporal_window;
     uint64_t batches;        /* batches applied since build                     */
+    uint64_t compactions;    /* pool compactions since build                    */
 } hgt_info;
 
 int hgt_get_info(hgt_graph* g, hgt_info* out);

@@ -263,6 +263,7 @@ struct hgt_graph {
     uint32_t epoch = 0;
     int sticky = HGT_OK;
     uint64_t batches = 0;
+    uint64_t compactions = 0;       // pool compactions since build
     int force_stage = 0;            // HGT_FORCE_STAGE (tests): see He2Params
     int pair_agg = 1;               // HGT_PAIR_AGG=0: pairs enumerated per run (see He2Params)
     int global_wg_per_cu = 4;       // HGT_GLOBAL_WG_PER_CU: workgroups per CU of the global stage
@@ -496,6 +497,12 @@ void phase_ctx_free(PhaseCtx& c) {
 std::mutex g_ctx_mu;
 std::vector<PhaseCtx*> g_ctx;  // by device
 
+// The phase scratch a call on this thread uses: the request server gives each
+// of its in-flight rounds its own, so their triad phases can overlap on the
+// device; every other call uses the device's shared one.
+thread_local PhaseCtx* t_ph = nullptr;
+PhaseCtx& ctx_of(hgt_graph* g) { return t_ph ? *t_ph : *g->ph; }
+
 PhaseCtx* phase_ctx_acquire(int device) {
     std::lock_guard<std::mutex> lk(g_ctx_mu);
     if ((int)g_ctx.size() <= device) g_ctx.resize(device + 1, nullptr);
@@ -710,7 +717,7 @@ int phase_reserve(PhaseCtx& c, int family, const PhaseShape& z) {
 // histogram stages pass on, 6-8 temporal, 10-11 entry count, 16-18 stage queues,
 // 19-21 stage hand-over counts.
 int run_phase(hgt_graph* owner, const PhaseJob* jobs, uint32_t nj, bool minus, bool full, hipStream_t s) {
-    PhaseCtx& c = *owner->ph;
+    PhaseCtx& c = ctx_of(owner);
     uint64_t* stats = owner->prof ? owner->stats.as<uint64_t>() : nullptr;
     std::vector<HeGraph> G;
     std::vector<uint64_t> base, id_base;
@@ -985,7 +992,7 @@ inline unsigned iv_grid_global(const hgt_graph* g) { return t_na ? 16u : (unsign
 inline unsigned iv_grid_global2() { return t_na ? 2u : 32u; }
 
 int iv_reserve(hgt_graph* g, const IvPlan& ip) {
-    PhaseCtx& c = *g->ph;
+    PhaseCtx& c = ctx_of(g);
     if (ensure(c.iv_list, (ip.n_keys + 1) * 4) || ensure(c.iv_list2, (ip.n_keys + 1) * 4) ||
         ensure(c.iv_garena, (uint64_t)iv_grid_global(g) * kIvGarenaWords * 4) ||
         ensure(c.iv_garena2, (uint64_t)iv_grid_global2() * kIvGarena2Words * 4))
@@ -997,7 +1004,7 @@ int iv_phase(hgt_graph* g, const IvPlan& ip, bool minus, hipStream_t s) {
     if (ip.n_keys == 0) return HGT_OK;
     const uint64_t gwords = kIvGarenaWords;
     const unsigned grid_g = iv_grid_global(g);
-    PhaseCtx& c = *g->ph;
+    PhaseCtx& c = ctx_of(g);
     if (int rc = iv_reserve(g, ip)) return rc;
     IvParams P{};
     P.g = view_of(g);
@@ -1048,6 +1055,71 @@ struct Pending {
     int rc = HGT_OK;  // this batch's result so far
 };
 
+// Moves every live list into fresh pools: the blocks of free IDs and the
+// blocks that relocated lists left behind are dropped (the pools otherwise
+// only grow).  Queued on s after the graph's earlier work; waits for s.
+int compact_pools(hgt_graph* g, hipStream_t s) {
+    if (g->last_stream != s) HIP_OK(hipStreamSynchronize(g->last_stream));
+    const uint64_t n_ids = g->next_id, V = g->st.n_vertices;
+    const uint64_t nmax = std::max<uint64_t>(n_ids, V) + 1;
+    DevBuf need_h, need_v, off_h, off_v, tmp, tot;
+    DevBuf h2v_new, hpool_new, v2h_new, ts_new;
+    auto cleanup = [&] {
+        for (DevBuf* b : {&need_h, &need_v, &off_h, &off_v, &tmp, &tot, &h2v_new, &hpool_new, &v2h_new, &ts_new})
+            dev_free(*b);
+    };
+    int rc = 0;
+    rc |= dev_alloc(need_h, nmax * 8);
+    rc |= dev_alloc(need_v, nmax * 8);
+    rc |= dev_alloc(off_h, nmax * 8);
+    rc |= dev_alloc(off_v, nmax * 8);
+    rc |= dev_alloc(tmp, hgt_scan_tmp_bytes(nmax));
+    rc |= dev_alloc(tot, 64);
+    if (rc) { cleanup(); return HGT_ENOMEM; }
+    uint64_t* t = tot.as<uint64_t>();
+    hgt_fill_u64(t, 0, 2, s);
+    store_compact_need(g->st, n_ids, need_h.as<uint64_t>(), need_v.as<uint64_t>(), s);
+    if (n_ids) hgt_scan_u64(need_h.as<uint64_t>(), off_h.as<uint64_t>(), n_ids, nullptr, t, tmp.p, s);
+    hgt_scan_u64(need_v.as<uint64_t>(), off_v.as<uint64_t>(), V, nullptr, t + 1, tmp.p, s);
+    uint64_t totals[2] = {0, 0};
+    if (hip_failed(hipMemcpyAsync(totals, t, 16, hipMemcpyDeviceToHost, s), "compact totals", __LINE__) ||
+        hip_failed(hipStreamSynchronize(s), "compact sync", __LINE__)) {
+        cleanup();
+        return HGT_EDEVICE;
+    }
+    const uint64_t hw = totals[0] + totals[0] / 4 + 1024, vw = totals[1] + totals[1] / 4 + 1024;
+    const bool he = g->track_mask & (1u << HGT_TRIAD_HYPEREDGE), tm = g->track_mask & (1u << HGT_TRIAD_TEMPORAL);
+    rc |= dev_alloc(h2v_new, hw * 4);
+    rc |= dev_alloc(v2h_new, vw * 4);
+    if (he) rc |= dev_alloc(hpool_new, hw * 8);
+    if (tm) rc |= dev_alloc(ts_new, vw * 8);
+    if (rc) { cleanup(); return HGT_ENOMEM; }
+    store_compact_h2v(g->st, n_ids, need_h.as<uint64_t>(), off_h.as<uint64_t>(), h2v_new.as<uint32_t>(),
+                      he ? g->hpool.as<uint32_t>() : nullptr, he ? hpool_new.as<uint32_t>() : nullptr, s);
+    store_compact_v2h(g->st, need_v.as<uint64_t>(), off_v.as<uint64_t>(), v2h_new.as<uint32_t>(),
+                      tm ? ts_new.as<int64_t>() : nullptr, s);
+    store_compact_scalars(g->st.sc, t, t + 1, s);
+    if (hip_failed(hipStreamSynchronize(s), "compact copy", __LINE__)) { cleanup(); return HGT_EDEVICE; }
+    std::swap(g->h2v, h2v_new);
+    std::swap(g->v2h, v2h_new);
+    if (he) std::swap(g->hpool, hpool_new);
+    if (tm) std::swap(g->v2h_ts, ts_new);
+    cleanup();  // frees the old pools (now in the *_new buffers) and the scratch
+    g->h_bump = totals[0];
+    g->v_bump = totals[1];
+    g->compactions++;
+    refresh_view(g);
+    return HGT_OK;
+}
+
+// The pools hold more than twice what their live lists need (power-of-two
+// blocks of at least 4 words), plus 1M words of slack.
+bool pools_bloated(const hgt_graph* g) {
+    const uint64_t h_est = 2 * g->n_inc + 4 * g->n_live;
+    const uint64_t v_est = 2 * g->n_inc + 4 * std::min<uint64_t>(g->st.n_vertices, g->n_inc);
+    return g->h_bump > 2 * h_est + (1ull << 20) || g->v_bump > 2 * v_est + (1ull << 20);
+}
+
 // Host checks, scratch, and the non-mutating planning pass; the summary is
 // copied to pinned memory, read after the caller synchronises.
 int plan_begin(Pending& p, const uint32_t* del, uint64_t n_del, const uint64_t* ins_off, const uint32_t* ins_mem,
@@ -1059,8 +1131,10 @@ int plan_begin(Pending& p, const uint32_t* del, uint64_t n_del, const uint64_t* 
     if (n_ins > 0xfffffff0ull || n_del > 0xfffffff0ull) return HGT_EINVAL;
     if (n_mem > n_ins * (uint64_t)HGT_MAX_CARD) return HGT_EINVAL;
     if (n_del > g->n_live) return HGT_ENOENT;
+    int rc;
+    if (!t_na && pools_bloated(g) && (rc = compact_pools(g, s))) return rc;
     g->last_stream = s;
-    int rc = ensure_id_cap(g, g->next_id + n_ins + 1, s);
+    rc = ensure_id_cap(g, g->next_id + n_ins + 1, s);
     if (rc) return rc;
     g->st.next_id_host = g->next_id;
     g->st.hb = bits_for(g->next_id + n_ins);
@@ -1132,7 +1206,7 @@ PhaseJob job_plus(const Pending& p) {
 // arena before the first kernel that changes the graph, so a batch whose
 // scratch does not fit is rejected with nothing changed.
 int reserve_all_phases(hgt_graph* owner, std::vector<Pending*>& ps) {
-    PhaseCtx& c = *owner->ph;
+    PhaseCtx& c = ctx_of(owner);
     std::vector<HeGraph> G;
     std::vector<uint64_t> base, id_base;
     for (int phase = 0; phase < 2; phase++) {
@@ -1210,7 +1284,7 @@ int apply_locked(hgt_graph* owner, std::vector<Pending*>& ps, hipStream_t s) {
 }
 
 int apply_planned(hgt_graph* owner, std::vector<Pending*>& ps, hipStream_t s) {
-    PhaseCtx& c = *owner->ph;
+    PhaseCtx& c = ctx_of(owner);
     std::lock_guard<std::mutex> lk(c.mu);
     HIP_OK(hipStreamWaitEvent(s, c.done, 0));
     int rc = apply_locked(owner, ps, s);
@@ -1276,6 +1350,27 @@ void destroy_graph(hgt_graph* g) {
 }  // namespace
 
 // ---- hooks for the request server (internal.h) -----------------------------
+PhaseCtx* hgt_phase_ctx_create(int device) {
+    PhaseCtx* c = new (std::nothrow) PhaseCtx();
+    if (!c) return nullptr;
+    c->device = device;
+    if (hipEventCreateWithFlags(&c->done, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        delete c;
+        return nullptr;
+    }
+    return c;
+}
+
+void hgt_phase_ctx_destroy(PhaseCtx* c) {
+    if (!c) return;
+    (void)hipEventSynchronize(c->done);
+    phase_ctx_free(*c);
+    delete c;
+}
+
+void hgt_use_phase_ctx(PhaseCtx* c) { t_ph = c; }
+
 int hgt_counts_async(hgt_graph* g, uint64_t* dst, hipStream_t s) {
     static_assert(CNT_N == HGT_COUNT_WORDS, "count layout");
     HIP_OK(hipMemcpyAsync(dst, g->counts.p, CNT_N * 8, hipMemcpyDeviceToHost, s));
@@ -1634,6 +1729,14 @@ int hgt_destroy(hgt_graph* g) {
     return HGT_OK;
 }
 
+int hgt_compact(hgt_graph* g, void* stream) {
+    if (!g) return HGT_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    int rc = compact_pools(g, s);
+    if (!rc) g->last_stream = s;
+    return rc;
+}
+
 int hgt_get_info(hgt_graph* g, hgt_info* o) {
     if (!g || !o) return HGT_EINVAL;
     HIP_OK(hipStreamSynchronize(g->last_stream));
@@ -1649,6 +1752,7 @@ int hgt_get_info(hgt_graph* g, hgt_info* o) {
     o->v2h_used_words = g->v_bump;
     o->temporal_window = g->window;
     o->batches = g->batches;
+    o->compactions = g->compactions;
     return HGT_OK;
 }
 

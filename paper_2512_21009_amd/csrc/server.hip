@@ -5,9 +5,10 @@
 // arrival order, admits those whose tenant is idle and whose buffers and
 // footprint fit, stages their inputs into a device arena, and applies them as
 // one round through hgt_apply_batches (one planning wait for the whole round,
-// shared triad launches).  Rounds alternate between two streams, so the
-// planning of round k+1 runs while round k's triad phases are still on the
-// GPU; completion is observed through an event per round.
+// shared triad launches).  Rounds alternate between two streams, each with
+// its own triad-phase scratch, so round k+1 is planned and its triad phases
+// run while round k's are still on the GPU; completion is observed through an
+// event per round.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -105,6 +106,7 @@ struct hgt_server {
     hgt_server_desc desc{};
     int device = 0;
     hipStream_t streams[2] = {nullptr, nullptr};
+    PhaseCtx* ctx[2] = {nullptr, nullptr};  // phase scratch of the rounds on each stream
     void* d_arena = nullptr;   // device
     char* h_arena = nullptr;   // pinned mirror
     RangeAlloc arena;
@@ -184,7 +186,10 @@ int launch_round(hgt_server* s, Round* R) {
         b.n_ins = q->n_ins;
         b.out_ins_ids = q->n_ins ? (uint32_t*)(D + q->o_ids) : nullptr;
     }
+    // the round's own phase scratch: rounds on the two streams overlap on the device
+    hgt_use_phase_ctx(s->ctx[R->stream]);
     (void)hgt_apply_batches(bs.data(), (uint32_t)bs.size(), st);
+    hgt_use_phase_ctx(nullptr);
     for (size_t i = 0; i < R->reqs.size(); i++) {
         Request* q = R->reqs[i];
         q->res.status = bs[i].status;
@@ -370,6 +375,10 @@ int hgt_server_create(const hgt_server_desc* d, hgt_server** out) {
             rc = HGT_EDEVICE;
             break;
         }
+        if (!(s->ctx[0] = hgt_phase_ctx_create(s->device)) || !(s->ctx[1] = hgt_phase_ctx_create(s->device))) {
+            rc = HGT_ENOMEM;
+            break;
+        }
         if (hipMalloc(&s->d_arena, s->desc.arena_bytes) != hipSuccess ||
             hipHostMalloc((void**)&s->h_arena, s->desc.arena_bytes, hipHostMallocDefault) != hipSuccess) {
             rc = HGT_ENOMEM;
@@ -380,6 +389,7 @@ int hgt_server_create(const hgt_server_desc* d, hgt_server** out) {
         (void)hipGetLastError();
         if (s->d_arena) (void)hipFree(s->d_arena);
         if (s->h_arena) (void)hipHostFree(s->h_arena);
+        for (PhaseCtx* c : s->ctx) hgt_phase_ctx_destroy(c);
         for (hipStream_t st : s->streams)
             if (st) (void)hipStreamDestroy(st);
         delete s;
@@ -525,6 +535,7 @@ int hgt_server_destroy(hgt_server* s) {
     for (auto& kv : s->by_ticket) delete kv.second;
     for (hgt_graph* g : s->tenants) hgt_destroy(g);
     for (hipEvent_t e : s->ev_pool) (void)hipEventDestroy(e);
+    for (PhaseCtx* c : s->ctx) hgt_phase_ctx_destroy(c);
     (void)hipFree(s->d_arena);
     (void)hipHostFree(s->h_arena);
     for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);

@@ -103,3 +103,16 @@ void store_commit(StoreDev& g, BatchIn& b, PlanScratch& w, const BatchSummary& s
 void store_max_ts(const int64_t* ts, uint64_t n, DevScalars* sc, hipStream_t s);
 void store_counts_update(uint64_t* counts, const uint64_t* plus, const uint64_t* minus, int n,
                          const DevScalars* sc, hipStream_t s);
+
+// Compaction of the pools (every live list into a fresh pool; the blocks of
+// free IDs and the blocks left behind by relocations are dropped):
+// per-ID / per-vertex block words (0 for free IDs and empty lists) ...
+void store_compact_need(const StoreDev& g, uint64_t n_ids, uint64_t* h_need, uint64_t* v_need, hipStream_t s);
+// ... and, after the caller's exclusive scans gave new offsets and fresh pools,
+// the copies (h2v with its 2-word-per-word histograms, v2h with its
+// timestamps, either side array may be NULL) and the new offsets/capacities.
+void store_compact_h2v(const StoreDev& g, uint64_t n_ids, const uint64_t* need, const uint64_t* new_off,
+                       uint32_t* h2v_new, const uint32_t* hpool, uint32_t* hpool_new, hipStream_t s);
+void store_compact_v2h(const StoreDev& g, const uint64_t* need, const uint64_t* new_off, uint32_t* v2h_new,
+                       int64_t* v2h_ts_new, hipStream_t s);
+void store_compact_scalars(DevScalars* sc, const uint64_t* h_total, const uint64_t* v_total, hipStream_t s);

@@ -16,6 +16,8 @@
 // region (Cases 2 and 3: block sizes -> prefix sum -> start addresses).
 // Every kernel that runs before the host has read the batch summary leaves
 // the graph unchanged, so a rejected batch has no effect.
+#include <algorithm>
+
 #include "store.h"
 
 namespace {
@@ -490,12 +492,95 @@ __global__ void k_counts_update(uint64_t* counts, const uint64_t* plus, const ui
     if (i < n) counts[i] += plus[i] - minus[i];
 }
 
+// ---------------------------------------------------------------------------
+// compaction: every live list moved into a fresh pool, blocks of dead IDs and
+// blocks left behind by relocations dropped
+// ---------------------------------------------------------------------------
+__global__ void k_cmp_hneed(uint64_t n_ids, const uint64_t* __restrict__ free_bm, const uint32_t* __restrict__ h_len,
+                            uint64_t* need) {
+    for (uint64_t id = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; id < n_ids;
+         id += (uint64_t)gridDim.x * blockDim.x) {
+        const bool live = !((free_bm[id >> 6] >> (id & 63)) & 1ull);
+        const uint64_t len = h_len[id];
+        need[id] = live ? pow2ceil64(len < 4 ? 4 : len) : 0;
+    }
+}
+
+__global__ void k_cmp_vneed(uint64_t n_vertices, const uint32_t* __restrict__ v_len, uint64_t* need) {
+    for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n_vertices;
+         v += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t len = v_len[v];
+        need[v] = len ? pow2ceil64(len < 4 ? 4 : len) : 0;
+    }
+}
+
+// one wave per list: `len` words (and `side` words per word of a side array
+// that follows the pool: histograms, timestamps) to the list's new offset
+template <class S>
+__global__ void k_cmp_copy(uint64_t n, const uint64_t* __restrict__ need, const uint64_t* __restrict__ new_off,
+                           const uint64_t* __restrict__ old_off, const uint32_t* __restrict__ len,
+                           const uint32_t* __restrict__ pool, uint32_t* pool_new, const S* __restrict__ side,
+                           S* side_new, int side_per_word) {
+    const int lane = threadIdx.x & 63;
+    for (uint64_t i = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; i < n;
+         i += ((uint64_t)gridDim.x * blockDim.x) >> 6) {
+        if (!need[i]) continue;
+        const uint64_t o = old_off[i], d = new_off[i], l = len[i];
+        for (uint64_t k = lane; k < l; k += 64) pool_new[d + k] = pool[o + k];
+        if (side)
+            for (uint64_t k = lane; k < l * side_per_word; k += 64)
+                side_new[d * side_per_word + k] = side[o * side_per_word + k];
+    }
+}
+
+__global__ void k_cmp_commit(uint64_t n, const uint64_t* __restrict__ need, const uint64_t* __restrict__ new_off,
+                             uint64_t* off, uint32_t* cap) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+        off[i] = need[i] ? new_off[i] : 0;
+        cap[i] = (uint32_t)need[i];
+    }
+}
+
+__global__ void k_cmp_scalars(DevScalars* sc, const uint64_t* h_total, const uint64_t* v_total) {
+    if (threadIdx.x || blockIdx.x) return;
+    sc->h_bump = *h_total;
+    sc->v_bump = *v_total;
+}
+
 inline unsigned blocks_for(uint64_t n, unsigned per = 256) {
     uint64_t b = (n + per - 1) / per;
     return (unsigned)(b ? b : 1);
 }
 
 }  // namespace
+
+void store_compact_need(const StoreDev& g, uint64_t n_ids, uint64_t* h_need, uint64_t* v_need, hipStream_t s) {
+    if (n_ids) k_cmp_hneed<<<blocks_for(n_ids > 262144 ? 262144 : n_ids), 256, 0, s>>>(n_ids, g.free_bm, g.h_len, h_need);
+    const uint64_t V = g.n_vertices;
+    k_cmp_vneed<<<blocks_for(V > 262144 ? 262144 : V), 256, 0, s>>>(V, g.v_len, v_need);
+}
+
+void store_compact_h2v(const StoreDev& g, uint64_t n_ids, const uint64_t* need, const uint64_t* new_off,
+                       uint32_t* h2v_new, const uint32_t* hpool, uint32_t* hpool_new, hipStream_t s) {
+    if (!n_ids) return;
+    const unsigned grid = (unsigned)std::min<uint64_t>(65536, (n_ids * 64 + 255) / 256);
+    k_cmp_copy<uint32_t><<<grid, 256, 0, s>>>(n_ids, need, new_off, g.h_off, g.h_len, g.h2v, h2v_new, hpool,
+                                              hpool_new, 2);
+    k_cmp_commit<<<blocks_for(n_ids > 262144 ? 262144 : n_ids), 256, 0, s>>>(n_ids, need, new_off, g.h_off, g.h_cap);
+}
+
+void store_compact_v2h(const StoreDev& g, const uint64_t* need, const uint64_t* new_off, uint32_t* v2h_new,
+                       int64_t* v2h_ts_new, hipStream_t s) {
+    const uint64_t V = g.n_vertices;
+    const unsigned grid = (unsigned)std::min<uint64_t>(65536, (V * 64 + 255) / 256);
+    k_cmp_copy<int64_t><<<grid, 256, 0, s>>>(V, need, new_off, g.v_off, g.v_len, g.v2h, v2h_new, g.v2h_ts,
+                                             v2h_ts_new, 1);
+    k_cmp_commit<<<blocks_for(V > 262144 ? 262144 : V), 256, 0, s>>>(V, need, new_off, g.v_off, g.v_cap);
+}
+
+void store_compact_scalars(DevScalars* sc, const uint64_t* h_total, const uint64_t* v_total, hipStream_t s) {
+    k_cmp_scalars<<<1, 64, 0, s>>>(sc, h_total, v_total);
+}
 
 // ===========================================================================
 // host launchers

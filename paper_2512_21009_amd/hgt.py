@@ -57,6 +57,7 @@ class Info(ctypes.Structure):
         ("v2h_used_words", ctypes.c_uint64),
         ("temporal_window", ctypes.c_int64),
         ("batches", ctypes.c_uint64),
+        ("compactions", ctypes.c_uint64),
     ]
 
 
@@ -156,6 +157,7 @@ def load(path: str = LIB_PATH):
     lib.hgt_apply_batch_noalloc.argtypes = [P, P, U64, P, P, U64, P, U64, P, P]
     lib.hgt_apply_batches.argtypes = [P, U32, P]
     lib.hgt_apply_vertex_ops.argtypes = [P, P, P, P, U64, P]
+    lib.hgt_compact.argtypes = [P, P]
     lib.hgt_triad_counts.argtypes = [P, I32, I64, P, U32]
     lib.hgt_sync.argtypes = [P, ctypes.POINTER(I32)]
     lib.hgt_destroy.argtypes = [P]
@@ -382,6 +384,12 @@ class Graph:
         if rc != OK:
             raise HgtError(rc, "hgt_get_info")
         return {f: getattr(inf, f) for f, _ in Info._fields_}
+
+    def compact(self, stream=None):
+        """Move every live incidence list into fresh pools (see hgt_compact)."""
+        rc = load().hgt_compact(self._h, _stream(stream))
+        if rc != OK:
+            raise HgtError(rc, "hgt_compact")
 
     def profile(self, enable=True):
         """Reset the per-kernel-group profile and set its level: 0/False off,

@@ -302,3 +302,25 @@ def test_dyadic_graph_triangles(gpu_lib):
         iv = p.g.triad_counts("incident_vertex")
         assert iv[0] == 0 and iv[1] == 0 and iv[2] == triangles() > 0, (k, iv)
     p.close()
+
+
+def test_compaction_keeps_store_and_counts(gpu_lib):
+    """Pool compaction (every live list moved into fresh pools) in the middle of
+    a stream of batches: the used pool words shrink, and the exported store and
+    every count still equal the oracle's, also after the following batches."""
+    st = W.temporal_stream("compact", 80, 400, 120, 5, 2.0, 1, 9, 7.0, 2000, 400, seed=W.SEED_BASE + 600)
+    p = Pair(st, track=ALL)
+    for k, b in enumerate(st.batches):
+        p.apply(b, f"compaction batch {k}")
+        if k == 2:
+            before = p.g.info()
+            p.g.compact()
+            after = p.g.info()
+            assert after["compactions"] == before["compactions"] + 1
+            assert after["h2v_used_words"] < before["h2v_used_words"]
+            assert after["v2h_used_words"] < before["v2h_used_words"]
+            compare_store(p.g, p.o, "after compaction")
+            compare_counts(p.g, p.o, ALL, "after compaction")
+    compare_store(p.g, p.o, "compaction end")
+    compare_counts(p.g, p.o, ALL, "compaction end")
+    p.close()

@@ -57,6 +57,9 @@ def parse():
                     default="medium")
     ap.add_argument("--sweep-sizes", default="20e6,30e6,40e6,55e6", help="sweep: hyperedge counts")
     ap.add_argument("--requests", type=int, default=256, help="served: number of requests")
+    ap.add_argument("--launch", choices=("stream", "graph", "tuned"), default="graph",
+                    help="served: rounds launched kernel by kernel, as captured HIP graphs, or as graphs with the "
+                         "autotuner's launch choices")
     ap.add_argument("--rate-multiples", default="0.5,1,2,4",
                     help="served: offered request rates as multiples of the plain path's request rate")
     ap.add_argument("--scale", type=float, default=1.0, help="workload scale (1.0 = the named configuration)")
@@ -254,13 +257,19 @@ def bench_single(args, st, track, name, workload):
 
 
 def bench_batched(args):
-    """256 graphs; each round applies every graph's next batch, first with one
-    call per graph (plain), then, on an identical copy, with one call for all."""
+    """256 graphs; each round applies every graph's next batch.  Identical
+    copies take the same rounds (`warmup` untimed, then `steps` timed): one
+    call per graph (plain); one call for all with the kernels launched one by
+    one (stream); the same launched as one captured HIP graph per round
+    (graph); and the graph launch with the autotuner's choices (tuned), after a
+    pass over the same rounds on a copy of its own in which the tuner times its
+    choices.  The rounds after the timed ones are profiled on the stream copy."""
     import numpy as np
     import torch
     from paper_2512_21009_amd import hgt
     from paper_2512_21009_amd import workloads as W
-    n_timed_end = args.warmup + args.steps
+    n_timed_beg = args.warmup
+    n_timed_end = n_timed_beg + args.steps
     n_b = n_timed_end + max(1, args.prof_steps)
     t0 = time.perf_counter()
     sc = args.scale
@@ -269,7 +278,11 @@ def bench_batched(args):
               f"{sum(s.batches[0].n_updates for s in sts)} updates per round in {time.perf_counter() - t0:.1f}s")
     ins = [[(to_dev(b.ins.offsets, np.int64) if b.ins.n else None, to_dev(b.ins.members, np.int32) if b.ins.n else None)
             for b in st.batches] for st in sts]
-    dels = [ids_of_stream(hgt, st, i) for st, i in zip(sts, ins)]
+    dels = []
+    for gi, (st, i) in enumerate(zip(sts, ins)):
+        dels.append(ids_of_stream(hgt, st, i))
+        if gi % 64 == 63:
+            log(args, f"deletion IDs replayed for {gi + 1} graphs")
     track = ("hyperedge",)
 
     def build_all():
@@ -281,64 +294,76 @@ def bench_batched(args):
         torch.cuda.synchronize()
         return out
 
-    t0 = time.perf_counter()
-    plain = build_all()
-    build_s = time.perf_counter() - t0
-    batch = build_all()
-    log(args, f"built 2 x {len(sts)} graphs ({build_s:.2f}s per copy)")
     ups = [sum(st.batches[k].n_updates for st in sts) for k in range(n_b)]
-    # plain: one call per graph (the rounds after the timed ones keep the copies equal)
-    lat_p = []
-    for k in range(n_b):
-        torch.cuda.synchronize()
-        tb = time.perf_counter()
-        for gi, g in enumerate(plain):
-            g.apply_batch(dels[gi][k], *ins[gi][k])
-        torch.cuda.synchronize()
-        if args.warmup <= k < n_timed_end:
-            lat_p.append(time.perf_counter() - tb)
-    # batched: one call per round; the rounds after the timed ones are profiled
-    lat_b = []
-    for k in range(n_b):
-        if k == n_timed_end:
-            for g in batch:
-                g.profile(1)
-        items = [(g, dels[gi][k]) + ins[gi][k] for gi, g in enumerate(batch)]
-        torch.cuda.synchronize()
-        tb = time.perf_counter()
-        hgt.apply_batches(items)
-        torch.cuda.synchronize()
-        if args.warmup <= k < n_timed_end:
-            lat_b.append(time.perf_counter() - tb)
-    prof = {}
-    for g in batch:
-        add_profiles(prof, g.profile_read())
-    same = all(a.triad_counts("hyperedge") == b.triad_counts("hyperedge") for a, b in zip(plain, batch))
-    assert same, "batched and plain counts differ"
-    total = sum(sum(g.triad_counts("hyperedge")) for g in batch)
-    for g in plain + batch:
-        assert g.sync() == hgt.OK
-        g.close()
+    variants = [("plain", None), ("stream", {}), ("graph", {"graph": True}),
+                ("tuning", {"graph": True, "autotune": True}), ("tuned", {"graph": True, "autotune": True})]
+    lat, counts, prof = {}, {}, {}
+    build_s = 0.0
+    for name, kw in variants:
+        t0 = time.perf_counter()
+        gs = build_all()
+        build_s = time.perf_counter() - t0
+        lat[name] = []
+        log(args, f"{name}: built in {build_s:.2f}s")
+        rounds = n_b if name == "stream" else n_timed_end
+        for k in range(rounds):
+            if name == "stream" and k == n_timed_end:  # the rounds after the timed ones are profiled
+                for g in gs:
+                    g.profile(1)
+            torch.cuda.synchronize()
+            tb = time.perf_counter()
+            if kw is None:
+                for gi, g in enumerate(gs):
+                    g.apply_batch(dels[gi][k], *ins[gi][k])
+            else:
+                hgt.apply_batches([(g, dels[gi][k]) + ins[gi][k] for gi, g in enumerate(gs)], **kw)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - tb
+            if n_timed_beg <= k < n_timed_end:
+                lat[name].append(dt)
+            log(args, f"{name}: round {k} ({ups[k]} updates) {dt * 1e3:.1f} ms")
+            if name == "stream" and k == n_timed_end - 1:
+                counts["stream@timed"] = [g.triad_counts("hyperedge") for g in gs]
+        if name == "stream":
+            for g in gs:
+                add_profiles(prof, g.profile_read())
+        counts[name] = [g.triad_counts("hyperedge") for g in gs]
+        for g in gs:
+            assert g.sync() == hgt.OK
+            g.close()
+        log(args, f"{name}: {sum(ups[n_timed_beg:n_timed_end]) / sum(lat[name]):,.0f} updates/s "
+                  f"(build {build_s:.2f}s)")
+        if name == "tuning":
+            settled = hgt.tune_flush()
+    for name in ("plain", "graph", "tuning", "tuned"):
+        assert counts[name] == counts["stream@timed"], f"{name} and stream counts differ"
+    total = sum(sum(c) for c in counts["stream@timed"])
     calibration_copy()
-    n_upd = sum(ups[args.warmup:n_timed_end])
-    v_b = n_upd / sum(lat_b)
-    v_p = n_upd / sum(lat_p)
-    log(args, f"plain {v_p:,.0f} updates/s, batched {v_b:,.0f} updates/s ({v_b / v_p:.2f}x)")
+    n_upd = sum(ups[n_timed_beg:n_timed_end])
+    rate = {name: n_upd / sum(lat[name]) for name, _ in variants}
+    ms = {name: np.array(lat[name]) * 1e3 for name, _ in variants}
+    best = max(("stream", "graph", "tuned"), key=lambda n: rate[n])
+    log(args, f"plain {rate['plain']:,.0f}, stream {rate['stream']:,.0f}, graph {rate['graph']:,.0f}, "
+              f"tuned {rate['tuned']:,.0f} updates/s; tuner keys settled: {settled}")
     log_profile(args, prof)
-    lb, lp = np.array(lat_b) * 1e3, np.array(lat_p) * 1e3
+
+    def leg(n):
+        return {"value": round(rate[n], 1), "ms_per_step": round(float(ms[n].mean()), 3),
+                "p50_ms": round(float(np.percentile(ms[n], 50)), 3), "p99_ms": round(float(np.percentile(ms[n], 99)), 3)}
+
     return {
-        "metric": METRIC, "value": round(v_b, 1), "unit": "updates/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(float(lb.mean()), 3),
-        "p50_ms": round(float(np.percentile(lb, 50)), 3), "p99_ms": round(float(np.percentile(lb, 99)), 3),
+        "metric": METRIC, "value": round(rate[best], 1), "unit": "updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": n_timed_beg, "ms_per_step": round(float(ms[best].mean()), 3),
+        "p50_ms": round(float(np.percentile(ms[best], 50)), 3), "p99_ms": round(float(np.percentile(ms[best], 99)), 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
         "config": {"workload": "batched: 256 graphs, |E| log-uniform [1k,200k], |V|=|E|/2, card power-law 2.5 on "
                                "[2,256], batches log-uniform [10,50k] (60% inserts), hyperedge triads",
-                   "scale": sc, "round_updates": int(np.mean(ups[args.warmup:n_timed_end])),
-                   "build_s_per_copy": round(build_s, 3),
+                   "scale": sc, "round_updates": int(np.mean(ups[n_timed_beg:n_timed_end])),
+                   "build_s_per_copy": round(build_s, 3), "launch": best,
                    "he_triads_total": int(total)},
-        "plain": {"value": round(v_p, 1), "p50_ms": round(float(np.percentile(lp, 50)), 3),
-                  "p99_ms": round(float(np.percentile(lp, 99)), 3)},
-        "speedup_vs_plain": round(v_b / v_p, 3),
+        "plain": leg("plain"), "stream": leg("stream"), "graph": leg("graph"), "tuned": leg("tuned"),
+        "tuner_keys_settled": settled,
+        "speedup_vs_plain": round(rate[best] / rate["plain"], 3),
         "roofline": roofline_of(prof),
     }, sts
 
@@ -403,7 +428,8 @@ def bench_served(args):
     del plain
     plain_rate = n_req / sum(lat_p)
     # served: a server over an identical copy
-    srv = hgt.Server(hbm_budget_bytes=64 << 30, arena_bytes=2 << 30)
+    srv = hgt.Server(hbm_budget_bytes=64 << 30, arena_bytes=2 << 30, graph=args.launch != "stream",
+                     autotune=args.launch == "tuned")
     for i, st in enumerate(sv.tenants):
         srv.add_tenant(*build_args(st), track=fams, window=st.window)
         if i % 16 == 15:
@@ -460,7 +486,7 @@ def bench_served(args):
                                "inserts), all families tracked, Poisson arrivals swept to saturation",
                    "scale": sc, "total_hyperedges": int(sum(t.initial.n for t in sv.tenants)), "requests": n_req,
                    "build_s": round(build_s, 3), "rounds": info["rounds"], "max_round_size": info["max_round_size"],
-                   "max_rounds_in_flight": info["max_inflight_seen"]},
+                   "max_rounds_in_flight": info["max_inflight_seen"], "launch": args.launch},
         "plain": {"value": v_p, "request_rate": round(plain_rate, 2), "p50_ms": round(float(np.percentile(lp, 50)), 3),
                   "p99_ms": round(float(np.percentile(lp, 99)), 3)},
         "speedup_vs_plain": round(v_s / v_p, 3),

@@ -181,6 +181,38 @@ typedef struct {
  * applied, else the first failing batch's status. */
 int hgt_apply_batches(hgt_batch* batches, uint32_t n, void* stream);
 
+/* Flags of hgt_apply_batches_ex. */
+#define HGT_BATCHES_GRAPH 1u     /* the triad phases and the commit of the round
+                                  * are captured into a HIP graph (every scratch
+                                  * buffer reserved and every work descriptor
+                                  * uploaded first) and launched as one; the
+                                  * executable graph is kept per triad-scratch
+                                  * context and updated in place by the next
+                                  * round of the same shape.  Where the capture
+                                  * fails the round is launched kernel by kernel. */
+#define HGT_BATCHES_AUTOTUNE 2u  /* launch choices (workgroups per CU of the
+                                  * global histogram stage, whether centres skip
+                                  * the 148 KB stage, slots of the per-wave
+                                  * 2-hop hashes) picked per key of the round:
+                                  * tracked families, number of graphs, changes
+                                  * and the 2-hop load of the heaviest centre,
+                                  * in log2/log4 buckets.  Each choice is timed
+                                  * on live rounds (HIP events, read back without
+                                  * a wait), up to twice; one far slower than the
+                                  * best is dropped after its first trial; the
+                                  * fastest is kept and appended to the cache
+                                  * file named by
+                                  * HGT_TUNE_CACHE (default ~/.cache/hgt_tune.txt,
+                                  * "off": none), which later processes read. */
+
+/* hgt_apply_batches with flags (0: the same call).  Every choice gives the
+ * same results; only the launch differs.  HGT_EINVAL for unknown flags. */
+int hgt_apply_batches_ex(hgt_batch* batches, uint32_t n, void* stream, uint32_t flags);
+
+/* Waits for the autotuner's timed rounds, records what they measured, and
+ * returns in *n_settled (may be NULL) how many round keys have a kept choice. */
+int hgt_tune_flush(uint32_t* n_settled);
+
 /* ---- served form ------------------------------------------------------- */
 /* A request server over many resident hypergraphs ("tenants").  Clients
  * submit update batches from host memory at any time; a server thread merges
@@ -201,7 +233,9 @@ typedef struct {
     uint64_t hbm_budget_bytes;  /* footprint limit of the admitted requests     */
     uint64_t arena_bytes;       /* device arena for request buffers (0: 256 MiB) */
     uint32_t max_round;         /* most requests merged into one round (0: 256) */
-    uint32_t max_inflight;      /* rounds on the GPU at once, 1 or 2 (0: 2)      */
+    uint32_t max_inflight;      /* rounds on the GPU at once, 1..4 (0: 4)        */
+    uint32_t launch_flags;      /* HGT_BATCHES_* flags of every round (0: none)  */
+    uint32_t pad0;
 } hgt_server_desc;
 
 /* One update request (host buffers, copied by hgt_server_submit): the

@@ -4,8 +4,10 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "hops.h"
@@ -130,6 +132,19 @@ struct NoAllocArena {
     char stage[4][512];    // host staging of the per-graph phase descriptors (one graph)
 };
 thread_local NoAllocArena* t_na = nullptr;
+// Set while the post-planning half of a round is captured into a HIP graph:
+// nothing may allocate, wait or upload then (all of it was done before).
+thread_local int t_capture = 0;
+
+// Launch choices the autotuner picks between (workgroups per CU of the global
+// histogram stage, whether centres skip the 148 KB stage, slots of the 2-hop
+// kernels' per-wave hashes); t_tune overrides the graph's own for one round.
+struct TuneChoice {
+    int wg_per_cu, skip_lds148;
+    uint32_t wave_slots;
+};
+thread_local const TuneChoice* t_tune = nullptr;
+thread_local hipEvent_t t_tune_ev[2] = {nullptr, nullptr};  // recorded around an autotuned round's launches
 
 int dev_alloc(DevBuf& b, size_t bytes) {
     if (t_na) {  // the no-allocation entry point allocates nothing
@@ -179,6 +194,7 @@ int arena_take(NoAllocArena& a, DevBuf& b, size_t bytes) {
 int ensure(DevBuf& b, size_t bytes) {
     if (t_na) return arena_take(*t_na, b, bytes);
     if (b.p && b.bytes >= bytes) return HGT_OK;
+    if (t_capture) return HGT_ENOMEM;  // everything was reserved before the capture
     size_t nb = std::max(bytes, b.bytes + b.bytes / 2);
     nb = (nb + 4095) & ~(size_t)4095;
     dev_free(b);
@@ -234,6 +250,12 @@ struct PhaseCtx {
     char* desc_host = nullptr;
     uint64_t desc_cap = 0;       // graphs per slot
     hipEvent_t desc_ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    // HIP-graph launches of a round: descriptors uploaded before the capture, and
+    // the executable graph of the last round (updated in place when the next
+    // round's capture has the same shape)
+    Multi pre[4] = {};
+    bool pre_ok[4] = {false, false, false, false};
+    hipGraphExec_t gexec = nullptr;
 };
 
 struct hgt_graph {
@@ -307,7 +329,7 @@ struct ProfScope {
     hipStream_t s;
     hipEvent_t a = nullptr;
     ProfScope(hgt_graph* g_, int k, hipStream_t s_) : g(g_), kind(k), s(s_) {
-        if (g->prof && !t_na && (a = prof_event(g))) (void)hipEventRecord(a, s);
+        if (g->prof && !t_na && !t_capture && (a = prof_event(g))) (void)hipEventRecord(a, s);
     }
     ~ProfScope() {
         if (!a) return;
@@ -492,6 +514,8 @@ void phase_ctx_free(PhaseCtx& c) {
     c.desc_cap = 0;
     if (c.done) (void)hipEventDestroy(c.done);
     c.done = nullptr;
+    if (c.gexec) (void)hipGraphExecDestroy(c.gexec);
+    c.gexec = nullptr;
 }
 
 std::mutex g_ctx_mu;
@@ -548,6 +572,11 @@ inline size_t desc_slot_bytes(uint64_t cap) { return cap * sizeof(HeGraph) + 2 *
 int upload_multi(PhaseCtx& c, int slot, const std::vector<HeGraph>& G, const std::vector<uint64_t>& base,
                  const std::vector<uint64_t>& id_base, Multi& M, hipStream_t s) {
     const uint64_t n = G.size();
+    if (t_capture) {  // uploaded before the capture
+        if (!c.pre_ok[slot]) return HGT_EINVAL;
+        M = c.pre[slot];
+        return HGT_OK;
+    }
     if (t_na) {
         // no-allocation call (one graph): the four slots live in the arena and are
         // staged from the thread's arena record; the stream orders the copies
@@ -667,7 +696,7 @@ PhaseShape phase_shape(const hgt_graph* owner, uint64_t n, uint64_t max_lh, uint
     z.grid_small = std::min<uint64_t>(n_cu * 2, n);
     z.grid_tmp = std::min<uint64_t>(lean ? 32 : n_cu * 3, n);
     // 2-hop hashes in global memory, one per wave of the 2-hop kernels (64 KB each)
-    z.wave_slots = owner->wave_slots;
+    z.wave_slots = t_tune ? t_tune->wave_slots : owner->wave_slots;
     z.grid_2hop = std::max<uint64_t>(z.grid_big, z.grid_tmp);
     z.ecap = std::max<uint64_t>(sum_lh, 1);
     z.nb_words = 2 * pow2ceil64(2 * std::max<uint64_t>(z.lhm, 32)) + 3 * z.max_card + 8;
@@ -676,7 +705,8 @@ PhaseShape phase_shape(const hgt_graph* owner, uint64_t n, uint64_t max_lh, uint
     z.grid_s1 = std::min<uint64_t>(n_cu, n);
     // the global stage holds little LDS, so several workgroups share a CU and hide
     // each other's memory latency
-    z.grid_g = std::min<uint64_t>(lean ? 16 : n_cu * (uint64_t)owner->global_wg_per_cu, n);
+    const int wg_per_cu = t_tune ? t_tune->wg_per_cu : owner->global_wg_per_cu;
+    z.grid_g = std::min<uint64_t>(lean ? 16 : n_cu * (uint64_t)wg_per_cu, n);
     z.total_ids = total_ids;
     return z;
 }
@@ -796,7 +826,7 @@ int run_phase(hgt_graph* owner, const PhaseJob* jobs, uint32_t nj, bool minus, b
             E.phase_ticks = (stats && owner->prof_phases) ? 1 : 0;
             E.force_stage = owner->force_stage;
             E.pair_agg = owner->pair_agg;
-            E.skip_lds148 = owner->skip_lds148;
+            E.skip_lds148 = t_tune ? t_tune->skip_lds148 : owner->skip_lds148;
             E.static_mode = full ? 1 : 0;
             hgt_fill_u32(ctr + 16, 0, 6, s);
             hgt_fill_u32(ctr + 5, 0, 1, s);
@@ -1199,16 +1229,18 @@ PhaseJob job_plus(const Pending& p) {
                     p.sum.next_id_new};
 }
 
-// Applies the planned batches of `ps` (all with rc == 0) on stream s: deltas on
-// the old graphs, delete + insert, deltas on the new graphs, count update.  The
-// hyperedge and temporal phases of all graphs share one launch per kernel.
-// No-allocation call: every phase buffer of both phases is taken from the
-// arena before the first kernel that changes the graph, so a batch whose
-// scratch does not fit is rejected with nothing changed.
-int reserve_all_phases(hgt_graph* owner, std::vector<Pending*>& ps) {
+// Every scratch buffer of both phases, reserved before the first kernel that
+// changes the graph.  In a no-allocation call they come from the arena, so a
+// batch whose scratch does not fit is rejected with nothing changed.  With
+// upload_s non-NULL the descriptors of every (phase, family) are uploaded too,
+// for a round that is then captured into a HIP graph (a second pass if the
+// descriptor buffer had to grow under the first, which moves it).
+int reserve_all_phases(hgt_graph* owner, std::vector<Pending*>& ps, hipStream_t upload_s = nullptr) {
     PhaseCtx& c = ctx_of(owner);
     std::vector<HeGraph> G;
     std::vector<uint64_t> base, id_base;
+    const uint64_t cap0 = c.desc_cap;
+    for (int slot = 0; slot < 4; slot++) c.pre_ok[slot] = false;
     for (int phase = 0; phase < 2; phase++) {
         std::vector<PhaseJob> jobs;
         for (Pending* p : ps) jobs.push_back(phase == 0 ? job_minus(*p) : job_plus(*p));
@@ -1216,17 +1248,28 @@ int reserve_all_phases(hgt_graph* owner, std::vector<Pending*>& ps) {
             uint64_t max_lh, sum_lh;
             collect(jobs.data(), (uint32_t)jobs.size(), family, phase == 0, G, base, id_base, max_lh, sum_lh);
             if (base.back() == 0) continue;
-            const PhaseShape z = phase_shape(owner, base.back(), max_lh, sum_lh, id_base.back(), true);
+            const PhaseShape z = phase_shape(owner, base.back(), max_lh, sum_lh, id_base.back(), t_na != nullptr);
             if (int rc = phase_reserve(c, family, z)) return rc;
+            if (upload_s) {
+                const int slot = (phase == 0 ? 0 : 2) + (family == HGT_TRIAD_TEMPORAL ? 1 : 0);
+                if (int rc = upload_multi(c, slot, G, base, id_base, c.pre[slot], upload_s)) return rc;
+                c.pre_ok[slot] = true;
+            }
         }
     }
-    if (int rc = ensure(c.desc, 4 * desc_slot_bytes(1))) return rc;
+    if (upload_s && c.desc_cap != cap0) return reserve_all_phases(owner, ps, upload_s);
+    if (t_na)
+        if (int rc = ensure(c.desc, 4 * desc_slot_bytes(1))) return rc;
     for (Pending* p : ps)
         if ((p->g->track_mask & (1u << HGT_TRIAD_INCIDENT_VERTEX)) && p->ip.n_keys)
             if (int rc = iv_reserve(p->g, p->ip)) return rc;
     return HGT_OK;
 }
 
+// Applies the planned batches of `ps` (all with rc == 0) on stream s: deltas on
+// the old graphs, delete + insert, deltas on the new graphs, count update.  The
+// hyperedge and temporal phases of all graphs share one launch per kernel.
+// Changes no host state, so a round whose capture failed can be launched again.
 int apply_locked(hgt_graph* owner, std::vector<Pending*>& ps, hipStream_t s) {
     int rc;
     if (t_na && (rc = reserve_all_phases(owner, ps))) return rc;
@@ -1247,11 +1290,6 @@ int apply_locked(hgt_graph* owner, std::vector<Pending*>& ps, hipStream_t s) {
             ProfScope sc(g, PK_COMMIT, s);
             store_commit(g->st, p->b, p->w, p->sum, g->h_bump, g->v_bump, g->next_seq, s);
         }
-        // algorithmic bytes of the store update: an insert of cardinality d reads its
-        // input (4d + 8) and writes its h2v block (4d) and v2h entries (4d, locating
-        // them reads 4d); a delete reads its h2v block (4d) and rewrites its v2h
-        // entries (8d)
-        if (g->prof) g->store_bytes += 16 * p->n_mem + 16 * p->b.n_ins + 12 * p->sum.del_members + 8 * p->b.n_del;
         if (p->out_ids && p->b.n_ins)
             HIP_OK(hipMemcpyAsync(p->out_ids, p->w.assigned, p->b.n_ins * 4, hipMemcpyDeviceToDevice, s));
     }
@@ -1270,7 +1308,15 @@ int apply_locked(hgt_graph* owner, std::vector<Pending*>& ps, hipStream_t s) {
         k_he_tmp_update<<<1, 128, 0, s>>>(cnt);
         if (g->track_mask & (1u << HGT_TRIAD_INCIDENT_VERTEX))
             k_iv_update<<<1, 64, 0, s>>>(cnt, CNT_IV, ACC_IV_M, ACC_IV_P, ACC_T1);
-        // host mirrors
+    }
+    HIP_OK(hipGetLastError());
+    return HGT_OK;
+}
+
+// The host mirrors of the graphs, once the round's work is queued.
+void commit_mirrors(std::vector<Pending*>& ps) {
+    for (Pending* p : ps) {
+        hgt_graph* g = p->g;
         g->next_id = p->sum.next_id_new;
         g->h_bump += p->sum.h2v_need;
         g->v_bump += p->sum.v2h_need;
@@ -1278,16 +1324,71 @@ int apply_locked(hgt_graph* owner, std::vector<Pending*>& ps, hipStream_t s) {
         g->n_live = g->n_live + p->b.n_ins - p->b.n_del;
         g->n_inc = g->n_inc + p->n_mem - p->sum.del_members;
         g->batches++;
+        // algorithmic bytes of the store update: an insert of cardinality d reads its
+        // input (4d + 8) and writes its h2v block (4d) and v2h entries (4d, locating
+        // them reads 4d); a delete reads its h2v block (4d) and rewrites its v2h
+        // entries (8d)
+        if (g->prof) g->store_bytes += 16 * p->n_mem + 16 * p->b.n_ins + 12 * p->sum.del_members + 8 * p->b.n_del;
     }
-    HIP_OK(hipGetLastError());
+}
+
+// The post-planning half of a round captured into a HIP graph and launched as
+// one: every scratch buffer is reserved and every descriptor uploaded before
+// the capture.  The executable graph of the previous round on this phase
+// context is updated in place when the shapes agree, else instantiated anew.
+// kCaptureFailed: the capture did not succeed and nothing was launched.
+constexpr int kCaptureFailed = 1;
+int apply_graph(hgt_graph* owner, std::vector<Pending*>& ps, hipStream_t s) {
+    PhaseCtx& c = ctx_of(owner);
+    int rc = reserve_all_phases(owner, ps, s);
+    if (rc) return rc;
+    if (hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed) != hipSuccess) {
+        (void)hipGetLastError();
+        return kCaptureFailed;
+    }
+    t_capture = 1;
+    rc = apply_locked(owner, ps, s);
+    t_capture = 0;
+    hipGraph_t gr = nullptr;
+    const hipError_t e = hipStreamEndCapture(s, &gr);
+    for (int slot = 0; slot < 4; slot++) c.pre_ok[slot] = false;
+    if (rc || e != hipSuccess || !gr) {
+        (void)hipGetLastError();
+        if (gr) (void)hipGraphDestroy(gr);
+        return kCaptureFailed;
+    }
+    bool updated = false;
+    if (c.gexec) {
+        hipGraphNode_t err_node = nullptr;
+        hipGraphExecUpdateResult res;
+        updated = hipGraphExecUpdate(c.gexec, gr, &err_node, &res) == hipSuccess && res == hipGraphExecUpdateSuccess;
+        if (!updated) {
+            (void)hipGetLastError();
+            (void)hipGraphExecDestroy(c.gexec);
+            c.gexec = nullptr;
+        }
+    }
+    if (!updated && hipGraphInstantiate(&c.gexec, gr, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        c.gexec = nullptr;
+        (void)hipGraphDestroy(gr);
+        return kCaptureFailed;
+    }
+    (void)hipGraphDestroy(gr);
+    HIP_OK(hipGraphLaunch(c.gexec, s));
     return HGT_OK;
 }
 
-int apply_planned(hgt_graph* owner, std::vector<Pending*>& ps, hipStream_t s) {
+int apply_planned(hgt_graph* owner, std::vector<Pending*>& ps, hipStream_t s, bool graph = false) {
     PhaseCtx& c = ctx_of(owner);
     std::lock_guard<std::mutex> lk(c.mu);
     HIP_OK(hipStreamWaitEvent(s, c.done, 0));
-    int rc = apply_locked(owner, ps, s);
+    if (t_tune_ev[0]) (void)hipEventRecord(t_tune_ev[0], s);
+    int rc = kCaptureFailed;
+    if (graph && !t_na) rc = apply_graph(owner, ps, s);
+    if (rc == kCaptureFailed) rc = apply_locked(owner, ps, s);  // launched one by one
+    if (rc == HGT_OK) commit_mirrors(ps);
+    if (t_tune_ev[1]) (void)hipEventRecord(t_tune_ev[1], s);
     if (hipEventRecord(c.done, s) != hipSuccess && rc == HGT_OK) rc = HGT_EDEVICE;
     return rc;
 }
@@ -1646,9 +1747,168 @@ int hgt_apply_batch_noalloc(hgt_graph* g, const uint32_t* del_ids, uint64_t n_de
     return rc;
 }
 
-int hgt_apply_batches(hgt_batch* bs, uint32_t n, void* stream) {
+namespace {
+
+// Online autotuner of the batched form.  A round's key bins it by the tracked
+// families, the number of graphs (log2), the changes and the 2-hop load of its
+// heaviest centre (log4 buckets).  Each round is timed by two events around
+// its launches, read back without a wait at a later call.  The choices are
+// tried in turn; one whose quickest trial is more than kTuneDrop times the
+// best choice's is dropped, and once every remaining choice has kTuneTrials
+// trials the fastest (by its quickest trial) is kept for the key and appended
+// to the cache file, which later processes read first.
+constexpr TuneChoice kTune[] = {{4, 1, 8192}, {2, 1, 8192}, {8, 1, 8192}, {4, 0, 8192}, {4, 1, 32768}};
+constexpr int kTuneN = (int)(sizeof(kTune) / sizeof(kTune[0]));
+constexpr int kTuneTrials = 2;
+constexpr float kTuneDrop = 1.25f;
+
+struct TuneEntry {
+    float best_ms[kTuneN];
+    int trials[kTuneN];
+    int pick = -1;
+    TuneEntry() {
+        for (int i = 0; i < kTuneN; i++) best_ms[i] = 1e30f, trials[i] = 0;
+    }
+};
+
+struct Tuner {
+    std::mutex mu;
+    std::map<uint64_t, TuneEntry> tab;
+    bool loaded = false;
+    std::string path;  // empty: no cache file
+    struct Open {
+        uint64_t key;
+        int choice;
+        hipEvent_t a, b;
+    };
+    std::vector<Open> open;
+};
+
+Tuner& tuner() {
+    static Tuner* t = new Tuner();  // outlives every graph (never destroyed)
+    return *t;
+}
+
+inline int ilog2_bucket(uint64_t x) { return x ? 64 - __builtin_clzll(x) : 0; }
+
+uint64_t tune_key(const std::vector<Pending*>& ps, int n_cu) {
+    uint64_t changes = 0, lh = 0;
+    uint32_t mask = 0;
+    for (const Pending* p : ps) {
+        changes += p->b.n_del + p->b.n_ins;
+        lh = std::max(lh, std::max(p->sum.max_lh_del, p->sum.max_lh_ins));
+        mask |= p->g->track_mask;
+    }
+    return ((uint64_t)(n_cu & 0xffff) << 40) | ((uint64_t)(mask & 0xff) << 32) |
+           ((uint64_t)ilog2_bucket(ps.size()) << 24) | ((uint64_t)(ilog2_bucket(changes) / 2) << 16) |
+           ((uint64_t)(ilog2_bucket(lh) / 2) << 8);
+}
+
+// Cache file: one line per settled key, "key choice wg_per_cu skip_lds148
+// wave_slots best_ms"; lines whose choice does not match this library's table
+// are ignored.
+void tune_load(Tuner& T) {
+    if (T.loaded) return;
+    T.loaded = true;
+    const char* e = std::getenv("HGT_TUNE_CACHE");
+    if (e) {
+        T.path = e;
+    } else if (const char* home = std::getenv("HOME")) {
+        T.path = std::string(home) + "/.cache/hgt_tune.txt";
+    }
+    if (T.path.empty() || T.path == "off") {
+        T.path.clear();
+        return;
+    }
+    FILE* f = std::fopen(T.path.c_str(), "r");
+    if (!f) return;
+    unsigned long long key;
+    int choice, wg, skip;
+    unsigned slots;
+    float ms;
+    while (std::fscanf(f, "%llx %d %d %d %u %f", &key, &choice, &wg, &skip, &slots, &ms) == 6) {
+        if (choice < 0 || choice >= kTuneN || kTune[choice].wg_per_cu != wg || kTune[choice].skip_lds148 != skip ||
+            kTune[choice].wave_slots != slots)
+            continue;
+        TuneEntry& t = T.tab[(uint64_t)key];
+        t.pick = choice;
+        t.best_ms[choice] = ms;
+    }
+    std::fclose(f);
+}
+
+// Whether choice c is still in the running: untried, or within kTuneDrop of
+// the best quickest trial so far.
+bool tune_live(const TuneEntry& t, int c) {
+    float best = 1e30f;
+    for (int i = 0; i < kTuneN; i++) best = std::min(best, t.best_ms[i]);
+    return t.trials[c] == 0 || t.best_ms[c] <= kTuneDrop * best;
+}
+
+void tune_settle(Tuner& T, uint64_t key, TuneEntry& t) {
+    int best = 0;
+    for (int i = 1; i < kTuneN; i++)
+        if (t.best_ms[i] < t.best_ms[best]) best = i;
+    t.pick = best;
+    if (T.path.empty()) return;
+    if (FILE* f = std::fopen(T.path.c_str(), "a")) {
+        const TuneChoice& c = kTune[best];
+        std::fprintf(f, "%llx %d %d %d %u %.4f\n", (unsigned long long)key, best, c.wg_per_cu, c.skip_lds148,
+                     c.wave_slots, t.best_ms[best]);
+        std::fclose(f);
+    }
+}
+
+// Reads back the timed rounds whose second event has passed (all of them,
+// waiting, when wait is set).
+void tune_harvest(Tuner& T, bool wait) {
+    size_t kept = 0;
+    for (size_t i = 0; i < T.open.size(); i++) {
+        Tuner::Open& o = T.open[i];
+        if (wait) (void)hipEventSynchronize(o.b);
+        const hipError_t q = hipEventQuery(o.b);
+        if (q == hipErrorNotReady) {
+            T.open[kept++] = o;
+            continue;
+        }
+        float ms = 0.f;
+        if (q == hipSuccess && hipEventElapsedTime(&ms, o.a, o.b) == hipSuccess) {
+            TuneEntry& t = T.tab[o.key];
+            if (t.pick < 0) {
+                t.best_ms[o.choice] = std::min(t.best_ms[o.choice], ms);
+                t.trials[o.choice]++;
+                bool done = true;
+                for (int c = 0; c < kTuneN; c++) done &= !tune_live(t, c) || t.trials[c] >= kTuneTrials;
+                if (done) tune_settle(T, o.key, t);
+            }
+        }
+        (void)hipGetLastError();
+        (void)hipEventDestroy(o.a);
+        (void)hipEventDestroy(o.b);
+    }
+    T.open.resize(kept);
+}
+
+// The choice for a round's key: the settled one, else the one with the fewest
+// trials (HGT_TUNE_FORCE=k, for tests, forces choice k).
+int tune_pick(Tuner& T, uint64_t key) {
+    if (const char* f = std::getenv("HGT_TUNE_FORCE")) {
+        const int k = std::atoi(f);
+        if (k >= 0 && k < kTuneN) return k;
+    }
+    TuneEntry& t = T.tab[key];
+    if (t.pick >= 0) return t.pick;
+    int c = -1, pending[kTuneN] = {};
+    for (const Tuner::Open& o : T.open)
+        if (o.key == key) pending[o.choice]++;
+    for (int i = 0; i < kTuneN; i++)
+        if (tune_live(t, i) && (c < 0 || t.trials[i] + pending[i] < t.trials[c] + pending[c])) c = i;
+    return c < 0 ? 0 : c;
+}
+
+int apply_batches(hgt_batch* bs, uint32_t n, void* stream, uint32_t flags) {
     if (n == 0) return HGT_OK;
-    if (!bs) return HGT_EINVAL;
+    if (!bs || (flags & ~(uint32_t)(HGT_BATCHES_GRAPH | HGT_BATCHES_AUTOTUNE))) return HGT_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     {
         std::vector<hgt_graph*> gs;
@@ -1680,7 +1940,39 @@ int hgt_apply_batches(hgt_batch* bs, uint32_t n, void* stream) {
         if (P[i].rc == HGT_OK) act.push_back(&P[i]);
     }
     if (!act.empty()) {
-        int rc = apply_planned(act[0]->g, act, s);
+        hgt_graph* owner = act[0]->g;
+        const bool graph = flags & HGT_BATCHES_GRAPH;
+        int rc;
+        if (flags & HGT_BATCHES_AUTOTUNE) {
+            Tuner& T = tuner();
+            std::lock_guard<std::mutex> lk(T.mu);
+            tune_load(T);
+            tune_harvest(T, false);
+            const uint64_t key = tune_key(act, owner->n_cu);
+            const int choice = tune_pick(T, key);
+            const bool timed = T.tab[key].pick < 0;
+            Tuner::Open o{key, choice, nullptr, nullptr};
+            if (timed && (hipEventCreate(&o.a) != hipSuccess || hipEventCreate(&o.b) != hipSuccess)) {
+                (void)hipGetLastError();
+                if (o.a) (void)hipEventDestroy(o.a);
+                o.a = o.b = nullptr;
+            }
+            // the first event after the wait for the context's previous round
+            t_tune = &kTune[choice];
+            t_tune_ev[0] = o.a;
+            t_tune_ev[1] = o.b;
+            rc = apply_planned(owner, act, s, graph);
+            t_tune = nullptr;
+            t_tune_ev[0] = t_tune_ev[1] = nullptr;
+            if (o.a && rc == HGT_OK) {
+                T.open.push_back(o);
+            } else if (o.a) {
+                (void)hipEventDestroy(o.a);
+                (void)hipEventDestroy(o.b);
+            }
+        } else {
+            rc = apply_planned(owner, act, s, graph);
+        }
         if (rc)
             for (Pending* p : act) p->rc = rc;
     }
@@ -1692,6 +1984,27 @@ int hgt_apply_batches(hgt_batch* bs, uint32_t n, void* stream) {
         if (rc && first == HGT_OK) first = rc;
     }
     return first;
+}
+
+}  // namespace
+
+int hgt_apply_batches(hgt_batch* bs, uint32_t n, void* stream) { return apply_batches(bs, n, stream, 0); }
+
+int hgt_apply_batches_ex(hgt_batch* bs, uint32_t n, void* stream, uint32_t flags) {
+    return apply_batches(bs, n, stream, flags);
+}
+
+int hgt_tune_flush(uint32_t* n_settled) {
+    Tuner& T = tuner();
+    std::lock_guard<std::mutex> lk(T.mu);
+    tune_load(T);
+    tune_harvest(T, true);
+    if (n_settled) {
+        uint32_t k = 0;
+        for (auto& kv : T.tab) k += kv.second.pick >= 0;
+        *n_settled = k;
+    }
+    return HGT_OK;
 }
 
 int hgt_sync(hgt_graph* g, int* status) {

@@ -5,10 +5,10 @@
 // arrival order, admits those whose tenant is idle and whose buffers and
 // footprint fit, stages their inputs into a device arena, and applies them as
 // one round through hgt_apply_batches (one planning wait for the whole round,
-// shared triad launches).  Rounds alternate between two streams, each with
-// its own triad-phase scratch, so round k+1 is planned and its triad phases
-// run while round k's are still on the GPU; completion is observed through an
-// event per round.
+// shared triad launches).  Up to four rounds are in flight, each on a stream
+// of its own with its own triad-phase scratch, so a round is planned and its
+// triad phases run while earlier rounds are still on the GPU; completion is
+// observed through an event per round, in any order.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -105,8 +105,10 @@ struct Round {
 struct hgt_server {
     hgt_server_desc desc{};
     int device = 0;
-    hipStream_t streams[2] = {nullptr, nullptr};
-    PhaseCtx* ctx[2] = {nullptr, nullptr};  // phase scratch of the rounds on each stream
+    static constexpr int kStreams = 4;      // most rounds in flight
+    hipStream_t streams[kStreams] = {};
+    PhaseCtx* ctx[kStreams] = {};           // phase scratch of the round on each stream
+    bool stream_busy[kStreams] = {};
     void* d_arena = nullptr;   // device
     char* h_arena = nullptr;   // pinned mirror
     RangeAlloc arena;
@@ -119,7 +121,6 @@ struct hgt_server {
     std::vector<hipEvent_t> ev_pool;
     uint64_t next_ticket = 1, footprint_in_use = 0, rounds = 0, done_count = 0, running = 0;
     uint64_t max_round_seen = 0, max_inflight_seen = 0;
-    int next_stream = 0;
     bool stop = false;
     int fatal = HGT_OK;
     std::mutex mu;
@@ -188,7 +189,7 @@ int launch_round(hgt_server* s, Round* R) {
     }
     // the round's own phase scratch: rounds on the two streams overlap on the device
     hgt_use_phase_ctx(s->ctx[R->stream]);
-    (void)hgt_apply_batches(bs.data(), (uint32_t)bs.size(), st);
+    (void)hgt_apply_batches_ex(bs.data(), (uint32_t)bs.size(), st, s->desc.launch_flags);
     hgt_use_phase_ctx(nullptr);
     for (size_t i = 0; i < R->reqs.size(); i++) {
         Request* q = R->reqs[i];
@@ -298,10 +299,12 @@ void worker_main(hgt_server* s) {
     (void)hipSetDevice(s->device);
     std::unique_lock<std::mutex> lk(s->mu);
     for (;;) {
-        // completed rounds, oldest first
-        while (!s->inflight.empty() && hipEventQuery(s->inflight.front()->ev) == hipSuccess) {
-            Round* R = s->inflight.front();
-            s->inflight.erase(s->inflight.begin());
+        // completed rounds, in any order (their tenants are distinct)
+        for (size_t i = 0; i < s->inflight.size();) {
+            Round* R = s->inflight[i];
+            if (hipEventQuery(R->ev) != hipSuccess) { ++i; continue; }
+            s->inflight.erase(s->inflight.begin() + i);
+            s->stream_busy[R->stream] = false;
             complete_round_locked(s, R);
             s->cv_done.notify_all();
         }
@@ -320,8 +323,9 @@ void worker_main(hgt_server* s) {
             }
             R->ev = s->ev_pool.back();
             s->ev_pool.pop_back();
-            R->stream = s->next_stream;
-            s->next_stream ^= (s->desc.max_inflight > 1 ? 1 : 0);
+            R->stream = 0;  // a stream with no round in flight (there is one: inflight < max_inflight)
+            while (s->stream_busy[R->stream]) R->stream++;
+            s->stream_busy[R->stream] = true;
             R->id = s->rounds++;
             s->max_round_seen = std::max<uint64_t>(s->max_round_seen, R->reqs.size());
             s->inflight.push_back(R);
@@ -338,13 +342,18 @@ void worker_main(hgt_server* s) {
             continue;
         }
         if (!s->inflight.empty()) {
-            // wait for the oldest round without the lock; new submissions
-            // are taken when it (or the wait's time limit) ends
-            hipEvent_t e = s->inflight.front()->ev;
+            // wait without the lock until a round completes or 200 us pass; new
+            // submissions are taken after that
+            std::vector<hipEvent_t> evs;
+            for (Round* R : s->inflight) evs.push_back(R->ev);
             lk.unlock();
             auto t_end = std::chrono::steady_clock::now() + std::chrono::microseconds(200);
-            while (hipEventQuery(e) == hipErrorNotReady && std::chrono::steady_clock::now() < t_end)
-                std::this_thread::yield();
+            bool any = false;
+            while (!any && std::chrono::steady_clock::now() < t_end) {
+                for (hipEvent_t e : evs)
+                    if (hipEventQuery(e) != hipErrorNotReady) any = true;
+                if (!any) std::this_thread::yield();
+            }
             lk.lock();
             continue;
         }
@@ -359,26 +368,23 @@ extern "C" {
 int hgt_server_create(const hgt_server_desc* d, hgt_server** out) {
     if (!d || !out) return HGT_EINVAL;
     *out = nullptr;
+    if (d->launch_flags & ~(uint32_t)(HGT_BATCHES_GRAPH | HGT_BATCHES_AUTOTUNE)) return HGT_EINVAL;
     hgt_server* s = new (std::nothrow) hgt_server();
     if (!s) return HGT_ENOMEM;
     s->desc = *d;
     if (!s->desc.arena_bytes) s->desc.arena_bytes = 256ull << 20;
     if (!s->desc.max_round) s->desc.max_round = 256;
-    if (!s->desc.max_inflight) s->desc.max_inflight = 2;
-    s->desc.max_inflight = std::min<uint32_t>(s->desc.max_inflight, 2);
+    if (!s->desc.max_inflight) s->desc.max_inflight = hgt_server::kStreams;
+    s->desc.max_inflight = std::min<uint32_t>(s->desc.max_inflight, hgt_server::kStreams);
     s->desc.arena_bytes = align_up(s->desc.arena_bytes);
     int rc = HGT_OK;
     do {
         if (hipGetDevice(&s->device) != hipSuccess) { rc = HGT_EDEVICE; break; }
-        if (hipStreamCreateWithFlags(&s->streams[0], hipStreamNonBlocking) != hipSuccess ||
-            hipStreamCreateWithFlags(&s->streams[1], hipStreamNonBlocking) != hipSuccess) {
-            rc = HGT_EDEVICE;
-            break;
+        for (uint32_t i = 0; i < s->desc.max_inflight && !rc; i++) {
+            if (hipStreamCreateWithFlags(&s->streams[i], hipStreamNonBlocking) != hipSuccess) rc = HGT_EDEVICE;
+            else if (!(s->ctx[i] = hgt_phase_ctx_create(s->device))) rc = HGT_ENOMEM;
         }
-        if (!(s->ctx[0] = hgt_phase_ctx_create(s->device)) || !(s->ctx[1] = hgt_phase_ctx_create(s->device))) {
-            rc = HGT_ENOMEM;
-            break;
-        }
+        if (rc) break;
         if (hipMalloc(&s->d_arena, s->desc.arena_bytes) != hipSuccess ||
             hipHostMalloc((void**)&s->h_arena, s->desc.arena_bytes, hipHostMallocDefault) != hipSuccess) {
             rc = HGT_ENOMEM;
@@ -531,14 +537,16 @@ int hgt_server_destroy(hgt_server* s) {
     }
     s->cv_work.notify_all();
     if (s->worker.joinable()) s->worker.join();
-    for (hipStream_t st : s->streams) (void)hipStreamSynchronize(st);
+    for (hipStream_t st : s->streams)
+        if (st) (void)hipStreamSynchronize(st);
     for (auto& kv : s->by_ticket) delete kv.second;
     for (hgt_graph* g : s->tenants) hgt_destroy(g);
     for (hipEvent_t e : s->ev_pool) (void)hipEventDestroy(e);
     for (PhaseCtx* c : s->ctx) hgt_phase_ctx_destroy(c);
     (void)hipFree(s->d_arena);
     (void)hipHostFree(s->h_arena);
-    for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
+    for (hipStream_t st : s->streams)
+        if (st) (void)hipStreamDestroy(st);
     delete s;
     return HGT_OK;
 }

@@ -94,6 +94,8 @@ class ServerDesc(ctypes.Structure):
         ("arena_bytes", ctypes.c_uint64),
         ("max_round", ctypes.c_uint32),
         ("max_inflight", ctypes.c_uint32),
+        ("launch_flags", ctypes.c_uint32),
+        ("pad0", ctypes.c_uint32),
     ]
 
 
@@ -134,7 +136,8 @@ class ServerInfo(ctypes.Structure):
 
 _lib = None
 
-EXPORTS = ["hgt_build", "hgt_apply_batch", "hgt_apply_batches", "hgt_triad_counts", "hgt_sync", "hgt_destroy", "hgt_status_str",
+EXPORTS = ["hgt_build", "hgt_apply_batch", "hgt_apply_batch_noalloc", "hgt_apply_batches", "hgt_apply_batches_ex",
+           "hgt_tune_flush", "hgt_apply_vertex_ops", "hgt_compact", "hgt_triad_counts", "hgt_sync", "hgt_destroy", "hgt_status_str",
            "hgt_get_info", "hgt_export_h2v", "hgt_export_v2h", "hgt_class_codes", "hgt_profile",
            "hgt_profile_read", "hgt_profile_counters", "hgt_server_create", "hgt_server_add_tenant", "hgt_server_tenant_graph",
            "hgt_server_submit", "hgt_server_wait", "hgt_server_query", "hgt_server_get_info", "hgt_server_destroy"]
@@ -156,6 +159,8 @@ def load(path: str = LIB_PATH):
     lib.hgt_apply_batch.argtypes = [P, P, U64, P, P, U64, P, U64, P, P]
     lib.hgt_apply_batch_noalloc.argtypes = [P, P, U64, P, P, U64, P, U64, P, P]
     lib.hgt_apply_batches.argtypes = [P, U32, P]
+    lib.hgt_apply_batches_ex.argtypes = [P, U32, P, U32]
+    lib.hgt_tune_flush.argtypes = [ctypes.POINTER(U32)]
     lib.hgt_apply_vertex_ops.argtypes = [P, P, P, P, U64, P]
     lib.hgt_compact.argtypes = [P, P]
     lib.hgt_triad_counts.argtypes = [P, I32, I64, P, U32]
@@ -237,11 +242,17 @@ def _batch_args(del_ids, ins_offsets, ins_members, ins_ts):
     return n_del, n_ins, n_mem
 
 
-def apply_batches(items, stream=None, raise_on_error: bool = True):
+BATCHES_GRAPH = 1
+BATCHES_AUTOTUNE = 2
+
+
+def apply_batches(items, stream=None, raise_on_error: bool = True, graph: bool = False, autotune: bool = False):
     """Batched form: items = [(graph, del_ids, ins_offsets, ins_members, ins_ts), ...]
     with distinct graphs.  Applies all of them in one call (one wait, shared
-    triad launches).  Returns the list of assigned-ID tensors (or, with
-    raise_on_error=False, (first_status, [status...], [ids...]))."""
+    triad launches).  graph=True launches the round as one captured HIP graph;
+    autotune=True lets the library's autotuner pick the launch choices.
+    Returns the list of assigned-ID tensors (or, with raise_on_error=False,
+    (first_status, [status...], [ids...]))."""
     import torch
     lib = load()
     n = len(items)
@@ -262,13 +273,25 @@ def apply_batches(items, stream=None, raise_on_error: bool = True):
         b.ins_ts = _ptr(ins_ts)
         b.n_ins = n_ins
         b.out_ins_ids = _ptr(out) if n_ins else None
-    rc = lib.hgt_apply_batches(ctypes.cast(arr, ctypes.c_void_p), n, _stream(stream))
+    flags = (BATCHES_GRAPH if graph else 0) | (BATCHES_AUTOTUNE if autotune else 0)
+    rc = lib.hgt_apply_batches_ex(ctypes.cast(arr, ctypes.c_void_p), n, _stream(stream), flags)
     status = [arr[i].status for i in range(n)]
     if raise_on_error:
         if rc != OK:
             raise HgtError(rc, f"hgt_apply_batches (statuses {status})")
         return outs
     return rc, status, outs
+
+
+def tune_flush() -> int:
+    """Waits for the autotuner's timed rounds; returns how many round keys have
+    a kept launch choice."""
+    lib = load()
+    k = ctypes.c_uint32(0)
+    rc = lib.hgt_tune_flush(ctypes.byref(k))
+    if rc != OK:
+        raise HgtError(rc, "hgt_tune_flush")
+    return int(k.value)
 
 
 def _build_desc(n_vertices, offsets, members, timestamps, track, window, edge_capacity, pool_words):
@@ -463,9 +486,10 @@ class Server:
     library's server thread."""
 
     def __init__(self, hbm_budget_bytes: int = 8 << 30, arena_bytes: int = 0, max_round: int = 0,
-                 max_inflight: int = 0):
+                 max_inflight: int = 0, graph: bool = False, autotune: bool = False):
         lib = load()
-        d = ServerDesc(int(hbm_budget_bytes), int(arena_bytes), int(max_round), int(max_inflight))
+        flags = (BATCHES_GRAPH if graph else 0) | (BATCHES_AUTOTUNE if autotune else 0)
+        d = ServerDesc(int(hbm_budget_bytes), int(arena_bytes), int(max_round), int(max_inflight), flags, 0)
         out = ctypes.c_void_p()
         rc = lib.hgt_server_create(ctypes.byref(d), ctypes.byref(out))
         if rc != OK:

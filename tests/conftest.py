@@ -6,6 +6,8 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
+# the autotuner's cache file: none for tests (a test that checks it names its own)
+os.environ.setdefault("HGT_TUNE_CACHE", "off")
 
 
 def pytest_configure(config):

@@ -120,9 +120,9 @@ class Pair:
         self.g.close()
 
 
-def apply_many(pairs, batches, where=""):
-    """Applies batches[i] to pairs[i] through the batched entry point (one call)
-    and to each oracle; checks the assigned IDs."""
+def apply_many(pairs, batches, where="", **kw):
+    """Applies batches[i] to pairs[i] through the batched entry point (one call,
+    keyword arguments passed on) and to each oracle; checks the assigned IDs."""
     import torch
     from paper_2512_21009_amd import hgt
     items, fins = [], []
@@ -130,7 +130,7 @@ def apply_many(pairs, batches, where=""):
         args, fin = p.prepare(b, f"{where} graph {k}")
         items.append((p.g,) + args)
         fins.append(fin)
-    outs = hgt.apply_batches(items)
+    outs = hgt.apply_batches(items, **kw)
     torch.cuda.synchronize()
     for fin, out in zip(fins, outs):
         fin(out)

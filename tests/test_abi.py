@@ -59,3 +59,24 @@ def test_status_strings():
     for code in range(0, -8, -1):
         assert lib.hgt_status_str(code)
     assert lib.hgt_apply_batch(None, None, 0, None, None, 0, None, 0, None, None) == -1
+
+
+def test_tune_cache_is_read_and_filtered(tmp_path):
+    """The autotuner's cache file: a line whose choice matches the library's
+    table is taken as a settled key; lines that do not match are ignored.
+    (Reading the file and reporting settled keys makes no GPU call.)"""
+    cache = tmp_path / "tune.txt"
+    cache.write_text("1000aa0800 3 4 0 8192 1.25\n"      # choice 3 = (4 per CU, 148 KB stage kept, 8192 slots)
+                     "1000aa0900 3 8 1 8192 1.00\n"      # wrong parameters for choice 3
+                     "1000aa0a00 9 4 1 8192 1.00\n"      # no such choice
+                     "1000aa0b00 0 4 1 8192 0.50\n")
+    code = ("import ctypes, sys\n"
+            "lib = ctypes.CDLL(sys.argv[1])\n"
+            "k = ctypes.c_uint32(0)\n"
+            "assert lib.hgt_tune_flush(ctypes.byref(k)) == 0\n"
+            "print(k.value)\n")
+    env = dict(os.environ, HGT_TUNE_CACHE=str(cache))
+    r = subprocess.run([os.sys.executable, "-c", code, _lib_path()], env=env, capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 0, r.stderr[-2000:]
+    assert r.stdout.strip().splitlines()[-1] == "2"

@@ -98,3 +98,88 @@ def test_batched_every_kernel_path(gpu_lib, monkeypatch, stage):
         compare_counts(p.g, p.o, p.track, f"stage {stage} graph {k}")
     for p in pairs:
         p.close()
+
+
+@pytest.mark.parametrize("choice", [0, 1, 2, 3, 4])
+def test_graph_launch_every_tuned_choice(gpu_lib, monkeypatch, choice):
+    """Rounds launched as captured HIP graphs (the executable updated in place
+    from the second round on) under each of the autotuner's launch choices,
+    forced, give the oracle's counts and store exactly."""
+    monkeypatch.setenv("HGT_TUNE_FORCE", str(choice))
+    specs = _mixed_streams(51 + choice, n_batches=3)
+    pairs = [Pair(st, track=tr) for st, tr in specs]
+    for r in range(3):
+        act = [(p, st.batches[r]) for p, (st, _) in zip(pairs, specs) if r < len(st.batches)]
+        apply_many([a for a, _ in act], [b for _, b in act], f"choice {choice} round {r}", graph=True, autotune=True)
+        for k, p in enumerate(pairs):
+            compare_counts(p.g, p.o, p.track, f"choice {choice} round {r} graph {k}")
+            compare_store(p.g, p.o, f"choice {choice} round {r} graph {k}")
+    for p in pairs:
+        p.close()
+
+
+def _churn_rounds(st, n_rounds, k, seed):
+    """Rounds that delete k live hyperedges and insert their rows again under
+    fresh handles: every round has the same shape (same changes, same degrees)."""
+    rng = np.random.default_rng(seed)
+    ini = st.initial
+    live = rng.choice(ini.n, size=k, replace=False).astype(np.int64)
+    rows = ini.rows(live)
+    t0 = int(ini.ts.max()) + 1 if ini.ts is not None else 0
+    nxt = ini.n
+    out = []
+    for r in range(n_rounds):
+        handles = np.arange(nxt, nxt + k, dtype=np.int64)
+        ins = W.CSR(rows.offsets, rows.members)
+        if ini.ts is not None:  # inserted timestamps never go back in time
+            ins.ts = t0 + r * k + np.arange(k, dtype=np.int64)
+        out.append(W.Batch(del_handles=live.copy(), ins=ins, ins_handles=handles))
+        live, nxt = handles, nxt + k
+    return out
+
+
+def test_autotuner_settles_and_writes_its_cache(gpu_lib, tmp_path):
+    """Rounds of one shape, autotuned: after every choice has been timed the
+    tuner keeps one for the round's key and appends it to its cache file; the
+    counts stay exact throughout.  (The cache path is read once per process,
+    so this runs in a child process with its own HGT_TUNE_CACHE.)"""
+    import os
+    import subprocess
+    import sys
+    cache = tmp_path / "tune.txt"
+    env = dict(os.environ, HGT_TUNE_CACHE=str(cache))
+    env.pop("HGT_TUNE_FORCE", None)
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = (
+        "import sys; sys.path.insert(0, %r)\n"
+        "from tests import test_gpu_batched as T\n"
+        "T._autotune_child()\n" % root)
+    r = subprocess.run([sys.executable, "-c", code], env=env, cwd=root, capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-2000:]
+    assert "settled" in r.stdout, r.stdout[-2000:]
+    lines = [ln.split() for ln in cache.read_text().splitlines() if ln.strip()]
+    assert len(lines) >= 1 and all(len(ln) == 6 for ln in lines)
+    assert all(0 <= int(ln[1]) < 5 for ln in lines)
+
+
+def _autotune_child():
+    import torch
+    from paper_2512_21009_amd import hgt
+    hgt.load()
+    specs = _mixed_streams(61, n_batches=1)[6:9]  # hyperedge + incident-vertex, and the temporal graphs
+    pairs = [Pair(st, track=tr) for st, tr in specs]
+    rounds = [_churn_rounds(st, 18, 12, 70 + k) for k, (st, _) in enumerate(specs)]
+    for r in range(18):
+        apply_many(pairs, [rs[r] for rs in rounds], f"tuned round {r}", graph=(r % 2 == 0), autotune=True)
+        torch.cuda.synchronize()
+        if r % 6 == 5:
+            for k, p in enumerate(pairs):
+                compare_counts(p.g, p.o, p.track, f"tuned round {r} graph {k}")
+    n = hgt.tune_flush()
+    for k, p in enumerate(pairs):
+        compare_counts(p.g, p.o, p.track, f"tuned end graph {k}")
+        compare_store(p.g, p.o, f"tuned end graph {k}")
+    for p in pairs:
+        p.close()
+    print(f"settled {n}", flush=True)
+    assert n >= 1

@@ -63,11 +63,15 @@ def _alone_with_oracle(gpu_lib, sv):
     return args, results
 
 
-def test_served_mix_equals_alone_and_oracle(gpu_lib):
+@pytest.mark.parametrize("launch", ["stream", "graph_tuned"])
+def test_served_mix_equals_alone_and_oracle(gpu_lib, launch):
     sv = _mini()
     args, alone = _alone_with_oracle(gpu_lib, sv)
     # the mix: every request submitted at once, merged into rounds by the server
-    srv = gpu_lib.Server(hbm_budget_bytes=1 << 30, arena_bytes=64 << 20)
+    # (rounds launched kernel by kernel, or as captured HIP graphs with the
+    # autotuner picking the launch choices)
+    kw = {} if launch == "stream" else {"graph": True, "autotune": True}
+    srv = gpu_lib.Server(hbm_budget_bytes=1 << 30, arena_bytes=64 << 20, **kw)
     _add_tenants(srv, sv)
     tickets = [srv.submit(tn, *a) for tn, a in args]
     mixed = [srv.wait(t) for t in tickets]

@@ -141,6 +141,8 @@ def log_phases(args, ctr):
         tot = sum(ph)
         if tot:
             log(args, f"  stage {s} phases: " + " ".join(f"{n}={100.0 * v / tot:.1f}%" for n, v in zip(PHASES, ph)))
+            # the wall clock the kernels read runs at 100 MHz
+            log(args, f"  stage {s}: longest single centre {int(ctr[16 + 12 * s + 11]) / 1e5:.2f} ms")
     log(args, f"  aggregated pairs: long runs {int(ctr[12])}, pairs sharing several vertices {int(ctr[13])}, "
               f"centres enumerated {int(ctr[14])}")
 
@@ -309,7 +311,7 @@ def bench_batched(args):
         for k in range(rounds):
             if name == "stream" and k == n_timed_end:  # the rounds after the timed ones are profiled
                 for g in gs:
-                    g.profile(1)
+                    g.profile(2 if args.phases else 1)
             torch.cuda.synchronize()
             tb = time.perf_counter()
             if kw is None:
@@ -327,6 +329,12 @@ def bench_batched(args):
         if name == "stream":
             for g in gs:
                 add_profiles(prof, g.profile_read())
+            if args.phases:  # counters of all graphs: sums, and the maxima of the longest-centre slots
+                ctrs = [list(g.profile_counters()) for g in gs]
+                tot = [sum(c[i] for c in ctrs) for i in range(len(ctrs[0]))]
+                for st_ in range(3):
+                    tot[16 + 12 * st_ + 11] = max(c[16 + 12 * st_ + 11] for c in ctrs)
+                log_phases(args, tot)
         counts[name] = [g.triad_counts("hyperedge") for g in gs]
         for g in gs:
             assert g.sync() == hgt.OK

@@ -243,6 +243,7 @@ struct PhaseCtx {
     hipEvent_t done = nullptr;    // recorded after the last user's phases
     DevBuf iv_list, iv_list2, iv_garena, iv_garena2;  // incident-vertex stage scratch
     DevBuf t_ctr, t_big_list, t_big_rank, t_big_scratch, t_list1, t_rank1, t_list2, t_rank2, t_garena, t_whash;
+    DevBuf t_slices, t_slice_scan;       // slices of the 2-hop kernel's centres
     DevBuf ent_x, ent_d, ent_pay, bl_cnt, bl_off, bl_cur, bl_d, bl_pay, nb_scratch, bl_scan;
     // per-graph phase descriptors: device copies and their pinned staging, one
     // slot per (phase, family) so no upload overwrites one still in flight
@@ -290,6 +291,8 @@ struct hgt_graph {
     int pair_agg = 1;               // HGT_PAIR_AGG=0: pairs enumerated per run (see He2Params)
     int global_wg_per_cu = 4;       // HGT_GLOBAL_WG_PER_CU: workgroups per CU of the global stage
     int iv_direct = 0;              // HGT_IV_DIRECT=1 (tests): incident-vertex owners without maps
+    int iv_wg_per_cu = 8;           // HGT_IV_WG_PER_CU: workgroups per CU of the incident-vertex global stage
+    uint32_t slice_lh = 0;          // HGT_SLICE_LH (tests): list entries per slice of a 2-hop kernel centre
     int iv_force_stage = 0;         // HGT_IV_FORCE_STAGE (tests): incident-vertex stages below it pass owners on
     uint32_t wave_slots = 8192;     // HGT_WAVE_SLOTS (tests): slots of the 2-hop kernels' per-wave global hashes
     int skip_lds148 = 1;            // HGT_SKIP_LDS148=0: centres go through the 148 KB stage (one workgroup
@@ -500,6 +503,7 @@ int ensure_plan_scratch(hgt_graph* g, const Sizes& z, PlanScratch& w) {
 // ---- triad phases ---------------------------------------------------------
 void phase_ctx_free(PhaseCtx& c) {
     DevBuf* all[] = {&c.t_ctr, &c.t_whash, &c.t_big_list, &c.t_big_rank, &c.t_big_scratch, &c.t_list1, &c.t_rank1, &c.t_list2,
+                     &c.t_slices, &c.t_slice_scan,
                      &c.t_rank2, &c.t_garena, &c.ent_x, &c.ent_d, &c.ent_pay, &c.bl_cnt, &c.bl_off, &c.bl_cur,
                      &c.bl_d, &c.bl_pay, &c.nb_scratch, &c.bl_scan, &c.desc, &c.iv_list, &c.iv_list2, &c.iv_garena,
                      &c.iv_garena2};
@@ -724,6 +728,8 @@ int phase_reserve(PhaseCtx& c, int family, const PhaseShape& z) {
     rc |= ensure(c.t_rank2, n * 4);
     rc |= ensure(c.t_big_scratch, z.grid_big * z.L.words_per_wg * 4);
     rc |= ensure(c.t_whash, z.grid_2hop * 4 * 2ull * z.wave_slots * 4);
+    rc |= ensure(c.t_slices, (n + 2) * 8);
+    rc |= ensure(c.t_slice_scan, hgt_scan_tmp_bytes(n));
     if (family == HGT_TRIAD_HYPEREDGE) {
         const uint64_t ids = z.total_ids;
         rc |= ensure(c.ent_x, z.ecap * 4);
@@ -775,6 +781,10 @@ int run_phase(hgt_graph* owner, const PhaseJob* jobs, uint32_t nj, bool minus, b
         P.big_scratch = c.t_big_scratch.as<uint32_t>();
         P.wave_hash = c.t_whash.as<uint32_t>();
         P.wave_slots = z.wave_slots;
+        P.slice_pre = c.t_slices.as<uint64_t>();
+        P.slice_cap = n;
+        P.slice_scan_tmp = c.t_slice_scan.p;
+        P.slice_lh = owner->slice_lh;
         P.big = L;
         P.stats = stats;
         const unsigned grid_small = (unsigned)z.grid_small;
@@ -824,7 +834,10 @@ int run_phase(hgt_graph* owner, const PhaseJob* jobs, uint32_t nj, bool minus, b
             E.garena_words = kGarenaWords;
             E.stats = stats;
             E.phase_ticks = (stats && owner->prof_phases) ? 1 : 0;
-            E.force_stage = owner->force_stage;
+            // read again at every phase, so that a test can force the stages of a batch
+            // without forcing those of the build's full count
+            const char* fs = std::getenv("HGT_FORCE_STAGE");
+            E.force_stage = fs ? std::atoi(fs) : owner->force_stage;
             E.pair_agg = owner->pair_agg;
             E.skip_lds148 = t_tune ? t_tune->skip_lds148 : owner->skip_lds148;
             E.static_mode = full ? 1 : 0;
@@ -851,6 +864,7 @@ int run_phase(hgt_graph* owner, const PhaseJob* jobs, uint32_t nj, bool minus, b
             B.static_he = full ? 1 : 0;
             {
                 ProfScope ps(owner, PK_DELTA_BIG, s);
+                triad_he_slices(B, s);
                 triad_he_launch_big(B, (unsigned)grid_big, s);
             }
             if (minus) he2_remove_deleted(N, s);
@@ -865,6 +879,7 @@ int run_phase(hgt_graph* owner, const PhaseJob* jobs, uint32_t nj, bool minus, b
             triad_he_prepare(Q, s);
             ProfScope ps(owner, PK_TMP, s);
             triad_he_launch_small(Q, (unsigned)z.grid_tmp, s);
+            triad_he_slices(Q, s);
             triad_he_launch_big(Q, (unsigned)grid_big, s);
         }
     }
@@ -1018,7 +1033,7 @@ int iv_prepare(hgt_graph* g, const BatchIn& b, const PlanScratch& w, const Batch
 // members), 32 workgroups.  The no-allocation entry point runs 16 and 2.
 constexpr uint64_t kIvGarenaWords = 1ull << 18;
 constexpr uint64_t kIvGarena2Words = 1ull << 22;
-inline unsigned iv_grid_global(const hgt_graph* g) { return t_na ? 16u : (unsigned)(g->n_cu * 4); }
+inline unsigned iv_grid_global(const hgt_graph* g) { return t_na ? 16u : (unsigned)(g->n_cu * g->iv_wg_per_cu); }
 inline unsigned iv_grid_global2() { return t_na ? 2u : 32u; }
 
 int iv_reserve(hgt_graph* g, const IvPlan& ip) {
@@ -1570,6 +1585,8 @@ int hgt_build(const hgt_build_desc* d, hgt_graph** out) {
     if (const char* pa = std::getenv("HGT_PAIR_AGG")) g->pair_agg = std::atoi(pa) != 0;
     if (const char* gw = std::getenv("HGT_GLOBAL_WG_PER_CU")) g->global_wg_per_cu = std::max(1, std::min(16, std::atoi(gw)));
     if (const char* sk = std::getenv("HGT_SKIP_LDS148")) g->skip_lds148 = std::atoi(sk) != 0;
+    if (const char* iw = std::getenv("HGT_IV_WG_PER_CU")) g->iv_wg_per_cu = std::max(1, std::min(16, std::atoi(iw)));
+    if (const char* sl = std::getenv("HGT_SLICE_LH")) g->slice_lh = (uint32_t)std::max(1, std::atoi(sl));
     if (const char* iv = std::getenv("HGT_IV_DIRECT")) g->iv_direct = std::atoi(iv) != 0;
     if (const char* fs = std::getenv("HGT_IV_FORCE_STAGE")) g->iv_force_stage = std::atoi(fs);
     if (const char* ws = std::getenv("HGT_WAVE_SLOTS")) {  // a power of two, 64 .. 2^20

@@ -63,6 +63,15 @@ struct TriadParams {
     uint32_t wave_slots;      // whose 2-hop list is too long for LDS: 2 * wave_slots words each
     uint64_t* stats;          // optional counters (see TriadStat), NULL = off
     int static_he;            // hyperedge family as a full count (see He2Params::static_mode)
+    // Slices of the large kernel's centres (NULL: one per centre): a centre whose
+    // members' lists hold many entries is shared by several workgroups, each
+    // taking every S-th neighbour.  slice_pre[c] is the first slice of deferred
+    // centre c (exclusive prefix); slice_pre[slice_cap] holds the number of
+    // deferred centres, slice_pre[slice_cap + 1] the number of slices.
+    uint64_t* slice_pre;
+    uint64_t slice_cap;
+    uint32_t slice_lh;        // member-list entries per slice (0: the default)
+    void* slice_scan_tmp;     // hgt_scan_tmp_bytes(slice_cap)
 };
 
 // Counters accumulated by the triad kernels when TriadParams.stats is set.
@@ -80,6 +89,7 @@ enum TriadStat {
     ST_AGG_MULTI = 13,   // ... pairs sharing two or more vertices, corrected
     ST_AGG_ENUM = 14,    // centres whose pairs were enumerated per run instead
     ST_PH0 = 16,         // wall-clock ticks per phase of histogram-kernel stage s: ST_PH0 + HE2_PHASES s + phase
+                         // (the last slot of a stage: the longest single centre, a maximum)
     ST_TMP0 = 56,        // the temporal launches' counters: ST_TMP0 + (ST_BYTES_SMALL .. ST_EXPANDED)
     ST_N = 64
 };
@@ -87,6 +97,8 @@ enum TriadStat {
 BigLayout triad_big_layout(uint64_t max_lh, uint64_t max_card);
 void triad_he_prepare(TriadParams& P, hipStream_t s);
 void triad_he_launch_small(TriadParams& P, unsigned grid, hipStream_t s);
+// After the small kernel: the slices of the deferred centres (when P.slice_pre is set).
+void triad_he_slices(TriadParams& P, hipStream_t s);
 void triad_he_launch_big(TriadParams& P, unsigned grid, hipStream_t s);
 
 // hyperedge family through neighbour histograms (triad_he2.hip)
@@ -118,7 +130,7 @@ struct He2Params {
     uint32_t* queue;             // per stage (3 consecutive counters)
     uint32_t* count;             // items moved on by each stage (3 consecutive)
     uint64_t* list[3];           // list[s]: items stage s could not fit; list[2] feeds
-    uint32_t* rank[3];           // the 2-hop kernel (k_delta_big)
+    uint32_t* rank[3];           // the 2-hop kernel (k_delta_big), as do the densest centres
     uint32_t* garena;            // stage-2 tables: garena_words per workgroup
     uint64_t garena_words;
     uint64_t* stats;             // byte and hand-over counters (profiling), NULL = off

@@ -60,6 +60,7 @@ struct WgStore {
 
 struct Shared {
     uint32_t h, rank, hlen, lh, K, Kt, defer, stop;
+    uint32_t slice, nslice;  // this workgroup's share of the centre: neighbours slice, slice + nslice, ...
     uint32_t gi, cur_g, skip;
     uint64_t hoff;
     int64_t th;
@@ -67,6 +68,12 @@ struct Shared {
     uint32_t ws[NWAVE];
     uint64_t g[8];
 };
+
+// The slice of a sliced centre that owns neighbour x (a property of x alone, so
+// every slice, whatever order its lists come in, agrees on it).
+__device__ __forceinline__ uint32_t slice_of(uint32_t x, uint32_t nslice) {
+    return (uint32_t)(((uint64_t)(x * 2654435761u) * nslice) >> 32);
+}
 
 // classify the intersecting pair (x, y) found in x's 2-hop lists
 __device__ __forceinline__ void classify(const TriadParams& P, const HeGraph& G, const Tables& T, const WgStore& S,
@@ -298,9 +305,21 @@ __device__ void run_centres(const TriadParams& P, const Tables& T, const WgStore
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     for (;;) {
         if (tid == 0) {
-            uint64_t n = BIG ? (uint64_t)*P.big_count : P.M.total;
+            const bool sliced = BIG && P.slice_pre;
+            uint64_t n = sliced ? P.slice_pre[P.slice_cap + 1] : BIG ? (uint64_t)*P.big_count : P.M.total;
             uint32_t c = atomicAdd(BIG ? P.big_queue : P.queue, 1u);
             sh.stop = c >= n;
+            sh.slice = 0;
+            sh.nslice = 1;
+            if (!sh.stop && sliced) {  // slice c of the deferred centres' slices
+                const uint64_t nc = P.slice_pre[P.slice_cap];
+                const uint32_t ci = seg_of<uint64_t>(P.slice_pre, (uint32_t)nc, c);
+                const uint64_t first = P.slice_pre[ci];
+                const uint64_t next = ci + 1 < nc ? P.slice_pre[ci + 1] : n;
+                sh.slice = (uint32_t)(c - first);
+                sh.nslice = (uint32_t)(next - first);
+                c = ci;
+            }
             if (!sh.stop) {
                 uint32_t gi, h, rank;
                 if (BIG) {
@@ -427,8 +446,10 @@ __device__ void run_centres(const TriadParams& P, const Tables& T, const WgStore
         }
         __syncthreads();
         const uint32_t K = sh.K;
+        const uint32_t slice = sh.slice, nslice = sh.nslice;
         // 2a. hyperedge family: every eligible pair of neighbours classified as disjoint
-        if (P.do_he) {
+        // (by the centre's first slice)
+        if (P.do_he && slice == 0) {
             uint32_t* cnt = S.warea;  // cnt[f * (hlen + 1) + c]
             const uint32_t W = hlen + 1;
             for (uint32_t i = tid; i < 2 * W; i += HGT_WG) cnt[i] = 0;
@@ -492,11 +513,29 @@ __device__ void run_centres(const TriadParams& P, const Tables& T, const WgStore
         // 2b. temporal family: eligible in-window neighbour pairs enumerated directly
         if (P.do_tmp) {
             uint32_t* tl = S.warea;  // 4 words per entry: x, meta, t lo, t hi
+            // A sliced centre lists the neighbours that its slice owns first (rows
+            // 0 .. Ko-1), the others after them; unsliced, every entry is a row.
+            if (nslice > 1) {
+                if (tid == 0) sh.g[0] = 0;
+                __syncthreads();
+                for (uint32_t i = tid; i < K; i += HGT_WG) {
+                    const uint32_t m = S.nl_meta[i];
+                    if (meta_elig(m) && meta_win(m) && slice_of(S.nl_x[i], nslice) == slice)
+                        atomicAdd((unsigned long long*)&sh.g[0], 1ull);
+                }
+                __syncthreads();
+            }
+            const uint32_t Ko0 = nslice > 1 ? (uint32_t)sh.g[0] : 0;
+            if (tid == 0) sh.g[1] = 0;
+            __syncthreads();
             for (uint32_t i = tid; i < K; i += HGT_WG) {
                 uint32_t m = S.nl_meta[i];
                 if (!meta_elig(m) || !meta_win(m)) continue;
-                uint32_t q = atomicAdd(&sh.Kt, 1u);
                 uint32_t x = S.nl_x[i];
+                uint32_t q;
+                if (nslice == 1) q = atomicAdd(&sh.Kt, 1u);
+                else if (slice_of(x, nslice) == slice) q = (uint32_t)atomicAdd((unsigned long long*)&sh.g[1], 1ull);
+                else q = Ko0 + atomicAdd(&sh.Kt, 1u);
                 int64_t t = G.g.h_ts[x];
                 tl[4 * q] = x;
                 tl[4 * q + 1] = m;
@@ -504,9 +543,12 @@ __device__ void run_centres(const TriadParams& P, const Tables& T, const WgStore
                 tl[4 * q + 3] = (uint32_t)((uint64_t)t >> 32);
             }
             __syncthreads();
-            const uint32_t Kt = sh.Kt;
-            // pairs (i, j), i < j, over the Kt x Kt square (the lower half is skipped)
-            const uint64_t nsq = (uint64_t)Kt * Kt;
+            const uint32_t Kt = sh.Kt + Ko0;
+            // Unsliced: pairs (i, j), i < j, over the Kt x Kt square (the lower half is
+            // skipped).  Sliced: each unordered pair belongs to the slice that owns its
+            // endpoint of smaller ID; rows i < Ko against every j, kept when x_j > x_i.
+            const uint64_t rows = nslice == 1 ? Kt : Ko0;
+            const uint64_t nsq = rows * Kt;
             for (uint64_t q = tid; q < nsq; q += HGT_WG) {
                 uint32_t i, j;
                 if (Kt < 65536u) {
@@ -516,7 +558,7 @@ __device__ void run_centres(const TriadParams& P, const Tables& T, const WgStore
                     i = (uint32_t)(q / Kt);
                     j = (uint32_t)(q - (uint64_t)i * Kt);
                 }
-                if (j <= i) continue;
+                if (nslice == 1 ? j <= i : tl[4 * j] <= tl[4 * i]) continue;
                 int64_t ti = (int64_t)((uint64_t)tl[4 * i + 2] | ((uint64_t)tl[4 * i + 3] << 32));
                 int64_t tj = (int64_t)((uint64_t)tl[4 * j + 2] | ((uint64_t)tl[4 * j + 3] << 32));
                 if (!within(sh.th, ti, tj, G.window)) continue;
@@ -540,6 +582,7 @@ __device__ void run_centres(const TriadParams& P, const Tables& T, const WgStore
             uint32_t x = S.nl_x[i];
             uint32_t m = S.nl_meta[i];
             if (!meta_elig(m)) continue;
+            if (nslice > 1 && slice_of(x, nslice) != slice) continue;  // another slice's neighbour
             if (!P.do_he && !meta_win(m)) continue;
             expand_x(P, G, T, S, sh, nh_log, wmem[wave], wk, wv, x, m, acc_he, acc_tmp, acc_st);
         }
@@ -628,6 +671,45 @@ void triad_he_prepare(TriadParams& P, hipStream_t s) {
 
 void triad_he_launch_small(TriadParams& P, unsigned grid, hipStream_t s) {
     if (P.M.total) k_delta_small<<<grid, HGT_WG, 0, s>>>(P);
+}
+
+namespace {
+
+constexpr uint32_t kSliceLh = 4096;  // member-list entries per slice of a deferred centre (default)
+constexpr uint32_t kMaxSlices = 32;
+
+// one wave per deferred centre: its slice count from its members' list lengths
+__global__ void k_slice_count(Multi M, const uint64_t* __restrict__ list, const uint32_t* n_p, uint64_t cap,
+                              uint32_t per, uint64_t* pre) {
+    const int lane = threadIdx.x & 63;
+    const uint64_t c = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint32_t n = *n_p;
+    if (c == 0 && lane == 0) pre[cap] = n;
+    if (c >= n) return;
+    const uint64_t it = list[c];
+    const GraphView& g = M.graphs[(uint32_t)(it >> 32)].g;
+    const uint32_t h = (uint32_t)it;
+    const uint32_t* row = g.h2v + g.h_off[h];
+    const uint32_t len = g.h_len[h];
+    uint64_t lh = 0;
+    for (uint32_t i = lane; i < len; i += 64) lh += g.v_len[row[i]];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) lh += __shfl_xor(lh, o, 64);
+    if (lane == 0) {
+        const uint64_t sl = (lh + per - 1) / per;
+        pre[c] = sl < 1 ? 1 : (sl > kMaxSlices ? kMaxSlices : sl);
+    }
+}
+
+}  // namespace
+
+void triad_he_slices(TriadParams& P, hipStream_t s) {
+    if (!P.slice_pre || !P.M.total) return;
+    const uint64_t cap = P.slice_cap;
+    k_slice_count<<<(unsigned)((cap * 64 + 255) / 256), 256, 0, s>>>(P.M, P.big_list, P.big_count, cap,
+                                                                     P.slice_lh ? P.slice_lh : kSliceLh, P.slice_pre);
+    // exclusive prefix over the deferred centres; the total after the count
+    hgt_scan_u64(P.slice_pre, P.slice_pre, cap, P.slice_pre + cap, P.slice_pre + cap + 1, P.slice_scan_tmp, s);
 }
 
 void triad_he_launch_big(TriadParams& P, unsigned grid, hipStream_t s) {

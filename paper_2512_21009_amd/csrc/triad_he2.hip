@@ -26,8 +26,19 @@ using namespace tri;
 
 constexpr uint32_t ARENA_S = 8192;    // 32 KB of LDS: four workgroups per CU
 constexpr uint32_t ARENA_M = 37888;   // 148 KB of LDS: one workgroup per CU
-constexpr uint32_t K_MAX = 0x3fffu;   // neighbours with 14 bits
-// entry key: vertex << 15 | [vertex in h] << 14 | neighbour index (14 bits)
+constexpr uint32_t K_MAX = 0xfffffu;  // neighbours with 20 bits
+constexpr int KEY_IN = 20;             // entry key: vertex << KEY_V | [vertex in h] << KEY_IN | neighbour
+constexpr int KEY_V = 21;
+constexpr uint32_t W_MAX = 1u << 21;   // entries of a centre: run starts take 21 bits
+constexpr int EMIT_HI = 20;            // vertex-pair key: lo run << EMIT_LO | hi run << EMIT_HI | neighbour
+constexpr int EMIT_LO = 41;
+// A centre with this many neighbour-row entries or neighbours goes to the 2-hop
+// kernel, which shares it among several workgroups: in dense neighbourhoods its
+// runs are long (enumerating their pairs is quadratic in one workgroup) and its
+// neighbours share many vertices (the vertex pairs of the aggregated phase blow up).
+constexpr uint32_t W_2HOP = 65536;
+constexpr uint32_t K_2HOP = 0x4000u;
+// entry key: vertex << 21 | [vertex in h] << 20 | neighbour index (20 bits)
 
 // open-addressing tables of any capacity: slot = multiply-shift hash scaled to cap
 __device__ __forceinline__ uint32_t fr_slot(uint32_t key, uint32_t cap) {
@@ -490,8 +501,8 @@ __device__ __forceinline__ void multi_pair(const GraphView& g, const Tables& T, 
                                            const uint64_t* keys, const uint32_t* nl_x, const uint32_t* nl_meta,
                                            uint64_t ex, uint64_t ey, uint64_t* stats, uint32_t* myacc32) {
     const uint32_t xi = (uint32_t)ex & K_MAX, yi = (uint32_t)ey & K_MAX;
-    const uint32_t vu = (uint32_t)(keys[(uint32_t)(ex >> 30)] >> 15);
-    const uint32_t vw = (uint32_t)(keys[(uint32_t)(ex >> 14) & 0xffffu] >> 15);
+    const uint32_t vu = (uint32_t)(keys[(uint32_t)(ex >> EMIT_LO)] >> KEY_V);
+    const uint32_t vw = (uint32_t)(keys[(uint32_t)(ex >> EMIT_HI) & (W_MAX - 1)] >> KEY_V);
     const uint32_t mx = nl_meta[xi], my = nl_meta[yi];
     uint32_t s, shh, f1, f2;
     row_meet2(g.h2v + g.h_off[nl_x[xi]], meta_len(mx), g.h2v + g.h_off[nl_x[yi]], meta_len(my), hm, hlen, s, shh, f1, f2);
@@ -523,7 +534,8 @@ template <int STAGE>
 __device__ void he2_body(const He2Params& P, uint32_t* arena, const uint32_t ARENA_WORDS, Sh2& sh, const Tables& T,
                          uint64_t* acc_all, uint32_t* acc32_all, uint64_t* st, uint64_t* ph) {
     const int tid = threadIdx.x;
-    uint64_t t_mark = 0;  // thread 0: wall clock at the last phase mark (profiling)
+    uint64_t t_mark = 0;    // thread 0: wall clock at the last phase mark (profiling)
+    uint64_t t_centre = 0;  // ... at the start of the current centre
 #define HE2_MARK(i)                                     \
     do {                                                \
         if (P.phase_ticks && tid == 0) {                \
@@ -565,7 +577,7 @@ __device__ void he2_body(const He2Params& P, uint32_t* arena, const uint32_t ARE
         }
         __syncthreads();
         if (sh.stop) break;
-        if (P.phase_ticks && tid == 0) t_mark = wall_clock64();
+        if (P.phase_ticks && tid == 0) t_mark = t_centre = wall_clock64();
         if (sh.gi != sh.cur_g) {  // the counts so far belong to the previous graph
             he2_flush_graph(P, sh.cur_g, acc_all);
             if (tid == 0) sh.cur_g = sh.gi;
@@ -656,15 +668,18 @@ __device__ void he2_body(const He2Params& P, uint32_t* arena, const uint32_t ARE
                 o_ent = (o_ent + 1) & ~1ull;
                 uint64_t need = 2ull * carry > 2ull * hlen + 2 ? 2ull * carry : 2ull * hlen + 2;
                 sh.o_ent = (uint32_t)o_ent;
-                sh.defer = (K > K_MAX || o_ent + need > ARENA_WORDS) ? 1u : 0u;
+                // too large for this arena: the next stage; too dense for any: the 2-hop kernel
+                sh.defer = (o_ent + need > ARENA_WORDS) ? 1u : 0u;
+                if (K >= K_2HOP || carry >= W_2HOP) sh.defer = 2u;
             }
             __syncthreads();
         }
         if (sh.defer) {
             if (tid == 0) {
-                uint32_t q = atomicAdd(&P.count[STAGE], 1u);
-                P.list[STAGE][q] = item_of(sh.gi, h);
-                P.rank[STAGE][q] = sh.rank;
+                const int to = sh.defer == 2u ? 2 : STAGE;
+                uint32_t q = atomicAdd(&P.count[to], 1u);
+                P.list[to][q] = item_of(sh.gi, h);
+                P.rank[to][q] = sh.rank;
                 atomicAdd((unsigned long long*)&st[0], 1ull);
             }
             HE2_MARK(7);
@@ -741,14 +756,14 @@ __device__ void he2_body(const He2Params& P, uint32_t* arena, const uint32_t ARE
             uint32_t x = nl_x[xi];
             uint32_t v = G.g.h2v[G.g.h_off[x] + (p - nl_mo[xi])];
             uint64_t inh = contains_u32(hm, hlen, v) ? 1ull : 0ull;
-            keys[p] = ((uint64_t)v << 15) | (inh << 14) | xi;
+            keys[p] = ((uint64_t)v << KEY_V) | (inh << KEY_IN) | xi;
         }
         __syncthreads();
         sort_keys(keys, W);
         // vertices met by two or more neighbours; per neighbour, how many it has
         for (uint32_t i = tid; i < W; i += HGT_WG) {
-            uint64_t v = keys[i] >> 15;
-            bool shared = (i > 0 && (keys[i - 1] >> 15) == v) || (i + 1 < W && (keys[i + 1] >> 15) == v);
+            uint64_t v = keys[i] >> KEY_V;
+            bool shared = (i > 0 && (keys[i - 1] >> KEY_V) == v) || (i + 1 < W && (keys[i + 1] >> KEY_V) == v);
             if (shared) atomicAdd(&nl_msh[keys[i] & K_MAX], 1u);
         }
         __syncthreads();
@@ -813,9 +828,9 @@ __device__ void he2_body(const He2Params& P, uint32_t* arena, const uint32_t ARE
         }
         __syncthreads();
         const uint32_t nb_cap = W / (RUN_DIRECT + 1) + 1, n_hist = 4u * (hlen + 1);
-        const uint64_t o_big = (uint64_t)sh.o_ent + 2ull * W, o_hist = o_big + nb_cap, o_off = o_hist + n_hist;
+        const uint64_t o_big = (uint64_t)sh.o_ent + 2ull * W, o_hist = o_big + 2ull * nb_cap, o_off = o_hist + n_hist;
         const uint64_t o_eoff = o_off + K + 1, o_cur = o_eoff + K + 1, o_sl = o_cur + K;
-        if (!P.static_mode && P.pair_agg && W < 65536u) {
+        if (!P.static_mode && P.pair_agg && W < W_2HOP) {
             for (uint32_t i = tid; i < K; i += HGT_WG) {
                 const uint64_t m = nl_msh[i];
                 if (m >= 2) {
@@ -886,20 +901,24 @@ __device__ void he2_body(const He2Params& P, uint32_t* arena, const uint32_t ARE
             // runs: shared vertices per neighbour, long runs listed, short runs enumerated
             for (uint32_t i = tid; i < W; i += HGT_WG) {
                 const uint64_t ki = keys[i];
-                const uint64_t v = ki >> 15;
-                const uint32_t st0 = lower_bound_u64(keys, W, v << 15);
-                const uint32_t en = lower_bound_u64(keys, W, (v + 1) << 15);
+                const uint64_t v = ki >> KEY_V;
+                const uint32_t st0 = lower_bound_u64(keys, W, v << KEY_V);
+                const uint32_t en = lower_bound_u64(keys, W, (v + 1) << KEY_V);
                 const uint32_t R = en - st0;
                 if (R < 2) continue;
                 const uint32_t xi = (uint32_t)ki & K_MAX;
                 if (nl_msh[xi] >= 2) sl[off[xi] + atomicAdd(&cur[xi], 1u)] = st0;
                 if (R > RUN_DIRECT) {
-                    if (i == st0) big[atomicAdd(&sh.nbig, 1u)] = st0 | (R << 16);
+                    if (i == st0) {
+                        const uint32_t q = atomicAdd(&sh.nbig, 1u);
+                        big[2 * q] = st0;
+                        big[2 * q + 1] = R;
+                    }
                     continue;
                 }
                 const uint32_t mx = nl_meta[xi];
                 if (!meta_elig(mx)) continue;
-                const uint32_t vin = (uint32_t)(ki >> 14) & 1u;
+                const uint32_t vin = (uint32_t)(ki >> KEY_IN) & 1u;
                 const uint32_t xl = meta_len(mx), cx = meta_c(mx), dx = hlen - cx;
                 const uint32_t ob = (hlen > cx ? 1u : 0u) | 24u | (xl - cx > 1 ? 2u : 0u);
                 // partners counted per (gy, rng) cell in 6-bit fields (a run holds at most 63)
@@ -941,7 +960,7 @@ __device__ void he2_body(const He2Params& P, uint32_t* arena, const uint32_t ARE
                 for (uint32_t q = j + 1; q < m; q++) {
                     const uint32_t w = sl[o + q];
                     const uint32_t lo = u < w ? u : w, hi = u < w ? w : u;
-                    emit[pos++] = ((uint64_t)lo << 30) | ((uint64_t)hi << 14) | x;
+                    emit[pos++] = ((uint64_t)lo << EMIT_LO) | ((uint64_t)hi << EMIT_HI) | x;
                 }
             }
             __syncthreads();
@@ -951,8 +970,8 @@ __device__ void he2_body(const He2Params& P, uint32_t* arena, const uint32_t ARE
             const uint32_t nbig = sh.nbig;
             if (P.stats && tid == 0 && nbig) atomicAdd((unsigned long long*)&P.stats[ST_AGG_LONG], (unsigned long long)nbig);
             for (uint32_t r = 0; r < nbig; r++) {
-                const uint32_t br = big[r], st0 = br & 0xffffu, R = br >> 16;
-                const uint32_t vin = (uint32_t)(keys[st0] >> 14) & 1u;
+                const uint32_t st0 = big[2 * r], R = big[2 * r + 1];
+                const uint32_t vin = (uint32_t)(keys[st0] >> KEY_IN) & 1u;
                 for (uint32_t c = tid; c < n_hist; c += HGT_WG) hist[c] = 0;
                 if (tid == 0) sh.nb1 = 0;
                 __syncthreads();
@@ -1023,9 +1042,9 @@ __device__ void he2_body(const He2Params& P, uint32_t* arena, const uint32_t ARE
                     const uint32_t i = b + tid;
                     uint32_t c = 0;
                     if (i < E2) {
-                        const uint64_t uw = emit[i] >> 14;
-                        if (i == 0 || (emit[i - 1] >> 14) != uw) {
-                            const uint64_t R = lower_bound_u64(emit, E2, (uw + 1) << 14) - i;
+                        const uint64_t uw = emit[i] >> EMIT_HI;
+                        if (i == 0 || (emit[i - 1] >> EMIT_HI) != uw) {
+                            const uint64_t R = lower_bound_u64(emit, E2, (uw + 1) << EMIT_HI) - i;
                             const uint64_t c64 = R * (R - 1) / 2;
                             atomicAdd((unsigned long long*)&sh.g[5], (unsigned long long)c64);
                             c = (uint32_t)c64;  // used only when the total fits 31 bits
@@ -1042,16 +1061,16 @@ __device__ void he2_body(const He2Params& P, uint32_t* arena, const uint32_t ARE
             if (T2 < 0x80000000ull) {
                 for (uint32_t p = tid; p < (uint32_t)T2; p += HGT_WG) {
                     const uint32_t i = seg_of<uint32_t>(pp, E2, p);  // the run's head
-                    const uint64_t uw = emit[i] >> 14;
-                    const uint32_t R = lower_bound_u64(emit, E2, (uw + 1) << 14) - i;
+                    const uint64_t uw = emit[i] >> EMIT_HI;
+                    const uint32_t R = lower_bound_u64(emit, E2, (uw + 1) << EMIT_HI) - i;
                     uint32_t a, b;
                     tri_decode(R, p - pp[i], a, b);
                     multi_pair(G.g, T, hlen, hm, keys, nl_x, nl_meta, emit[i + a], emit[i + b], P.stats, myacc32);
                 }
             } else {
                 for (uint32_t i = tid; i < E2; i += HGT_WG) {
-                    const uint64_t uw = emit[i] >> 14;
-                    for (uint32_t j = i + 1; j < E2 && (emit[j] >> 14) == uw; j++)
+                    const uint64_t uw = emit[i] >> EMIT_HI;
+                    for (uint32_t j = i + 1; j < E2 && (emit[j] >> EMIT_HI) == uw; j++)
                         multi_pair(G.g, T, hlen, hm, keys, nl_x, nl_meta, emit[i], emit[j], P.stats, myacc32);
                 }
             }
@@ -1062,14 +1081,14 @@ __device__ void he2_body(const He2Params& P, uint32_t* arena, const uint32_t ARE
         // merging the two rows).
             for (uint32_t i = tid; i + 1 < W; i += HGT_WG) {
                 const uint64_t ki = keys[i];
-                const uint64_t v = ki >> 15;
-                if ((keys[i + 1] >> 15) != v) continue;
+                const uint64_t v = ki >> KEY_V;
+                if ((keys[i + 1] >> KEY_V) != v) continue;
                 const uint32_t xi = (uint32_t)ki & K_MAX;
-                const uint32_t vin = (uint32_t)(ki >> 14) & 1u;
+                const uint32_t vin = (uint32_t)(ki >> KEY_IN) & 1u;
                 const uint32_t xsh = nl_msh[xi];
                 for (uint32_t j = i + 1; j < W; j++) {
                     const uint64_t kj = keys[j];
-                    if ((kj >> 15) != v) break;
+                    if ((kj >> KEY_V) != v) break;
                     const uint32_t yi = (uint32_t)kj & K_MAX;
                     uint32_t sc = 1, shh = vin;
                     if (xsh > 1 && nl_msh[yi] > 1) {
@@ -1103,14 +1122,19 @@ __device__ void he2_body(const He2Params& P, uint32_t* arena, const uint32_t ARE
         }
         __syncthreads();
         HE2_MARK(6);
+        // the longest centre this workgroup finished (slot HE2_PHASES - 1 holds a maximum)
+        if (P.phase_ticks && tid == 0 && t_mark - t_centre > ph[HE2_PHASES - 1]) ph[HE2_PHASES - 1] = t_mark - t_centre;
     }
 #undef HE2_MARK
 }
 
 template <int STAGE>
 __device__ void he2_flush_stats(const He2Params& P, const uint64_t* st, const uint64_t* ph) {
-    if (P.phase_ticks && threadIdx.x < HE2_PHASES && ph[threadIdx.x])
+    if (P.phase_ticks && threadIdx.x < HE2_PHASES - 1 && ph[threadIdx.x])
         atomicAdd((unsigned long long*)&P.stats[ST_PH0 + HE2_PHASES * STAGE + threadIdx.x],
+                  (unsigned long long)ph[threadIdx.x]);
+    if (P.phase_ticks && threadIdx.x == HE2_PHASES - 1 && ph[threadIdx.x])
+        atomicMax((unsigned long long*)&P.stats[ST_PH0 + HE2_PHASES * STAGE + threadIdx.x],
                   (unsigned long long)ph[threadIdx.x]);
     if (P.stats && threadIdx.x == 0 && st[0])
         atomicAdd((unsigned long long*)&P.stats[ST_DEFER0 + STAGE], (unsigned long long)st[0]);

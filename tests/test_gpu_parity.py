@@ -324,3 +324,69 @@ def test_compaction_keeps_store_and_counts(gpu_lib):
     compare_store(p.g, p.o, "compaction end")
     compare_counts(p.g, p.o, ALL, "compaction end")
     p.close()
+
+
+_ORACLE_CACHE = {}
+
+
+@pytest.mark.parametrize("slice_lh", ["0", "100000000"])
+def test_dense_centres(gpu_lib, monkeypatch, slice_lh):
+    """A dense graph (3,000 hyperedges with up to 400 members on 900 vertices):
+    a batch that deletes its largest hyperedges and inserts their rows again.
+    Those centres hold more than 65,536 neighbour-row entries, so they go to
+    the 2-hop kernel, shared among several workgroups (or, with a slice size
+    above every centre's lists, one workgroup each); the change of the counts
+    equals the oracle's delta by definition."""
+    from .test_gpu_fullsize import _gpu_delta, _oracle_delta
+    if slice_lh != "0":
+        monkeypatch.setenv("HGT_SLICE_LH", slice_lh)
+    monkeypatch.delenv("HGT_FORCE_STAGE", raising=False)
+    st = W.plain_stream("dense", 900, 3000, ("power", 1.4, 2, 400), 0.0, 0.0, 1, 1, 1, W.SEED_BASE + 91)
+    ini = st.initial
+    cards = np.diff(ini.offsets.astype(np.int64))
+    big = np.argsort(-cards, kind="stable")[:2].astype(np.int64)
+    neighbour_entries = 0
+    rows = ini.rows(big)
+    mem = set(ini.members[ini.offsets[big[0]]:ini.offsets[big[0] + 1]].tolist())
+    for i in range(ini.n):  # the entries of the largest centre's neighbour rows
+        r = ini.members[ini.offsets[i]:ini.offsets[i + 1]]
+        if i != big[0] and mem.intersection(r.tolist()):
+            neighbour_entries += len(r)
+    assert neighbour_entries > 65536, neighbour_entries
+    p = Pair(W.Stream("dense", st.n_vertices, ini), track=("hyperedge",))
+    before = np.array(p.g.triad_counts("hyperedge"), np.uint64)
+    batch = W.Batch(del_handles=big, ins=rows, ins_handles=np.arange(ini.n, ini.n + len(big), dtype=np.int64))
+    args, fin = p.prepare(batch, "dense")
+    out = p.g.apply_batch(*args)
+    ids = out.cpu().numpy().astype(np.int64)
+    after = np.array(p.g.triad_counts("hyperedge"), np.uint64)
+    if "dense" not in _ORACLE_CACHE:  # the same oracle delta serves both launches
+        _ORACLE_CACHE["dense"] = _oracle_delta(p.o, big, rows, None, ("hyperedge",))
+    _, oids, want = _ORACLE_CACHE["dense"]
+    assert ids.tolist() == [int(x) for x in oids]
+    got = _gpu_delta({"hyperedge": before}, {"hyperedge": after})["hyperedge"]
+    bad = np.nonzero(got != want["hyperedge"])[0]
+    assert len(bad) == 0, f"classes {bad.tolist()[:8]}: gpu {got[bad][:8]} oracle {want['hyperedge'][bad][:8]}"
+    p.close()
+
+
+def test_sliced_two_hop_centres(gpu_lib, monkeypatch):
+    """Centres of the 2-hop kernel shared by several workgroups (a tiny slice
+    size makes nearly every centre sliced): hyperedge centres all sent there,
+    temporal centres use it anyway.  Same counts as the oracle."""
+    monkeypatch.setenv("HGT_SLICE_LH", "48")
+    monkeypatch.setenv("HGT_FORCE_STAGE", "3")
+    st = W.plain_stream("slices", 400, 700, ("power", 1.6, 2, 150), 1.3, 0.0, 2, 80, 90, W.SEED_BASE + 83)
+    p = Pair(st, track=("hyperedge",))
+    compare_counts(p.g, p.o, p.track, "sliced build")
+    for k, b in enumerate(st.batches):
+        p.apply(b, f"sliced batch {k}")
+        compare_counts(p.g, p.o, p.track, f"sliced batch {k}")
+    p.close()
+    st = W.temporal_stream("tslices", 300, 1500, 300, 2, 1.8, 2, 40, 50.0, 40_000, 20_000, W.SEED_BASE + 84, pop_s=1.1)
+    p = Pair(st, track=("temporal", "hyperedge"))
+    compare_counts(p.g, p.o, p.track, "sliced temporal build")
+    for k, b in enumerate(st.batches):
+        p.apply(b, f"sliced temporal batch {k}")
+        compare_counts(p.g, p.o, p.track, f"sliced temporal batch {k}")
+    p.close()

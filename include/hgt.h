@@ -193,7 +193,9 @@ int hgt_apply_batches(hgt_batch* batches, uint32_t n, void* stream);
 #define HGT_BATCHES_AUTOTUNE 2u  /* launch choices (workgroups per CU of the
                                   * global histogram stage, whether centres skip
                                   * the 148 KB stage, slots of the per-wave
-                                  * 2-hop hashes) picked per key of the round:
+                                  * 2-hop hashes, the vertex-pair count from
+                                  * which a dense centre goes to the 2-hop
+                                  * kernel) picked per key of the round:
                                   * tracked families, number of graphs, changes
                                   * and the 2-hop load of the heaviest centre,
                                   * in log2/log4 buckets.  Each choice is timed

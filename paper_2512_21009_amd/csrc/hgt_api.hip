@@ -142,6 +142,7 @@ thread_local int t_capture = 0;
 struct TuneChoice {
     int wg_per_cu, skip_lds148;
     uint32_t wave_slots;
+    uint64_t e2_2hop;  // vertex pairs from which a hyperedge centre goes to the 2-hop kernel (0: default)
 };
 thread_local const TuneChoice* t_tune = nullptr;
 thread_local hipEvent_t t_tune_ev[2] = {nullptr, nullptr};  // recorded around an autotuned round's launches
@@ -293,6 +294,7 @@ struct hgt_graph {
     int iv_direct = 0;              // HGT_IV_DIRECT=1 (tests): incident-vertex owners without maps
     int iv_wg_per_cu = 8;           // HGT_IV_WG_PER_CU: workgroups per CU of the incident-vertex global stage
     uint32_t slice_lh = 0;          // HGT_SLICE_LH (tests): list entries per slice of a 2-hop kernel centre
+    uint64_t e2_2hop = 0;           // HGT_E2_2HOP: vertex pairs from which a centre goes to the 2-hop kernel
     int iv_force_stage = 0;         // HGT_IV_FORCE_STAGE (tests): incident-vertex stages below it pass owners on
     uint32_t wave_slots = 8192;     // HGT_WAVE_SLOTS (tests): slots of the 2-hop kernels' per-wave global hashes
     int skip_lds148 = 1;            // HGT_SKIP_LDS148=0: centres go through the 148 KB stage (one workgroup
@@ -840,6 +842,7 @@ int run_phase(hgt_graph* owner, const PhaseJob* jobs, uint32_t nj, bool minus, b
             E.force_stage = fs ? std::atoi(fs) : owner->force_stage;
             E.pair_agg = owner->pair_agg;
             E.skip_lds148 = t_tune ? t_tune->skip_lds148 : owner->skip_lds148;
+            E.e2_2hop = t_tune && t_tune->e2_2hop ? t_tune->e2_2hop : owner->e2_2hop;
             E.static_mode = full ? 1 : 0;
             hgt_fill_u32(ctr + 16, 0, 6, s);
             hgt_fill_u32(ctr + 5, 0, 1, s);
@@ -1587,6 +1590,7 @@ int hgt_build(const hgt_build_desc* d, hgt_graph** out) {
     if (const char* sk = std::getenv("HGT_SKIP_LDS148")) g->skip_lds148 = std::atoi(sk) != 0;
     if (const char* iw = std::getenv("HGT_IV_WG_PER_CU")) g->iv_wg_per_cu = std::max(1, std::min(16, std::atoi(iw)));
     if (const char* sl = std::getenv("HGT_SLICE_LH")) g->slice_lh = (uint32_t)std::max(1, std::atoi(sl));
+    if (const char* e2 = std::getenv("HGT_E2_2HOP")) g->e2_2hop = std::strtoull(e2, nullptr, 10);
     if (const char* iv = std::getenv("HGT_IV_DIRECT")) g->iv_direct = std::atoi(iv) != 0;
     if (const char* fs = std::getenv("HGT_IV_FORCE_STAGE")) g->iv_force_stage = std::atoi(fs);
     if (const char* ws = std::getenv("HGT_WAVE_SLOTS")) {  // a power of two, 64 .. 2^20
@@ -1774,7 +1778,9 @@ namespace {
 // best choice's is dropped, and once every remaining choice has kTuneTrials
 // trials the fastest (by its quickest trial) is kept for the key and appended
 // to the cache file, which later processes read first.
-constexpr TuneChoice kTune[] = {{4, 1, 8192}, {2, 1, 8192}, {8, 1, 8192}, {4, 0, 8192}, {4, 1, 32768}};
+constexpr TuneChoice kTune[] = {{4, 1, 8192, 0},       {2, 1, 8192, 0},       {8, 1, 8192, 0},
+                                {4, 0, 8192, 0},       {4, 1, 32768, 0},      {4, 1, 8192, 1u << 18},
+                                {4, 1, 8192, 1u << 21}};
 constexpr int kTuneN = (int)(sizeof(kTune) / sizeof(kTune[0]));
 constexpr int kTuneTrials = 2;
 constexpr float kTuneDrop = 1.25f;
@@ -1822,8 +1828,8 @@ uint64_t tune_key(const std::vector<Pending*>& ps, int n_cu) {
 }
 
 // Cache file: one line per settled key, "key choice wg_per_cu skip_lds148
-// wave_slots best_ms"; lines whose choice does not match this library's table
-// are ignored.
+// wave_slots e2_2hop best_ms"; lines whose choice does not match this library's
+// table are ignored.
 void tune_load(Tuner& T) {
     if (T.loaded) return;
     T.loaded = true;
@@ -1839,13 +1845,13 @@ void tune_load(Tuner& T) {
     }
     FILE* f = std::fopen(T.path.c_str(), "r");
     if (!f) return;
-    unsigned long long key;
+    unsigned long long key, e2;
     int choice, wg, skip;
     unsigned slots;
     float ms;
-    while (std::fscanf(f, "%llx %d %d %d %u %f", &key, &choice, &wg, &skip, &slots, &ms) == 6) {
+    while (std::fscanf(f, "%llx %d %d %d %u %llu %f", &key, &choice, &wg, &skip, &slots, &e2, &ms) == 7) {
         if (choice < 0 || choice >= kTuneN || kTune[choice].wg_per_cu != wg || kTune[choice].skip_lds148 != skip ||
-            kTune[choice].wave_slots != slots)
+            kTune[choice].wave_slots != slots || kTune[choice].e2_2hop != e2)
             continue;
         TuneEntry& t = T.tab[(uint64_t)key];
         t.pick = choice;
@@ -1870,8 +1876,8 @@ void tune_settle(Tuner& T, uint64_t key, TuneEntry& t) {
     if (T.path.empty()) return;
     if (FILE* f = std::fopen(T.path.c_str(), "a")) {
         const TuneChoice& c = kTune[best];
-        std::fprintf(f, "%llx %d %d %d %u %.4f\n", (unsigned long long)key, best, c.wg_per_cu, c.skip_lds148,
-                     c.wave_slots, t.best_ms[best]);
+        std::fprintf(f, "%llx %d %d %d %u %llu %.4f\n", (unsigned long long)key, best, c.wg_per_cu, c.skip_lds148,
+                     c.wave_slots, (unsigned long long)c.e2_2hop, t.best_ms[best]);
         std::fclose(f);
     }
 }

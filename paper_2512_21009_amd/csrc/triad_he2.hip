@@ -38,6 +38,8 @@ constexpr int EMIT_LO = 41;
 // neighbours share many vertices (the vertex pairs of the aggregated phase blow up).
 constexpr uint32_t W_2HOP = 65536;
 constexpr uint32_t K_2HOP = 0x4000u;
+constexpr uint64_t E2_2HOP = 65536;  // ... and so does one whose neighbours hold this many vertex pairs
+                                     // (He2Params::e2_2hop overrides it)
 // entry key: vertex << 21 | [vertex in h] << 20 | neighbour index (20 bits)
 
 // open-addressing tables of any capacity: slot = multiply-shift hash scaled to cap
@@ -130,6 +132,7 @@ struct Sh2 {
     uint32_t o_nh, o_ent;  // arena word offsets
     uint32_t agg, nbig, nb1;   // aggregated pair phase: taken, long runs, long-run members of length > 1
     uint32_t fits_g;           // ... its tables fit the global stage's arena
+    uint32_t to2;              // too many vertex pairs: the centre goes to the 2-hop kernel
     uint64_t acc2[NWAVE * HGT_N_HE_CLASSES];  // the centre's changes, doubled (ordered pairs once)
     uint32_t ws[NWAVE];
     uint64_t g[8];
@@ -822,6 +825,7 @@ __device__ void he2_body(const He2Params& P, uint32_t* arena, const uint32_t ARE
         if (tid == 0) {
             sh.agg = 0;
             sh.fits_g = 0;
+            sh.to2 = 0;
             sh.nbig = 0;
             sh.g[6] = 0;  // shared entries of neighbours with two or more
             sh.g[7] = 0;  // their vertex pairs
@@ -844,21 +848,23 @@ __device__ void he2_body(const He2Params& P, uint32_t* arena, const uint32_t ARE
                 const uint64_t need = o_emit + 3ull * sh.g[7];
                 sh.agg = (o_sl <= ARENA_WORDS && need <= ARENA_WORDS) ? 1u : 0u;
                 sh.fits_g = need <= P.garena_words ? 1u : 0u;
+                if (sh.g[7] >= (P.e2_2hop ? P.e2_2hop : E2_2HOP)) sh.agg = sh.fits_g = 0, sh.to2 = 1;
             }
             __syncthreads();
         }
         // no room to aggregate here: a centre that the global stage can aggregate moves on
         // (dropping its changes so far); one that no stage can aggregate enumerates here
         const bool hand_on = STAGE < 2 && !sh.agg && sh.fits_g;
-        if (hand_on) {
+        if (hand_on || sh.to2) {
             for (uint32_t i = tid; i < NWAVE * HGT_N_HE_CLASSES; i += HGT_WG) {
                 sh.acc2[i] = 0;
                 acc32_all[i] = 0;
             }
             if (tid == 0) {
-                uint32_t q = atomicAdd(&P.count[STAGE], 1u);
-                P.list[STAGE][q] = item_of(sh.gi, h);
-                P.rank[STAGE][q] = sh.rank;
+                const int to = sh.to2 ? 2 : STAGE;  // list 2 feeds the 2-hop kernel
+                uint32_t q = atomicAdd(&P.count[to], 1u);
+                P.list[to][q] = item_of(sh.gi, h);
+                P.rank[to][q] = sh.rank;
                 atomicAdd((unsigned long long*)&st[0], 1ull);
             }
             HE2_MARK(7);

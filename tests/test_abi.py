@@ -66,10 +66,11 @@ def test_tune_cache_is_read_and_filtered(tmp_path):
     table is taken as a settled key; lines that do not match are ignored.
     (Reading the file and reporting settled keys makes no GPU call.)"""
     cache = tmp_path / "tune.txt"
-    cache.write_text("1000aa0800 3 4 0 8192 1.25\n"      # choice 3 = (4 per CU, 148 KB stage kept, 8192 slots)
-                     "1000aa0900 3 8 1 8192 1.00\n"      # wrong parameters for choice 3
-                     "1000aa0a00 9 4 1 8192 1.00\n"      # no such choice
-                     "1000aa0b00 0 4 1 8192 0.50\n")
+    cache.write_text("1000aa0800 3 4 0 8192 0 1.25\n"        # choice 3 = (4 per CU, 148 KB stage kept, 8192 slots)
+                     "1000aa0900 3 8 1 8192 0 1.00\n"        # wrong parameters for choice 3
+                     "1000aa0a00 9 4 1 8192 0 1.00\n"        # no such choice
+                     "1000aa0c00 5 4 1 8192 4096 1.00\n"     # choice 5 with the wrong vertex-pair threshold
+                     "1000aa0b00 0 4 1 8192 0 0.50\n")
     code = ("import ctypes, sys\n"
             "lib = ctypes.CDLL(sys.argv[1])\n"
             "k = ctypes.c_uint32(0)\n"

@@ -100,7 +100,7 @@ def test_batched_every_kernel_path(gpu_lib, monkeypatch, stage):
         p.close()
 
 
-@pytest.mark.parametrize("choice", [0, 1, 2, 3, 4])
+@pytest.mark.parametrize("choice", [0, 1, 2, 3, 4, 5, 6])
 def test_graph_launch_every_tuned_choice(gpu_lib, monkeypatch, choice):
     """Rounds launched as captured HIP graphs (the executable updated in place
     from the second round on) under each of the autotuner's launch choices,
@@ -158,8 +158,8 @@ def test_autotuner_settles_and_writes_its_cache(gpu_lib, tmp_path):
     assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-2000:]
     assert "settled" in r.stdout, r.stdout[-2000:]
     lines = [ln.split() for ln in cache.read_text().splitlines() if ln.strip()]
-    assert len(lines) >= 1 and all(len(ln) == 6 for ln in lines)
-    assert all(0 <= int(ln[1]) < 5 for ln in lines)
+    assert len(lines) >= 1 and all(len(ln) == 7 for ln in lines)
+    assert all(0 <= int(ln[1]) < 7 for ln in lines)
 
 
 def _autotune_child():

@@ -329,19 +329,22 @@ def test_compaction_keeps_store_and_counts(gpu_lib):
 _ORACLE_CACHE = {}
 
 
-@pytest.mark.parametrize("slice_lh", ["0", "100000000"])
-def test_dense_centres(gpu_lib, monkeypatch, slice_lh):
-    """A dense graph (3,000 hyperedges with up to 400 members on 900 vertices):
-    a batch that deletes its largest hyperedges and inserts their rows again.
-    Those centres hold more than 65,536 neighbour-row entries, so they go to
-    the 2-hop kernel, shared among several workgroups (or, with a slice size
-    above every centre's lists, one workgroup each); the change of the counts
-    equals the oracle's delta by definition."""
+@pytest.mark.parametrize("shape,slice_lh", [("entries", "0"), ("entries", "100000000"), ("vertex-pairs", "0")])
+def test_dense_centres(gpu_lib, monkeypatch, shape, slice_lh):
+    """Dense graphs, and a batch that deletes their largest hyperedges and
+    inserts their rows again.  In the first (3,000 hyperedges with up to 400
+    members on 900 vertices) those centres hold more than 65,536 neighbour-row
+    entries; in the second (600 hyperedges with up to 120 members on 150
+    vertices) fewer, but their neighbours share more than 65,536 vertex pairs.
+    Either way they go to the 2-hop kernel, shared among several workgroups
+    (or, with a slice size above every centre's lists, one workgroup each);
+    the change of the counts equals the oracle's delta by definition."""
     from .test_gpu_fullsize import _gpu_delta, _oracle_delta
     if slice_lh != "0":
         monkeypatch.setenv("HGT_SLICE_LH", slice_lh)
     monkeypatch.delenv("HGT_FORCE_STAGE", raising=False)
-    st = W.plain_stream("dense", 900, 3000, ("power", 1.4, 2, 400), 0.0, 0.0, 1, 1, 1, W.SEED_BASE + 91)
+    nv, ne, hi = (900, 3000, 400) if shape == "entries" else (150, 600, 120)
+    st = W.plain_stream("dense", nv, ne, ("power", 1.4, 2, hi), 0.0, 0.0, 1, 1, 1, W.SEED_BASE + 91)
     ini = st.initial
     cards = np.diff(ini.offsets.astype(np.int64))
     big = np.argsort(-cards, kind="stable")[:2].astype(np.int64)
@@ -352,7 +355,10 @@ def test_dense_centres(gpu_lib, monkeypatch, slice_lh):
         r = ini.members[ini.offsets[i]:ini.offsets[i + 1]]
         if i != big[0] and mem.intersection(r.tolist()):
             neighbour_entries += len(r)
-    assert neighbour_entries > 65536, neighbour_entries
+    if shape == "entries":
+        assert neighbour_entries > 65536, neighbour_entries
+    else:
+        assert neighbour_entries < 65536, neighbour_entries
     p = Pair(W.Stream("dense", st.n_vertices, ini), track=("hyperedge",))
     before = np.array(p.g.triad_counts("hyperedge"), np.uint64)
     batch = W.Batch(del_handles=big, ins=rows, ins_handles=np.arange(ini.n, ini.n + len(big), dtype=np.int64))
@@ -360,9 +366,9 @@ def test_dense_centres(gpu_lib, monkeypatch, slice_lh):
     out = p.g.apply_batch(*args)
     ids = out.cpu().numpy().astype(np.int64)
     after = np.array(p.g.triad_counts("hyperedge"), np.uint64)
-    if "dense" not in _ORACLE_CACHE:  # the same oracle delta serves both launches
-        _ORACLE_CACHE["dense"] = _oracle_delta(p.o, big, rows, None, ("hyperedge",))
-    _, oids, want = _ORACLE_CACHE["dense"]
+    if shape not in _ORACLE_CACHE:  # the same oracle delta serves both slice sizes
+        _ORACLE_CACHE[shape] = _oracle_delta(p.o, big, rows, None, ("hyperedge",))
+    _, oids, want = _ORACLE_CACHE[shape]
     assert ids.tolist() == [int(x) for x in oids]
     got = _gpu_delta({"hyperedge": before}, {"hyperedge": after})["hyperedge"]
     bad = np.nonzero(got != want["hyperedge"])[0]

@@ -226,11 +226,11 @@ __device__ void expand_x(const TriadParams& P, const HeGraph& G, const Tables& T
         const int wave = threadIdx.x >> 6;
         hk = P.wave_hash + ((uint64_t)blockIdx.x * NWAVE + wave) * 2ull * P.wave_slots;
         hv = hk + P.wave_slots;
-        cap = (uint32_t)pow2ceil64(4 * (uint64_t)lx);
+        cap = (uint32_t)pow2ceil64(2 * (uint64_t)lx);
         if (cap > P.wave_slots) cap = P.wave_slots;
     }
-    // parts of about a quarter of the table each
-    while ((uint64_t)mod * (cap / 4) < lx) mod <<= 1;
+    // parts of at most half the table each: one pass whenever the table holds 2 lx slots
+    while ((uint64_t)mod * (cap / 2) < lx) mod <<= 1;
     if (mod > 1 && lane == 0 && P.stats) atomicAdd((unsigned long long*)&acc_st[2], 1ull);
     const uint32_t log_cap = log2u64(cap);
     constexpr int kStack = 48;

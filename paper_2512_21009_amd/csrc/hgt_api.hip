@@ -295,6 +295,7 @@ struct hgt_graph {
     int iv_wg_per_cu = 8;           // HGT_IV_WG_PER_CU: workgroups per CU of the incident-vertex global stage
     uint32_t slice_lh = 0;          // HGT_SLICE_LH (tests): list entries per slice of a 2-hop kernel centre
     uint64_t e2_2hop = 0;           // HGT_E2_2HOP: vertex pairs from which a centre goes to the 2-hop kernel
+    uint32_t w_2hop = 0;            // HGT_W_2HOP: neighbour-row entries from which it does
     int iv_force_stage = 0;         // HGT_IV_FORCE_STAGE (tests): incident-vertex stages below it pass owners on
     uint32_t wave_slots = 8192;     // HGT_WAVE_SLOTS (tests): slots of the 2-hop kernels' per-wave global hashes
     int skip_lds148 = 1;            // HGT_SKIP_LDS148=0: centres go through the 148 KB stage (one workgroup
@@ -843,6 +844,7 @@ int run_phase(hgt_graph* owner, const PhaseJob* jobs, uint32_t nj, bool minus, b
             E.pair_agg = owner->pair_agg;
             E.skip_lds148 = t_tune ? t_tune->skip_lds148 : owner->skip_lds148;
             E.e2_2hop = t_tune && t_tune->e2_2hop ? t_tune->e2_2hop : owner->e2_2hop;
+            E.w_2hop = owner->w_2hop;
             E.static_mode = full ? 1 : 0;
             hgt_fill_u32(ctr + 16, 0, 6, s);
             hgt_fill_u32(ctr + 5, 0, 1, s);
@@ -1591,6 +1593,7 @@ int hgt_build(const hgt_build_desc* d, hgt_graph** out) {
     if (const char* iw = std::getenv("HGT_IV_WG_PER_CU")) g->iv_wg_per_cu = std::max(1, std::min(16, std::atoi(iw)));
     if (const char* sl = std::getenv("HGT_SLICE_LH")) g->slice_lh = (uint32_t)std::max(1, std::atoi(sl));
     if (const char* e2 = std::getenv("HGT_E2_2HOP")) g->e2_2hop = std::strtoull(e2, nullptr, 10);
+    if (const char* w2 = std::getenv("HGT_W_2HOP")) g->w_2hop = (uint32_t)std::min<uint64_t>(std::strtoull(w2, nullptr, 10), 1u << 21);
     if (const char* iv = std::getenv("HGT_IV_DIRECT")) g->iv_direct = std::atoi(iv) != 0;
     if (const char* fs = std::getenv("HGT_IV_FORCE_STAGE")) g->iv_force_stage = std::atoi(fs);
     if (const char* ws = std::getenv("HGT_WAVE_SLOTS")) {  // a power of two, 64 .. 2^20

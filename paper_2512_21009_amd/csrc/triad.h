@@ -141,6 +141,7 @@ struct He2Params {
     int pair_agg;                // 1: pairs counted per shared vertex by class histograms, pairs
                                  // sharing several vertices found through their vertex pairs
     uint64_t e2_2hop;            // vertex pairs from which a centre goes to the 2-hop kernel (0: default)
+    uint32_t w_2hop;             // neighbour-row entries from which it does (0: default)
     int static_mode;             // full count (build): no batch ranks, no open paths through
                                  // neighbours; open triples at their centre, closed ones at the
                                  // smallest-ID centre

@@ -124,6 +124,76 @@ __device__ __forceinline__ void sort_keys(uint64_t* k, uint32_t n) {
     }
 }
 
+// The same sort for keys in global memory, staged through an LDS tile of TILE_K
+// keys: every tile is first sorted in LDS (all levels up to TILE_K), and in each
+// larger level only the strides of TILE_K and more go through global memory; the
+// strides below run in the tile.  Absent keys past n are +infinity as above.
+constexpr uint32_t TILE_K = 4096;  // 32 KB of LDS
+
+// one compare-exchange step in the tile: i against i ^ mask, the smaller key first
+__device__ __forceinline__ void tile_cx(uint64_t* t, uint32_t mask) {
+    for (uint32_t i = threadIdx.x; i < TILE_K; i += HGT_WG) {
+        const uint32_t p = i ^ mask;
+        if (p > i) {
+            const uint64_t a = t[i], b = t[p];
+            if (b < a) { t[i] = b; t[p] = a; }
+        }
+    }
+    __syncthreads();
+}
+
+// strides stride .. 1 of a level inside the tile (strides below 64 in registers)
+__device__ __forceinline__ void tile_strides(uint64_t* t, uint32_t stride) {
+    for (; stride >= 64; stride >>= 1) tile_cx(t, stride);
+    sort_lane_steps(t, TILE_K, false);
+}
+
+__device__ void sort_keys_tiled(uint64_t* k, uint32_t n, uint64_t* tile) {
+    if (n < 2) return;
+    const uint32_t N = (uint32_t)pow2ceil64(n);
+    // every tile sorted on its own: all levels up to TILE_K
+    for (uint32_t t0 = 0; t0 < n; t0 += TILE_K) {
+        const uint32_t m = n - t0 < TILE_K ? n - t0 : TILE_K;
+        for (uint32_t i = threadIdx.x; i < TILE_K; i += HGT_WG) tile[i] = i < m ? k[t0 + i] : ~0ull;
+        __syncthreads();
+        sort_lane_steps(tile, TILE_K, true);
+        for (uint32_t size = 128; size <= TILE_K; size <<= 1) {
+            tile_cx(tile, size - 1);
+            tile_strides(tile, size >> 2);
+        }
+        for (uint32_t i = threadIdx.x; i < m; i += HGT_WG) k[t0 + i] = tile[i];
+        __syncthreads();
+    }
+    for (uint32_t size = 2 * TILE_K; size <= N; size <<= 1) {
+        for (uint32_t i = threadIdx.x; i < n; i += HGT_WG) {  // the mirror step, in global memory
+            uint32_t p = i ^ (size - 1);
+            if (p > i && p < n) {
+                uint64_t a = k[i], b = k[p];
+                if (b < a) { k[i] = b; k[p] = a; }
+            }
+        }
+        __syncthreads();
+        for (uint32_t stride = size >> 2; stride >= TILE_K; stride >>= 1) {
+            for (uint32_t i = threadIdx.x; i < n; i += HGT_WG) {
+                uint32_t p = i ^ stride;
+                if (p > i && p < n) {
+                    uint64_t a = k[i], b = k[p];
+                    if (b < a) { k[i] = b; k[p] = a; }
+                }
+            }
+            __syncthreads();
+        }
+        for (uint32_t t0 = 0; t0 < n; t0 += TILE_K) {  // strides below TILE_K, per tile
+            const uint32_t m = n - t0 < TILE_K ? n - t0 : TILE_K;
+            for (uint32_t i = threadIdx.x; i < TILE_K; i += HGT_WG) tile[i] = i < m ? k[t0 + i] : ~0ull;
+            __syncthreads();
+            tile_strides(tile, TILE_K >> 1);
+            for (uint32_t i = threadIdx.x; i < m; i += HGT_WG) k[t0 + i] = tile[i];
+            __syncthreads();
+        }
+    }
+}
+
 struct Sh2 {
     uint32_t h, rank, hlen, lh, K, W, defer, stop;
     uint32_t gi, cur_g, skip;
@@ -535,7 +605,12 @@ __device__ void he2_flush_graph(const He2Params& P, uint32_t g, uint64_t* acc_al
 
 template <int STAGE>
 __device__ void he2_body(const He2Params& P, uint32_t* arena, const uint32_t ARENA_WORDS, Sh2& sh, const Tables& T,
-                         uint64_t* acc_all, uint32_t* acc32_all, uint64_t* st, uint64_t* ph) {
+                         uint64_t* acc_all, uint32_t* acc32_all, uint64_t* st, uint64_t* ph, uint64_t* tile) {
+    // keys in a global arena are sorted through the LDS tile; in an LDS arena in place
+    auto sort_any = [tile](uint64_t* k, uint32_t n) {
+        if (tile && n > TILE_K / 2) sort_keys_tiled(k, n, tile);
+        else sort_keys(k, n);
+    };
     const int tid = threadIdx.x;
     uint64_t t_mark = 0;    // thread 0: wall clock at the last phase mark (profiling)
     uint64_t t_centre = 0;  // ... at the start of the current centre
@@ -673,7 +748,7 @@ __device__ void he2_body(const He2Params& P, uint32_t* arena, const uint32_t ARE
                 sh.o_ent = (uint32_t)o_ent;
                 // too large for this arena: the next stage; too dense for any: the 2-hop kernel
                 sh.defer = (o_ent + need > ARENA_WORDS) ? 1u : 0u;
-                if (K >= K_2HOP || carry >= W_2HOP) sh.defer = 2u;
+                if (K >= K_2HOP || carry >= (P.w_2hop ? P.w_2hop : W_2HOP)) sh.defer = 2u;
             }
             __syncthreads();
         }
@@ -762,7 +837,7 @@ __device__ void he2_body(const He2Params& P, uint32_t* arena, const uint32_t ARE
             keys[p] = ((uint64_t)v << KEY_V) | (inh << KEY_IN) | xi;
         }
         __syncthreads();
-        sort_keys(keys, W);
+        sort_any(keys, W);
         // vertices met by two or more neighbours; per neighbour, how many it has
         for (uint32_t i = tid; i < W; i += HGT_WG) {
             uint64_t v = keys[i] >> KEY_V;
@@ -970,7 +1045,7 @@ __device__ void he2_body(const He2Params& P, uint32_t* arena, const uint32_t ARE
                 }
             }
             __syncthreads();
-            sort_keys(emit, E2);
+            sort_any(emit, E2);
             HE2_MARK(9);
             // long runs, one at a time: histogram over (gy, c_y) of the eligible members
             const uint32_t nbig = sh.nbig;
@@ -1169,7 +1244,7 @@ __device__ void he2_flush_stats(const He2Params& P, const uint64_t* st, const ui
 __global__ void __launch_bounds__(HGT_WG) k_he2_s0(He2Params P) {
     __shared__ __attribute__((aligned(16))) uint32_t arena[ARENA_S];
     HE2_PROLOGUE
-    he2_body<0>(P, arena, ARENA_S, sh, T, &acc[0][0], &acc32[0][0], st, ph);
+    he2_body<0>(P, arena, ARENA_S, sh, T, &acc[0][0], &acc32[0][0], st, ph, nullptr);
     he2_flush_graph(P, sh.cur_g, &acc[0][0]);
     he2_flush_stats<0>(P, st, ph);
 }
@@ -1177,15 +1252,16 @@ __global__ void __launch_bounds__(HGT_WG) k_he2_s0(He2Params P) {
 __global__ void __launch_bounds__(HGT_WG) k_he2_s1(He2Params P) {
     __shared__ __attribute__((aligned(16))) uint32_t arena[ARENA_M];
     HE2_PROLOGUE
-    he2_body<1>(P, arena, ARENA_M, sh, T, &acc[0][0], &acc32[0][0], st, ph);
+    he2_body<1>(P, arena, ARENA_M, sh, T, &acc[0][0], &acc32[0][0], st, ph, nullptr);
     he2_flush_graph(P, sh.cur_g, &acc[0][0]);
     he2_flush_stats<1>(P, st, ph);
 }
 
 __global__ void __launch_bounds__(HGT_WG) k_he2_s2(He2Params P) {
+    __shared__ uint64_t tile[TILE_K];
     HE2_PROLOGUE
     he2_body<2>(P, P.garena + (uint64_t)blockIdx.x * P.garena_words, (uint32_t)P.garena_words, sh, T, &acc[0][0],
-                &acc32[0][0], st, ph);
+                &acc32[0][0], st, ph, tile);
     he2_flush_graph(P, sh.cur_g, &acc[0][0]);
     he2_flush_stats<2>(P, st, ph);
 }

@@ -829,14 +829,32 @@ __device__ void he2_body(const He2Params& P, uint32_t* arena, const uint32_t ARE
         // --- entries: (vertex, v in h, neighbour) for every member of every neighbour,
         // sorted by vertex so that the neighbours meeting at a vertex are contiguous
         for (uint32_t i = tid; i < K; i += HGT_WG) nl_msh[i] = 0;
-        for (uint32_t p = tid; p < W; p += HGT_WG) {
-            uint32_t xi = seg_of<uint32_t>(nl_mo, K, p);
-            uint32_t x = nl_x[xi];
-            uint32_t v = G.g.h2v[G.g.h_off[x] + (p - nl_mo[xi])];
-            uint64_t inh = contains_u32(hm, hlen, v) ? 1ull : 0ull;
-            keys[p] = ((uint64_t)v << KEY_V) | (inh << KEY_IN) | xi;
+        {
+            // with a global arena, the neighbours' row offsets and entry prefix and h's
+            // members are staged in the LDS tile (free until the sort) when they fit
+            const uint32_t* mo_p = nl_mo;
+            const uint32_t* hm_p = hm;
+            const uint64_t* xo_p = nullptr;
+            if (tile && 3ull * K + 3 + hlen <= 2ull * TILE_K) {
+                uint64_t* xo = tile;
+                uint32_t* t32 = (uint32_t*)(tile + K);
+                for (uint32_t i = tid; i < K; i += HGT_WG) xo[i] = G.g.h_off[nl_x[i]];
+                for (uint32_t i = tid; i <= K; i += HGT_WG) t32[i] = nl_mo[i];
+                for (uint32_t i = tid; i < hlen; i += HGT_WG) t32[K + 1 + i] = hm[i];
+                __syncthreads();
+                xo_p = xo;
+                mo_p = t32;
+                hm_p = t32 + K + 1;
+            }
+            for (uint32_t p = tid; p < W; p += HGT_WG) {
+                uint32_t xi = seg_of<uint32_t>(mo_p, K, p);
+                const uint64_t xoff = xo_p ? xo_p[xi] : G.g.h_off[nl_x[xi]];
+                uint32_t v = G.g.h2v[xoff + (p - mo_p[xi])];
+                uint64_t inh = contains_u32(hm_p, hlen, v) ? 1ull : 0ull;
+                keys[p] = ((uint64_t)v << KEY_V) | (inh << KEY_IN) | xi;
+            }
+            __syncthreads();
         }
-        __syncthreads();
         sort_any(keys, W);
         // vertices met by two or more neighbours; per neighbour, how many it has
         for (uint32_t i = tid; i < W; i += HGT_WG) {

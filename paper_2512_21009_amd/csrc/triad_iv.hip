@@ -175,11 +175,26 @@ struct IvSh {
     uint32_t ws[NWAVE];
 };
 
-// map slot layout: key | m | w lo | w hi  (4 words)
-__device__ __forceinline__ uint32_t map_find(const uint32_t* mp, uint32_t cap, uint32_t key) {
+// The clique map of an owner: open addressing over cap slots, kept as three
+// arrays (keys, m, w) so that the probes of a wave read consecutive key words
+// rather than every fourth one (fewer LDS bank conflicts); 4 words per slot.
+struct IvMap {
+    uint32_t* key;
+    uint32_t* m;
+    uint64_t* w;  // 8-byte aligned
+    uint32_t cap;
+};
+
+__device__ __forceinline__ IvMap iv_map(uint32_t* arena, uint32_t cap) {
+    const uint32_t c2 = (cap + 1) & ~1u;
+    return IvMap{arena, arena + c2, (uint64_t*)(arena + 2 * c2), cap};
+}
+
+__device__ __forceinline__ uint32_t map_find(const IvMap& mp, uint32_t key) {
+    const uint32_t cap = mp.cap;
     uint32_t s = (uint32_t)(((uint64_t)(key * 2654435761u) * cap) >> 32);
     for (uint32_t probe = 0; probe < cap; probe++) {
-        uint32_t k = mp[4 * s];
+        uint32_t k = mp.key[s];
         if (k == key) return s;
         if (k == HGT_EMPTY) return HGT_EMPTY;
         s = s + 1 == cap ? 0 : s + 1;
@@ -187,20 +202,21 @@ __device__ __forceinline__ uint32_t map_find(const uint32_t* mp, uint32_t cap, u
     return HGT_EMPTY;
 }
 
-__device__ __forceinline__ void map_add(uint32_t* mp, uint32_t cap, uint32_t key, uint32_t w) {
+__device__ __forceinline__ void map_add(const IvMap& mp, uint32_t key, uint32_t w) {
+    const uint32_t cap = mp.cap;
     uint32_t s = (uint32_t)(((uint64_t)(key * 2654435761u) * cap) >> 32);
     for (uint32_t probe = 0; probe < cap; probe++) {
-        uint32_t k = __atomic_load_n(&mp[4 * s], __ATOMIC_RELAXED);
+        uint32_t k = __atomic_load_n(&mp.key[s], __ATOMIC_RELAXED);
         if (k == HGT_EMPTY) {
-            uint32_t prev = atomicCAS(&mp[4 * s], HGT_EMPTY, key);
+            uint32_t prev = atomicCAS(&mp.key[s], HGT_EMPTY, key);
             if (prev == HGT_EMPTY || prev == key) break;
         } else if (k == key) {
             break;
         }
         s = s + 1 == cap ? 0 : s + 1;
     }
-    atomicAdd(&mp[4 * s + 1], 1u);
-    atomicAdd((unsigned long long*)&mp[4 * s + 2], (unsigned long long)w);
+    atomicAdd(&mp.m[s], 1u);
+    atomicAdd((unsigned long long*)&mp.w[s], (unsigned long long)w);
 }
 
 template <int STAGE>
@@ -237,7 +253,7 @@ __device__ void iv_body(const IvParams& P, uint32_t* arena, uint32_t arena_words
         if (tid == 0) {
             sh.L = L;
             sh.cap = L + L / 2 + 32;
-            sh.defer = (4ull * sh.cap > arena_words || P.force_direct || STAGE < P.force_stage) ? 1u : 0u;
+            sh.defer = (4ull * sh.cap + 2 > arena_words || P.force_direct || STAGE < P.force_stage) ? 1u : 0u;
         }
         __syncthreads();
         if (sh.defer && STAGE < 2) {
@@ -262,12 +278,11 @@ __device__ void iv_body(const IvParams& P, uint32_t* arena, uint32_t arena_words
             continue;
         }
         const uint32_t cap = sh.cap;
-        uint32_t* mp = arena;
+        const IvMap mp = iv_map(arena, cap);
         for (uint32_t s = tid; s < cap; s += HGT_WG) {
-            mp[4 * s] = HGT_EMPTY;
-            mp[4 * s + 1] = 0;
-            mp[4 * s + 2] = 0;
-            mp[4 * s + 3] = 0;
+            mp.key[s] = HGT_EMPTY;
+            mp.m[s] = 0;
+            mp.w[s] = 0;
         }
         __syncthreads();
         // M_a from a's hyperedges: one wave per hyperedge, lanes over members
@@ -277,7 +292,7 @@ __device__ void iv_body(const IvParams& P, uint32_t* arena, uint32_t arena_words
             const uint32_t* M = P.g.h2v + P.g.h_off[h];
             for (uint32_t k = lane; k < d; k += 64) {
                 uint32_t w = M[k];
-                if (w != a) map_add(mp, cap, w, d - 2);
+                if (w != a) map_add(mp, w, d - 2);
             }
         }
         __syncthreads();
@@ -285,11 +300,11 @@ __device__ void iv_body(const IvParams& P, uint32_t* arena, uint32_t arena_words
         // touched pairs (a, b), b > a: one wave each
         for (uint64_t q = sh.p0 + wave; q < sh.p1; q += NWAVE) {
             const uint32_t b = (uint32_t)P.pairs[q];
-            uint32_t sb = map_find(mp, cap, b);
+            uint32_t sb = map_find(mp, b);
             uint64_t m_ab = 0, w_ab = 0;
             if (sb != HGT_EMPTY) {
-                m_ab = mp[4 * sb + 1];
-                w_ab = (uint64_t)mp[4 * sb + 2] | ((uint64_t)mp[4 * sb + 3] << 32);
+                m_ab = mp.m[sb];
+                w_ab = mp.w[sb];
             }
             if (lane == 0) s_sum += m_ab * w_ab;
             if (m_ab == 0) continue;
@@ -318,11 +333,11 @@ __device__ void iv_body(const IvParams& P, uint32_t* arena, uint32_t arena_words
                     uint32_t hk = B[base + k];
                     uint32_t w = P.g.h2v[P.g.h_off[hk] + (p - wpre[wave][k])];
                     if (w == a || w == b) continue;
-                    uint32_t sw = map_find(mp, cap, w);
+                    uint32_t sw = map_find(mp, w);
                     if (sw == HGT_EMPTY) continue;
                     if (w < hi && touched(P.tab, P.tab_mask, lo, w)) continue;
                     if (w < lo && touched(P.tab, P.tab_mask, hi, w)) continue;
-                    sum += mp[4 * sw + 1];
+                    sum += mp.m[sw];
                 }
                 __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
                 __builtin_amdgcn_wave_barrier();

@@ -335,6 +335,8 @@ typedef struct {
     int64_t temporal_window;
     uint64_t batches;        /* batches applied since build                     */
     uint64_t compactions;    /* pool compactions since build                    */
+    uint64_t graph_launches; /* batched rounds with this graph first that ran
+                              * as one captured HIP graph (HGT_BATCHES_GRAPH)  */
 } hgt_info;
 
 int hgt_get_info(hgt_graph* g, hgt_info* out);

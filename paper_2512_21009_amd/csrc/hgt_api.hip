@@ -258,6 +258,10 @@ struct PhaseCtx {
     Multi pre[4] = {};
     bool pre_ok[4] = {false, false, false, false};
     hipGraphExec_t gexec = nullptr;
+    // the null stream cannot be captured: rounds called on it are captured on this
+    // stream, ordered after and before the caller's work by the two events
+    hipStream_t cap_stream = nullptr;
+    hipEvent_t cap_in = nullptr, cap_out = nullptr;
 };
 
 struct hgt_graph {
@@ -288,6 +292,7 @@ struct hgt_graph {
     int sticky = HGT_OK;
     uint64_t batches = 0;
     uint64_t compactions = 0;       // pool compactions since build
+    uint64_t graph_launches = 0;    // rounds launched as captured HIP graphs (with this graph first)
     int force_stage = 0;            // HGT_FORCE_STAGE (tests): see He2Params
     int pair_agg = 1;               // HGT_PAIR_AGG=0: pairs enumerated per run (see He2Params)
     int global_wg_per_cu = 4;       // HGT_GLOBAL_WG_PER_CU: workgroups per CU of the global stage
@@ -523,6 +528,11 @@ void phase_ctx_free(PhaseCtx& c) {
     c.done = nullptr;
     if (c.gexec) (void)hipGraphExecDestroy(c.gexec);
     c.gexec = nullptr;
+    if (c.cap_stream) (void)hipStreamDestroy(c.cap_stream);
+    if (c.cap_in) (void)hipEventDestroy(c.cap_in);
+    if (c.cap_out) (void)hipEventDestroy(c.cap_out);
+    c.cap_stream = nullptr;
+    c.cap_in = c.cap_out = nullptr;
 }
 
 std::mutex g_ctx_mu;
@@ -1252,10 +1262,11 @@ PhaseJob job_plus(const Pending& p) {
 // Every scratch buffer of both phases, reserved before the first kernel that
 // changes the graph.  In a no-allocation call they come from the arena, so a
 // batch whose scratch does not fit is rejected with nothing changed.  With
-// upload_s non-NULL the descriptors of every (phase, family) are uploaded too,
-// for a round that is then captured into a HIP graph (a second pass if the
-// descriptor buffer had to grow under the first, which moves it).
-int reserve_all_phases(hgt_graph* owner, std::vector<Pending*>& ps, hipStream_t upload_s = nullptr) {
+// upload set the descriptors of every (phase, family) are uploaded too (on
+// stream s, which may be the null stream), for a round that is then captured
+// into a HIP graph (a second pass if the descriptor buffer had to grow under the
+// first, which moves it).
+int reserve_all_phases(hgt_graph* owner, std::vector<Pending*>& ps, bool upload = false, hipStream_t s = nullptr) {
     PhaseCtx& c = ctx_of(owner);
     std::vector<HeGraph> G;
     std::vector<uint64_t> base, id_base;
@@ -1270,14 +1281,14 @@ int reserve_all_phases(hgt_graph* owner, std::vector<Pending*>& ps, hipStream_t 
             if (base.back() == 0) continue;
             const PhaseShape z = phase_shape(owner, base.back(), max_lh, sum_lh, id_base.back(), t_na != nullptr);
             if (int rc = phase_reserve(c, family, z)) return rc;
-            if (upload_s) {
+            if (upload) {
                 const int slot = (phase == 0 ? 0 : 2) + (family == HGT_TRIAD_TEMPORAL ? 1 : 0);
-                if (int rc = upload_multi(c, slot, G, base, id_base, c.pre[slot], upload_s)) return rc;
+                if (int rc = upload_multi(c, slot, G, base, id_base, c.pre[slot], s)) return rc;
                 c.pre_ok[slot] = true;
             }
         }
     }
-    if (upload_s && c.desc_cap != cap0) return reserve_all_phases(owner, ps, upload_s);
+    if (upload && c.desc_cap != cap0) return reserve_all_phases(owner, ps, upload, s);
     if (t_na)
         if (int rc = ensure(c.desc, 4 * desc_slot_bytes(1))) return rc;
     for (Pending* p : ps)
@@ -1358,23 +1369,51 @@ void commit_mirrors(std::vector<Pending*>& ps) {
 // context is updated in place when the shapes agree, else instantiated anew.
 // kCaptureFailed: the capture did not succeed and nothing was launched.
 constexpr int kCaptureFailed = 1;
+// HGT_GRAPH_DEBUG=1: say on stderr why a capture fell back to the launch kernel by kernel
+void capture_note(const char* what, int code) {
+    static const bool on = std::getenv("HGT_GRAPH_DEBUG") != nullptr;
+    if (on) std::fprintf(stderr, "[hgt] graph launch fell back: %s (%d)\n", what, code);
+}
 int apply_graph(hgt_graph* owner, std::vector<Pending*>& ps, hipStream_t s) {
     PhaseCtx& c = ctx_of(owner);
-    int rc = reserve_all_phases(owner, ps, s);
+    int rc = reserve_all_phases(owner, ps, true, s);
     if (rc) return rc;
-    if (hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed) != hipSuccess) {
+    hipStream_t cs = s;  // the stream captured and launched on
+    if (!s) {
+        if (!c.cap_stream) {
+            hipStream_t st = nullptr;
+            hipEvent_t e_in = nullptr, e_out = nullptr;
+            if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess ||
+                hipEventCreateWithFlags(&e_in, hipEventDisableTiming) != hipSuccess ||
+                hipEventCreateWithFlags(&e_out, hipEventDisableTiming) != hipSuccess) {
+                (void)hipGetLastError();
+                if (st) (void)hipStreamDestroy(st);
+                if (e_in) (void)hipEventDestroy(e_in);
+                return kCaptureFailed;
+            }
+            c.cap_stream = st;
+            c.cap_in = e_in;
+            c.cap_out = e_out;
+        }
+        cs = c.cap_stream;
+        HIP_OK(hipEventRecord(c.cap_in, s));
+        HIP_OK(hipStreamWaitEvent(cs, c.cap_in, 0));
+    }
+    if (hipError_t be = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed); be != hipSuccess) {
         (void)hipGetLastError();
+        capture_note("begin capture", (int)be);
         return kCaptureFailed;
     }
     t_capture = 1;
-    rc = apply_locked(owner, ps, s);
+    rc = apply_locked(owner, ps, cs);
     t_capture = 0;
     hipGraph_t gr = nullptr;
-    const hipError_t e = hipStreamEndCapture(s, &gr);
+    const hipError_t e = hipStreamEndCapture(cs, &gr);
     for (int slot = 0; slot < 4; slot++) c.pre_ok[slot] = false;
     if (rc || e != hipSuccess || !gr) {
         (void)hipGetLastError();
         if (gr) (void)hipGraphDestroy(gr);
+        capture_note(rc ? "launch under capture" : "end capture", rc ? rc : (int)e);
         return kCaptureFailed;
     }
     bool updated = false;
@@ -1390,12 +1429,18 @@ int apply_graph(hgt_graph* owner, std::vector<Pending*>& ps, hipStream_t s) {
     }
     if (!updated && hipGraphInstantiate(&c.gexec, gr, nullptr, nullptr, 0) != hipSuccess) {
         (void)hipGetLastError();
+        capture_note("instantiate", 0);
         c.gexec = nullptr;
         (void)hipGraphDestroy(gr);
         return kCaptureFailed;
     }
     (void)hipGraphDestroy(gr);
-    HIP_OK(hipGraphLaunch(c.gexec, s));
+    HIP_OK(hipGraphLaunch(c.gexec, cs));
+    if (cs != s) {
+        HIP_OK(hipEventRecord(c.cap_out, cs));
+        HIP_OK(hipStreamWaitEvent(s, c.cap_out, 0));
+    }
+    owner->graph_launches++;
     return HGT_OK;
 }
 
@@ -2092,6 +2137,7 @@ int hgt_get_info(hgt_graph* g, hgt_info* o) {
     o->temporal_window = g->window;
     o->batches = g->batches;
     o->compactions = g->compactions;
+    o->graph_launches = g->graph_launches;
     return HGT_OK;
 }
 

@@ -58,6 +58,7 @@ class Info(ctypes.Structure):
         ("temporal_window", ctypes.c_int64),
         ("batches", ctypes.c_uint64),
         ("compactions", ctypes.c_uint64),
+        ("graph_launches", ctypes.c_uint64),
     ]
 
 

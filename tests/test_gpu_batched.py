@@ -114,6 +114,9 @@ def test_graph_launch_every_tuned_choice(gpu_lib, monkeypatch, choice):
         for k, p in enumerate(pairs):
             compare_counts(p.g, p.o, p.track, f"choice {choice} round {r} graph {k}")
             compare_store(p.g, p.o, f"choice {choice} round {r} graph {k}")
+    # every round ran as a captured graph (the default stream's rounds are captured on
+    # a stream of the library's own)
+    assert sum(p.g.info()["graph_launches"] for p in pairs) == 3
     for p in pairs:
         p.close()
 

@@ -188,8 +188,11 @@ int hgt_apply_batches(hgt_batch* batches, uint32_t n, void* stream);
                                   * uploaded first) and launched as one; the
                                   * executable graph is kept per triad-scratch
                                   * context and updated in place by the next
-                                  * round of the same shape.  Where the capture
-                                  * fails the round is launched kernel by kernel. */
+                                  * round of the same shape.  A round called on
+                                  * the null stream is captured on a stream of
+                                  * the library's own, ordered by events with the
+                                  * caller's.  Where the capture fails the round
+                                  * is launched kernel by kernel. */
 #define HGT_BATCHES_AUTOTUNE 2u  /* launch choices (workgroups per CU of the
                                   * global histogram stage, whether centres skip
                                   * the 148 KB stage, slots of the per-wave

@@ -1,0 +1,59 @@
+"""Host-side helpers of bench.py: the roofline figure of the dominant kernel
+group and the committed counter traffic it reports."""
+import json
+import os
+
+import pytest
+
+import bench
+
+
+def _prof(**groups):
+    return {k: dict(launches=v[0], total_ms=v[1], algo_bytes=v[2], events=0, aux=0) for k, v in groups.items()}
+
+
+def test_roofline_takes_the_dominant_group():
+    prof = _prof(he_hist_global=(4, 40.0, 8_000_000_000), iv_pairs=(4, 60.0, 4_000_000_000),
+                 store_plan=(2, 1.0, 0))
+    rl = bench.roofline_of(prof)
+    assert rl["kernel"] == "iv_pairs"
+    assert rl["avg_launch_ms"] == pytest.approx(15.0)
+    assert rl["algo_bytes_per_launch"] == 1_000_000_000
+    # achieved = algorithmic bytes / summed time: 4 GB in 60 ms
+    assert rl["achieved"] == pytest.approx(4e9 / 60e-3 / 1e9, rel=1e-3)
+    assert rl["frac"] == pytest.approx(rl["achieved"] / bench.HBM_PEAK_GBS, rel=1e-3)
+
+
+def test_roofline_store_only_joins_plan_and_commit():
+    prof = _prof(store_plan=(2, 3.0, 0), store_commit=(2, 1.0, 40_000_000))
+    rl = bench.roofline_of(prof, store_only=True)
+    assert rl["kernel"] == "store_plan+store_commit"
+    assert rl["avg_launch_ms"] == pytest.approx(2.0)
+    assert rl["achieved"] == pytest.approx(40e6 / 4e-3 / 1e9, rel=1e-3)
+
+
+def test_traffic_only_for_the_sources_it_was_taken_on(tmp_path, monkeypatch):
+    prof_dir = tmp_path / "profiles"
+    prof_dir.mkdir()
+    doc = {"source_sha256": bench.source_digest(), "workload": "w",
+           "groups": {"g": {"fetch_bytes_per_launch": 100, "write_bytes_per_launch": 20}}}
+    (prof_dir / "w_traffic.json").write_text(json.dumps(doc))
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    # the digest is taken over the sources under ROOT; keep the real ones
+    digest = doc["source_sha256"]
+    monkeypatch.setattr(bench, "source_digest", lambda: digest)
+    assert bench.traffic_of("w", "g") == 120
+    assert bench.traffic_of("w", "other") is None
+    assert bench.traffic_of("missing", "g") is None
+    doc["source_sha256"] = "0" * 64
+    (prof_dir / "w_traffic.json").write_text(json.dumps(doc))
+    assert bench.traffic_of("w", "g") is None
+
+
+def test_committed_traffic_matches_the_sources():
+    """The committed counter summaries were taken on the current HIP sources."""
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    for wl, group in (("medium", "iv_pairs"), ("temporal", "temporal")):
+        with open(os.path.join(root, "profiles", f"{wl}_traffic.json")) as f:
+            assert json.load(f)["source_sha256"] == bench.source_digest(), wl
+        assert bench.traffic_of(wl, group) > 0

@@ -26,6 +26,12 @@
  *  - A batch that fails validation is rejected as a whole: graph state and
  *    counts stay as they were, and the error is returned by that call and
  *    again by hgt_sync().
+ *  - A batch that fails after validation, once its first mutating kernel may
+ *    have been queued (a HIP runtime failure), leaves the graph partly
+ *    updated.  The graph is then "poisoned": that call returns
+ *    HGT_EPOISONED, hgt_sync() reports it, and every call that reads or
+ *    updates the graph returns HGT_EPOISONED until hgt_restore() loads a
+ *    snapshot into it (or hgt_destroy() releases it).
  */
 #ifndef HGT_H
 #define HGT_H
@@ -44,7 +50,8 @@ extern "C" {
 #define HGT_EORDER (-4)      /* temporal insert older than the resident stream, or unsorted batch */
 #define HGT_ENOMEM (-5)      /* device memory exhausted */
 #define HGT_ENOTTRACKED (-6) /* the triad type (or window) is not maintained by this graph */
-#define HGT_EDEVICE (-7)     /* HIP runtime failure; the graph must be destroyed */
+#define HGT_EDEVICE (-7)     /* HIP runtime failure (outside a batch the graph is left as it was) */
+#define HGT_EPOISONED (-8)   /* a batch failed part-way: restore a snapshot or destroy the graph */
 
 /* ---- triad families (Sec. II) ----------------------------------------- */
 /* Hyperedge-based: 30 uint64 classes.  A class is a Venn pattern of three
@@ -313,8 +320,72 @@ int hgt_triad_counts(hgt_graph* g, int type, int64_t window, uint64_t* out_host,
  * sticky status of the graph (HGT_OK or the first error). */
 int hgt_sync(hgt_graph* g, int* status);
 
-/* Releases every device buffer of the graph. */
+/* Releases every device buffer of the graph (also a poisoned one). */
 int hgt_destroy(hgt_graph* g);
+
+/* ---- snapshot and restore ---------------------------------------------- */
+/* A snapshot is a host-memory copy of everything a graph's future batches and
+ * queries depend on: the ID table (offset, length, capacity, arrival sequence
+ * and timestamp of every ID below next_id, and the free-ID bitmap), both
+ * incidence pools up to their used words, the maintained hyperedge-neighbour
+ * histograms, the per-vertex list table, the 129 maintained counts and the
+ * scalars (next_id, used pool words, next arrival sequence, largest
+ * timestamp, live hyperedges, incidences).  It is owned by the library until
+ * hgt_snap_free(); it can be written out as bytes and loaded back, in the
+ * same or another process, to restore a graph built with the same
+ * n_vertices, track_mask and temporal_window (for example an empty one).
+ *
+ * Byte format (little-endian): a 128-byte header of
+ *   char magic[8] = "HGTSNAP1"; uint32 version = 1; uint32 track_mask;
+ *   uint32 n_vertices; uint32 n_counts = 129; int64 temporal_window;
+ *   uint64 next_id, h_bump, v_bump, next_seq, n_live, n_incidences;
+ *   int64 last_ts; uint64 payload_bytes; uint64 checksum; zero padding;
+ * then the sections, each padded with zeros to a multiple of 8 bytes:
+ *   uint64 counts[129] (hyperedge 30, incident-vertex 3, temporal 96);
+ *   uint64 h_off[next_id]; uint32 h_len[next_id]; uint32 h_cap[next_id];
+ *   uint64 h_seq[next_id]; int64 h_ts[next_id] (temporal graphs only);
+ *   uint64 free_bitmap[(next_id + 63) / 64] (bit i set: ID i is free);
+ *   uint32 h2v[h_bump]; uint32 histograms[2 * h_bump] (hyperedge family only);
+ *   uint64 v_off[n_vertices]; uint32 v_len[n_vertices]; uint32 v_cap[n_vertices];
+ *   uint32 v2h[v_bump]; int64 v2h_ts[v_bump] (temporal graphs only).
+ * checksum: over the payload read as uint64 words w, h = 0xcbf29ce484222325
+ * and for each word h = (h ^ w) * 0x100000001b3 (mod 2^64).
+ * Like every call on a graph, hgt_snapshot and hgt_restore must not overlap
+ * another call on the same graph; for a served tenant (hgt_server_tenant_graph)
+ * none of the tenant's requests may be in flight. */
+typedef struct hgt_snap hgt_snap;
+
+/* Copies graph g into a new snapshot *out (host memory).  Waits for the
+ * graph's queued work and for `stream`, on which the copies run.
+ * HGT_EPOISONED for a poisoned graph. */
+int hgt_snapshot(hgt_graph* g, hgt_snap** out, void* stream);
+
+/* Replaces the whole state of graph g (poisoned or not) by the snapshot's:
+ * afterwards g answers every query and applies every batch exactly as the
+ * graph the snapshot was taken from did at that moment (assigned IDs
+ * included).  g must have the snapshot's n_vertices, track_mask and
+ * temporal_window (else HGT_EINVAL, g unchanged).  The pools grow when the
+ * snapshot needs more words (HGT_ENOMEM, g unchanged, when they cannot).
+ * The copies run on `stream` and the call waits for them; the batch and
+ * compaction statistics of g are kept.  A HIP failure during the copies
+ * leaves g poisoned. */
+int hgt_restore(hgt_graph* g, const hgt_snap* snap, void* stream);
+
+/* Byte form of a snapshot: *n_bytes receives its size; when out_host is not
+ * NULL the bytes are written there (HGT_EINVAL if cap < the size). */
+int hgt_snap_bytes(const hgt_snap* snap, void* out_host, uint64_t cap, uint64_t* n_bytes);
+
+/* Loads a snapshot from its byte form (host memory, not kept).  The header,
+ * the section sizes and the checksum are checked, and so is the structure:
+ * every live ID's list lies inside the used h2v words, is strictly
+ * ascending and names vertices below n_vertices; every vertex's list lies
+ * inside the used v2h words, is strictly ascending and names live IDs; the
+ * two maps hold the same incidences; n_live, n_incidences and the v2h
+ * timestamps agree with the ID table.  HGT_EINVAL when any check fails. */
+int hgt_snap_load(const void* bytes, uint64_t n_bytes, hgt_snap** out);
+
+/* Releases a snapshot. */
+int hgt_snap_free(hgt_snap* snap);
 
 /* Moves every live incidence list into fresh pools, dropping the blocks of
  * free IDs and the blocks that relocated lists left behind (the pools only

@@ -290,6 +290,7 @@ struct hgt_graph {
     uint64_t next_id = 0, h_bump = 0, v_bump = 0, next_seq = 0, n_live = 0, n_inc = 0;
     uint32_t epoch = 0;
     int sticky = HGT_OK;
+    bool poisoned = false;          // a batch failed part-way: only hgt_restore / hgt_destroy apply
     uint64_t batches = 0;
     uint64_t compactions = 0;       // pool compactions since build
     uint64_t graph_launches = 0;    // rounds launched as captured HIP graphs (with this graph first)
@@ -1301,9 +1302,20 @@ int reserve_all_phases(hgt_graph* owner, std::vector<Pending*>& ps, bool upload 
 // the old graphs, delete + insert, deltas on the new graphs, count update.  The
 // hyperedge and temporal phases of all graphs share one launch per kernel.
 // Changes no host state, so a round whose capture failed can be launched again.
-int apply_locked(hgt_graph* owner, std::vector<Pending*>& ps, hipStream_t s) {
+// HGT_INJECT_FAULT=1 (tests): a batch that passed validation stops right after
+// its store update has been queued and fails as a HIP launch would, leaving
+// the graph part-way (every kernel queued so far still runs to completion).
+bool fault_injected() {
+    const char* f = std::getenv("HGT_INJECT_FAULT");
+    return f && std::atoi(f) == 1;
+}
+
+// *began is set once the first kernel that changes graph state or counts may
+// have been queued: a failure after that leaves the graphs of `ps` part-way.
+int apply_locked(hgt_graph* owner, std::vector<Pending*>& ps, hipStream_t s, bool* began) {
     int rc;
     if (t_na && (rc = reserve_all_phases(owner, ps))) return rc;
+    *began = true;
     std::vector<PhaseJob> jobs;
     jobs.reserve(ps.size());
     for (Pending* p : ps) jobs.push_back(job_minus(*p));
@@ -1324,6 +1336,7 @@ int apply_locked(hgt_graph* owner, std::vector<Pending*>& ps, hipStream_t s) {
         if (p->out_ids && p->b.n_ins)
             HIP_OK(hipMemcpyAsync(p->out_ids, p->w.assigned, p->b.n_ins * 4, hipMemcpyDeviceToDevice, s));
     }
+    if (!t_capture && fault_injected()) return HGT_EDEVICE;
     // step 5: deltas on the new graph
     jobs.clear();
     for (Pending* p : ps) jobs.push_back(job_plus(*p));
@@ -1374,7 +1387,7 @@ void capture_note(const char* what, int code) {
     static const bool on = std::getenv("HGT_GRAPH_DEBUG") != nullptr;
     if (on) std::fprintf(stderr, "[hgt] graph launch fell back: %s (%d)\n", what, code);
 }
-int apply_graph(hgt_graph* owner, std::vector<Pending*>& ps, hipStream_t s) {
+int apply_graph(hgt_graph* owner, std::vector<Pending*>& ps, hipStream_t s, bool* began) {
     PhaseCtx& c = ctx_of(owner);
     int rc = reserve_all_phases(owner, ps, true, s);
     if (rc) return rc;
@@ -1405,7 +1418,8 @@ int apply_graph(hgt_graph* owner, std::vector<Pending*>& ps, hipStream_t s) {
         return kCaptureFailed;
     }
     t_capture = 1;
-    rc = apply_locked(owner, ps, cs);
+    bool captured_only = false;  // nothing runs while the stream is captured
+    rc = apply_locked(owner, ps, cs, &captured_only);
     t_capture = 0;
     hipGraph_t gr = nullptr;
     const hipError_t e = hipStreamEndCapture(cs, &gr);
@@ -1435,6 +1449,7 @@ int apply_graph(hgt_graph* owner, std::vector<Pending*>& ps, hipStream_t s) {
         return kCaptureFailed;
     }
     (void)hipGraphDestroy(gr);
+    *began = true;
     HIP_OK(hipGraphLaunch(c.gexec, cs));
     if (cs != s) {
         HIP_OK(hipEventRecord(c.cap_out, cs));
@@ -1450,11 +1465,21 @@ int apply_planned(hgt_graph* owner, std::vector<Pending*>& ps, hipStream_t s, bo
     HIP_OK(hipStreamWaitEvent(s, c.done, 0));
     if (t_tune_ev[0]) (void)hipEventRecord(t_tune_ev[0], s);
     int rc = kCaptureFailed;
-    if (graph && !t_na) rc = apply_graph(owner, ps, s);
-    if (rc == kCaptureFailed) rc = apply_locked(owner, ps, s);  // launched one by one
+    bool began = false;
+    if (graph && !t_na && !fault_injected()) rc = apply_graph(owner, ps, s, &began);
+    if (rc == kCaptureFailed) rc = apply_locked(owner, ps, s, &began);  // launched one by one
     if (rc == HGT_OK) commit_mirrors(ps);
     if (t_tune_ev[1]) (void)hipEventRecord(t_tune_ev[1], s);
     if (hipEventRecord(c.done, s) != hipSuccess && rc == HGT_OK) rc = HGT_EDEVICE;
+    if (rc != HGT_OK && began) {
+        // part of the round may have run: its graphs' device state no longer
+        // matches their host mirrors or their counts
+        for (Pending* p : ps) {
+            p->g->poisoned = true;
+            p->g->sticky = HGT_EPOISONED;
+        }
+        rc = HGT_EPOISONED;
+    }
     return rc;
 }
 
@@ -1598,6 +1623,7 @@ const char* hgt_status_str(int status) {
         case HGT_ENOMEM: return "device memory exhausted";
         case HGT_ENOTTRACKED: return "triad family or window not tracked";
         case HGT_EDEVICE: return "HIP runtime failure";
+        case HGT_EPOISONED: return "graph left part-way through a batch: restore a snapshot or destroy it";
         default: return "unknown status";
     }
 }
@@ -1712,6 +1738,7 @@ int hgt_apply_batch(hgt_graph* g, const uint32_t* del_ids, uint64_t n_del, const
                     const uint32_t* ins_members, uint64_t n_ins_members, const int64_t* ins_ts, uint64_t n_ins,
                     uint32_t* out_ins_ids, void* stream) {
     if (!g) return HGT_EINVAL;
+    if (g->poisoned) return HGT_EPOISONED;
     if (n_del == 0 && n_ins == 0) return HGT_OK;
     int rc = apply(g, del_ids, n_del, ins_offsets, ins_members, n_ins_members, ins_ts, n_ins, out_ins_ids,
                    (hipStream_t)stream);
@@ -1722,6 +1749,7 @@ int hgt_apply_batch(hgt_graph* g, const uint32_t* del_ids, uint64_t n_del, const
 int hgt_apply_vertex_ops(hgt_graph* g, const uint32_t* edge_ids, const uint32_t* vertices, const uint8_t* insert,
                          uint64_t n_ops, void* stream) {
     if (!g) return HGT_EINVAL;
+    if (g->poisoned) return HGT_EPOISONED;
     if (n_ops == 0) return HGT_OK;
     if (!edge_ids || !vertices || !insert || n_ops > 0xfffffff0ull) return HGT_EINVAL;
     hipStream_t s = (hipStream_t)stream;
@@ -1795,6 +1823,7 @@ int hgt_apply_batch_noalloc(hgt_graph* g, const uint32_t* del_ids, uint64_t n_de
                             const uint32_t* ins_members, uint64_t n_ins_members, const int64_t* ins_ts,
                             uint64_t n_ins, uint32_t* out_ins_ids, void* stream) {
     if (!g) return HGT_EINVAL;
+    if (g->poisoned) return HGT_EPOISONED;
     if (n_del == 0 && n_ins == 0) return HGT_OK;
     int cur = -1;
     HIP_OK(hipGetDevice(&cur));
@@ -1998,6 +2027,10 @@ int apply_batches(hgt_batch* bs, uint32_t n, void* stream, uint32_t flags) {
         P[i].g = b.graph;
         P[i].out_ids = b.out_ins_ids;
         P[i].rc = 1;  // nothing to apply
+        if (b.graph->poisoned) {
+            P[i].rc = HGT_EPOISONED;
+            continue;
+        }
         if (b.n_del == 0 && b.n_ins == 0) continue;
         P[i].rc = plan_begin(P[i], b.del_ids, b.n_del, b.ins_offsets, b.ins_members, b.n_ins_members, b.ins_ts,
                              b.n_ins, s);
@@ -2085,12 +2118,13 @@ int hgt_sync(hgt_graph* g, int* status) {
         if (status) *status = HGT_EDEVICE;
         return HGT_EDEVICE;
     }
-    if (status) *status = g->sticky;
+    if (status) *status = g->poisoned ? HGT_EPOISONED : g->sticky;
     return HGT_OK;
 }
 
 int hgt_triad_counts(hgt_graph* g, int type, int64_t window, uint64_t* out_host, uint32_t n_out) {
     if (!g || !out_host) return HGT_EINVAL;
+    if (g->poisoned) return HGT_EPOISONED;
     int off, n;
     switch (type) {
         case HGT_TRIAD_HYPEREDGE: off = CNT_HE; n = 30; break;
@@ -2115,6 +2149,7 @@ int hgt_destroy(hgt_graph* g) {
 
 int hgt_compact(hgt_graph* g, void* stream) {
     if (!g) return HGT_EINVAL;
+    if (g->poisoned) return HGT_EPOISONED;
     hipStream_t s = (hipStream_t)stream;
     int rc = compact_pools(g, s);
     if (!rc) g->last_stream = s;
@@ -2200,6 +2235,7 @@ int hgt_profile_counters(hgt_graph* g, uint64_t* out, uint32_t n_max, uint32_t* 
 
 int hgt_export_h2v(hgt_graph* g, uint64_t* offsets_host, uint32_t* members_host, uint8_t* live_host) {
     if (!g || !offsets_host || !members_host || !live_host) return HGT_EINVAL;
+    if (g->poisoned) return HGT_EPOISONED;
     hipStream_t s = g->last_stream;
     HIP_OK(hipStreamSynchronize(s));
     uint64_t n = g->next_id;
@@ -2228,6 +2264,7 @@ int hgt_export_h2v(hgt_graph* g, uint64_t* offsets_host, uint32_t* members_host,
 
 int hgt_export_v2h(hgt_graph* g, uint64_t* offsets_host, uint32_t* members_host) {
     if (!g || !offsets_host || !members_host) return HGT_EINVAL;
+    if (g->poisoned) return HGT_EPOISONED;
     HIP_OK(hipStreamSynchronize(g->last_stream));
     uint64_t V = g->st.n_vertices;
     std::vector<uint64_t> off(V);
@@ -2245,6 +2282,306 @@ int hgt_export_v2h(hgt_graph* g, uint64_t* offsets_host, uint32_t* members_host)
         }
     }
     offsets_host[V] = k;
+    return HGT_OK;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Snapshot and restore: a host copy of a graph's whole state, in the byte
+// form that include/hgt.h documents, and the way back into a graph.
+// ===========================================================================
+struct hgt_snap {
+    std::vector<uint64_t> words;  // header and sections, 8-byte aligned
+};
+
+namespace {
+
+constexpr char kSnapMagic[8] = {'H', 'G', 'T', 'S', 'N', 'A', 'P', '1'};
+constexpr uint32_t kSnapVersion = 1;
+
+struct SnapHeader {
+    char magic[8];
+    uint32_t version, track_mask, n_vertices, n_counts;
+    int64_t window;
+    uint64_t next_id, h_bump, v_bump, next_seq, n_live, n_inc;
+    int64_t last_ts;
+    uint64_t payload_bytes, checksum;
+    uint8_t pad[24];
+};
+static_assert(sizeof(SnapHeader) == 128, "the snapshot header is 128 bytes");
+
+enum SnapSec { SS_COUNTS, SS_H_OFF, SS_H_LEN, SS_H_CAP, SS_H_SEQ, SS_H_TS, SS_FREE_BM, SS_H2V, SS_HIST, SS_V_OFF,
+               SS_V_LEN, SS_V_CAP, SS_V2H, SS_V2H_TS, SS_N };
+
+// Byte offset (from the start of the payload) and unpadded size of each section.
+struct SnapLayout {
+    uint64_t off[SS_N], bytes[SS_N], total;
+};
+
+SnapLayout snap_layout(uint32_t track, uint64_t V, uint64_t next_id, uint64_t hb, uint64_t vb) {
+    const bool tmp = track & (1u << HGT_TRIAD_TEMPORAL), he = track & (1u << HGT_TRIAD_HYPEREDGE);
+    const uint64_t b[SS_N] = {CNT_N * 8ull, next_id * 8, next_id * 4, next_id * 4, next_id * 8, tmp ? next_id * 8 : 0,
+                              (next_id + 63) / 64 * 8, hb * 4, he ? hb * 8 : 0, V * 8, V * 4, V * 4, vb * 4,
+                              tmp ? vb * 8 : 0};
+    SnapLayout L;
+    uint64_t o = 0;
+    for (int i = 0; i < SS_N; i++) {
+        L.off[i] = o;
+        L.bytes[i] = b[i];
+        o += (b[i] + 7) & ~7ull;
+    }
+    L.total = o;
+    return L;
+}
+
+// FNV-1a applied to 64-bit words
+uint64_t snap_checksum(const uint64_t* w, uint64_t n) {
+    uint64_t h = 0xcbf29ce484222325ull;
+    for (uint64_t i = 0; i < n; i++) h = (h ^ w[i]) * 0x100000001b3ull;
+    return h;
+}
+
+template <class T> const T* snap_sec(const hgt_snap* s, const SnapLayout& L, int sec) {
+    return (const T*)((const char*)s->words.data() + sizeof(SnapHeader) + L.off[sec]);
+}
+
+// The structural checks of a snapshot read from bytes (see hgt_snap_load).
+bool snap_consistent(const hgt_snap* s) {
+    const SnapHeader& H = *(const SnapHeader*)s->words.data();
+    const SnapLayout L = snap_layout(H.track_mask, H.n_vertices, H.next_id, H.h_bump, H.v_bump);
+    const bool tmp = H.track_mask & (1u << HGT_TRIAD_TEMPORAL);
+    const uint64_t n = H.next_id, V = H.n_vertices;
+    const uint64_t* h_off = snap_sec<uint64_t>(s, L, SS_H_OFF);
+    const uint32_t* h_len = snap_sec<uint32_t>(s, L, SS_H_LEN);
+    const uint32_t* h_cap = snap_sec<uint32_t>(s, L, SS_H_CAP);
+    const uint64_t* h_seq = snap_sec<uint64_t>(s, L, SS_H_SEQ);
+    const int64_t* h_ts = tmp ? snap_sec<int64_t>(s, L, SS_H_TS) : nullptr;
+    const uint64_t* bm = snap_sec<uint64_t>(s, L, SS_FREE_BM);
+    const uint32_t* h2v = snap_sec<uint32_t>(s, L, SS_H2V);
+    const uint64_t* v_off = snap_sec<uint64_t>(s, L, SS_V_OFF);
+    const uint32_t* v_len = snap_sec<uint32_t>(s, L, SS_V_LEN);
+    const uint32_t* v_cap = snap_sec<uint32_t>(s, L, SS_V_CAP);
+    const uint32_t* v2h = snap_sec<uint32_t>(s, L, SS_V2H);
+    const int64_t* v2h_ts = tmp ? snap_sec<int64_t>(s, L, SS_V2H_TS) : nullptr;
+    auto is_free = [&](uint64_t id) { return (bm[id >> 6] >> (id & 63)) & 1ull; };
+    if (n & 63)
+        if (bm[n >> 6] >> (n & 63)) return false;  // IDs at or above next_id are not free
+    uint64_t live = 0, inc = 0;
+    for (uint64_t id = 0; id < n; id++) {
+        if (h_cap[id] && (h_off[id] > H.h_bump || h_cap[id] > H.h_bump - h_off[id])) return false;
+        if (is_free(id)) continue;
+        const uint32_t len = h_len[id];
+        if (len < 1 || len > HGT_MAX_CARD || len > h_cap[id] || h_seq[id] >= H.next_seq) return false;
+        if (tmp && h_ts[id] > H.last_ts) return false;
+        const uint32_t* row = h2v + h_off[id];
+        for (uint32_t k = 0; k < len; k++)
+            if (row[k] >= V || (k && row[k] <= row[k - 1])) return false;
+        live++;
+        inc += len;
+    }
+    if (live != H.n_live || inc != H.n_inc) return false;
+    uint64_t inc_v = 0;
+    for (uint64_t v = 0; v < V; v++) {
+        const uint32_t len = v_len[v];
+        if (v_cap[v] && (v_off[v] > H.v_bump || v_cap[v] > H.v_bump - v_off[v])) return false;
+        if (len > v_cap[v]) return false;
+        for (uint32_t k = 0; k < len; k++) {
+            const uint64_t w = v_off[v] + k;
+            const uint32_t id = v2h[w];
+            if (id >= n || is_free(id) || (k && id <= v2h[w - 1])) return false;
+            if (tmp && v2h_ts[w] != h_ts[id]) return false;
+        }
+        inc_v += len;
+    }
+    if (inc_v != inc) return false;
+    // every incidence of the h2v map is in the v2h map (equal totals and
+    // duplicate-free lists make the two maps equal)
+    for (uint64_t id = 0; id < n; id++) {
+        if (is_free(id)) continue;
+        const uint32_t* row = h2v + h_off[id];
+        for (uint32_t k = 0; k < h_len[id]; k++) {
+            if (!v_len[row[k]]) return false;
+            const uint32_t* a = v2h + v_off[row[k]];
+            const uint32_t* e = a + v_len[row[k]];
+            const uint32_t* f = std::lower_bound(a, e, (uint32_t)id);
+            if (f == e || *f != id) return false;
+        }
+    }
+    return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+int hgt_snapshot(hgt_graph* g, hgt_snap** out, void* stream) {
+    if (!g || !out) return HGT_EINVAL;
+    *out = nullptr;
+    if (g->poisoned) return HGT_EPOISONED;
+    hipStream_t s = (hipStream_t)stream;
+    HIP_OK(hipStreamSynchronize(g->last_stream));
+    DevScalars sc{};
+    HIP_OK(hipMemcpyAsync(&sc, g->scal.p, sizeof sc, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    if (sc.next_id != g->next_id || sc.h_bump != g->h_bump || sc.v_bump != g->v_bump || sc.n_live != g->n_live ||
+        sc.n_inc != g->n_inc || sc.next_seq != g->next_seq)
+        return HGT_EDEVICE;  // device scalars and host mirrors disagree
+    const uint64_t n = g->next_id, V = g->st.n_vertices;
+    const SnapLayout L = snap_layout(g->track_mask, V, n, g->h_bump, g->v_bump);
+    hgt_snap* snap = new (std::nothrow) hgt_snap();
+    if (!snap) return HGT_ENOMEM;
+    try {
+        snap->words.assign((sizeof(SnapHeader) + L.total) / 8, 0);
+    } catch (...) {
+        delete snap;
+        return HGT_ENOMEM;
+    }
+    SnapHeader& H = *(SnapHeader*)snap->words.data();
+    std::memcpy(H.magic, kSnapMagic, 8);
+    H.version = kSnapVersion;
+    H.track_mask = g->track_mask;
+    H.n_vertices = (uint32_t)V;
+    H.n_counts = CNT_N;
+    H.window = g->window;
+    H.next_id = n;
+    H.h_bump = g->h_bump;
+    H.v_bump = g->v_bump;
+    H.next_seq = g->next_seq;
+    H.n_live = g->n_live;
+    H.n_inc = g->n_inc;
+    H.last_ts = sc.last_ts;
+    H.payload_bytes = L.total;
+    const void* src[SS_N] = {g->counts.p, g->h_off.p, g->h_len.p, g->h_cap.p, g->h_seq.p, g->h_ts.p, g->free_bm.p,
+                             g->h2v.p, g->hpool.p, g->v_off.p, g->v_len.p, g->v_cap.p, g->v2h.p, g->v2h_ts.p};
+    char* pay = (char*)snap->words.data() + sizeof(SnapHeader);
+    int rc = HGT_OK;
+    for (int i = 0; i < SS_N && rc == HGT_OK; i++)
+        if (L.bytes[i] && hip_failed(hipMemcpyAsync(pay + L.off[i], src[i], L.bytes[i], hipMemcpyDeviceToHost, s),
+                                     "snapshot copy", __LINE__))
+            rc = HGT_EDEVICE;
+    if (hip_failed(hipStreamSynchronize(s), "snapshot sync", __LINE__)) rc = HGT_EDEVICE;
+    if (rc) {
+        delete snap;
+        return rc;
+    }
+    H.checksum = snap_checksum((const uint64_t*)pay, L.total / 8);
+    *out = snap;
+    return HGT_OK;
+}
+
+int hgt_restore(hgt_graph* g, const hgt_snap* snap, void* stream) {
+    if (!g || !snap || snap->words.size() < sizeof(SnapHeader) / 8) return HGT_EINVAL;
+    const SnapHeader& H = *(const SnapHeader*)snap->words.data();
+    if (H.n_vertices != g->st.n_vertices || H.track_mask != g->track_mask || H.window != g->window)
+        return HGT_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    const bool tmp = g->track_mask & (1u << HGT_TRIAD_TEMPORAL), he = g->track_mask & (1u << HGT_TRIAD_HYPEREDGE);
+    const uint64_t n = H.next_id, V = H.n_vertices;
+    const SnapLayout L = snap_layout(H.track_mask, V, n, H.h_bump, H.v_bump);
+    if (hip_failed(hipStreamSynchronize(g->last_stream), "restore wait", __LINE__)) return HGT_EDEVICE;
+    // room first (the ID arrays keep their contents when they grow; the pools
+    // are replaced only once every new one has been allocated)
+    int rc = ensure_id_cap(g, n, s);
+    if (rc) return rc;
+    const uint64_t h2v_b = std::max<uint64_t>(H.h_bump * 4, g->h2v.bytes);
+    const uint64_t v2h_b = std::max<uint64_t>(H.v_bump * 4, g->v2h.bytes);
+    DevBuf nb[4];  // h2v, histograms, v2h, v2h timestamps
+    DevBuf* cur[4] = {&g->h2v, &g->hpool, &g->v2h, &g->v2h_ts};
+    const uint64_t want[4] = {h2v_b, he ? 2 * h2v_b : 0, v2h_b, tmp ? 2 * v2h_b : 0};
+    for (int i = 0; i < 4 && rc == HGT_OK; i++)
+        if (want[i] > cur[i]->bytes) rc = dev_alloc(nb[i], (want[i] + 4095) & ~(size_t)4095);
+    if (rc) {
+        for (DevBuf& b : nb) dev_free(b);
+        return rc;
+    }
+    for (int i = 0; i < 4; i++)
+        if (nb[i].p) {
+            dev_free(*cur[i]);
+            *cur[i] = nb[i];
+        }
+    refresh_view(g);
+    // from here a failure leaves the graph part-way
+    g->poisoned = true;
+    g->sticky = HGT_EPOISONED;
+    void* dst[SS_N] = {g->counts.p, g->h_off.p, g->h_len.p, g->h_cap.p, g->h_seq.p, g->h_ts.p, g->free_bm.p,
+                       g->h2v.p, g->hpool.p, g->v_off.p, g->v_len.p, g->v_cap.p, g->v2h.p, g->v2h_ts.p};
+    const char* pay = (const char*)snap->words.data() + sizeof(SnapHeader);
+    for (int i = 0; i < SS_N; i++)
+        if (L.bytes[i]) HIP_OK(hipMemcpyAsync(dst[i], pay + L.off[i], L.bytes[i], hipMemcpyHostToDevice, s));
+    // IDs from next_id up are fresh: length and capacity 0, not free
+    const uint64_t cap = g->st.id_cap, bm_words = (n + 63) / 64;
+    HIP_OK(hipMemsetAsync(g->h_len.as<uint32_t>() + n, 0, (cap - n) * 4, s));
+    HIP_OK(hipMemsetAsync(g->h_cap.as<uint32_t>() + n, 0, (cap - n) * 4, s));
+    HIP_OK(hipMemsetAsync(g->free_bm.as<uint64_t>() + bm_words, 0, (cap / 64 - bm_words) * 8, s));
+    HIP_OK(hipMemsetAsync(g->counts.as<uint64_t>() + CNT_N, 0, (ACC_N - CNT_N) * 8, s));
+    DevScalars sc{};
+    sc.status = HGT_OK;
+    sc.next_id = n;
+    sc.h_bump = H.h_bump;
+    sc.v_bump = H.v_bump;
+    sc.next_seq = H.next_seq;
+    sc.last_ts = H.last_ts;
+    sc.n_live = H.n_live;
+    sc.n_inc = H.n_inc;
+    HIP_OK(hipMemcpyAsync(g->scal.p, &sc, sizeof sc, hipMemcpyHostToDevice, s));
+    HIP_OK(hipStreamSynchronize(s));
+    g->next_id = n;
+    g->h_bump = H.h_bump;
+    g->v_bump = H.v_bump;
+    g->next_seq = H.next_seq;
+    g->n_live = H.n_live;
+    g->n_inc = H.n_inc;
+    g->last_stream = s;
+    g->poisoned = false;
+    g->sticky = HGT_OK;
+    return HGT_OK;
+}
+
+int hgt_snap_bytes(const hgt_snap* snap, void* out_host, uint64_t cap, uint64_t* n_bytes) {
+    if (!snap || !n_bytes) return HGT_EINVAL;
+    const uint64_t nb = snap->words.size() * 8;
+    *n_bytes = nb;
+    if (out_host) {
+        if (cap < nb) return HGT_EINVAL;
+        std::memcpy(out_host, snap->words.data(), nb);
+    }
+    return HGT_OK;
+}
+
+int hgt_snap_load(const void* bytes, uint64_t n_bytes, hgt_snap** out) {
+    if (!bytes || !out) return HGT_EINVAL;
+    *out = nullptr;
+    if (n_bytes < sizeof(SnapHeader) || n_bytes % 8) return HGT_EINVAL;
+    SnapHeader H;
+    std::memcpy(&H, bytes, sizeof H);
+    if (std::memcmp(H.magic, kSnapMagic, 8) || H.version != kSnapVersion || (H.track_mask & ~7u) ||
+        H.n_vertices == 0 || H.n_vertices > 0x7fffffffu || H.n_counts != CNT_N || H.window < 0 ||
+        H.next_id > 0xfffffff0ull || H.h_bump > (1ull << 40) || H.v_bump > (1ull << 40))
+        return HGT_EINVAL;
+    const SnapLayout L = snap_layout(H.track_mask, H.n_vertices, H.next_id, H.h_bump, H.v_bump);
+    if (H.payload_bytes != L.total || n_bytes != sizeof(SnapHeader) + L.total) return HGT_EINVAL;
+    hgt_snap* snap = new (std::nothrow) hgt_snap();
+    if (!snap) return HGT_ENOMEM;
+    try {
+        snap->words.resize(n_bytes / 8);
+    } catch (...) {
+        delete snap;
+        return HGT_ENOMEM;
+    }
+    std::memcpy(snap->words.data(), bytes, n_bytes);
+    if (snap_checksum(snap->words.data() + sizeof(SnapHeader) / 8, L.total / 8) != H.checksum ||
+        !snap_consistent(snap)) {
+        delete snap;
+        return HGT_EINVAL;
+    }
+    *out = snap;
+    return HGT_OK;
+}
+
+int hgt_snap_free(hgt_snap* snap) {
+    if (!snap) return HGT_EINVAL;
+    delete snap;
     return HGT_OK;
 }
 

@@ -14,7 +14,7 @@ from typing import List, Optional, Sequence
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libhgt.so")
 
-OK, EINVAL, ENOENT, EDUP, EORDER, ENOMEM, ENOTTRACKED, EDEVICE = 0, -1, -2, -3, -4, -5, -6, -7
+OK, EINVAL, ENOENT, EDUP, EORDER, ENOMEM, ENOTTRACKED, EDEVICE, EPOISONED = 0, -1, -2, -3, -4, -5, -6, -7, -8
 HYPEREDGE, INCIDENT_VERTEX, TEMPORAL = 0, 1, 2
 N_CLASSES = {HYPEREDGE: 30, INCIDENT_VERTEX: 3, TEMPORAL: 96}
 MAX_CARD = 8192
@@ -141,7 +141,8 @@ EXPORTS = ["hgt_build", "hgt_apply_batch", "hgt_apply_batch_noalloc", "hgt_apply
            "hgt_tune_flush", "hgt_apply_vertex_ops", "hgt_compact", "hgt_triad_counts", "hgt_sync", "hgt_destroy", "hgt_status_str",
            "hgt_get_info", "hgt_export_h2v", "hgt_export_v2h", "hgt_class_codes", "hgt_profile",
            "hgt_profile_read", "hgt_profile_counters", "hgt_server_create", "hgt_server_add_tenant", "hgt_server_tenant_graph",
-           "hgt_server_submit", "hgt_server_wait", "hgt_server_query", "hgt_server_get_info", "hgt_server_destroy"]
+           "hgt_server_submit", "hgt_server_wait", "hgt_server_query", "hgt_server_get_info", "hgt_server_destroy",
+           "hgt_snapshot", "hgt_restore", "hgt_snap_bytes", "hgt_snap_load", "hgt_snap_free"]
 
 
 def load(path: str = LIB_PATH):
@@ -184,6 +185,11 @@ def load(path: str = LIB_PATH):
     lib.hgt_server_query.argtypes = [P, U64, ctypes.POINTER(I32)]
     lib.hgt_server_get_info.argtypes = [P, ctypes.POINTER(ServerInfo)]
     lib.hgt_server_destroy.argtypes = [P]
+    lib.hgt_snapshot.argtypes = [P, ctypes.POINTER(P), P]
+    lib.hgt_restore.argtypes = [P, P, P]
+    lib.hgt_snap_bytes.argtypes = [P, P, U64, ctypes.POINTER(U64)]
+    lib.hgt_snap_load.argtypes = [P, U64, ctypes.POINTER(P)]
+    lib.hgt_snap_free.argtypes = [P]
     for name in EXPORTS:
         getattr(lib, name).restype = getattr(lib, name).restype or ctypes.c_int
     lib.hgt_status_str.restype = ctypes.c_char_p
@@ -469,9 +475,65 @@ class Graph:
             raise HgtError(rc, "hgt_export_v2h")
         return off, mem[: int(off[-1])]
 
+    # ------------------------------------------------------------------ snapshots
+    def snapshot(self, stream=None) -> "Snapshot":
+        """Host copy of the graph's whole state (see hgt_snapshot)."""
+        out = ctypes.c_void_p()
+        rc = load().hgt_snapshot(self._h, ctypes.byref(out), _stream(stream))
+        if rc != OK:
+            raise HgtError(rc, "hgt_snapshot")
+        return Snapshot(out.value)
+
+    def restore(self, snap: "Snapshot", stream=None):
+        """Replace the graph's state by the snapshot's (also clears a poisoned graph)."""
+        rc = load().hgt_restore(self._h, snap._h, _stream(stream))
+        if rc != OK:
+            raise HgtError(rc, "hgt_restore")
+
     def close(self):
         if self._h and self._h.value:
             load().hgt_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Snapshot:
+    """A graph snapshot held by the library in host memory; to_bytes() gives
+    its documented byte form and from_bytes() loads (and checks) one."""
+
+    def __init__(self, handle: int):
+        self._h = ctypes.c_void_p(handle)
+
+    def to_bytes(self) -> bytes:
+        lib = load()
+        n = ctypes.c_uint64(0)
+        rc = lib.hgt_snap_bytes(self._h, None, 0, ctypes.byref(n))
+        if rc != OK:
+            raise HgtError(rc, "hgt_snap_bytes")
+        buf = ctypes.create_string_buffer(n.value)
+        rc = lib.hgt_snap_bytes(self._h, ctypes.cast(buf, ctypes.c_void_p), n.value, ctypes.byref(n))
+        if rc != OK:
+            raise HgtError(rc, "hgt_snap_bytes")
+        return buf.raw
+
+    @classmethod
+    def from_bytes(cls, data: bytes) -> "Snapshot":
+        lib = load()
+        out = ctypes.c_void_p()
+        buf = ctypes.create_string_buffer(bytes(data), len(data))
+        rc = lib.hgt_snap_load(ctypes.cast(buf, ctypes.c_void_p), len(data), ctypes.byref(out))
+        if rc != OK:
+            raise HgtError(rc, "hgt_snap_load")
+        return cls(out.value)
+
+    def close(self):
+        if self._h and self._h.value:
+            load().hgt_snap_free(self._h)
             self._h = ctypes.c_void_p()
 
     def __del__(self):

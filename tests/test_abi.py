@@ -56,7 +56,7 @@ def test_class_tables_agree_with_oracle():
 def test_status_strings():
     lib = ctypes.CDLL(_lib_path())
     lib.hgt_status_str.restype = ctypes.c_char_p
-    for code in range(0, -8, -1):
+    for code in range(0, -9, -1):
         assert lib.hgt_status_str(code)
     assert lib.hgt_apply_batch(None, None, 0, None, None, 0, None, 0, None, None) == -1
 

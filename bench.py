@@ -43,7 +43,7 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "hyperedge updates/sec incl. triad-count update; p50/p99 batch latency"
 
 
-def parse():
+def parse(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=9)
@@ -67,8 +67,12 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-static-baseline", action="store_true",
                     help="skip the oracle's one-thread static recount of the scaled-down workload")
+    ap.add_argument("--legs", default="temporal,batched",
+                    help="medium only: further workloads measured in the same run and reported in the same JSON "
+                         "line under 'legs' (temporal at full size; batched, one call per graph against one call "
+                         "for all); 'none' for none")
     ap.add_argument("--quiet", action="store_true")
-    return ap.parse_args()
+    return ap.parse_args(argv)
 
 
 def log(args, *a):
@@ -268,14 +272,18 @@ def bench_single(args, st, track, name, workload):
     }
 
 
-def bench_batched(args):
+BATCHED_VARIANTS = ("plain", "stream", "graph", "tuning", "tuned")
+
+
+def bench_batched(args, only=BATCHED_VARIANTS):
     """256 graphs; each round applies every graph's next batch.  Identical
     copies take the same rounds (`warmup` untimed, then `steps` timed): one
     call per graph (plain); one call for all with the kernels launched one by
     one (stream); the same launched as one captured HIP graph per round
     (graph); and the graph launch with the autotuner's choices (tuned), after a
     pass over the same rounds on a copy of its own in which the tuner times its
-    choices.  The rounds after the timed ones are profiled on the stream copy."""
+    choices.  The rounds after the timed ones are profiled on the stream copy.
+    `only` keeps a subset of the variants (plain and stream always run)."""
     import numpy as np
     import torch
     from paper_2512_21009_amd import hgt
@@ -309,8 +317,11 @@ def bench_batched(args):
     ups = [sum(st.batches[k].n_updates for st in sts) for k in range(n_b)]
     variants = [("plain", None), ("stream", {}), ("graph", {"graph": True}),
                 ("tuning", {"graph": True, "autotune": True}), ("tuned", {"graph": True, "autotune": True})]
+    variants = [v for v in variants if v[0] in only or v[0] in ("plain", "stream")]
+    names = [v[0] for v in variants]
     lat, counts, prof = {}, {}, {}
     build_s = 0.0
+    settled = None
     for name, kw in variants:
         t0 = time.perf_counter()
         gs = build_all()
@@ -353,16 +364,17 @@ def bench_batched(args):
                   f"(build {build_s:.2f}s)")
         if name == "tuning":
             settled = hgt.tune_flush()
-    for name in ("plain", "graph", "tuning", "tuned"):
-        assert counts[name] == counts["stream@timed"], f"{name} and stream counts differ"
+    for name in names:
+        if name != "stream":
+            assert counts[name] == counts["stream@timed"], f"{name} and stream counts differ"
     total = sum(sum(c) for c in counts["stream@timed"])
     calibration_copy()
     n_upd = sum(ups[n_timed_beg:n_timed_end])
     rate = {name: n_upd / sum(lat[name]) for name, _ in variants}
     ms = {name: np.array(lat[name]) * 1e3 for name, _ in variants}
-    best = max(("stream", "graph", "tuned"), key=lambda n: rate[n])
-    log(args, f"plain {rate['plain']:,.0f}, stream {rate['stream']:,.0f}, graph {rate['graph']:,.0f}, "
-              f"tuned {rate['tuned']:,.0f} updates/s; tuner keys settled: {settled}")
+    best = max((n for n in ("stream", "graph", "tuned") if n in names), key=lambda n: rate[n])
+    log(args, ", ".join(f"{n} {rate[n]:,.0f}" for n in names if n != "tuning") +
+        f" updates/s; tuner keys settled: {settled}")
     log_profile(args, prof)
 
     def leg(n):
@@ -379,7 +391,7 @@ def bench_batched(args):
                    "scale": sc, "round_updates": int(np.mean(ups[n_timed_beg:n_timed_end])),
                    "build_s_per_copy": round(build_s, 3), "launch": best,
                    "he_triads_total": int(total)},
-        "plain": leg("plain"), "stream": leg("stream"), "graph": leg("graph"), "tuned": leg("tuned"),
+        **{n: leg(n) for n in names if n != "tuning"},
         "tuner_keys_settled": settled,
         "speedup_vs_plain": round(rate[best] / rate["plain"], 3),
         "roofline": roofline_of(prof),
@@ -747,6 +759,46 @@ def cpu_baseline(args, st, families):
     return out
 
 
+WL_TEMPORAL = ("temporal: 500k vertices, 4M hyperedges, card power-law 2.2 on [2,128], Poisson arrivals 1e3/s, "
+               "batches of 200k arrivals, expiry 3600 s, temporal triads within 600 s")
+LEG_KEYS = ("value", "unit", "steps", "warmup", "ms_per_step", "p50_ms", "p99_ms", "roofline")
+
+
+def run_legs(args):
+    """Further workloads measured after the headline one, each on a fresh graph
+    (or set of graphs) with one untimed and two timed steps and one profiled
+    step: `temporal` (the temporal configuration at the run's scale) and
+    `batched` (the 256-graph rounds: one call per graph, one call for all
+    launched kernel by kernel, and one call launched as a captured HIP graph,
+    all on the same rounds).  A leg that fails reports its error and never
+    takes the headline line down."""
+    import argparse
+    from paper_2512_21009_amd import workloads as W
+    legs = {}
+    for name in [s for s in args.legs.split(",") if s]:
+        la = argparse.Namespace(**vars(args))
+        la.warmup, la.steps, la.prof_steps, la.phases = 1, 2, 1, False
+        t0 = time.perf_counter()
+        try:
+            if name == "temporal":
+                st = W.temporal(scale=la.scale, n_batches=la.warmup + la.steps + la.prof_steps)
+                r = bench_single(la, st, ("temporal",), "temporal", WL_TEMPORAL)
+                leg = {k: r[k] for k in LEG_KEYS}
+            elif name == "batched":
+                r, _ = bench_batched(la, only=("plain", "stream", "graph"))
+                leg = {k: r[k] for k in LEG_KEYS + ("plain", "stream", "graph", "speedup_vs_plain")}
+                leg["launch"] = r["config"]["launch"]
+            else:
+                raise ValueError(f"unknown leg {name!r}")
+            leg["workload"] = r["config"]["workload"]
+        except Exception as e:  # noqa: BLE001 -- reported in the line
+            leg = {"error": f"{type(e).__name__}: {e}"}
+        leg["wall_s"] = round(time.perf_counter() - t0, 1)
+        log(args, f"leg {name}: {leg.get('value', leg.get('error'))} ({leg['wall_s']} s)")
+        legs[name] = leg
+    return legs
+
+
 def W_medium(scale):
     from paper_2512_21009_amd import workloads as W
     return W.medium(q=1.0e4, scale=scale, n_batches=1)
@@ -803,14 +855,15 @@ def main():
         else:
             st = W.temporal(scale=args.scale, n_batches=n_b)
             track = ("temporal",)
-            wl = ("temporal: 500k vertices, 4M hyperedges, card power-law 2.2 on [2,128], Poisson arrivals 1e3/s, "
-                  "batches of 200k arrivals, expiry 3600 s, temporal triads within 600 s")
+            wl = WL_TEMPORAL
         log(args, f"generated {st.initial.n} hyperedges, {n_b} batches in {time.perf_counter() - t0:.1f}s")
         out = bench_single(args, st, track, args.config, wl)
         # no oracle sample on the literal popularity: its by-definition deltas at the hub
         # take the CPU far past the baseline's budget
         cpu_st, fam = (None, None) if args.config.startswith("literal") else (st, track)
     out["cpu_baseline"] = None if (args.no_cpu_baseline or cpu_st is None) else cpu_baseline(args, cpu_st, fam)
+    if args.config == "medium" and args.legs != "none":
+        out["legs"] = run_legs(args)
     print(json.dumps(out), flush=True)
 
 

@@ -57,3 +57,49 @@ def test_committed_traffic_matches_the_sources():
         with open(os.path.join(root, "profiles", f"{wl}_traffic.json")) as f:
             assert json.load(f)["source_sha256"] == bench.source_digest(), wl
         assert bench.traffic_of(wl, group) > 0
+
+
+def _fake_result(workload, **extra):
+    r = {k: 1 for k in bench.LEG_KEYS}
+    r["config"] = {"workload": workload, "launch": "graph"}
+    r.update(extra)
+    return r
+
+
+def test_legs_are_reported_and_a_failing_leg_is_contained(monkeypatch):
+    """The default (Medium) line carries a temporal and a batched leg; a leg
+    that raises reports its error instead of taking the line down."""
+    import types
+    import paper_2512_21009_amd.workloads as W
+    calls = []
+
+    def fake_single(la, st, track, name, wl):
+        calls.append(("single", la.warmup, la.steps, la.prof_steps, track, name))
+        return _fake_result(wl)
+
+    def fake_batched(la, only):
+        calls.append(("batched", la.warmup, la.steps, la.prof_steps, tuple(only)))
+        return _fake_result("b", plain={"value": 1}, stream={"value": 6}, graph={"value": 6},
+                            speedup_vs_plain=6.0), []
+
+    monkeypatch.setattr(bench, "bench_single", fake_single)
+    monkeypatch.setattr(bench, "bench_batched", fake_batched)
+    monkeypatch.setattr(W, "temporal", lambda scale, n_batches: types.SimpleNamespace(scale=scale, n=n_batches))
+    args = bench.parse(["--quiet"])
+    assert args.legs == "temporal,batched"
+    legs = bench.run_legs(args)
+    assert set(legs) == {"temporal", "batched"}
+    assert legs["temporal"]["workload"] == bench.WL_TEMPORAL
+    assert legs["batched"]["speedup_vs_plain"] == 6.0 and legs["batched"]["launch"] == "graph"
+    assert ("single", 1, 2, 1, ("temporal",), "temporal") in calls
+    assert ("batched", 1, 2, 1, ("plain", "stream", "graph")) in calls
+    # the caller's arguments are left as they were
+    assert (args.warmup, args.steps) == (1, 9)
+
+    def broken(la, only):
+        raise RuntimeError("no box")
+
+    monkeypatch.setattr(bench, "bench_batched", broken)
+    legs = bench.run_legs(bench.parse(["--quiet", "--legs", "batched,nosuch"]))
+    assert legs["batched"]["error"] == "RuntimeError: no box"
+    assert "unknown leg" in legs["nosuch"]["error"]

@@ -81,3 +81,17 @@ def test_tune_cache_is_read_and_filtered(tmp_path):
                        timeout=120)
     assert r.returncode == 0, r.stderr[-2000:]
     assert r.stdout.strip().splitlines()[-1] == "2"
+
+
+def test_binding_status_codes_match_the_header():
+    """Every HGT_E* code the header defines has the same value in the Python
+    binding, and the library names each one."""
+    from paper_2512_21009_amd import hgt
+    text = open(HEADER).read()
+    codes = {m.group(1): int(m.group(2)) for m in re.finditer(r"#define HGT_(E[A-Z]+|OK) \(?(-?\d+)\)?", text)}
+    assert codes["OK"] == 0 and len(codes) >= 9
+    lib = ctypes.CDLL(_lib_path())
+    lib.hgt_status_str.restype = ctypes.c_char_p
+    for name, value in codes.items():
+        assert getattr(hgt, name) == value, name
+        assert lib.hgt_status_str(value) != b"unknown status", name

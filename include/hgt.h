@@ -381,7 +381,9 @@ int hgt_snap_bytes(const hgt_snap* snap, void* out_host, uint64_t cap, uint64_t*
  * ascending and names vertices below n_vertices; every vertex's list lies
  * inside the used v2h words, is strictly ascending and names live IDs; the
  * two maps hold the same incidences; n_live, n_incidences and the v2h
- * timestamps agree with the ID table.  HGT_EINVAL when any check fails. */
+ * timestamps agree with the ID table.  The counts and the neighbour
+ * histograms are covered by the checksum only (the kernels use them as
+ * numbers, never as indices).  HGT_EINVAL when any check fails. */
 int hgt_snap_load(const void* bytes, uint64_t n_bytes, hgt_snap** out);
 
 /* Releases a snapshot. */

@@ -204,3 +204,43 @@ def test_structural_damage_is_refused(lib, case):
         hdr = lambda h: h.__setitem__("last_ts", 19)  # noqa: E731
     assert load(lib, s.encode())[0] == 0 or case in ("member_out_of_range", "seq_not_below_next")
     assert load(lib, s.encode(edit=he, header_edit=hdr))[0] == EINVAL, case
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_random_graphs_load_and_damage_is_refused(lib, seed):
+    """Seeded random states spanning several bitmap words (some IDs free, rows
+    up to 12 members): each loads; then one incidence is dropped from the v2h
+    map, one member is pushed out of range, or a free ID is marked live, with
+    header and checksum kept consistent, and each is refused."""
+    rng = np.random.default_rng(seed)
+    s = Spec(n_vertices=40, track=HE | IV if seed % 2 else HE | IV | TMP)
+    n = 150 + seed
+    s.rows = [None if rng.random() < 0.2 else sorted(rng.choice(40, rng.integers(1, 13), replace=False).tolist())
+              for _ in range(n)]
+    s.ts = sorted(rng.integers(0, 1000, n).tolist())
+    s.seq = list(range(n))
+    s.next_seq = n
+    assert load(lib, s.encode())[0] == 0
+    live = [i for i, r in enumerate(s.rows) if r is not None]
+    victim = int(rng.choice(live))
+    v = s.rows[victim][0]
+
+    def drop_incidence(sec):  # the victim disappears from its first member's list
+        o, ln = int(sec["v_off"][v]), int(sec["v_len"][v])
+        lst = [x for x in sec["v2h"][o:o + ln] if x != victim]
+        sec["v2h"][o:o + ln - 1] = lst
+        sec["v_len"][v] = ln - 1
+
+    def member_out_of_range(sec):
+        sec["h2v"][int(sec["h_off"][victim]) + len(s.rows[victim]) - 1] = 40
+
+    free = [i for i, r in enumerate(s.rows) if r is None]
+
+    def free_marked_live(sec):
+        i = free[0]
+        sec["free_bm"][i >> 6] &= ~np.uint64(1 << (i & 63))
+
+    for edit in (drop_incidence, member_out_of_range, free_marked_live):
+        # with free_marked_live, n_live is raised too, so only the structure is wrong
+        hdr = (lambda h: h.__setitem__("n_live", h["n_live"] + 1)) if edit is free_marked_live else None
+        assert load(lib, s.encode(edit=edit, header_edit=hdr))[0] == EINVAL, edit.__name__

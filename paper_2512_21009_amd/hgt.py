@@ -531,6 +531,16 @@ class Snapshot:
             raise HgtError(rc, "hgt_snap_load")
         return cls(out.value)
 
+    def save(self, path: str):
+        """Write the byte form to a file (a checkpoint another process can restore)."""
+        with open(path, "wb") as f:
+            f.write(self.to_bytes())
+
+    @classmethod
+    def load_file(cls, path: str) -> "Snapshot":
+        with open(path, "rb") as f:
+            return cls.from_bytes(f.read())
+
     def close(self):
         if self._h and self._h.value:
             load().hgt_snap_free(self._h)

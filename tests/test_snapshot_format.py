@@ -244,3 +244,22 @@ def test_random_graphs_load_and_damage_is_refused(lib, seed):
         # with free_marked_live, n_live is raised too, so only the structure is wrong
         hdr = (lambda h: h.__setitem__("n_live", h["n_live"] + 1)) if edit is free_marked_live else None
         assert load(lib, s.encode(edit=edit, header_edit=hdr))[0] == EINVAL, edit.__name__
+
+
+def test_binding_saves_and_loads_checkpoint_files(tmp_path):
+    """Snapshot.load_file / save (the binding's checkpoint files) keep the
+    bytes exactly, and a damaged file is refused."""
+    from paper_2512_21009_amd import hgt
+    _lib_path()
+    data = Spec().encode()
+    src = tmp_path / "a.snap"
+    src.write_bytes(data)
+    snap = hgt.Snapshot.load_file(str(src))
+    dst = tmp_path / "b.snap"
+    snap.save(str(dst))
+    assert dst.read_bytes() == data
+    snap.close()
+    src.write_bytes(data[:-8])
+    with pytest.raises(hgt.HgtError) as e:
+        hgt.Snapshot.load_file(str(src))
+    assert e.value.code == hgt.EINVAL
